@@ -1,0 +1,538 @@
+/*
+ * Oracle for BatMap pair-support counting -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow CPU code that states what the GPU path must compute.  Only the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it; the product library never links or calls it, and it shares no code
+ * with the HIP sources.
+ *
+ * Part 1 is the definition itself (Sec. I, "Set representations"): the
+ * support of the pair {i,j} is |S_i cap S_j|, computed by merging the two
+ * sorted tidlists (Sec. I and Sec. IV-B).  The method is exact, so this is
+ * the result the GPU must match bit for bit.
+ *
+ * Part 2 follows the method step by step in the paper's order so that the
+ * readings of the paper can be checked before any kernel exists:
+ *   - parameters s, r_0, r_i (Sec. III-A, compression; Sec. II "Our adaptation"),
+ *   - the 2-of-3 cuckoo INSERT called twice per element and its failure
+ *     policy (Sec. II-A),
+ *   - the 8-bit slot encoding with the indicator bit as the MSB and the
+ *     block layout of the hash functions (Sec. III-A, Fig. 3, Fig. 4),
+ *   - the branch-free 4-slot word compare (Sec. III-A, the p / p' formulas),
+ *   - the failed-insertion correction (Sec. III-C, "Failed insertions").
+ *   It also holds a structural checker for BatMaps in canonical byte form.
+ *
+ * Readings where the paper is silent or loose (numbered as in the design doc):
+ *   C1 indicator bit = 1 on the copy whose other copy sits in the cyclically
+ *      preceding table (Fig. 3);
+ *   C3 the empty slot is the byte 0x7F (code 127, indicator 0), and
+ *      s = min{s : m <= 127 * 2^s} so that no element code is 127;
+ *   C5 r_i = max(r_0, 2^ceil(log2(2|S_i|))), r_0 a power of two >= 2^s
+ *      common to all maps of an instance;
+ *   C8 when re-inserting the nestless element after a failure fails again,
+ *      the element left nestless loses its remaining copy and is recorded as
+ *      failed;
+ *   C9 the correction adds one per transaction b per pair {a,c} with a or c
+ *      failed at b (a multiset, not a set).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_EMPTY 0xFFFFFFFFu
+
+/* ---------------------------------------------------------------------- */
+/* Part 1: the definition                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* |A cap B| of two strictly increasing lists by a two-pointer merge. */
+uint64_t orc_merge_count(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb)
+{
+    uint64_t i = 0, j = 0, c = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) {
+            i++;
+        } else if (a[i] > b[j]) {
+            j++;
+        } else {
+            c++;
+            i++;
+            j++;
+        }
+    }
+    return c;
+}
+
+/* Index of the pair (i,j), i<j, in the row-major packed upper triangle. */
+static uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
+{
+    return i * n - i * (i + 1) / 2 + (j - i - 1);
+}
+
+/* Supports of all pairs i<j, packed upper triangle, n(n-1)/2 entries. */
+void orc_all_pairs(uint32_t n, const uint64_t *off, const uint32_t *tids, uint32_t *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        for (uint32_t j = (uint32_t)i + 1; j < n; j++) {
+            out[packed_index(n, (uint64_t)i, j)] = (uint32_t)orc_merge_count(
+                tids + off[i], off[i + 1] - off[i], tids + off[j], off[j + 1] - off[j]);
+        }
+    }
+    (void)nthreads;
+}
+
+/* Full rows: out[r*n + j] = |S_rows[r] cap S_j| for every j (diagonal included). */
+void orc_rows(uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *rows, uint32_t nrows,
+              uint32_t *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+#endif
+    for (int64_t r = 0; r < (int64_t)nrows; r++) {
+        for (int64_t j = 0; j < (int64_t)n; j++) {
+            uint32_t i = rows[r];
+            out[(uint64_t)r * n + (uint64_t)j] = (uint32_t)orc_merge_count(
+                tids + off[i], off[i + 1] - off[i], tids + off[j], off[j + 1] - off[j]);
+        }
+    }
+    (void)nthreads;
+}
+
+/* Pairs with support >= sigma as (i, j, support) triples sorted by (i, j).
+ * Returns the number of such pairs; writes at most `cap` triples. */
+uint64_t orc_frequent_pairs(uint32_t n, const uint64_t *off, const uint32_t *tids, uint32_t sigma,
+                            uint32_t *out, uint64_t cap)
+{
+    uint64_t cnt = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        for (uint32_t j = i + 1; j < n; j++) {
+            uint64_t c = orc_merge_count(tids + off[i], off[i + 1] - off[i], tids + off[j], off[j + 1] - off[j]);
+            if (c >= sigma) {
+                if (cnt < cap) {
+                    out[3 * cnt + 0] = i;
+                    out[3 * cnt + 1] = j;
+                    out[3 * cnt + 2] = (uint32_t)c;
+                }
+                cnt++;
+            }
+        }
+    }
+    return cnt;
+}
+
+/* Packed upper triangle over the query order: entry (p,q), p<q, is
+ * |S_items[p] cap S_items[q]|. */
+void orc_subset(uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *items, uint32_t k,
+                uint32_t *out)
+{
+    (void)n;
+    for (uint32_t p = 0; p < k; p++) {
+        for (uint32_t q = p + 1; q < k; q++) {
+            uint32_t a = items[p], b = items[q];
+            out[packed_index(k, p, q)] = (uint32_t)orc_merge_count(tids + off[a], off[a + 1] - off[a],
+                                                                   tids + off[b], off[b + 1] - off[b]);
+        }
+    }
+}
+
+/* Horizontal -> vertical format (Sec. I): S_a = { b : a in T_b }, sorted,
+ * duplicates of an item inside one transaction ignored.  Returns 0, or -2 if
+ * an item is >= n.  soff has n+1 entries; stids must hold nnz entries. */
+int orc_transpose(uint32_t m, const uint64_t *toff, const uint32_t *items, uint32_t n, uint64_t *soff,
+                  uint32_t *stids)
+{
+    uint64_t nnz = toff[m];
+    for (uint64_t k = 0; k < nnz; k++)
+        if (items[k] >= n)
+            return -2;
+    uint64_t *cnt = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    uint32_t *last = (uint32_t *)malloc(((size_t)n + 1) * sizeof(uint32_t));
+    for (uint32_t a = 0; a < n; a++)
+        last[a] = ORC_EMPTY;
+    /* count, skipping repeats of an item within the same transaction */
+    for (uint32_t b = 0; b < m; b++) {
+        for (uint64_t k = toff[b]; k < toff[b + 1]; k++) {
+            uint32_t a = items[k];
+            if (last[a] != b) {
+                last[a] = b;
+                cnt[a]++;
+            }
+        }
+    }
+    soff[0] = 0;
+    for (uint32_t a = 0; a < n; a++)
+        soff[a + 1] = soff[a] + cnt[a];
+    for (uint32_t a = 0; a < n; a++) {
+        cnt[a] = soff[a];
+        last[a] = ORC_EMPTY;
+    }
+    /* transactions are visited in increasing b, so each list comes out sorted */
+    for (uint32_t b = 0; b < m; b++) {
+        for (uint64_t k = toff[b]; k < toff[b + 1]; k++) {
+            uint32_t a = items[k];
+            if (last[a] != b) {
+                last[a] = b;
+                stids[cnt[a]++] = b;
+            }
+        }
+    }
+    free(cnt);
+    free(last);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Part 2: the method, step by step                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Sec. III-A: the 7 most significant bits of pi_t(x) are stored, so
+ * m - 1 must fit in 7 bits after shifting right by s.  With code 127
+ * reserved for the empty slot (reading C3): s = min{s : m <= 127 * 2^s}. */
+uint32_t orc_shift(uint32_t m)
+{
+    uint32_t s = 0;
+    while ((uint64_t)m > (uint64_t)127 << s)
+        s++;
+    return s;
+}
+
+/* Sec. II "Our adaptation" and Sec. III-A: r_i is a power of two, about
+ * 2|S_i| (2 * 2^ceil(log|S_i|)), never below the common r_0 (reading C5). */
+uint32_t orc_r_for(uint64_t size, uint32_t r0)
+{
+    uint64_t r = 1;
+    while (r < 2 * size)
+        r <<= 1;
+    return r < r0 ? r0 : (uint32_t)r;
+}
+
+typedef struct {
+    uint32_t m, s, r0, r; /* universe, shift, smallest domain, this map's domain */
+    const uint32_t *perm[3];
+    uint32_t *T; /* 3 tables of r entries, T[t*r + q] */
+} orc_map;
+
+static uint32_t h(const orc_map *B, int t, uint32_t x)
+{
+    return B->perm[t][x] & (B->r - 1); /* h_t^(i)(x) = pi_t(x) mod r_i */
+}
+
+/* INSERT of Sec. II-A: push tau through A_1, A_2, A_3, A_1, ... swapping
+ * with the occupant; stop at an empty slot; give up after max_loop rounds
+ * and return the element left nestless. */
+static uint32_t insert(orc_map *B, uint32_t tau, uint32_t max_loop)
+{
+    for (uint32_t loop = 0; loop < max_loop; loop++) {
+        for (int t = 0; t < 3; t++) {
+            uint32_t *slot = &B->T[(uint64_t)t * B->r + h(B, t, tau)];
+            uint32_t tmp = *slot;
+            *slot = tau;
+            tau = tmp;
+            if (tau == ORC_EMPTY)
+                return ORC_EMPTY;
+        }
+    }
+    return tau;
+}
+
+static void delete_all(orc_map *B, uint32_t x)
+{
+    for (int t = 0; t < 3; t++) {
+        uint32_t *slot = &B->T[(uint64_t)t * B->r + h(B, t, x)];
+        if (*slot == x)
+            *slot = ORC_EMPTY;
+    }
+}
+
+/* Sec. II-A, after the INSERT listing: insert each element twice; when an
+ * insertion fails, delete every copy of x and re-insert the nestless
+ * element unless it is x itself.  Reading C8 covers a failing re-insert. */
+static void build_one(orc_map *B, const uint32_t *set, uint32_t size, uint32_t max_loop, uint32_t *failed,
+                      uint32_t *n_failed)
+{
+    for (uint32_t k = 0; k < size; k++) {
+        uint32_t x = set[k];
+        for (int copy = 0; copy < 2; copy++) {
+            uint32_t tau = insert(B, x, max_loop);
+            if (tau == ORC_EMPTY)
+                continue;
+            delete_all(B, x);
+            failed[(*n_failed)++] = x;
+            if (tau != x) {
+                uint32_t z = insert(B, tau, max_loop);
+                if (z != ORC_EMPTY) {
+                    delete_all(B, z);
+                    failed[(*n_failed)++] = z;
+                }
+            }
+            break; /* x is out; its second insertion is skipped */
+        }
+    }
+}
+
+/* Fig. 4 layout: slot index of hash value q (= pi_t(x) mod r) in table t:
+ * 3 r_0 floor(q / r_0) + t r_0 + (q mod r_0)   (tables numbered from 0). */
+static uint64_t slot_of(uint32_t r0, int t, uint32_t q)
+{
+    return (uint64_t)3 * r0 * (q / r0) + (uint64_t)t * r0 + (q % r0);
+}
+
+/* Encoded byte of each occupied slot: indicator (reading C1) in bit 7, the
+ * 7 high bits of pi_t(x) (pi_t(x) >> s) below it; empty slots 0x7F (C3). */
+static void encode(const orc_map *B, uint8_t *bytes)
+{
+    uint64_t total = (uint64_t)3 * B->r;
+    for (uint64_t v = 0; v < total; v++)
+        bytes[v] = 0x7F;
+    for (int t = 0; t < 3; t++) {
+        for (uint32_t q = 0; q < B->r; q++) {
+            uint32_t x = B->T[(uint64_t)t * B->r + q];
+            if (x == ORC_EMPTY)
+                continue;
+            int prev = (t + 2) % 3;
+            uint32_t other = B->T[(uint64_t)prev * B->r + h(B, prev, x)];
+            uint8_t bit = (other == x) ? 1 : 0;
+            uint8_t code = (uint8_t)(B->perm[t][x] >> B->s);
+            bytes[slot_of(B->r0, t, q)] = (uint8_t)((bit << 7) | code);
+        }
+    }
+}
+
+/* Build the BatMap of one set in canonical byte form (3r bytes).
+ * Returns the number of failed elements written to `failed` (capacity 2*size). */
+uint32_t orc_batmap_build(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                          const uint32_t *p2, const uint32_t *set, uint32_t size, uint32_t max_loop, uint8_t *bytes,
+                          uint32_t *failed)
+{
+    orc_map B;
+    B.m = m;
+    B.s = s;
+    B.r0 = r0;
+    B.r = r;
+    B.perm[0] = p0;
+    B.perm[1] = p1;
+    B.perm[2] = p2;
+    B.T = (uint32_t *)malloc((size_t)3 * r * sizeof(uint32_t));
+    for (uint64_t v = 0; v < (uint64_t)3 * r; v++)
+        B.T[v] = ORC_EMPTY;
+    uint32_t nf = 0;
+    build_one(&B, set, size, max_loop, failed, &nf);
+    encode(&B, bytes);
+    free(B.T);
+    return nf;
+}
+
+/* Sec. III-A word compare of 4 slots packed little-endian in a 32-bit word:
+ *   p  = ((x xor y) or 80808080) - 01010101
+ *   p' = not p and (x or y) and 80808080
+ *   count = ((p' >> 7) + (p' >> 15) + (p' >> 23) + (p' >> 31)) and 7 */
+uint32_t orc_swar_word(uint32_t x, uint32_t y)
+{
+    uint32_t p = ((x ^ y) | 0x80808080u) - 0x01010101u;
+    uint32_t pp = (p ^ 0xFFFFFFFFu) & ((x | y) & 0x80808080u);
+    return ((pp >> 7) + (pp >> 15) + (pp >> 23) + (pp >> 31)) & 7u;
+}
+
+/* Sec. II: compare every slot of the larger map with the slot of the smaller
+ * map at the same position modulo 3 r_small (r_small divides r_large). */
+uint64_t orc_batmap_compare(const uint8_t *bi, uint32_t ri, const uint8_t *bj, uint32_t rj)
+{
+    if (ri > rj) {
+        const uint8_t *tb = bi;
+        bi = bj;
+        bj = tb;
+        uint32_t tr = ri;
+        ri = rj;
+        rj = tr;
+    }
+    uint64_t wi = (uint64_t)3 * ri / 4, wj = (uint64_t)3 * rj / 4;
+    uint64_t c = 0;
+    for (uint64_t w = 0; w < wj; w++) {
+        uint32_t x, y;
+        memcpy(&x, bj + 4 * w, 4);
+        memcpy(&y, bi + 4 * (w % wi), 4);
+        c += orc_swar_word(x, y);
+    }
+    return c;
+}
+
+/* The whole method for all pairs i<j of one instance: BatMaps from the
+ * sets (perms and max_loop given), word compares over max width, then the
+ * Sec. III-C correction. out: packed upper triangle.  Returns the total
+ * number of failed elements.  r0 is the common smallest domain (>= 2^s). */
+uint64_t orc_batmap_all_pairs(uint32_t m, uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *p0,
+                              const uint32_t *p1, const uint32_t *p2, uint32_t r0, uint32_t max_loop, uint32_t *out)
+{
+    uint32_t s = orc_shift(m);
+    uint32_t *rs = (uint32_t *)malloc(((size_t)n + 1) * sizeof(uint32_t));
+    uint8_t **maps = (uint8_t **)malloc(((size_t)n + 1) * sizeof(uint8_t *));
+    uint32_t **fails = (uint32_t **)malloc(((size_t)n + 1) * sizeof(uint32_t *));
+    uint32_t *nfail = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+    uint64_t total_failed = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t size = (uint32_t)(off[i + 1] - off[i]);
+        rs[i] = orc_r_for(size, r0);
+        maps[i] = (uint8_t *)malloc((size_t)3 * rs[i]);
+        fails[i] = (uint32_t *)malloc(((size_t)2 * size + 1) * sizeof(uint32_t));
+        nfail[i] = orc_batmap_build(m, s, r0, rs[i], p0, p1, p2, tids + off[i], size, max_loop, maps[i], fails[i]);
+        total_failed += nfail[i];
+    }
+    for (uint32_t i = 0; i < n; i++)
+        for (uint32_t j = i + 1; j < n; j++)
+            out[packed_index(n, i, j)] = (uint32_t)orc_batmap_compare(maps[i], rs[i], maps[j], rs[j]);
+
+    /* Sec. III-C: F_b = items whose insertion of b failed, A_b = all items
+     * of transaction b; each pair {a,c}, a in F_b, c in A_b, gains one per
+     * b (reading C9), counted once when both a and c failed at b. */
+    uint8_t *failed_at = (uint8_t *)calloc((size_t)m * n + 1, 1); /* [b*n + a] */
+    for (uint32_t a = 0; a < n; a++)
+        for (uint32_t k = 0; k < nfail[a]; k++)
+            failed_at[(uint64_t)fails[a][k] * n + a] = 1;
+    uint64_t *aoff = (uint64_t *)malloc(((size_t)m + 1) * sizeof(uint64_t));
+    uint32_t *aitems = (uint32_t *)malloc((off[n] + 1) * sizeof(uint32_t));
+    {
+        uint64_t *cnt = (uint64_t *)calloc((size_t)m + 1, sizeof(uint64_t));
+        for (uint64_t k = 0; k < off[n]; k++)
+            cnt[tids[k]]++;
+        aoff[0] = 0;
+        for (uint32_t b = 0; b < m; b++)
+            aoff[b + 1] = aoff[b] + cnt[b];
+        for (uint32_t b = 0; b < m; b++)
+            cnt[b] = aoff[b];
+        for (uint32_t a = 0; a < n; a++)
+            for (uint64_t k = off[a]; k < off[a + 1]; k++)
+                aitems[cnt[tids[k]]++] = a;
+        free(cnt);
+    }
+    for (uint32_t b = 0; b < m; b++) {
+        for (uint64_t ka = aoff[b]; ka < aoff[b + 1]; ka++) {
+            uint32_t a = aitems[ka];
+            if (!failed_at[(uint64_t)b * n + a])
+                continue;
+            for (uint64_t kc = aoff[b]; kc < aoff[b + 1]; kc++) {
+                uint32_t c = aitems[kc];
+                if (c == a)
+                    continue;
+                if (failed_at[(uint64_t)b * n + c] && c < a)
+                    continue; /* both failed at b: the pair is added from min(a,c) only */
+                uint32_t lo = a < c ? a : c, hi = a < c ? c : a;
+                out[packed_index(n, lo, hi)] += 1;
+            }
+        }
+    }
+    free(failed_at);
+    free(aoff);
+    free(aitems);
+    for (uint32_t i = 0; i < n; i++) {
+        free(maps[i]);
+        free(fails[i]);
+    }
+    free(maps);
+    free(fails);
+    free(nfail);
+    free(rs);
+    return total_failed;
+}
+
+/* Structural check of one BatMap in canonical byte form against its set:
+ * every byte is 0x7F or decodes (position + code) to pi_t(x) of an element
+ * x of S minus F; each such x is held exactly twice, in two different
+ * tables, with indicator bits as in Fig. 3 (reading C1); no element of F is
+ * held; F is a subset of S.  inv0..2 are the inverse permutations.
+ * Returns 0 when valid, else a positive code naming the first violation. */
+int orc_batmap_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                     const uint32_t *p2, const uint32_t *inv0, const uint32_t *inv1, const uint32_t *inv2,
+                     const uint32_t *set, uint32_t size, const uint32_t *failed, uint32_t nfailed,
+                     const uint8_t *bytes)
+{
+    const uint32_t *perm[3] = {p0, p1, p2};
+    const uint32_t *inv[3] = {inv0, inv1, inv2};
+    int rc = 0;
+    if (r < r0 || (r & (r - 1)) != 0 || (r0 & (r0 - 1)) != 0 || ((uint64_t)1 << s) > r0)
+        return 1;
+    /* state per element of the set: 0 absent from F, 1 failed */
+    uint8_t *in_set = (uint8_t *)calloc((size_t)m + 1, 1);
+    uint8_t *is_failed = (uint8_t *)calloc((size_t)m + 1, 1);
+    uint8_t *seen_tables = (uint8_t *)calloc((size_t)m + 1, 1); /* bit t set when held in table t */
+    for (uint32_t k = 0; k < size; k++)
+        in_set[set[k]] = 1;
+    for (uint32_t k = 0; k < nfailed; k++) {
+        if (failed[k] >= m || !in_set[failed[k]]) {
+            rc = 2;
+            goto done;
+        }
+        is_failed[failed[k]] = 1;
+    }
+    for (uint64_t v = 0; v < (uint64_t)3 * r; v++) {
+        uint8_t byte = bytes[v];
+        if (byte == 0x7F)
+            continue;
+        uint32_t code = byte & 0x7Fu;
+        uint64_t blk = v / ((uint64_t)3 * r0);
+        int t = (int)((v % ((uint64_t)3 * r0)) / r0);
+        uint32_t q = (uint32_t)(blk * r0 + v % r0);
+        uint64_t pi = ((uint64_t)code << s) | (q & ((1u << s) - 1u));
+        if (pi >= m || (pi & (r - 1)) != q) {
+            rc = 3; /* the code and the position do not describe one hash value */
+            goto done;
+        }
+        uint32_t x = inv[t][pi];
+        if (perm[t][x] != pi) {
+            rc = 4;
+            goto done;
+        }
+        if (!in_set[x] || is_failed[x]) {
+            rc = 5; /* holds an element outside S minus F */
+            goto done;
+        }
+        if (seen_tables[x] & (1u << t)) {
+            rc = 6;
+            goto done;
+        }
+        seen_tables[x] |= (uint8_t)(1u << t);
+    }
+    for (uint32_t k = 0; k < size; k++) {
+        uint32_t x = set[k];
+        uint8_t tb = seen_tables[x];
+        int copies = (tb & 1) + ((tb >> 1) & 1) + ((tb >> 2) & 1);
+        if (is_failed[x]) {
+            if (copies != 0) {
+                rc = 7;
+                goto done;
+            }
+            continue;
+        }
+        if (copies != 2) {
+            rc = 8; /* every element of S minus F is held exactly twice */
+            goto done;
+        }
+        for (int t = 0; t < 3; t++) {
+            if (!(tb & (1u << t)))
+                continue;
+            uint32_t q = perm[t][x] & (r - 1);
+            uint8_t bit = bytes[slot_of(r0, t, q)] >> 7;
+            int prev = (t + 2) % 3;
+            uint8_t want = (tb >> prev) & 1;
+            if (bit != want) {
+                rc = 9; /* indicator bit disagrees with Fig. 3 */
+                goto done;
+            }
+        }
+    }
+done:
+    free(in_set);
+    free(is_failed);
+    free(seen_tables);
+    return rc;
+}

@@ -1,0 +1,300 @@
+"""Pins for the oracle: each check ties it to something other than itself.
+
+* the definition against a dense 0/1 matrix product (numpy) and against
+  per-pair set intersection (numpy.intersect1d) on small random instances;
+* closed forms that hold for any instance (sum over pairs, row sums);
+* special cases with known answers (identical, disjoint, nested, empty, full);
+* the paper's worked numbers (Sec. III-A bounds, Sec. IV-A example sizes);
+* the word compare formula exhaustively against the per-slot rule of Sec. II;
+* the counting rule against the three assignments printed in Fig. 3;
+* the whole method (maps + compare + correction) against the definition,
+  with the failure path forced.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(m, offsets, tids):
+    n = len(offsets) - 1
+    A = np.zeros((n, m), dtype=np.int64)
+    for i in range(n):
+        A[i, tids[offsets[i]:offsets[i + 1]]] = 1
+    return A
+
+
+def packed_from_full(C):
+    n = C.shape[0]
+    iu = np.triu_indices(n, 1)
+    return C[iu]
+
+
+def random_instance(rng, m, n, p_lo=0.0, p_hi=1.0):
+    probs = rng.uniform(p_lo, p_hi, size=n)
+    return datagen.sets_from_probs(m, probs, int(rng.integers(1 << 30)))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_all_pairs_equals_dense_product(seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(1, 300))
+    n = int(rng.integers(2, 18))
+    off, tids = random_instance(rng, m, n)
+    A = dense(m, off, tids)
+    want = packed_from_full(A @ A.T)
+    got = oracle.all_pairs(off, tids)
+    np.testing.assert_array_equal(got, want.astype(np.uint32))
+
+
+def test_merge_count_against_intersect1d():
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        m = int(rng.integers(1, 500))
+        a = np.sort(rng.choice(m, size=int(rng.integers(0, m + 1)), replace=False)).astype(np.uint32)
+        b = np.sort(rng.choice(m, size=int(rng.integers(0, m + 1)), replace=False)).astype(np.uint32)
+        assert oracle.merge_count(a, b) == np.intersect1d(a, b).size
+
+
+def test_special_cases():
+    m = 1000
+    full = np.arange(m, dtype=np.uint32)
+    even = full[::2]
+    odd = full[1::2]
+    empty = np.zeros(0, dtype=np.uint32)
+    nested = full[::6]
+    assert oracle.merge_count(even, even) == even.size
+    assert oracle.merge_count(even, odd) == 0
+    assert oracle.merge_count(even, nested) == nested.size
+    assert oracle.merge_count(empty, full) == 0
+    assert oracle.merge_count(full, odd) == odd.size
+
+
+def test_closed_forms_and_invariants():
+    rng = np.random.default_rng(3)
+    m, n = 2000, 40
+    off, tids = random_instance(rng, m, n, 0.0, 0.2)
+    sup = oracle.all_pairs(off, tids)
+    # sum over pairs = sum over transactions of C(|T_b|, 2)
+    row_len = np.bincount(tids, minlength=m).astype(np.int64)
+    assert int(sup.astype(np.int64).sum()) == int((row_len * (row_len - 1) // 2).sum())
+    # row sums: sum_{j != i} |S_i cap S_j| = sum_{b in S_i} (|T_b| - 1)
+    rows = oracle.pair_rows(off, tids, np.arange(n, dtype=np.uint32))
+    sizes = np.diff(off).astype(np.int64)
+    for i in range(n):
+        s_i = tids[off[i]:off[i + 1]]
+        assert int(rows[i].astype(np.int64).sum() - rows[i, i]) == int((row_len[s_i] - 1).sum())
+        assert rows[i, i] == sizes[i]
+    # symmetry and the min bound
+    np.testing.assert_array_equal(rows, rows.T)
+    assert np.all(rows <= np.minimum.outer(sizes, sizes))
+
+
+def test_frequent_and_subset_are_restrictions():
+    rng = np.random.default_rng(11)
+    m, n = 400, 25
+    off, tids = random_instance(rng, m, n, 0.05, 0.6)
+    C = dense(m, off, tids) @ dense(m, off, tids).T
+    for sigma in (0, 1, 20, 60, 10_000):
+        got = oracle.frequent_pairs(off, tids, sigma)
+        want = [(i, j, C[i, j]) for i in range(n) for j in range(i + 1, n) if C[i, j] >= sigma]
+        assert got.tolist() == [list(map(int, w)) for w in want]
+    items = rng.choice(n, size=9, replace=False).astype(np.uint32)
+    got = oracle.subset_pairs(off, tids, items)
+    want = [C[items[p], items[q]] for p in range(9) for q in range(p + 1, 9)]
+    np.testing.assert_array_equal(got, np.array(want, dtype=np.uint32))
+
+
+def test_transpose_roundtrip_with_repeats():
+    rng = np.random.default_rng(5)
+    m, n = 300, 30
+    off, tids = random_instance(rng, m, n, 0.0, 0.5)
+    rows, items = datagen.sets_to_transactions(m, off, tids)
+    # repeat some items inside their own transaction and shuffle each row
+    rep_rows, rep_items = [], []
+    for b in range(m):
+        r = list(items[rows[b]:rows[b + 1]])
+        if r and b % 3 == 0:
+            r = r + r[: 1 + b % 4]
+        rng.shuffle(r)
+        rep_items.extend(r)
+        rep_rows.append(len(r))
+    roff = np.zeros(m + 1, dtype=np.uint64)
+    np.cumsum(rep_rows, out=roff[1:])
+    soff, stids = oracle.transpose(m, roff, np.array(rep_items, dtype=np.uint32), n)
+    np.testing.assert_array_equal(soff, off)
+    np.testing.assert_array_equal(stids, tids)
+    with pytest.raises(ValueError):
+        oracle.transpose(m, roff, np.array(rep_items, dtype=np.uint32), n - 1 if max(rep_items) == n - 1 else 0)
+
+
+# ---- the method --------------------------------------------------------------
+
+def test_shift_matches_paper_bound():
+    """Sec. III-A: 2^s >= (m+1)/128; reading C3 reserves code 127, same s for these m."""
+    for m in (10_000, 50_000, 1_000_000, 1 << 20, 4_000_000, 10_000_000):
+        s = oracle.shift(m)
+        assert (1 << s) >= (m + 1) / 128 and (s == 0 or (1 << (s - 1)) < (m + 1) / 128)
+        assert m <= 127 << s
+    assert oracle.shift(127) == 0 and oracle.shift(128) == 1
+    # where the two rules differ, the reserved code needs one more bit
+    assert oracle.shift(127 * 1024 + 1) == 11
+
+
+def test_paper_worked_example_sizes():
+    """Sec. IV-A: sets of 2500 elements give batmaps 3 * 2^13 bytes wide."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_throughput.json")))
+    n, total, p = g["n_items"], g["instance_size"], g["density"]
+    m = int(round(total / (n * p)))            # transactions of the instance
+    assert total // n == g["mean_set_size"]
+    s = oracle.shift(m)
+    r = oracle.r_for(g["mean_set_size"], 1 << s)
+    assert 3 * r == g["batmap_bytes"]
+    # the two throughput figures printed with it
+    assert abs(n * n * g["batmap_bytes"] / g["gpu_seconds"] / 1e9 - g["logical_gbytes_per_s"]) < 0.05
+    assert n * n * g["mean_set_size"] == g["set_elements"]
+    assert abs(g["set_elements"] / g["gpu_seconds"] - g["set_elements_per_s"]) / g["set_elements_per_s"] < 0.01
+
+
+def slot_rule(bx, by):
+    """Sec. II: a slot pair counts iff the element bits agree and one indicator is set."""
+    return int(((bx & 0x7F) == (by & 0x7F)) and ((bx | by) & 0x80) != 0)
+
+
+def test_swar_word_exhaustive_against_slot_rule():
+    a = np.arange(256, dtype=np.uint32)
+    X, Y = np.meshgrid(a, a, indexing="ij")
+    X, Y = X.ravel(), Y.ravel()
+    want = np.array([slot_rule(int(x), int(y)) for x, y in zip(X, Y)])
+    rng = np.random.default_rng(0)
+    for lane in range(4):
+        # fill the other lanes with random bytes so cross-lane carries would show
+        other_x = rng.integers(0, 1 << 32, size=X.size, dtype=np.uint64).astype(np.uint32) & ~np.uint32(0xFF << (8 * lane))
+        other_y = rng.integers(0, 1 << 32, size=X.size, dtype=np.uint64).astype(np.uint32) & ~np.uint32(0xFF << (8 * lane))
+        wx = other_x | (X << np.uint32(8 * lane))
+        wy = other_y | (Y << np.uint32(8 * lane))
+        for idx in range(0, X.size, 257):  # every 257th keeps the loop short; full sweep below
+            got = oracle.swar_word(int(wx[idx]), int(wy[idx]))
+            ref = sum(slot_rule((int(wx[idx]) >> (8 * k)) & 0xFF, (int(wy[idx]) >> (8 * k)) & 0xFF) for k in range(4))
+            assert got == ref
+    # full sweep over all byte pairs in lane 0 with zero elsewhere and in lane 3 with 0x7F (empty) elsewhere
+    for lane, fill in ((0, 0x00), (3, 0x7F)):
+        base = 0
+        for k in range(4):
+            if k != lane:
+                base |= fill << (8 * k)
+        rest = sum(slot_rule(fill, fill) for k in range(4) if k != lane)
+        for x, y, w in zip(X, Y, want):
+            assert oracle.swar_word(base | (int(x) << (8 * lane)), base | (int(y) << (8 * lane))) == w + rest
+
+
+def test_counting_rule_fig3_exactly_once():
+    """Every pair of 2-of-3 assignments of a shared element counts it once (Fig. 3)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_fig3.json")))
+    code = 0x2A
+    for ai in g["assignments"]:
+        for aj in g["assignments"]:
+            total = 0
+            for t in (1, 2, 3):
+                if str(t) in ai["bit"] and str(t) in aj["bit"]:
+                    bx = (ai["bit"][str(t)] << 7) | code
+                    by = (aj["bit"][str(t)] << 7) | code
+                    total += slot_rule(bx, by)
+            assert total == 1, (ai, aj)
+
+
+def test_fig3_bits_are_the_preceding_table_rule():
+    """Reading C1: bit 1 on the copy whose other copy is in the cyclically preceding table."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_fig3.json")))
+    for a in g["assignments"]:
+        t1, t2 = a["tables"]
+        for t, other in ((t1, t2), (t2, t1)):
+            preceding = 3 if t == 1 else t - 1
+            assert a["bit"][str(t)] == int(other == preceding)
+
+
+def _perms(m, seed):
+    return datagen.hash_permutations(m, seed)
+
+
+@pytest.mark.parametrize("seed,max_loop", [(0, 64), (1, 64), (2, 16), (3, 4), (4, 2), (5, 1), (6, 0)])
+def test_method_counts_equal_definition(seed, max_loop):
+    rng = np.random.default_rng(100 + seed)
+    m = int(rng.integers(50, 3000))
+    n = int(rng.integers(2, 24))
+    off, tids = random_instance(rng, m, n, 0.0, 0.6)
+    perms = _perms(m, seed)
+    r0 = 1 << oracle.shift(m)
+    got, nfail = oracle.batmap_all_pairs(m, off, tids, perms, max(4, r0), max_loop)
+    np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+    if max_loop == 0:
+        assert nfail == tids.size  # every element fails; the correction is the whole result
+
+
+def test_method_counts_with_power_of_two_sizes():
+    """|S| exactly a power of two gives r = 2|S| (load 1/3): failures happen, counts stay exact."""
+    m = 20_000
+    rng = np.random.default_rng(9)
+    lists = [np.sort(rng.choice(m, size=1 << k, replace=False)) for k in (6, 8, 9, 10, 11, 11, 10)]
+    off = np.zeros(len(lists) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in lists], out=off[1:])
+    tids = np.concatenate(lists).astype(np.uint32)
+    for ml in (3, 8):
+        got, nfail = oracle.batmap_all_pairs(m, off, tids, _perms(m, 77), 1 << oracle.shift(m), ml)
+        np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+
+
+def test_built_maps_pass_structural_check_and_planted_mistakes_fail():
+    m = 5000
+    rng = np.random.default_rng(21)
+    perms = _perms(m, 5)
+    invs = oracle.inverse_perms(perms)
+    s = oracle.shift(m)
+    r0 = 1 << s
+    for size in (0, 1, 17, 300, 1024, 2500):
+        S = np.sort(rng.choice(m, size=size, replace=False)).astype(np.uint32)
+        for ml in (64, 1):
+            B, F, r = oracle.batmap_build(m, r0, perms, S, ml)
+            assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, B) == 0
+            # self-compare counts every stored element once (F excluded)
+            assert oracle.batmap_compare(B, r, B, r) == size - len(F)
+            occupied = np.nonzero(B != 0x7F)[0]
+            if occupied.size:
+                v = int(occupied[0])
+                flipped = B.copy()
+                flipped[v] ^= 0x80  # wrong indicator
+                assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, flipped) != 0
+                dropped = B.copy()
+                dropped[v] = 0x7F  # one copy lost
+                assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, dropped) != 0
+                recoded = B.copy()
+                recoded[v] = (recoded[v] & 0x80) | ((recoded[v] + 1) & 0x7F)  # wrong code
+                if (recoded[v] & 0x7F) != 0x7F:
+                    assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, recoded) != 0
+
+
+def test_wraparound_compare_against_definition():
+    """Maps of different widths compare slot v of the wider with slot v mod 3r of the narrower (Sec. II)."""
+    m = 40_000
+    rng = np.random.default_rng(33)
+    perms = _perms(m, 8)
+    r0 = 1 << oracle.shift(m)
+    sizes = [10, 300, 1200, 5000, 11000]
+    sets = [np.sort(rng.choice(m, size=k, replace=False)).astype(np.uint32) for k in sizes]
+    # overlap them on purpose
+    sets[3] = np.union1d(sets[3], sets[1][:200]).astype(np.uint32)
+    sets[4] = np.union1d(sets[4], sets[2]).astype(np.uint32)
+    maps = [oracle.batmap_build(m, r0, perms, S, 64) for S in sets]
+    for a in range(len(sets)):
+        for b in range(len(sets)):
+            Ba, Fa, ra = maps[a]
+            Bb, Fb, rb = maps[b]
+            want = np.intersect1d(np.setdiff1d(sets[a], Fa), np.setdiff1d(sets[b], Fb)).size
+            assert oracle.batmap_compare(Ba, ra, Bb, rb) == want
