@@ -1,0 +1,188 @@
+/*
+ * batmap.h -- C ABI of the MI355X BatMap pair-support library.
+ *
+ * The library computes exact pair supports |S_i cap S_j| over item tidlists
+ * (Amossen & Pagh, "A New Data Layout For Set Intersection on GPUs",
+ * IPDPS 2011): each tidlist S_i is hashed into a BatMap -- three tables of
+ * r_i slots, every element held in two of them (Sec. II, "Our adaptation";
+ * Sec. II-A, INSERT) -- and all BatMaps are compared slot-wise pair by pair
+ * (Sec. II, Fig. 1; Sec. III-A).  Elements whose insertion fails are added
+ * back exactly (Sec. III-C, "Failed insertions").  All counts are exact
+ * integers.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a bm_status: BM_OK (0) or a negative error code.
+ *    No exception or abort crosses the ABI; bm_last_error() on the context
+ *    returns a message for the last failing call made through it.
+ *  - Pointers marked "host or device" may point to host memory or to
+ *    device memory of the context's GPU; the library finds out which.
+ *  - The caller owns every buffer it passes.  Build calls copy their
+ *    inputs; an index owns its device memory until bm_index_destroy.
+ *  - Work is queued on the context's HIP stream.  Results written to
+ *    device memory are complete after bm_synchronize() (or any later work
+ *    on that stream); results written to host memory are complete when the
+ *    call returns.
+ *  - A context and the indexes built on it must not be used from two host
+ *    threads at the same time.
+ *  - Item ids are 0..n-1 in the caller's numbering; transaction ids (tids)
+ *    are 0..m-1.  Pair outputs never contain i == j and always have i < j.
+ *  - Packed upper triangle: pair (i, j), i < j, of n items sits at index
+ *    i*n - i*(i+1)/2 + (j - i - 1); n(n-1)/2 uint32 entries.
+ */
+#ifndef BATMAP_H
+#define BATMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BM_OK = 0,
+    BM_EINVAL = -1,     /* null pointer, zero size, bad option, mismatched index */
+    BM_ERANGE = -2,     /* a tid >= m or an item >= n */
+    BM_EUNSORTED = -3,  /* a set's tids are not strictly increasing */
+    BM_ENOMEM = -4,     /* device or host allocation failed */
+    BM_EDEVICE = -5,    /* a HIP runtime call failed */
+    BM_ECAPACITY = -6,  /* output buffer too small; the required size is returned */
+    BM_EBUSY = -7,      /* serving queue full */
+    BM_ENOTFOUND = -8   /* no such request */
+} bm_status;
+
+typedef struct bm_context bm_context; /* device, stream, scratch memory */
+typedef struct bm_index bm_index;     /* device-resident BatMaps of one instance */
+
+/* Build options (bm_build_opts_init gives the defaults below). */
+typedef struct {
+    uint64_t seed;          /* seeds the three permutations pi_t when perm[] is NULL (default 0x5eed) */
+    uint32_t max_loop;      /* MaxLoop of INSERT, Sec. II-A (default 64; 0 makes every insertion fail) */
+    uint32_t min_support;   /* items with |S_i| < min_support get no BatMap (Sec. I-B pruning; default 0) */
+    const uint32_t *perm[3];/* optional, host or device: three permutations of 0..m-1 (Sec. III-A pi_t);
+                               all three or none; validated as permutations */
+    uint32_t flags;         /* reserved, must be 0 */
+} bm_build_opts;
+
+typedef struct {
+    uint32_t i, j, support; /* i < j, caller's item ids */
+} bm_pair;
+
+typedef struct {
+    uint32_t n_items;        /* n */
+    uint32_t m;              /* transactions (universe of tids) */
+    uint32_t shift;          /* s: stored code = pi_t(x) >> s (Sec. III-A) */
+    uint32_t r0;             /* common smallest hash domain r_0 */
+    uint32_t max_loop;
+    uint32_t n_classes;      /* distinct widths r_i among the built BatMaps */
+    uint32_t n_built;        /* items with a BatMap (|S_i| >= min_support) */
+    uint32_t min_support;
+    uint64_t nnz;            /* sum of |S_i| */
+    uint64_t batmap_bytes;   /* sum of 3 r_i over built BatMaps */
+    uint64_t n_failed;       /* failed insertions (Sec. III-C F_b entries) */
+    uint64_t n_corrections;  /* +1 pair corrections derived from them */
+} bm_index_stats;
+
+/* Per-phase device times of the last build and the last query on a context,
+ * taken with HIP events on the context's stream while profiling is on.
+ * compare_slot_pairs is the algorithmic work of the last query's compare:
+ * the sum over its pairs of 3 max(r_i, r_j) slot comparisons. */
+typedef struct {
+    double ingest_ms;     /* validation / transactions -> tidlists */
+    double layout_ms;     /* permutations, size order, r_i and offsets */
+    double construct_ms;  /* 2-of-3 insertion and failure resolution */
+    double encode_ms;     /* slot bytes, bit planes */
+    double correct_ms;    /* failed-insertion correction list */
+    double fill_ms;       /* zeroing of the output */
+    double compare_ms;    /* compare kernels of the last query */
+    double apply_ms;      /* corrections added to the last query */
+    double threshold_ms;  /* support >= sigma compaction */
+    double compare_slot_pairs;
+    uint64_t compare_launches;
+} bm_timings;
+
+/* Fills *o with the defaults. */
+void bm_build_opts_init(bm_build_opts *o);
+
+/* Context on HIP device `device`.  hip_stream is a hipStream_t to borrow
+ * (e.g. the caller's current stream), or NULL for a library-owned stream.
+ * BM_EINVAL if out is NULL; BM_EDEVICE if the device cannot be used. */
+bm_status bm_context_create(int device, void *hip_stream, bm_context **out);
+void bm_context_destroy(bm_context *ctx);
+/* Message of the last failing call on ctx ("" if none); valid until the next call. */
+const char *bm_last_error(const bm_context *ctx);
+/* Waits for all work queued on the context's stream. */
+bm_status bm_synchronize(bm_context *ctx);
+/* Turns per-phase event timing on (enable != 0) or off; off by default. */
+bm_status bm_context_set_profiling(bm_context *ctx, int enable);
+/* Waits for the recorded events and fills *out (phases never run read 0). */
+bm_status bm_context_timings(bm_context *ctx, bm_timings *out);
+
+/* Sets -> index (Sec. II: preprocess the sets S_i for intersection sizes).
+ * offsets: n_sets+1 uint64, host or device, offsets[0] = 0, non-decreasing;
+ * tids: offsets[n_sets] uint32, host or device; set i is
+ * tids[offsets[i] .. offsets[i+1]) and must be strictly increasing with every
+ * tid < m.  Errors: BM_EINVAL (null, n_sets = 0, m = 0, bad offsets, bad
+ * options), BM_ERANGE (tid >= m), BM_EUNSORTED, BM_ENOMEM, BM_EDEVICE.
+ * Returns when the index is complete. */
+bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, const uint64_t *offsets,
+                              const uint32_t *tids, const bm_build_opts *opts, bm_index **out);
+
+/* Transactions -> index (Sec. I: horizontal format T_1..T_m, converted to the
+ * vertical format S_i = {b : i in T_b}).  offsets: m_txn+1 uint64, items:
+ * offsets[m_txn] uint32, host or device; transaction b is
+ * items[offsets[b] .. offsets[b+1]) in any order; an item repeated inside one
+ * transaction counts once.  Errors as bm_index_build_sets, BM_ERANGE for an
+ * item >= n_items. */
+bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_t m_txn, const uint64_t *offsets,
+                                      const uint32_t *items, const bm_build_opts *opts, bm_index **out);
+
+bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out);
+/* Frees the index's device memory.  Valid even after its context was
+ * destroyed; every other call on an index needs its context alive. */
+void bm_index_destroy(bm_index *idx);
+
+/* Exact |S_i cap S_j| for all i < j (Sec. II; the output of Sec. IV-A is "the
+ * support of every pair"), packed upper triangle.  out: host or device,
+ * out_len >= n(n-1)/2.  BM_EINVAL if the index was built with min_support > 0. */
+bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len);
+
+/* Frequent pair mining (Sec. I: pairs with support at least sigma): every
+ * (i, j, support) with i < j and support >= min_support, sorted by (i, j).
+ * out: host or device, `capacity` entries.  *n_out (host) receives the
+ * number of pairs; if it exceeds capacity the call returns BM_ECAPACITY and
+ * writes nothing.  BM_EINVAL if min_support is below the build's. */
+bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity, uint64_t *n_out);
+
+/* Pair supports among a subset of items (k distinct ids, host or device):
+ * out (host or device) gets k(k-1)/2 entries, packed upper triangle in the
+ * order given.  BM_EINVAL on a repeated id or an item without a BatMap,
+ * BM_ERANGE on an id >= n. */
+bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t k, uint32_t *out);
+
+/* Many instances at once: all pairs of count indexes (same context) in one
+ * persistent launch.  outs[q] (device) sized n_q(n_q-1)/2. */
+bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs);
+
+/* Same result as bm_all_pair_supports by the plain bitmap route (Sec. I-A,
+ * bitmaps: AND and count): a 0/1 int8 item x transaction matrix A and the
+ * product A A^T on the int8 matrix cores with int32 accumulation. */
+bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_len);
+
+/* Inspection (tests, tools).  Copies to host buffers:
+ *   sorted_items[n_built]: item ids in BatMap order (by |S_i| then id),
+ *   r[n_built]:            r_i in that order,
+ *   bytes[batmap_bytes]:   every BatMap in the canonical byte form of
+ *                          Sec. III-A (slot = indicator << 7 | pi_t(x) >> s,
+ *                          empty slot 0x7F), concatenated in that order,
+ *   failed[2*n_failed]:    (item, tid) of every failed insertion,
+ *   perms[3*m]:            pi_0, pi_1, pi_2.
+ * Any pointer may be NULL to skip that output. */
+bm_status bm_index_export(const bm_index *idx, uint32_t *sorted_items, uint32_t *r, uint8_t *bytes, uint32_t *failed,
+                          uint32_t *perms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BATMAP_H */

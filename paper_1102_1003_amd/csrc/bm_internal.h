@@ -1,0 +1,142 @@
+// Internal declarations of the BatMap library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/batmap.h"
+
+namespace bm {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+// Slots are stored bit-sliced: a "group" is 32 consecutive slots held as
+// 8 uint32 planes (planes 0..6: code bits, plane 7: indicator bits).
+constexpr uint32_t kSlotsPerGroup = 32;
+constexpr uint32_t kWordsPerGroup = 8;
+// Smallest hash domain: r_0 = max(kMinR0, 2^s).  128 keeps 3 r_0 a multiple
+// of 64 slots (one wavefront of the encoder) and of 4 groups (one compare stage).
+constexpr uint32_t kMinR0 = 128;
+// Compare kernel: groups staged per step.
+constexpr uint32_t kStageGroups = 4;
+
+struct Status {
+    bm_status code = BM_OK;
+    std::string msg;
+    bool ok() const { return code == BM_OK; }
+};
+
+// One unit of compare work: a tile of row maps (narrower width class) against
+// a tile of column maps (wider or equal class) over column groups [c0, c1).
+struct WorkItem {
+    uint32_t row0;       // first sorted index of the row tile
+    uint32_t col0;       // first sorted index of the column tile
+    uint16_t nrow;       // valid rows
+    uint16_t ncol;       // valid columns
+    uint32_t c0, c1;     // column-group range, multiples of kStageGroups (c1 may be the map end)
+    uint32_t row_blocks; // r_row / r_0 (power of two): row group = block & (row_blocks-1)
+    uint32_t inst;       // instance (descriptor index)
+    uint32_t flags;      // bit 0: same width class and overlapping tiles -> emit only row < col
+};
+static_assert(sizeof(WorkItem) == 32, "work item layout");
+
+// Per-instance view used by the compare kernel.
+struct InstDesc {
+    const uint4 *arena;     // BatMap groups, 2 x uint4 per group
+    const uint64_t *goff;   // group offset of each sorted index
+    const uint32_t *outpos; // sorted index -> output position (item id or query slot)
+    uint32_t *out;          // packed upper triangle over output positions
+    uint64_t n_out;         // number of output positions (packing width)
+    uint32_t gb;            // groups per block = 3 r_0 / 32
+    uint32_t pad;
+};
+
+// ------------------------------------------------------------------ device
+// Host-side launchers.  All take a stream; none synchronises.
+hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
+
+// Exclusive scans.  `tmp` must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(uint64_t n);
+hipError_t exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, void *tmp, hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, void *tmp, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `key_bits` bits.
+// Result ends in (keys, vals); k2/v2 are same-sized scratch.
+size_t radix_tmp_bytes(uint64_t n);
+hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2, uint64_t n, int key_bits,
+                            void *tmp, hipStream_t s);
+
+// Ingest.
+hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s);
+hipError_t launch_check_items(const uint32_t *items, uint64_t nnz, uint32_t n, uint32_t *flag, hipStream_t s);
+hipError_t launch_mark_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t *keep,
+                            uint32_t *n_dup, hipStream_t s);
+hipError_t launch_compact_pairs(const uint32_t *keys, const uint32_t *vals, const uint32_t *keep,
+                                const uint64_t *pos, uint64_t nnz, uint32_t *ko, uint32_t *vo, hipStream_t s);
+hipError_t launch_offsets_from_sorted(const uint32_t *keys, uint64_t nnz, uint32_t n, uint64_t *off, hipStream_t s);
+hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t nnz, uint32_t m,
+                                uint32_t *flags, hipStream_t s);
+
+// Construction.
+hipError_t launch_gen_perms(uint32_t m, const uint64_t keys[3][5], uint32_t *pi, hipStream_t s);
+hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, uint32_t *flag, hipStream_t s);
+hipError_t launch_size_keys(const uint64_t *off, uint32_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_map_layout(const uint32_t *sorted_items, const uint64_t *off, uint32_t n, uint32_t first_built,
+                             uint32_t r0, uint32_t *r_sorted, uint32_t *gcount, hipStream_t s);
+struct BuildBatch {
+    uint32_t p0, p1;            // sorted-index range [p0, p1) of this batch
+    uint64_t g0;                // first group of the batch in the arena
+};
+hipError_t launch_insert(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                         const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, BuildBatch b,
+                         uint64_t n_elems, const uint32_t *pi, uint32_t m, uint32_t max_loop, uint32_t *stage,
+                         uint32_t *cand, uint32_t cand_cap, uint32_t *cand_count, hipStream_t s);
+hipError_t launch_resolve(const uint32_t *cand, uint32_t n_cand, const uint32_t *tids, const uint64_t *off,
+                          const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
+                          const uint32_t *pi, uint32_t m, uint32_t *stage, uint32_t *failed_bits, uint32_t *failed,
+                          uint32_t *n_failed, hipStream_t s);
+hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
+                         uint64_t n_groups, const uint32_t *pi, uint32_t m, uint32_t shift, uint32_t r0,
+                         uint32_t *arena, hipStream_t s);
+hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
+
+// Corrections (Sec. III-C).
+hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off, const uint32_t *tids,
+                              const uint32_t *failed_bits, const uint8_t *has_map, uint32_t n, uint32_t *pairs,
+                              uint64_t cap, unsigned long long *count, hipStream_t s);
+hipError_t launch_apply_corrections(const uint32_t *pairs, uint64_t n_corr, uint32_t *out, uint64_t n,
+                                    hipStream_t s);
+hipError_t launch_apply_corrections_subset(const uint32_t *pairs, uint64_t n_corr, const uint32_t *pos_of_item,
+                                           uint32_t *out, uint64_t k, hipStream_t s);
+
+// Compare (Sec. II / III-A).
+// descs == nullptr: every item uses d0 (passed by value).
+hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
+                          int variant, hipStream_t s);
+hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
+                                     const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
+                                     hipStream_t s);
+int compare_variant_count();
+void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj);
+
+// Threshold + compaction.
+hipError_t launch_threshold_count(const uint32_t *sup, uint64_t n_pairs, uint32_t sigma, uint32_t *block_counts,
+                                  uint32_t n_blocks, hipStream_t s);
+hipError_t launch_threshold_write(const uint32_t *sup, uint64_t n_pairs, uint64_t n, uint32_t sigma,
+                                  const uint64_t *block_off, uint32_t n_blocks, bm_pair *out, hipStream_t s);
+uint32_t threshold_blocks(uint64_t n_pairs);
+
+// Subset queries.
+hipError_t launch_subset_prepare(const uint32_t *items, uint32_t k, uint32_t n, const int32_t *sorted_pos,
+                                 uint32_t *pos_of_item, uint32_t *flag, hipStream_t s);
+
+// Dense comparator.
+hipError_t launch_bitmap_build(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t ld, int8_t *A,
+                               hipStream_t s);
+hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t k_len, uint32_t *out,
+                             uint32_t k_split, hipStream_t s);
+
+}  // namespace bm

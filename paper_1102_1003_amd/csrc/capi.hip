@@ -1,0 +1,1459 @@
+// C ABI of the BatMap library: contexts, index build, queries, planning.
+//
+// Build (Sec. II-A, III-A, III-C):
+//   ingest -> validate -> size order -> layout (r_i, offsets) -> permutations
+//   -> per batch of maps: insert, resolve failures, encode -> corrections.
+// Queries (Sec. II, III-B, III-C):
+//   tile plan over width classes -> compare kernel -> corrections
+//   [-> threshold + compaction].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bm_internal.h"
+
+using namespace bm;
+
+// ----------------------------------------------------------------- helpers
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    uint64_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void reset()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(uint64_t count)
+    {
+        reset();
+        if (count == 0)
+            count = 1;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return e;
+        }
+        n = count;
+        return hipSuccess;
+    }
+    hipError_t ensure(uint64_t count)
+    {
+        if (p && n >= count)
+            return hipSuccess;
+        return alloc(count);
+    }
+};
+
+struct Cls {
+    uint32_t r, start, count;  // width r; sorted-index range [start, start + count)
+};
+
+enum PtrKind { PTR_HOST, PTR_DEVICE };
+
+PtrKind ptr_kind(const void *p)
+{
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return PTR_HOST;
+    }
+    if (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged)
+        return PTR_DEVICE;
+    return PTR_HOST;
+}
+
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int bits_for(uint64_t v)  // bits needed to hold values 0..v
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0)
+        b++;
+    return b;
+}
+
+uint64_t n_pairs(uint64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
+
+}  // namespace
+
+enum Phase { PH_INGEST, PH_LAYOUT, PH_CONSTRUCT, PH_ENCODE, PH_CORRECT, PH_FILL, PH_COMPARE, PH_APPLY,
+             PH_THRESHOLD, PH_COUNT };
+
+struct bm_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 256;
+    std::string err;
+    DevBuf<uint32_t> counter;  // persistent-kernel work counter
+    // profiling: event spans per phase of the last build / last query
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[PH_COUNT];
+    std::vector<hipEvent_t> event_pool;
+    double slot_pairs = 0;
+    uint64_t launches = 0;
+};
+
+namespace {
+
+hipEvent_t take_event(bm_context *ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void clear_phases(bm_context *ctx, int first, int last)
+{
+    for (int p = first; p <= last; p++) {
+        for (auto &sp : ctx->spans[p]) {
+            ctx->event_pool.push_back(sp.first);
+            ctx->event_pool.push_back(sp.second);
+        }
+        ctx->spans[p].clear();
+    }
+}
+
+void begin_build(bm_context *ctx) { clear_phases(ctx, PH_INGEST, PH_CORRECT); }
+void begin_query(bm_context *ctx)
+{
+    clear_phases(ctx, PH_FILL, PH_THRESHOLD);
+    ctx->slot_pairs = 0;
+    ctx->launches = 0;
+}
+
+// Records events on the context's stream around a phase while profiling is on.
+struct Span {
+    bm_context *ctx;
+    int phase;
+    hipEvent_t start = nullptr;
+    Span(bm_context *c, int ph) : ctx(c), phase(ph)
+    {
+        if (ctx->profiling) {
+            start = take_event(ctx);
+            if (start)
+                (void)hipEventRecord(start, ctx->stream);
+        }
+    }
+    Span(const Span &) = delete;
+    Span &operator=(const Span &) = delete;
+    void end()
+    {
+        if (!start)
+            return;
+        hipEvent_t stop = take_event(ctx);
+        if (!stop) {
+            ctx->event_pool.push_back(start);
+            start = nullptr;
+            return;
+        }
+        (void)hipEventRecord(stop, ctx->stream);
+        ctx->spans[phase].push_back({start, stop});
+        start = nullptr;
+    }
+    ~Span() { end(); }
+};
+
+}  // namespace
+
+struct bm_index {
+    bm_context *ctx = nullptr;
+    int device = 0;
+    uint32_t m = 0, n = 0, shift = 0, r0 = 0, gb = 0, max_loop = 0, min_support = 0;
+    uint64_t nnz = 0;
+    uint32_t first_built = 0;  // sorted indices below this have no BatMap
+    uint64_t total_groups = 0, n_failed = 0, n_corr = 0;
+
+    DevBuf<uint64_t> off;
+    DevBuf<uint32_t> tids;
+    DevBuf<uint32_t> pi;            // 3 m
+    DevBuf<uint32_t> sorted_items;  // n
+    DevBuf<uint32_t> r_sorted;      // n
+    DevBuf<uint64_t> goff;          // n + 1
+    DevBuf<uint32_t> arena;         // total_groups * 8
+    DevBuf<uint32_t> failed;        // 2 n_failed
+    DevBuf<uint32_t> corr;          // 2 n_corr
+    DevBuf<int32_t> sorted_pos;     // item -> sorted index or -1
+    std::vector<uint64_t> h_goff;   // n + 1
+
+    std::vector<uint64_t> h_off;
+    std::vector<uint32_t> h_sorted_items, h_r_sorted, h_sizes_sorted;
+    std::vector<Cls> classes;
+
+    // query scratch
+    DevBuf<uint32_t> pairbuf;
+    DevBuf<WorkItem> work;
+    std::vector<std::pair<int, uint32_t>> work_ranges;  // (variant, count) in order
+    uint32_t planned_first = UINT32_MAX;
+    double planned_slot_pairs = 0;
+    DevBuf<uint32_t> thr_counts;
+    DevBuf<uint64_t> thr_off;
+    DevBuf<char> scan_tmp;
+    DevBuf<bm_pair> pair_out;
+    // subset queries
+    DevBuf<uint32_t> pos_of_item;
+    DevBuf<uint32_t> sub_items, sub_flag, sub_outpos, sub_out;
+    DevBuf<uint64_t> sub_goff;
+    DevBuf<WorkItem> sub_work;
+    // dense comparator
+    DevBuf<int8_t> dense_A;
+    uint64_t dense_ld = 0;
+};
+
+namespace {
+
+bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIPC(ctx, expr)                                                                                \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            (void)hipGetLastError();                                                                   \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? BM_ENOMEM : BM_EDEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                    \
+        }                                                                                              \
+    } while (0)
+
+// ------------------------------------------------------------------ planner
+// Tiles of a width-class pair (a <= b): rows from class a, columns from class
+// b; within one class only tiles holding some row < column.  A variant (tile
+// shape) is chosen per class pair to minimise padded work, and every tile's
+// column-group range is cut into pieces of about `piece` groups.
+
+struct Plan {
+    std::vector<std::vector<WorkItem>> by_variant;
+    double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
+};
+
+void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
+               std::vector<std::pair<uint32_t, uint32_t>> *out, uint64_t *count)
+{
+    uint64_t c = 0;
+    for (uint32_t I = 0; I * bi < A.count; I++) {
+        for (uint32_t J = 0; J * bj < B.count; J++) {
+            if (same) {
+                uint32_t row_start = I * bi;
+                uint32_t col_end = std::min(B.count, (J + 1) * bj);
+                if (!(row_start + 1 < col_end))
+                    continue;  // no row < column in this tile
+            }
+            c++;
+            if (out)
+                out->push_back({I, J});
+        }
+    }
+    *count = c;
+}
+
+void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan)
+{
+    int nv = compare_variant_count();
+    plan.by_variant.assign(nv, {});
+    plan.slot_pairs = 0;
+    struct Choice {
+        size_t a, b;
+        int v;
+    };
+    std::vector<Choice> choices;
+    uint64_t total_groups = 0;
+    for (size_t a = 0; a < cls.size(); a++) {
+        for (size_t b = a; b < cls.size(); b++) {
+            bool same = a == b;
+            if (same && cls[a].count < 2)
+                continue;
+            int best = 0;
+            uint64_t best_cost = UINT64_MAX;
+            for (int v = 0; v < nv; v++) {
+                uint32_t bi, bj;
+                compare_variant_shape(v, &bi, &bj);
+                uint64_t cnt;
+                tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
+                uint64_t cost = cnt * bi * bj;
+                // prefer larger tiles on ties (more reuse per loaded group)
+                if (cost < best_cost || (cost == best_cost && bi * bj > 0)) {
+                    if (cost < best_cost) {
+                        best_cost = cost;
+                        best = v;
+                    }
+                }
+            }
+            uint32_t bi, bj;
+            compare_variant_shape(best, &bi, &bj);
+            uint64_t cnt;
+            tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
+            double pairs = same ? 0.5 * cls[a].count * (cls[a].count - 1.0) : (double)cls[a].count * cls[b].count;
+            plan.slot_pairs += pairs * 3.0 * cls[b].r;
+            total_groups += cnt * (3ull * cls[b].r / kSlotsPerGroup);
+            choices.push_back({a, b, best});
+        }
+    }
+    uint64_t piece = (total_groups + target_items - 1) / std::max<uint64_t>(target_items, 1);
+    piece = std::max<uint64_t>(piece, 16 * kStageGroups);
+    piece = (piece + kStageGroups - 1) / kStageGroups * kStageGroups;
+    std::vector<std::pair<uint32_t, uint32_t>> tiles;
+    for (const Choice &ch : choices) {
+        const Cls &A = cls[ch.a], &B = cls[ch.b];
+        bool same = ch.a == ch.b;
+        uint32_t bi, bj;
+        compare_variant_shape(ch.v, &bi, &bj);
+        tiles.clear();
+        uint64_t cnt;
+        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
+        uint32_t G = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+        uint32_t pieces = (uint32_t)((G + piece - 1) / piece);
+        for (auto &t : tiles) {
+            for (uint32_t k = 0; k < pieces; k++) {
+                uint64_t c0 = (uint64_t)G * k / pieces, c1 = (uint64_t)G * (k + 1) / pieces;
+                c0 = c0 / kStageGroups * kStageGroups;
+                c1 = (k + 1 == pieces) ? G : c1 / kStageGroups * kStageGroups;
+                if (c1 <= c0)
+                    continue;
+                WorkItem w;
+                w.row0 = A.start + t.first * bi;
+                w.col0 = B.start + t.second * bj;
+                w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
+                w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
+                w.c0 = (uint32_t)c0;
+                w.c1 = (uint32_t)c1;
+                w.row_blocks = A.r / r0;
+                w.inst = inst;
+                w.flags = same ? 1u : 0u;
+                plan.by_variant[ch.v].push_back(w);
+            }
+        }
+    }
+    for (auto &v : plan.by_variant)
+        std::stable_sort(v.begin(), v.end(),
+                         [](const WorkItem &x, const WorkItem &y) { return (x.c1 - x.c0) > (y.c1 - y.c0); });
+}
+
+// Classes restricted to sorted indices >= first.
+std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first)
+{
+    std::vector<Cls> out;
+    for (const Cls &c : cls) {
+        uint32_t e = c.start + c.count;
+        if (e <= first)
+            continue;
+        uint32_t s = std::max(c.start, first);
+        out.push_back({c.r, s, e - s});
+    }
+    return out;
+}
+
+bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
+                      std::vector<std::pair<int, uint32_t>> &ranges)
+{
+    bm_context *ctx = idx->ctx;
+    uint64_t total = 0;
+    for (auto &v : plan.by_variant)
+        total += v.size();
+    std::vector<WorkItem> flat;
+    flat.reserve(total);
+    ranges.clear();
+    for (size_t v = 0; v < plan.by_variant.size(); v++) {
+        if (plan.by_variant[v].empty())
+            continue;
+        ranges.push_back({(int)v, (uint32_t)plan.by_variant[v].size()});
+        flat.insert(flat.end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
+    }
+    HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
+    if (total) {
+        HIPC(ctx, hipMemcpyAsync(dst.p, flat.data(), total * sizeof(WorkItem), hipMemcpyHostToDevice, ctx->stream));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));  // `flat` is released on return
+    }
+    return BM_OK;
+}
+
+bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<std::pair<int, uint32_t>> &ranges,
+                      const InstDesc &d0)
+{
+    uint64_t at = 0;
+    for (auto &r : ranges) {
+        HIPC(ctx, launch_compare(items + at, r.second, nullptr, d0, r.first, ctx->stream));
+        at += r.second;
+    }
+    return BM_OK;
+}
+
+uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 32; }
+
+// ------------------------------------------------------------- build steps
+
+bm_status copy_in(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
+{
+    if (bytes == 0)
+        return BM_OK;
+    hipMemcpyKind kind = ptr_kind(src) == PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPC(ctx, hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
+    return BM_OK;
+}
+
+bm_status read_back(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
+{
+    if (bytes == 0)
+        return BM_OK;
+    HIPC(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    return BM_OK;
+}
+
+bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
+{
+    if (o->flags != 0)
+        return fail(ctx, BM_EINVAL, "bm_build_opts.flags must be 0");
+    int given = (o->perm[0] != nullptr) + (o->perm[1] != nullptr) + (o->perm[2] != nullptr);
+    if (given != 0 && given != 3)
+        return fail(ctx, BM_EINVAL, "give all three permutations or none");
+    return BM_OK;
+}
+
+// Everything after the tidlists (idx->off, idx->tids, idx->h_off) are on the device.
+bm_status build_common(bm_index *idx, const bm_build_opts *o)
+{
+    bm_context *ctx = idx->ctx;
+    hipStream_t s = ctx->stream;
+    const uint32_t n = idx->n, m = idx->m;
+
+    // Sec. III-A parameters (reading: code 127 is the empty slot).
+    uint32_t shift = 0;
+    while ((uint64_t)m > ((uint64_t)127 << shift))
+        shift++;
+    idx->shift = shift;
+    idx->r0 = std::max<uint32_t>(kMinR0, 1u << shift);
+    idx->gb = 3 * idx->r0 / kSlotsPerGroup;
+    idx->max_loop = o->max_loop;
+    idx->min_support = o->min_support;
+
+    // permutations pi_t
+    Span span_layout(ctx, PH_LAYOUT);
+    HIPC(ctx, idx->pi.alloc(3ull * m));
+    if (o->perm[0]) {
+        for (int t = 0; t < 3; t++) {
+            bm_status st = copy_in(ctx, idx->pi.p + (uint64_t)t * m, o->perm[t], (uint64_t)m * 4);
+            if (st != BM_OK)
+                return st;
+        }
+    } else {
+        uint64_t sm = o->seed ^ 0xB47A5EEDull;
+        uint64_t keys[3][5];
+        for (int t = 0; t < 3; t++)
+            for (int k = 0; k < 5; k++)
+                keys[t][k] = splitmix64(sm);
+        HIPC(ctx, launch_gen_perms(m, keys, idx->pi.p, s));
+    }
+    {
+        DevBuf<uint32_t> bits, flag;
+        uint64_t words = ((uint64_t)m + 31) / 32;
+        HIPC(ctx, bits.alloc(3 * words));
+        HIPC(ctx, flag.alloc(1));
+        HIPC(ctx, fill_u32(bits.p, 3 * words, 0, s));
+        HIPC(ctx, fill_u32(flag.p, 1, 0, s));
+        HIPC(ctx, launch_check_perms(idx->pi.p, m, bits.p, flag.p, s));
+        uint32_t h = 0;
+        bm_status st = read_back(ctx, &h, flag.p, 4);
+        if (st != BM_OK)
+            return st;
+        if (h)
+            return fail(ctx, BM_EINVAL, "bm_build_opts.perm: not three permutations of 0..m-1");
+    }
+
+    // size order (Sec. III-C: sort by increasing width; ties by size then id)
+    uint32_t max_size = 0;
+    for (uint32_t i = 0; i < n; i++)
+        max_size = std::max<uint32_t>(max_size, (uint32_t)(idx->h_off[i + 1] - idx->h_off[i]));
+    {
+        DevBuf<uint32_t> keys, k2, v2;
+        DevBuf<char> tmp;
+        HIPC(ctx, keys.alloc(n));
+        HIPC(ctx, k2.alloc(n));
+        HIPC(ctx, v2.alloc(n));
+        HIPC(ctx, idx->sorted_items.alloc(n));
+        HIPC(ctx, tmp.alloc(radix_tmp_bytes(n)));
+        HIPC(ctx, launch_size_keys(idx->off.p, n, keys.p, idx->sorted_items.p, s));
+        HIPC(ctx, radix_sort_pairs(keys.p, idx->sorted_items.p, k2.p, v2.p, n, bits_for(max_size), tmp.p, s));
+    }
+    idx->h_sorted_items.resize(n);
+    bm_status st = read_back(ctx, idx->h_sorted_items.data(), idx->sorted_items.p, (uint64_t)n * 4);
+    if (st != BM_OK)
+        return st;
+    idx->h_sizes_sorted.resize(n);
+    uint32_t first_built = 0;
+    for (uint32_t p = 0; p < n; p++) {
+        uint32_t it = idx->h_sorted_items[p];
+        idx->h_sizes_sorted[p] = (uint32_t)(idx->h_off[it + 1] - idx->h_off[it]);
+        if (idx->h_sizes_sorted[p] < o->min_support)
+            first_built = p + 1;
+    }
+    idx->first_built = first_built;
+
+    // layout: r_i and group offsets
+    HIPC(ctx, idx->r_sorted.alloc(n));
+    HIPC(ctx, idx->goff.alloc((uint64_t)n + 1));
+    {
+        DevBuf<uint32_t> gcount;
+        DevBuf<char> tmp;
+        HIPC(ctx, gcount.alloc((uint64_t)n + 1));
+        HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
+        HIPC(ctx, tmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
+        HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                    gcount.p, s));
+        HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, tmp.p, s));
+    }
+    idx->h_r_sorted.resize(n);
+    std::vector<uint64_t> &h_goff = idx->h_goff;
+    h_goff.assign((size_t)n + 1, 0);
+    st = read_back(ctx, idx->h_r_sorted.data(), idx->r_sorted.p, (uint64_t)n * 4);
+    if (st != BM_OK)
+        return st;
+    st = read_back(ctx, h_goff.data(), idx->goff.p, ((uint64_t)n + 1) * 8);
+    if (st != BM_OK)
+        return st;
+    idx->total_groups = h_goff[n];
+    idx->classes.clear();
+    for (uint32_t p = first_built; p < n; p++) {
+        uint32_t r = idx->h_r_sorted[p];
+        if (idx->classes.empty() || idx->classes.back().r != r)
+            idx->classes.push_back({r, p, 0});
+        idx->classes.back().count++;
+    }
+
+    // sorted_pos: item -> sorted index (or -1 when unbuilt)
+    {
+        std::vector<int32_t> sp(n, -1);
+        for (uint32_t p = first_built; p < n; p++)
+            sp[idx->h_sorted_items[p]] = (int32_t)p;
+        HIPC(ctx, idx->sorted_pos.alloc(n));
+        HIPC(ctx, hipMemcpyAsync(idx->sorted_pos.p, sp.data(), (uint64_t)n * 4, hipMemcpyHostToDevice, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+
+    // construction, in batches of maps whose staging fits the budget
+    span_layout.end();
+    HIPC(ctx, idx->arena.alloc(std::max<uint64_t>(idx->total_groups, 1) * kWordsPerGroup));
+    DevBuf<uint32_t> failed_bits;
+    uint64_t fb_words = (idx->nnz + 31) / 32;
+    HIPC(ctx, failed_bits.alloc(fb_words + 1));
+    HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+    size_t free_b = 0, total_b = 0;
+    HIPC(ctx, hipMemGetInfo(&free_b, &total_b));
+    uint64_t stage_budget_groups = std::max<uint64_t>((uint64_t)(free_b / 4) / (kSlotsPerGroup * 4), 1);
+    stage_budget_groups = std::min<uint64_t>(stage_budget_groups, idx->total_groups);
+    DevBuf<uint32_t> stage, cand, counters, ebase_d;
+    DevBuf<uint64_t> ebase;
+    HIPC(ctx, stage.alloc(std::max<uint64_t>(stage_budget_groups, 1) * kSlotsPerGroup));
+    HIPC(ctx, counters.alloc(2));
+    uint32_t fail_cap = 1024;
+    HIPC(ctx, idx->failed.alloc(2ull * fail_cap));
+    uint64_t n_failed_total = 0;
+    uint32_t cand_cap = 4096;
+    HIPC(ctx, cand.alloc(2ull * cand_cap));
+
+    uint32_t p = first_built;
+    while (p < n) {
+        // batch [p, q): at least one map
+        uint32_t q = p + 1;
+        while (q < n && h_goff[q + 1] - h_goff[p] <= stage_budget_groups)
+            q++;
+        uint64_t groups = h_goff[q] - h_goff[p];
+        if (groups > stage_budget_groups) {
+            HIPC(ctx, stage.alloc(groups * kSlotsPerGroup));
+            stage_budget_groups = groups;
+        }
+        std::vector<uint64_t> eb(q - p + 1, 0);
+        for (uint32_t k = p; k < q; k++)
+            eb[k - p + 1] = eb[k - p] + idx->h_sizes_sorted[k];
+        uint64_t n_elems = eb.back();
+        HIPC(ctx, ebase.alloc(eb.size()));
+        HIPC(ctx, hipMemcpyAsync(ebase.p, eb.data(), eb.size() * 8, hipMemcpyHostToDevice, s));
+        BuildBatch bb{p, q, h_goff[p]};
+        Span span_construct(ctx, PH_CONSTRUCT);
+        for (;;) {
+            HIPC(ctx, fill_u32(stage.p, groups * kSlotsPerGroup, kEmpty, s));
+            HIPC(ctx, fill_u32(counters.p, 2, 0, s));
+            HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
+                                    ebase.p, bb, n_elems, idx->pi.p, m, o->max_loop, stage.p, cand.p, cand_cap,
+                                    counters.p, s));
+            uint32_t nc = 0;
+            st = read_back(ctx, &nc, counters.p, 4);
+            if (st != BM_OK)
+                return st;
+            if (nc <= cand_cap) {
+                // room for the failures of this batch in the index list
+                if (n_failed_total + nc > fail_cap) {
+                    uint64_t want = std::max<uint64_t>(2ull * fail_cap, n_failed_total + nc);
+                    DevBuf<uint32_t> bigger;
+                    HIPC(ctx, bigger.alloc(2 * want));
+                    if (n_failed_total)
+                        HIPC(ctx, hipMemcpyAsync(bigger.p, idx->failed.p, n_failed_total * 8, hipMemcpyDeviceToDevice,
+                                                 s));
+                    HIPC(ctx, hipStreamSynchronize(s));
+                    std::swap(bigger.p, idx->failed.p);
+                    std::swap(bigger.n, idx->failed.n);
+                    fail_cap = (uint32_t)want;
+                }
+                HIPC(ctx, fill_u32(counters.p + 1, 1, (uint32_t)n_failed_total, s));
+                HIPC(ctx, launch_resolve(cand.p, nc, idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
+                                         idx->goff.p, bb, idx->pi.p, m, stage.p, failed_bits.p, idx->failed.p,
+                                         counters.p + 1, s));
+                uint32_t nf = 0;
+                st = read_back(ctx, &nf, counters.p + 1, 4);
+                if (st != BM_OK)
+                    return st;
+                n_failed_total = nf;
+                break;
+            }
+            cand_cap = nc + nc / 2 + 1024;
+            HIPC(ctx, cand.alloc(2ull * cand_cap));
+        }
+        span_construct.end();
+        {
+            Span span_encode(ctx, PH_ENCODE);
+            HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, groups, idx->pi.p, m, shift, idx->r0,
+                                    idx->arena.p, s));
+        }
+        p = q;
+    }
+    HIPC(ctx, hipStreamSynchronize(s));
+    stage.reset();
+    cand.reset();
+    idx->n_failed = n_failed_total;
+
+    // corrections (Sec. III-C)
+    {
+        Span span_correct(ctx, PH_CORRECT);
+        std::vector<uint8_t> hm(n, 0);
+        for (uint32_t k = first_built; k < n; k++)
+            hm[idx->h_sorted_items[k]] = 1;
+        DevBuf<uint8_t> has_map;
+        DevBuf<unsigned long long> cnt;
+        HIPC(ctx, has_map.alloc(n));
+        HIPC(ctx, cnt.alloc(1));
+        HIPC(ctx, hipMemcpyAsync(has_map.p, hm.data(), n, hipMemcpyHostToDevice, s));
+        HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
+        HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p, failed_bits.p,
+                                     has_map.p, n, nullptr, 0, cnt.p, s));
+        unsigned long long total = 0;
+        st = read_back(ctx, &total, cnt.p, 8);
+        if (st != BM_OK)
+            return st;
+        idx->n_corr = total;
+        HIPC(ctx, idx->corr.alloc(2 * std::max<uint64_t>(total, 1)));
+        if (total) {
+            HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
+            HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p,
+                                         failed_bits.p, has_map.p, n, idx->corr.p, total, cnt.p, s));
+        }
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+
+    return BM_OK;
+}
+
+InstDesc whole_desc(const bm_index *idx, uint32_t *out)
+{
+    InstDesc d;
+    d.arena = reinterpret_cast<const uint4 *>(idx->arena.p);
+    d.goff = idx->goff.p;
+    d.outpos = idx->sorted_items.p;
+    d.out = out;
+    d.n_out = idx->n;
+    d.gb = idx->gb;
+    d.pad = 0;
+    return d;
+}
+
+// Counts of all pairs among sorted indices >= first into the packed buffer `out` (device, zeroed here).
+bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
+{
+    bm_context *ctx = idx->ctx;
+    {
+        Span sp(ctx, PH_FILL);
+        HIPC(ctx, fill_u32(out, n_pairs(idx->n), 0, ctx->stream));
+    }
+    if (idx->planned_first != first) {
+        Plan plan;
+        plan_classes(classes_from(idx->classes, first), idx->r0, 0, target_items(ctx), plan);
+        bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
+        if (st != BM_OK)
+            return st;
+        idx->planned_first = first;
+        idx->planned_slot_pairs = plan.slot_pairs;
+    }
+    ctx->slot_pairs = idx->planned_slot_pairs;
+    {
+        Span sp(ctx, PH_COMPARE);
+        bm_status st = run_compare(ctx, idx->work.p, idx->work_ranges, whole_desc(idx, out));
+        if (st != BM_OK)
+            return st;
+    }
+    Span sp(ctx, PH_APPLY);
+    HIPC(ctx, launch_apply_corrections(idx->corr.p, idx->n_corr, out, idx->n, ctx->stream));
+    return BM_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void bm_build_opts_init(bm_build_opts *o)
+{
+    if (!o)
+        return;
+    memset(o, 0, sizeof(*o));
+    o->seed = 0x5eed;
+    o->max_loop = 64;
+    o->min_support = 0;
+}
+
+bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
+{
+    if (!out)
+        return BM_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return BM_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess)
+        return BM_EDEVICE;
+    bm_context *ctx = new (std::nothrow) bm_context();
+    if (!ctx)
+        return BM_ENOMEM;
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return BM_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+        ctx->n_cu = prop.multiProcessorCount;
+    *out = ctx;
+    return BM_OK;
+}
+
+void bm_context_destroy(bm_context *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    ctx->counter.reset();
+    clear_phases(ctx, 0, PH_COUNT - 1);
+    for (hipEvent_t e : ctx->event_pool)
+        (void)hipEventDestroy(e);
+    if (ctx->own_stream)
+        (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *bm_last_error(const bm_context *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+bm_status bm_context_set_profiling(bm_context *ctx, int enable)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    ctx->profiling = enable != 0;
+    return BM_OK;
+}
+
+bm_status bm_context_timings(bm_context *ctx, bm_timings *out)
+{
+    if (!ctx || !out)
+        return BM_EINVAL;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    double ms[PH_COUNT] = {0};
+    for (int p = 0; p < PH_COUNT; p++) {
+        for (auto &sp : ctx->spans[p]) {
+            HIPC(ctx, hipEventSynchronize(sp.second));
+            float t = 0;
+            HIPC(ctx, hipEventElapsedTime(&t, sp.first, sp.second));
+            ms[p] += t;
+        }
+    }
+    out->ingest_ms = ms[PH_INGEST];
+    out->layout_ms = ms[PH_LAYOUT];
+    out->construct_ms = ms[PH_CONSTRUCT];
+    out->encode_ms = ms[PH_ENCODE];
+    out->correct_ms = ms[PH_CORRECT];
+    out->fill_ms = ms[PH_FILL];
+    out->compare_ms = ms[PH_COMPARE];
+    out->apply_ms = ms[PH_APPLY];
+    out->threshold_ms = ms[PH_THRESHOLD];
+    out->compare_slot_pairs = ctx->slot_pairs;
+    out->compare_launches = ctx->spans[PH_COMPARE].size();
+    return BM_OK;
+}
+
+bm_status bm_synchronize(bm_context *ctx)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    return BM_OK;
+}
+
+bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, const uint64_t *offsets,
+                              const uint32_t *tids, const bm_build_opts *opts, bm_index **out)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    ctx->err.clear();
+    begin_build(ctx);
+    if (!out || !offsets || m == 0 || n_sets == 0)
+        return fail(ctx, BM_EINVAL, "bm_index_build_sets: null pointer or zero size");
+    *out = nullptr;
+    bm_build_opts o;
+    bm_build_opts_init(&o);
+    if (opts)
+        o = *opts;
+    bm_status st = check_opts(ctx, &o);
+    if (st != BM_OK)
+        return st;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    std::unique_ptr<bm_index> idx(new (std::nothrow) bm_index());
+    if (!idx)
+        return fail(ctx, BM_ENOMEM, "host allocation");
+    idx->ctx = ctx;
+    idx->device = ctx->device;
+    idx->m = m;
+    idx->n = n_sets;
+    hipStream_t s = ctx->stream;
+
+    idx->h_off.resize((size_t)n_sets + 1);
+    if (ptr_kind(offsets) == PTR_DEVICE) {
+        st = read_back(ctx, idx->h_off.data(), offsets, ((uint64_t)n_sets + 1) * 8);
+        if (st != BM_OK)
+            return st;
+    } else {
+        memcpy(idx->h_off.data(), offsets, ((size_t)n_sets + 1) * 8);
+    }
+    if (idx->h_off[0] != 0)
+        return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+    for (uint32_t i = 0; i < n_sets; i++)
+        if (idx->h_off[i + 1] < idx->h_off[i])
+            return fail(ctx, BM_EINVAL, "offsets decrease at set %u", i);
+    idx->nnz = idx->h_off[n_sets];
+    if (idx->nnz && !tids)
+        return fail(ctx, BM_EINVAL, "tids is null");
+    for (uint32_t i = 0; i < n_sets; i++)
+        if (idx->h_off[i + 1] - idx->h_off[i] > m)
+            return fail(ctx, BM_EUNSORTED, "set %u has more than m elements", i);
+
+    Span span_ingest(ctx, PH_INGEST);
+    HIPC(ctx, idx->off.alloc((uint64_t)n_sets + 1));
+    HIPC(ctx, idx->tids.alloc(std::max<uint64_t>(idx->nnz, 1)));
+    HIPC(ctx, hipMemcpyAsync(idx->off.p, idx->h_off.data(), ((uint64_t)n_sets + 1) * 8, hipMemcpyHostToDevice, s));
+    st = copy_in(ctx, idx->tids.p, tids, idx->nnz * 4);
+    if (st != BM_OK)
+        return st;
+    {
+        DevBuf<uint32_t> flags;
+        HIPC(ctx, flags.alloc(2));
+        HIPC(ctx, fill_u32(flags.p, 2, 0, s));
+        HIPC(ctx, launch_validate_sets(idx->off.p, idx->tids.p, n_sets, idx->nnz, m, flags.p, s));
+        uint32_t h[2] = {0, 0};
+        st = read_back(ctx, h, flags.p, 8);
+        if (st != BM_OK)
+            return st;
+        if (h[0])
+            return fail(ctx, BM_ERANGE, "a tid is >= m");
+        if (h[1])
+            return fail(ctx, BM_EUNSORTED, "a set's tids are not strictly increasing");
+    }
+    span_ingest.end();
+    st = build_common(idx.get(), &o);
+    if (st != BM_OK)
+        return st;
+    *out = idx.release();
+    return BM_OK;
+}
+
+bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_t m_txn, const uint64_t *offsets,
+                                      const uint32_t *items, const bm_build_opts *opts, bm_index **out)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    ctx->err.clear();
+    begin_build(ctx);
+    if (!out || !offsets || m_txn == 0 || n_items == 0)
+        return fail(ctx, BM_EINVAL, "bm_index_build_transactions: null pointer or zero size");
+    *out = nullptr;
+    bm_build_opts o;
+    bm_build_opts_init(&o);
+    if (opts)
+        o = *opts;
+    bm_status st = check_opts(ctx, &o);
+    if (st != BM_OK)
+        return st;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    std::unique_ptr<bm_index> idx(new (std::nothrow) bm_index());
+    if (!idx)
+        return fail(ctx, BM_ENOMEM, "host allocation");
+    idx->ctx = ctx;
+    idx->device = ctx->device;
+    idx->m = m_txn;
+    idx->n = n_items;
+    hipStream_t s = ctx->stream;
+
+    std::vector<uint64_t> roff((size_t)m_txn + 1);
+    if (ptr_kind(offsets) == PTR_DEVICE) {
+        st = read_back(ctx, roff.data(), offsets, ((uint64_t)m_txn + 1) * 8);
+        if (st != BM_OK)
+            return st;
+    } else {
+        memcpy(roff.data(), offsets, ((size_t)m_txn + 1) * 8);
+    }
+    if (roff[0] != 0)
+        return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+    for (uint32_t b = 0; b < m_txn; b++)
+        if (roff[b + 1] < roff[b])
+            return fail(ctx, BM_EINVAL, "offsets decrease at transaction %u", b);
+    uint64_t nnz_in = roff[m_txn];
+    if (nnz_in && !items)
+        return fail(ctx, BM_EINVAL, "items is null");
+    if (nnz_in > 0xFFFFFFFFull)
+        return fail(ctx, BM_EINVAL, "more than 2^32-1 incidences");
+
+    Span span_ingest(ctx, PH_INGEST);
+    DevBuf<uint64_t> d_roff;
+    DevBuf<uint32_t> keys, vals, k2, v2, flag;
+    DevBuf<char> tmp;
+    uint64_t N = std::max<uint64_t>(nnz_in, 1);
+    HIPC(ctx, d_roff.alloc((uint64_t)m_txn + 1));
+    HIPC(ctx, keys.alloc(N));
+    HIPC(ctx, vals.alloc(N));
+    HIPC(ctx, k2.alloc(N));
+    HIPC(ctx, v2.alloc(N));
+    HIPC(ctx, flag.alloc(1));
+    HIPC(ctx, hipMemcpyAsync(d_roff.p, roff.data(), ((uint64_t)m_txn + 1) * 8, hipMemcpyHostToDevice, s));
+    st = copy_in(ctx, keys.p, items, nnz_in * 4);
+    if (st != BM_OK)
+        return st;
+    HIPC(ctx, fill_u32(flag.p, 1, 0, s));
+    HIPC(ctx, launch_check_items(keys.p, nnz_in, n_items, flag.p, s));
+    uint32_t hflag = 0;
+    st = read_back(ctx, &hflag, flag.p, 4);
+    if (st != BM_OK)
+        return st;
+    if (hflag)
+        return fail(ctx, BM_ERANGE, "an item id is >= n_items");
+    HIPC(ctx, launch_expand_rows(d_roff.p, m_txn, vals.p, s));
+    HIPC(ctx, tmp.alloc(std::max(radix_tmp_bytes(N), scan_tmp_bytes(N))));
+    HIPC(ctx, radix_sort_pairs(keys.p, vals.p, k2.p, v2.p, nnz_in, bits_for(n_items - 1), tmp.p, s));
+    // drop an item repeated within one transaction (now adjacent equal pairs)
+    uint64_t nnz = nnz_in;
+    {
+        DevBuf<uint32_t> keep, ndup;
+        HIPC(ctx, keep.alloc(N));
+        HIPC(ctx, ndup.alloc(1));
+        HIPC(ctx, fill_u32(ndup.p, 1, 0, s));
+        HIPC(ctx, launch_mark_dups(keys.p, vals.p, nnz_in, keep.p, ndup.p, s));
+        uint32_t nd = 0;
+        st = read_back(ctx, &nd, ndup.p, 4);
+        if (st != BM_OK)
+            return st;
+        if (nd) {
+            DevBuf<uint64_t> pos;
+            HIPC(ctx, pos.alloc(N));
+            HIPC(ctx, exclusive_scan_u32_to_u64(keep.p, pos.p, nnz_in, tmp.p, s));
+            HIPC(ctx, launch_compact_pairs(keys.p, vals.p, keep.p, pos.p, nnz_in, k2.p, v2.p, s));
+            HIPC(ctx, hipStreamSynchronize(s));
+            std::swap(keys.p, k2.p);
+            std::swap(vals.p, v2.p);
+            nnz = nnz_in - nd;
+        }
+    }
+    idx->nnz = nnz;
+    HIPC(ctx, idx->off.alloc((uint64_t)n_items + 1));
+    HIPC(ctx, launch_offsets_from_sorted(keys.p, nnz, n_items, idx->off.p, s));
+    idx->h_off.resize((size_t)n_items + 1);
+    st = read_back(ctx, idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8);
+    if (st != BM_OK)
+        return st;
+    // the sorted values are the tidlists
+    idx->tids.p = vals.p;
+    idx->tids.n = vals.n;
+    vals.p = nullptr;
+    vals.n = 0;
+    span_ingest.end();
+    st = build_common(idx.get(), &o);
+    if (st != BM_OK)
+        return st;
+    *out = idx.release();
+    return BM_OK;
+}
+
+bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
+{
+    if (!idx || !out)
+        return BM_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->n_items = idx->n;
+    out->m = idx->m;
+    out->shift = idx->shift;
+    out->r0 = idx->r0;
+    out->max_loop = idx->max_loop;
+    out->n_classes = (uint32_t)idx->classes.size();
+    out->n_built = idx->n - idx->first_built;
+    out->min_support = idx->min_support;
+    out->nnz = idx->nnz;
+    out->batmap_bytes = idx->total_groups * kSlotsPerGroup;
+    out->n_failed = idx->n_failed;
+    out->n_corrections = idx->n_corr;
+    return BM_OK;
+}
+
+void bm_index_destroy(bm_index *idx)
+{
+    // Uses only the index's own device id, so it stays valid after the
+    // context is gone; hipFree waits for outstanding work on the buffers.
+    if (!idx)
+        return;
+    (void)hipSetDevice(idx->device);
+    delete idx;
+}
+
+bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    uint64_t np = n_pairs(idx->n);
+    if (np == 0)
+        return BM_OK;
+    if (!out)
+        return fail(ctx, BM_EINVAL, "out is null");
+    if (out_len < np)
+        return fail(ctx, BM_ECAPACITY, "out holds %llu entries, %llu needed", (unsigned long long)out_len,
+                    (unsigned long long)np);
+    if (idx->first_built != 0)
+        return fail(ctx, BM_EINVAL, "index built with min_support > 0 has no BatMap for some items");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    bool host = ptr_kind(out) == PTR_HOST;
+    uint32_t *dst = out;
+    if (host) {
+        HIPC(ctx, idx->pairbuf.ensure(np));
+        dst = idx->pairbuf.p;
+    }
+    bm_status st = count_pairs(idx, 0, dst);
+    if (st != BM_OK)
+        return st;
+    if (host) {
+        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return BM_OK;
+}
+
+bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity, uint64_t *n_out)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    if (!n_out)
+        return fail(ctx, BM_EINVAL, "n_out is null");
+    *n_out = 0;
+    if (min_support < idx->min_support)
+        return fail(ctx, BM_EINVAL, "min_support %u is below the build's %u", min_support, idx->min_support);
+    uint64_t np = n_pairs(idx->n);
+    if (np == 0)
+        return BM_OK;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // items with |S_i| < min_support cannot be in a frequent pair: they are a
+    // prefix of the size order, so only the suffix is compared.
+    uint32_t first = (uint32_t)(std::lower_bound(idx->h_sizes_sorted.begin(), idx->h_sizes_sorted.end(), min_support) -
+                                idx->h_sizes_sorted.begin());
+    first = std::max(first, idx->first_built);
+    HIPC(ctx, idx->pairbuf.ensure(np));
+    bm_status st = count_pairs(idx, first, idx->pairbuf.p);
+    if (st != BM_OK)
+        return st;
+    uint32_t nb = threshold_blocks(np);
+    HIPC(ctx, idx->thr_counts.ensure((uint64_t)nb + 1));
+    HIPC(ctx, idx->thr_off.ensure((uint64_t)nb + 1));
+    HIPC(ctx, idx->scan_tmp.ensure(scan_tmp_bytes((uint64_t)nb + 1)));
+    Span span_thr(ctx, PH_THRESHOLD);
+    HIPC(ctx, fill_u32(idx->thr_counts.p + nb, 1, 0, s));
+    HIPC(ctx, launch_threshold_count(idx->pairbuf.p, np, min_support, idx->thr_counts.p, nb, s));
+    HIPC(ctx, exclusive_scan_u32_to_u64(idx->thr_counts.p, idx->thr_off.p, (uint64_t)nb + 1, idx->scan_tmp.p, s));
+    uint64_t total = 0;
+    span_thr.end();
+    st = read_back(ctx, &total, idx->thr_off.p + nb, 8);
+    if (st != BM_OK)
+        return st;
+    *n_out = total;
+    if (total == 0)
+        return BM_OK;
+    if (!out)
+        return fail(ctx, BM_EINVAL, "out is null");
+    if (total > capacity)
+        return fail(ctx, BM_ECAPACITY, "%llu frequent pairs, capacity %llu", (unsigned long long)total,
+                    (unsigned long long)capacity);
+    bool host = ptr_kind(out) == PTR_HOST;
+    bm_pair *dst = out;
+    if (host) {
+        HIPC(ctx, idx->pair_out.ensure(total));
+        dst = idx->pair_out.p;
+    }
+    {
+        Span sp(ctx, PH_THRESHOLD);
+        HIPC(ctx, launch_threshold_write(idx->pairbuf.p, np, idx->n, min_support, idx->thr_off.p, nb, dst, s));
+    }
+    if (host) {
+        HIPC(ctx, hipMemcpyAsync(out, dst, total * sizeof(bm_pair), hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+    return BM_OK;
+}
+
+bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t k, uint32_t *out)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    uint64_t np = n_pairs(k);
+    if (k == 0)
+        return BM_OK;
+    if (!items || (np && !out))
+        return fail(ctx, BM_EINVAL, "null pointer");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // host copy of the query (to plan) and device copy (to validate)
+    std::vector<uint32_t> q(k);
+    bm_status st;
+    if (ptr_kind(items) == PTR_DEVICE) {
+        st = read_back(ctx, q.data(), items, (uint64_t)k * 4);
+        if (st != BM_OK)
+            return st;
+    } else {
+        memcpy(q.data(), items, (size_t)k * 4);
+    }
+    for (uint32_t p = 0; p < k; p++)
+        if (q[p] >= idx->n)
+            return fail(ctx, BM_ERANGE, "item %u >= n", q[p]);
+    HIPC(ctx, idx->pos_of_item.ensure(idx->n));
+    HIPC(ctx, idx->sub_items.ensure(k));
+    HIPC(ctx, idx->sub_flag.ensure(1));
+    HIPC(ctx, hipMemcpyAsync(idx->sub_items.p, q.data(), (uint64_t)k * 4, hipMemcpyHostToDevice, s));
+    HIPC(ctx, fill_u32(idx->pos_of_item.p, idx->n, kEmpty, s));
+    HIPC(ctx, fill_u32(idx->sub_flag.p, 1, 0, s));
+    HIPC(ctx, launch_subset_prepare(idx->sub_items.p, k, idx->n, idx->sorted_pos.p, idx->pos_of_item.p,
+                                    idx->sub_flag.p, s));
+    uint32_t fl = 0;
+    st = read_back(ctx, &fl, idx->sub_flag.p, 4);
+    if (st != BM_OK)
+        return st;
+    if (fl & 1u)
+        return fail(ctx, BM_ERANGE, "item id >= n");
+    if (fl & 2u)
+        return fail(ctx, BM_EINVAL, "repeated item in the query");
+    if (fl & 4u)
+        return fail(ctx, BM_EINVAL, "an item of the query has no BatMap (pruned at build)");
+    if (np == 0)
+        return BM_OK;
+    // order the query's maps by width; output positions are query positions
+    std::vector<uint32_t> ord(k);
+    std::vector<int32_t> sp(k);
+    {
+        // sorted position of each queried item
+        std::vector<int32_t> all_sp(idx->n, -1);
+        for (uint32_t p2 = idx->first_built; p2 < idx->n; p2++)
+            all_sp[idx->h_sorted_items[p2]] = (int32_t)p2;
+        for (uint32_t p = 0; p < k; p++)
+            sp[p] = all_sp[q[p]];
+    }
+    for (uint32_t p = 0; p < k; p++)
+        ord[p] = p;
+    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return sp[a] < sp[b]; });
+    std::vector<uint64_t> h_goff(k);
+    std::vector<uint32_t> h_outpos(k);
+    const std::vector<uint64_t> &all_goff = idx->h_goff;
+    std::vector<Cls> cls;
+    for (uint32_t t = 0; t < k; t++) {
+        uint32_t p = ord[t];
+        uint32_t r = idx->h_r_sorted[sp[p]];
+        h_goff[t] = all_goff[sp[p]];
+        h_outpos[t] = p;
+        if (cls.empty() || cls.back().r != r)
+            cls.push_back({r, t, 0});
+        cls.back().count++;
+    }
+    HIPC(ctx, idx->sub_goff.ensure(k));
+    HIPC(ctx, idx->sub_outpos.ensure(k));
+    HIPC(ctx, hipMemcpyAsync(idx->sub_goff.p, h_goff.data(), (uint64_t)k * 8, hipMemcpyHostToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(idx->sub_outpos.p, h_outpos.data(), (uint64_t)k * 4, hipMemcpyHostToDevice, s));
+    bool host = ptr_kind(out) == PTR_HOST;
+    uint32_t *dst = out;
+    if (host) {
+        HIPC(ctx, idx->sub_out.ensure(np));
+        dst = idx->sub_out.p;
+    }
+    InstDesc d;
+    d.arena = reinterpret_cast<const uint4 *>(idx->arena.p);
+    d.goff = idx->sub_goff.p;
+    d.outpos = idx->sub_outpos.p;
+    d.out = dst;
+    d.n_out = k;
+    d.gb = idx->gb;
+    d.pad = 0;
+    Plan plan;
+    plan_classes(cls, idx->r0, 0, target_items(ctx), plan);
+    std::vector<std::pair<int, uint32_t>> ranges;
+    st = upload_plan(idx, plan, idx->sub_work, ranges);
+    if (st != BM_OK)
+        return st;
+    {
+        Span sp(ctx, PH_FILL);
+        HIPC(ctx, fill_u32(dst, np, 0, s));
+    }
+    ctx->slot_pairs = plan.slot_pairs;
+    {
+        Span sp(ctx, PH_COMPARE);
+        st = run_compare(ctx, idx->sub_work.p, ranges, d);
+        if (st != BM_OK)
+            return st;
+    }
+    {
+        Span sp(ctx, PH_APPLY);
+        HIPC(ctx, launch_apply_corrections_subset(idx->corr.p, idx->n_corr, idx->pos_of_item.p, dst, k, s));
+    }
+    if (host) {
+        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIPC(ctx, hipStreamSynchronize(s));
+    return BM_OK;
+}
+
+bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    ctx->err.clear();
+    begin_query(ctx);
+    if (count == 0)
+        return BM_OK;
+    if (!idxs || !outs)
+        return fail(ctx, BM_EINVAL, "null pointer");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    std::vector<InstDesc> descs(count);
+    Plan all;
+    all.by_variant.assign(compare_variant_count(), {});
+    for (uint32_t q = 0; q < count; q++) {
+        bm_index *idx = idxs[q];
+        if (!idx || idx->ctx != ctx)
+            return fail(ctx, BM_EINVAL, "index %u is null or belongs to another context", q);
+        if (idx->first_built != 0)
+            return fail(ctx, BM_EINVAL, "index %u was built with min_support > 0", q);
+        if (n_pairs(idx->n) && !outs[q])
+            return fail(ctx, BM_EINVAL, "outs[%u] is null", q);
+        if (n_pairs(idx->n) && ptr_kind(outs[q]) != PTR_DEVICE)
+            return fail(ctx, BM_EINVAL, "outs[%u] must be device memory", q);
+        InstDesc &d = descs[q];
+        d.arena = reinterpret_cast<const uint4 *>(idx->arena.p);
+        d.goff = idx->goff.p;
+        d.outpos = idx->sorted_items.p;
+        d.out = outs[q];
+        d.n_out = idx->n;
+        d.gb = idx->gb;
+        d.pad = 0;
+        Plan one;
+        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one);
+        ctx->slot_pairs += one.slot_pairs;
+        for (size_t v = 0; v < one.by_variant.size(); v++)
+            all.by_variant[v].insert(all.by_variant[v].end(), one.by_variant[v].begin(), one.by_variant[v].end());
+    }
+    for (auto &v : all.by_variant)
+        std::stable_sort(v.begin(), v.end(),
+                         [](const WorkItem &x, const WorkItem &y) { return (x.c1 - x.c0) > (y.c1 - y.c0); });
+    DevBuf<InstDesc> d_desc;
+    DevBuf<WorkItem> d_work;
+    HIPC(ctx, d_desc.alloc(count));
+    HIPC(ctx, hipMemcpyAsync(d_desc.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    HIPC(ctx, hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < count; q++)
+        if (n_pairs(idxs[q]->n))
+            HIPC(ctx, fill_u32(outs[q], n_pairs(idxs[q]->n), 0, s));
+    std::vector<std::pair<int, uint32_t>> ranges;
+    uint64_t total = 0;
+    std::vector<WorkItem> flat;
+    for (size_t v = 0; v < all.by_variant.size(); v++) {
+        if (all.by_variant[v].empty())
+            continue;
+        ranges.push_back({(int)v, (uint32_t)all.by_variant[v].size()});
+        flat.insert(flat.end(), all.by_variant[v].begin(), all.by_variant[v].end());
+    }
+    total = flat.size();
+    HIPC(ctx, d_work.alloc(std::max<uint64_t>(total, 1)));
+    if (total) {
+        HIPC(ctx, hipMemcpyAsync(d_work.p, flat.data(), total * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+    HIPC(ctx, ctx->counter.ensure(64));
+    uint64_t at = 0;
+    uint32_t grid = (uint32_t)ctx->n_cu * 4;
+    Span span_cmp(ctx, PH_COMPARE);
+    for (size_t r = 0; r < ranges.size(); r++) {
+        HIPC(ctx, fill_u32(ctx->counter.p + r, 1, 0, s));
+        HIPC(ctx, launch_compare_persistent(d_work.p + at, ranges[r].second, d_desc.p, descs[0], ranges[r].first,
+                                            ctx->counter.p + r, grid, s));
+        at += ranges[r].second;
+    }
+    span_cmp.end();
+    Span span_apply(ctx, PH_APPLY);
+    for (uint32_t q = 0; q < count; q++)
+        HIPC(ctx, launch_apply_corrections(idxs[q]->corr.p, idxs[q]->n_corr, outs[q], idxs[q]->n, s));
+    span_apply.end();
+    HIPC(ctx, hipStreamSynchronize(s));
+    return BM_OK;
+}
+
+bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_len)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    uint64_t np = n_pairs(idx->n);
+    if (np == 0)
+        return BM_OK;
+    if (!out)
+        return fail(ctx, BM_EINVAL, "out is null");
+    if (out_len < np)
+        return fail(ctx, BM_ECAPACITY, "out holds %llu entries, %llu needed", (unsigned long long)out_len,
+                    (unsigned long long)np);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    if (!idx->dense_A.p) {
+        Span sp(ctx, PH_ENCODE);
+        uint64_t ld = ((uint64_t)idx->m + 127) / 128 * 128;
+        uint64_t rows = ((uint64_t)idx->n + 127) / 128 * 128;
+        HIPC(ctx, idx->dense_A.alloc(rows * ld));
+        HIPC(ctx, fill_u8(reinterpret_cast<uint8_t *>(idx->dense_A.p), rows * ld, 0, s));
+        HIPC(ctx, launch_bitmap_build(idx->off.p, idx->tids.p, idx->n, ld, idx->dense_A.p, s));
+        idx->dense_ld = ld;
+    }
+    bool host = ptr_kind(out) == PTR_HOST;
+    uint32_t *dst = out;
+    if (host) {
+        HIPC(ctx, idx->pairbuf.ensure(np));
+        dst = idx->pairbuf.p;
+    }
+    {
+        Span sp(ctx, PH_FILL);
+        HIPC(ctx, fill_u32(dst, np, 0, s));
+    }
+    uint64_t T = ((uint64_t)idx->n + 127) / 128;
+    uint64_t tiles = T * (T + 1) / 2;
+    uint64_t want = (uint64_t)ctx->n_cu * 4;
+    uint32_t ksplit = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want / std::max<uint64_t>(tiles, 1),
+                                                                          idx->dense_ld / 1024));
+    {
+        Span sp(ctx, PH_COMPARE);
+        HIPC(ctx, launch_dense_gram(idx->dense_A.p, idx->n, idx->dense_ld, idx->dense_ld, dst, ksplit, s));
+    }
+    if (host) {
+        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+    return BM_OK;
+}
+
+bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t *r, uint8_t *bytes, uint32_t *failed,
+                          uint32_t *perms)
+{
+    if (!cidx)
+        return BM_EINVAL;
+    bm_index *idx = const_cast<bm_index *>(cidx);
+    bm_context *ctx = idx->ctx;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    uint32_t nb = idx->n - idx->first_built;
+    if (sorted_items)
+        memcpy(sorted_items, idx->h_sorted_items.data() + idx->first_built, (size_t)nb * 4);
+    if (r)
+        memcpy(r, idx->h_r_sorted.data() + idx->first_built, (size_t)nb * 4);
+    if (bytes && idx->total_groups) {
+        DevBuf<uint8_t> tmp;
+        HIPC(ctx, tmp.alloc(idx->total_groups * kSlotsPerGroup));
+        HIPC(ctx, launch_decode(idx->arena.p, idx->total_groups, tmp.p, ctx->stream));
+        bm_status st = read_back(ctx, bytes, tmp.p, idx->total_groups * kSlotsPerGroup);
+        if (st != BM_OK)
+            return st;
+    }
+    if (failed && idx->n_failed) {
+        bm_status st = read_back(ctx, failed, idx->failed.p, idx->n_failed * 8);
+        if (st != BM_OK)
+            return st;
+    }
+    if (perms) {
+        bm_status st = read_back(ctx, perms, idx->pi.p, 3ull * idx->m * 4);
+        if (st != BM_OK)
+            return st;
+    }
+    return BM_OK;
+}
+
+}  // extern "C"

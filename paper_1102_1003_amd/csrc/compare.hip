@@ -1,0 +1,232 @@
+// Pair compare-and-count (Sec. II "Our adaptation", Fig. 1; Sec. III-A).
+//
+// For a pair of maps with r_i <= r_j, slot v of the wider map B_j is compared
+// with slot v mod 3 r_i of B_i (r_i divides r_j).  A slot pair counts when the
+// 7-bit codes are equal and at least one indicator bit is set (Sec. II, the
+// counting rule behind Fig. 3); empty slots (0x7F, indicator 0) never count.
+// Summed over all slots this is |S_i cap S_j| minus the elements whose
+// insertion failed, which are added back separately (Sec. III-C).
+//
+// Storage is bit-sliced (32 slots per group, 8 planes), so one group pair of
+// two maps is 32 slot comparisons done with 9 VALU instructions:
+//   mm  = OR_b (x_b xor y_b), b = 0..6     -- 7 v_bitop3 / v_xor
+//   hit = ~mm & (x_7 | y_7)                -- 1 v_bitop3
+//   acc += popcount(hit)                   -- 1 v_bcnt_u32_b32
+//
+// Work is tiled as in Sec. III-B (all maps of a tile share loop bounds, Sec.
+// III-C sorting by width): a workgroup takes a tile of BI row maps of one
+// width class against BJ column maps of an equal or wider class, over a range
+// of column groups, stages KG groups of every map of the tile in LDS per step
+// and gives every thread an MI x MJ register tile of pairs.  Row groups wrap:
+// column group c meets row group (block(c) mod row_blocks) * gb + c mod gb,
+// which is c mod (3 r_row / 32) in the Fig. 4 block layout.  Partial counts are
+// added atomically into the packed output, so ranges of one pair may be split
+// across workgroups.
+#include "bm_internal.h"
+
+namespace bm {
+
+namespace {
+
+constexpr int KG = (int)kStageGroups;
+
+template <int MI, int MJ, int TX>
+struct Shape {
+    static constexpr int TY = 256 / TX;
+    static constexpr int BI = TX * MI;
+    static constexpr int BJ = TY * MJ;
+};
+
+template <int MI, int MJ, int TX>
+struct Smem {
+    uint4 row[KG][Shape<MI, MJ, TX>::BI][2];
+    uint4 col[KG][Shape<MI, MJ, TX>::BJ][2];
+    uint64_t goff_r[Shape<MI, MJ, TX>::BI];
+    uint64_t goff_c[Shape<MI, MJ, TX>::BJ];
+    uint32_t item;
+};
+
+// v_bitop3_b32 truth tables: bit (4a + 2b + c) of the immediate is f(a, b, c).
+constexpr int kXorOr = 0xBE;     // (a ^ b) | c
+constexpr int kNotAndOr = 0x0E;  // ~a & (b | c)
+
+// Hits among the 32 slot pairs of one group pair: codes (planes 0..6) all
+// equal and at least one indicator (plane 7) set.
+__device__ inline uint32_t group_hits(const uint32_t (&x)[8], const uint32_t (&y)[8], uint32_t acc)
+{
+    uint32_t mm = x[0] ^ y[0];
+#pragma unroll
+    for (int b = 1; b < 7; b++)
+        mm = __builtin_amdgcn_bitop3_b32(x[b], y[b], mm, kXorOr);
+    uint32_t hit = __builtin_amdgcn_bitop3_b32(mm, x[7], y[7], kNotAndOr);
+    return __builtin_popcount(hit) + acc;
+}
+
+__device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
+{
+    return i * n - i * (i + 1) / 2 + (j - i - 1);
+}
+
+template <int MI, int MJ, int TX>
+__device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, TX> &sm)
+{
+    using S = Shape<MI, MJ, TX>;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+
+    for (int i = tid; i < S::BI; i += 256) {
+        uint32_t rr = i < w.nrow ? i : w.nrow - 1;
+        sm.goff_r[i] = d.goff[w.row0 + rr];
+    }
+    for (int j = tid; j < S::BJ; j += 256) {
+        uint32_t cc = j < w.ncol ? j : w.ncol - 1;
+        sm.goff_c[j] = d.goff[w.col0 + cc];
+    }
+    __syncthreads();
+
+    uint32_t acc[MI][MJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[i][j] = 0;
+
+    const uint32_t gb = d.gb;
+    for (uint32_t c = w.c0; c < w.c1; c += KG) {
+        uint32_t blk = c / gb;
+        uint32_t within = c - blk * gb;
+        uint32_t rg = (blk & (w.row_blocks - 1)) * gb + within;
+        // global -> LDS: every map contributes KG consecutive groups (KG*32 bytes)
+        for (int u = tid; u < S::BI * KG * 2; u += 256) {
+            int rho = u / (KG * 2), rem = u % (KG * 2);
+            sm.row[rem / 2][rho][rem % 2] = d.arena[(sm.goff_r[rho] + rg + rem / 2) * 2 + (rem % 2)];
+        }
+        for (int u = tid; u < S::BJ * KG * 2; u += 256) {
+            int kap = u / (KG * 2), rem = u % (KG * 2);
+            sm.col[rem / 2][kap][rem % 2] = d.arena[(sm.goff_c[kap] + c + rem / 2) * 2 + (rem % 2)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gg = 0; gg < KG; gg++) {
+            uint32_t x[MI][8], y[MJ][8];
+#pragma unroll
+            for (int i = 0; i < MI; i++) {
+                uint4 a = sm.row[gg][tx + TX * i][0], b = sm.row[gg][tx + TX * i][1];
+                x[i][0] = a.x; x[i][1] = a.y; x[i][2] = a.z; x[i][3] = a.w;
+                x[i][4] = b.x; x[i][5] = b.y; x[i][6] = b.z; x[i][7] = b.w;
+            }
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                uint4 a = sm.col[gg][ty + S::TY * j][0], b = sm.col[gg][ty + S::TY * j][1];
+                y[j][0] = a.x; y[j][1] = a.y; y[j][2] = a.z; y[j][3] = a.w;
+                y[j][4] = b.x; y[j][5] = b.y; y[j][6] = b.z; y[j][7] = b.w;
+            }
+#pragma unroll
+            for (int i = 0; i < MI; i++) {
+#pragma unroll
+                for (int j = 0; j < MJ; j++) {
+                    acc[i][j] = group_hits(x[i], y[j], acc[i][j]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < MI; i++) {
+        int rho = tx + TX * i;
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            int kap = ty + S::TY * j;
+            if (rho < w.nrow && kap < w.ncol && acc[i][j] != 0) {
+                uint32_t p = w.row0 + rho, q = w.col0 + kap;
+                if ((w.flags & 1u) && p >= q)
+                    continue;
+                uint32_t a = d.outpos[p], b = d.outpos[q];
+                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[i][j]);
+            }
+        }
+    }
+}
+
+template <int MI, int MJ, int TX>
+__global__ __launch_bounds__(256) void compare_kernel(const WorkItem *__restrict__ items,
+                                                      const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    __shared__ Smem<MI, MJ, TX> sm;
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_item<MI, MJ, TX>(w, d, sm);
+}
+
+// Persistent form: a fixed grid pulls work items from a counter until the
+// list is exhausted (every workgroup exits once the counter passes n_items).
+template <int MI, int MJ, int TX>
+__global__ __launch_bounds__(256) void compare_persistent_kernel(const WorkItem *__restrict__ items,
+                                                                 uint32_t n_items,
+                                                                 const InstDesc *__restrict__ descs,
+                                                                 InstDesc d0, uint32_t *counter)
+{
+    __shared__ Smem<MI, MJ, TX> sm;
+    for (;;) {
+        if (threadIdx.x == 0)
+            sm.item = atomicAdd(counter, 1u);
+        __syncthreads();
+        uint32_t it = sm.item;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        const InstDesc d = descs ? descs[w.inst] : d0;
+        process_item<MI, MJ, TX>(w, d, sm);
+    }
+}
+
+struct Variant {
+    uint32_t bi, bj;
+    void (*grid_fn)(const WorkItem *, const InstDesc *, InstDesc);
+    void (*pers_fn)(const WorkItem *, uint32_t, const InstDesc *, InstDesc, uint32_t *);
+};
+
+#define BM_VARIANT(MI, MJ, TX)                                                                          \
+    Variant{Shape<MI, MJ, TX>::BI, Shape<MI, MJ, TX>::BJ, compare_kernel<MI, MJ, TX>,                  \
+            compare_persistent_kernel<MI, MJ, TX>}
+
+const Variant kVariants[] = {
+    BM_VARIANT(4, 4, 16),  // 64 x 64
+    BM_VARIANT(4, 4, 32),  // 128 x 32
+    BM_VARIANT(4, 4, 64),  // 256 x 16
+    BM_VARIANT(2, 4, 128), // 256 x 8
+};
+
+}  // namespace
+
+int compare_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj)
+{
+    *bi = kVariants[v].bi;
+    *bj = kVariants[v].bj;
+}
+
+hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
+                          int variant, hipStream_t s)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(kVariants[variant].grid_fn, dim3(n_items), dim3(256), 0, s, items, descs, d0);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
+                                     const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
+                                     hipStream_t s)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(kVariants[variant].pers_fn, dim3(grid), dim3(256), 0, s, items, n_items, descs, d0, counter);
+    return hipGetLastError();
+}
+
+}  // namespace bm

@@ -1,0 +1,129 @@
+// Dense comparator: the plain bitmap route (Sec. I-A, "bitmaps ... AND ... count
+// the number of 1s"; the PBI-GPU layout of Sec. I-B).  Every tidlist becomes a
+// row of a 0/1 int8 matrix A (n x m, zero padded), and all supports are the
+// Gram matrix A A^T, taken on the int8 matrix cores (v_mfma_i32_16x16x64_i8,
+// int32 accumulation, exact while m < 2^31).  Only tiles on or above the
+// diagonal are computed; the contraction dimension may be split across
+// workgroups, partial sums being added atomically.
+#include "bm_internal.h"
+
+namespace bm {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int DT = 128;   // output tile (rows and columns)
+constexpr int DK = 128;   // contraction bytes staged per step
+constexpr int DPAD = 16;  // LDS row padding against bank conflicts
+
+// One block per item row: A[i, t] = 1 for t in S_i (A zero-filled before).
+__global__ void bitmap_build_kernel(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t ld, int8_t *A)
+{
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        int8_t *row = A + (uint64_t)i * ld;
+        for (uint64_t k = off[i] + threadIdx.x; k < off[i + 1]; k += blockDim.x)
+            row[tids[k]] = 1;
+    }
+}
+
+__device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
+{
+    return i * n - i * (i + 1) / 2 + (j - i - 1);
+}
+
+// 256 threads = 2 x 2 wavefronts, each owning a 64 x 64 quarter of the tile as
+// 4 x 4 MFMA blocks of 16 x 16.  For the MFMA operands, lane l supplies row
+// (l mod 16) of its 16-row block and the 16 contraction bytes
+// [16 (l / 16), 16 (l / 16) + 16) of the current 64; the result lane l, element
+// e holds row 4 (l / 16) + e, column l mod 16 of the block.
+__global__ __launch_bounds__(256) void dense_gram_kernel(const int8_t *__restrict__ A, uint32_t n, uint64_t ld,
+                                                         uint64_t k_len, uint32_t T, uint64_t k_chunk,
+                                                         uint32_t *out)
+{
+    uint32_t ti = blockIdx.x / T, tj = blockIdx.x % T;
+    if (ti > tj)
+        return;
+    uint64_t k0 = (uint64_t)blockIdx.y * k_chunk;
+    uint64_t k1 = k0 + k_chunk < k_len ? k0 + k_chunk : k_len;
+    __shared__ __attribute__((aligned(16))) int8_t sA[DT][DK + DPAD];
+    __shared__ __attribute__((aligned(16))) int8_t sB[DT][DK + DPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+    v4i acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            acc[a][b] = v4i{0, 0, 0, 0};
+    const int8_t *Ar = A + (uint64_t)ti * DT * ld;
+    const int8_t *Br = A + (uint64_t)tj * DT * ld;
+    for (uint64_t k = k0; k < k1; k += DK) {
+#pragma unroll
+        for (int u = tid; u < DT * DK / 16; u += 256) {
+            int row = u / (DK / 16), ch = u % (DK / 16);
+            *reinterpret_cast<uint4 *>(&sA[row][ch * 16]) =
+                *reinterpret_cast<const uint4 *>(Ar + (uint64_t)row * ld + k + ch * 16);
+            *reinterpret_cast<uint4 *>(&sB[row][ch * 16]) =
+                *reinterpret_cast<const uint4 *>(Br + (uint64_t)row * ld + k + ch * 16);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < DK / 64; ks++) {
+            v4i fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+                fa[a] = *reinterpret_cast<const v4i *>(&sA[wr * 64 + a * 16 + (lane & 15)][ks * 64 + (lane >> 4) * 16]);
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+                fb[b] = *reinterpret_cast<const v4i *>(&sB[wc * 64 + b * 16 + (lane & 15)][ks * 64 + (lane >> 4) * 16]);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                uint64_t i = (uint64_t)ti * DT + wr * 64 + a * 16 + (lane >> 4) * 4 + e;
+                uint64_t j = (uint64_t)tj * DT + wc * 64 + b * 16 + (lane & 15);
+                int v = acc[a][b][e];
+                if (i < j && j < n && v != 0)
+                    atomicAdd(&out[packed_index(n, i, j)], (uint32_t)v);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bitmap_build(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t ld, int8_t *A,
+                               hipStream_t s)
+{
+    uint32_t g = n < 65536 ? n : 65536;
+    if (g == 0)
+        return hipSuccess;
+    bitmap_build_kernel<<<g, 256, 0, s>>>(off, tids, n, ld, A);
+    return hipGetLastError();
+}
+
+// A: n_pad x ld int8 with n_pad a multiple of 128 and ld (= k_len) a multiple of 128.
+hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t k_len, uint32_t *out,
+                             uint32_t k_split, hipStream_t s)
+{
+    uint32_t T = (n + DT - 1) / DT;
+    if (T == 0)
+        return hipSuccess;
+    uint64_t chunk = (k_len + k_split - 1) / k_split;
+    chunk = (chunk + DK - 1) / DK * DK;
+    uint32_t ks = (uint32_t)((k_len + chunk - 1) / chunk);
+    dense_gram_kernel<<<dim3(T * T, ks), 256, 0, s>>>(A, n, ld, k_len, T, chunk, out);
+    return hipGetLastError();
+}
+
+}  // namespace bm

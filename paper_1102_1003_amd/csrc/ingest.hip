@@ -1,0 +1,149 @@
+// Ingest (Sec. I, "Set representations"): validation of the vertical format
+// (sorted tidlists) and conversion of the horizontal format (transactions) to
+// it.  The conversion is a stable sort of (item, tid) pairs by item: pairs
+// arrive in tid order, so every tidlist comes out sorted.
+#include "bm_internal.h"
+
+namespace bm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 20)
+{
+    uint64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1)
+        g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+// row_of[k] = b for every k in transaction b.
+__global__ void expand_rows_kernel(const uint64_t *row_off, uint32_t m, uint32_t *row_of)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += stride) {
+        uint64_t e = row_off[b + 1];
+        for (uint64_t k = row_off[b]; k < e; k++)
+            row_of[k] = (uint32_t)b;
+    }
+}
+
+__global__ void check_items_kernel(const uint32_t *items, uint64_t nnz, uint32_t n, uint32_t *flag)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride)
+        bad |= items[k] >= n;
+    if (bad)
+        atomicOr(flag, 1u);
+}
+
+__global__ void mark_dups_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t *keep,
+                                 uint32_t *n_dup)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t dups = 0;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+        bool dup = k > 0 && keys[k] == keys[k - 1] && vals[k] == vals[k - 1];
+        keep[k] = dup ? 0u : 1u;
+        dups += dup;
+    }
+    if (dups)
+        atomicAdd(n_dup, dups);
+}
+
+__global__ void compact_pairs_kernel(const uint32_t *keys, const uint32_t *vals, const uint32_t *keep,
+                                     const uint64_t *pos, uint64_t nnz, uint32_t *ko, uint32_t *vo)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+        if (keep[k]) {
+            ko[pos[k]] = keys[k];
+            vo[pos[k]] = vals[k];
+        }
+    }
+}
+
+// off[a] = first position whose key is >= a, for a in [0, n]; keys sorted.
+__global__ void offsets_from_sorted_kernel(const uint32_t *keys, uint64_t nnz, uint32_t n, uint64_t *off)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nnz; k += stride) {
+        uint32_t lo = k == 0 ? 0u : keys[k - 1] + 1u;     // first key not yet started
+        uint32_t hi = k == nnz ? n : keys[k];              // keys that start here
+        for (uint32_t a = lo; a <= hi && a <= n; a++)
+            off[a] = k;
+    }
+}
+
+// One block per set: every tid < m and strictly increasing.
+// flags[0] |= 1 on a range error, flags[1] |= 1 on an order error.
+__global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, uint32_t n, uint32_t m,
+                                     uint32_t *flags)
+{
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        uint64_t b = off[i], e = off[i + 1];
+        bool range = false, order = false;
+        for (uint64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+            uint32_t t = tids[k];
+            range |= t >= m;
+            order |= (k > b) && (t <= tids[k - 1]);
+        }
+        if (range)
+            atomicOr(&flags[0], 1u);
+        if (order)
+            atomicOr(&flags[1], 1u);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s)
+{
+    expand_rows_kernel<<<blocks_for(m), kBlock, 0, s>>>(row_off, m, row_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_items(const uint32_t *items, uint64_t nnz, uint32_t n, uint32_t *flag, hipStream_t s)
+{
+    if (nnz == 0)
+        return hipSuccess;
+    check_items_kernel<<<blocks_for(nnz, 4096), kBlock, 0, s>>>(items, nnz, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t *keep,
+                            uint32_t *n_dup, hipStream_t s)
+{
+    if (nnz == 0)
+        return hipSuccess;
+    mark_dups_kernel<<<blocks_for(nnz, 4096), kBlock, 0, s>>>(keys, vals, nnz, keep, n_dup);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_pairs(const uint32_t *keys, const uint32_t *vals, const uint32_t *keep,
+                                const uint64_t *pos, uint64_t nnz, uint32_t *ko, uint32_t *vo, hipStream_t s)
+{
+    if (nnz == 0)
+        return hipSuccess;
+    compact_pairs_kernel<<<blocks_for(nnz, 4096), kBlock, 0, s>>>(keys, vals, keep, pos, nnz, ko, vo);
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets_from_sorted(const uint32_t *keys, uint64_t nnz, uint32_t n, uint64_t *off, hipStream_t s)
+{
+    offsets_from_sorted_kernel<<<blocks_for(nnz + 1, 4096), kBlock, 0, s>>>(keys, nnz, n, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t nnz, uint32_t m,
+                                uint32_t *flags, hipStream_t s)
+{
+    (void)nnz;
+    uint32_t g = n < 65536 ? n : 65536;
+    validate_sets_kernel<<<g, kBlock, 0, s>>>(off, tids, n, m, flags);
+    return hipGetLastError();
+}
+
+}  // namespace bm

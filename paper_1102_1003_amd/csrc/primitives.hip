@@ -1,0 +1,302 @@
+// Generic device primitives: fills, exclusive scans, stable LSD radix sort.
+// Wave64 throughout (gfx950).
+#include "bm_internal.h"
+
+namespace bm {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr uint64_t kScanTile = kBlock * kScanItems;  // 2048 elements per block
+constexpr int kRadixTile = 4096;                    // elements per wave tile (64 rounds of 64)
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, uint64_t n, uint8_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t n16 = n / 16;
+    uint4 w;
+    uint32_t b = v * 0x01010101u;
+    w.x = w.y = w.z = w.w = b;
+    for (uint64_t k = i; k < n16; k += stride)
+        reinterpret_cast<uint4 *>(p)[k] = w;
+    for (uint64_t k = n16 * 16 + i; k < n; k += stride)
+        p[k] = v;
+}
+
+uint32_t grid_for(uint64_t n, uint32_t per_block = kBlock)
+{
+    uint64_t g = (n + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    if (g > 65536)
+        g = 65536;
+    return (uint32_t)g;
+}
+
+// Inclusive scan of one value per lane across the 64-lane wavefront.
+template <typename T>
+__device__ T wave_inclusive_scan(T v)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T u = __shfl_up(v, d, 64);
+        if (lane >= d)
+            v += u;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block; *total gets the block sum.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *total)
+{
+    __shared__ T wave_tot[kBlock / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(v);
+    if (lane == 63)
+        wave_tot[w] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; k++) {
+        T t = wave_tot[k];
+        if (k < w)
+            before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+template <typename In, typename Out>
+__global__ void scan_reduce_kernel(const In *in, uint64_t n, Out *sums)
+{
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    Out s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + threadIdx.x + (uint64_t)i * kBlock;
+        if (idx < n)
+            s += (Out)in[idx];
+    }
+    Out total;
+    block_exclusive_scan<Out>(s, &total);
+    if (threadIdx.x == 0)
+        sums[blockIdx.x] = total;
+}
+
+// in and out may alias (each block reads its own tile before writing it).
+template <typename In, typename Out>
+__global__ void scan_apply_kernel(const In *in, uint64_t n, const Out *block_off, Out *out)
+{
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    Out v[kScanItems];
+    Out s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        Out x = idx < n ? (Out)in[idx] : (Out)0;
+        v[i] = s;
+        s += x;
+    }
+    Out total;
+    Out before = block_exclusive_scan<Out>(s, &total);
+    Out off = block_off ? block_off[blockIdx.x] : (Out)0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        if (idx < n)
+            out[idx] = off + before + v[i];
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename In, typename Out>
+hipError_t scan_rec(const In *in, Out *out, uint64_t n, char *tmp, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        scan_apply_kernel<In, Out><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+        return hipGetLastError();
+    }
+    Out *sums = reinterpret_cast<Out *>(tmp);
+    char *rest = tmp + align256(nb * sizeof(Out));
+    scan_reduce_kernel<In, Out><<<(uint32_t)nb, kBlock, 0, s>>>(in, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    e = scan_rec<Out, Out>(sums, sums, nb, rest, s);
+    if (e != hipSuccess)
+        return e;
+    scan_apply_kernel<In, Out><<<(uint32_t)nb, kBlock, 0, s>>>(in, n, sums, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- radix sort
+
+__global__ void radix_hist_kernel(const uint32_t *keys, uint64_t n, int shift, uint32_t *hist, uint32_t tiles)
+{
+    __shared__ uint32_t h[4][256];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = lane; i < 256; i += 64)
+        h[w][i] = 0;
+    __syncthreads();
+    uint32_t t = blockIdx.x * 4 + w;
+    if (t < tiles) {
+        uint64_t base = (uint64_t)t * kRadixTile;
+        for (int r = 0; r < kRadixTile / 64; r++) {
+            uint64_t idx = base + (uint64_t)r * 64 + lane;
+            if (idx < n)
+                atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    if (t < tiles)
+        for (int i = lane; i < 256; i += 64)
+            hist[(uint64_t)i * tiles + t] = h[w][i];
+}
+
+// Each wavefront re-reads its tile in order and scatters every element to
+// (bucket offset of its tile) + (rank among equal digits seen so far), which
+// keeps the sort stable.  Ranks within 64 lanes come from 8 ballots.
+__global__ void radix_scatter_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t n, int shift,
+                                     const uint32_t *hoff, uint32_t tiles, uint32_t *ko, uint32_t *vo)
+{
+    __shared__ uint32_t cnt[4][256];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t t = blockIdx.x * 4 + w;
+    if (t < tiles)
+        for (int i = lane; i < 256; i += 64)
+            cnt[w][i] = hoff[(uint64_t)i * tiles + t];
+    __syncthreads();
+    if (t >= tiles)
+        return;
+    uint64_t base = (uint64_t)t * kRadixTile;
+    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kRadixTile / 64; r++) {
+        uint64_t idx = base + (uint64_t)r * 64 + lane;
+        bool valid = idx < n;
+        uint32_t k = valid ? keys[idx] : 0u;
+        uint32_t v = valid ? vals[idx] : 0u;
+        uint32_t d = (k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        uint32_t start = cnt[w][d];
+        if (valid) {
+            ko[start + rank] = k;
+            vo[start + rank] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0)
+            cnt[w][d] = start + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+}  // namespace
+
+hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    fill_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    fill_u8_kernel<<<grid_for(n / 16 + 1), kBlock, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_bytes(uint64_t n)
+{
+    size_t total = 0;
+    while (n > kScanTile) {
+        n = (n + kScanTile - 1) / kScanTile;
+        total += align256(n * sizeof(uint64_t));
+    }
+    return total + 256;
+}
+
+hipError_t exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, void *tmp, hipStream_t s)
+{
+    return scan_rec<uint32_t, uint64_t>(in, out, n, reinterpret_cast<char *>(tmp), s);
+}
+
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, void *tmp, hipStream_t s)
+{
+    return scan_rec<uint32_t, uint32_t>(in, out, n, reinterpret_cast<char *>(tmp), s);
+}
+
+size_t radix_tmp_bytes(uint64_t n)
+{
+    uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t h = tiles * 256;
+    return 2 * align256(h * sizeof(uint32_t)) + scan_tmp_bytes(h);
+}
+
+hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2, uint64_t n, int key_bits,
+                            void *tmp, hipStream_t s)
+{
+    if (n <= 1 || key_bits <= 0)
+        return hipSuccess;
+    uint32_t tiles = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
+    uint64_t h = (uint64_t)tiles * 256;
+    char *base = reinterpret_cast<char *>(tmp);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(base);
+    uint32_t *hoff = reinterpret_cast<uint32_t *>(base + align256(h * sizeof(uint32_t)));
+    char *stmp = base + 2 * align256(h * sizeof(uint32_t));
+    uint32_t blocks = (tiles + 3) / 4;
+    uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+    int passes = 0;
+    for (int shift = 0; shift < key_bits; shift += 8, passes++) {
+        radix_hist_kernel<<<blocks, kBlock, 0, s>>>(ka, n, shift, hist, tiles);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        e = exclusive_scan_u32(hist, hoff, h, stmp, s);
+        if (e != hipSuccess)
+            return e;
+        radix_scatter_kernel<<<blocks, kBlock, 0, s>>>(ka, va, n, shift, hoff, tiles, kb, vb);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        uint32_t *t;
+        t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    if (passes & 1) {
+        hipError_t e = hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return e;
+        e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace bm

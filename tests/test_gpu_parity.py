@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path against the oracle, through the C ABI.
+
+Counts are integers, so every comparison is exact (tolerance 0).  BatMap
+bytes are not unique (any valid 2-of-3 placement is correct), so encodings
+are checked by the oracle's structural checker, never byte for byte.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+bm = pytest.importorskip("paper_1102_1003_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = bm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda:0")
+
+
+def supports_dev(idx, n):
+    out = torch.zeros(max(bm.n_pairs(n), 1), dtype=torch.int32, device="cuda:0")
+    idx.all_pair_supports(out)
+    idx.ctx.synchronize()
+    return out.cpu().numpy().view(np.uint32)[:bm.n_pairs(n)]
+
+
+def instance(seed, m, n, p_lo, p_hi, empty_every=0):
+    rng = np.random.default_rng(seed)
+    probs = rng.uniform(p_lo, p_hi, size=n)
+    if empty_every:
+        probs[::empty_every] = 0.0
+    return datagen.sets_from_probs(m, probs, seed)
+
+
+# ----------------------------------------------------------------- all pairs
+
+def test_tiny_config_all_pairs_and_filter(ctx):
+    w = datagen.TINY
+    off, tids = w.sets()
+    idx = bm.Index.from_sets(ctx, w.m, off, tids)
+    got = supports_dev(idx, w.n)
+    np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+    for sigma in (w.sigma, 8, 1):
+        np.testing.assert_array_equal(idx.frequent_pairs(sigma), oracle.frequent_pairs(off, tids, sigma))
+    # host output buffer gives the same result
+    np.testing.assert_array_equal(idx.all_pair_supports()[:bm.n_pairs(w.n)], got)
+
+
+@pytest.mark.parametrize("seed,m,n,plo,phi", [
+    (1, 3000, 150, 0.0, 0.3),      # several width classes
+    (2, 777, 67, 0.2, 0.9),        # dense, ragged tile edges
+    (3, 50_000, 90, 0.0, 0.05),    # sparse, floor-width maps
+    (4, 20_000, 300, 0.01, 0.02),  # near-uniform widths: many tiles in one class
+    (5, 129, 40, 0.0, 1.0),        # tiny universe
+])
+def test_random_instances(ctx, seed, m, n, plo, phi):
+    off, tids = instance(seed, m, n, plo, phi, empty_every=13)
+    idx = bm.Index.from_sets(ctx, m, dev(off), dev(tids))
+    np.testing.assert_array_equal(supports_dev(idx, n), oracle.all_pairs(off, tids))
+
+
+@pytest.mark.parametrize("max_loop", [0, 1, 2])
+def test_forced_failures_are_corrected(ctx, max_loop):
+    """MaxLoop 0 makes every insertion fail: the result is the correction alone (Sec. III-C)."""
+    off, tids = instance(11, 4000, 60, 0.0, 0.4)
+    idx = bm.Index.from_sets(ctx, 4000, off, tids, max_loop=max_loop)
+    st = idx.stats()
+    if max_loop == 0:
+        assert st["n_failed"] == tids.size
+    else:
+        assert st["n_failed"] > 0
+    np.testing.assert_array_equal(supports_dev(idx, 60), oracle.all_pairs(off, tids))
+
+
+def test_power_of_two_set_sizes(ctx):
+    """|S| a power of two gives load 1/3 (r = 2|S|): failures appear at MaxLoop 64 too."""
+    m = 200_000
+    rng = np.random.default_rng(5)
+    sizes = [1 << k for k in (7, 9, 10, 11, 12, 12, 13, 13, 14, 14)] * 3
+    lists = [np.sort(rng.choice(m, size=s, replace=False)).astype(np.uint32) for s in sizes]
+    off = np.zeros(len(lists) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in lists], out=off[1:])
+    tids = np.concatenate(lists)
+    for ml in (64, 4):
+        idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=ml)
+        np.testing.assert_array_equal(supports_dev(idx, len(lists)), oracle.all_pairs(off, tids))
+
+
+def test_edge_shapes(ctx):
+    # n = 1: no pairs; n = 2; m = 1; all-empty; identical sets; full sets
+    for m, lists in [
+        (10, [[1, 2, 3]]),
+        (10, [[1, 2, 3], [2, 3, 4]]),
+        (1, [[0], [0], []]),
+        (100, [[], [], []]),
+        (1000, [list(range(0, 1000, 3))] * 5),
+        (300, [list(range(300))] * 4 + [list(range(0, 300, 2))]),
+    ]:
+        off = np.zeros(len(lists) + 1, dtype=np.uint64)
+        np.cumsum([len(x) for x in lists], out=off[1:])
+        tids = np.array([t for x in lists for t in x], dtype=np.uint32)
+        idx = bm.Index.from_sets(ctx, m, off, tids)
+        n = len(lists)
+        got = idx.all_pair_supports()[:bm.n_pairs(n)]
+        np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+
+
+# ------------------------------------------------------------ transactions
+
+def test_transactions_path_with_repeats_and_shuffled_rows(ctx):
+    m, n = 5000, 120
+    off, tids = instance(21, m, n, 0.0, 0.2)
+    rows, items = datagen.sets_to_transactions(m, off, tids)
+    rng = np.random.default_rng(3)
+    new_items, lens = [], []
+    for b in range(m):
+        r = list(items[rows[b]:rows[b + 1]])
+        if r and b % 5 == 0:
+            r += r[:2]
+        rng.shuffle(r)
+        new_items += r
+        lens.append(len(r))
+    roff = np.zeros(m + 1, dtype=np.uint64)
+    np.cumsum(lens, out=roff[1:])
+    items2 = np.array(new_items, dtype=np.uint32)
+    soff, stids = oracle.transpose(m, roff, items2, n)
+    np.testing.assert_array_equal(soff, off)
+    idx = bm.Index.from_transactions(ctx, n, dev(roff), dev(items2))
+    assert idx.stats()["nnz"] == tids.size
+    np.testing.assert_array_equal(supports_dev(idx, n), oracle.all_pairs(soff, stids))
+    np.testing.assert_array_equal(idx.frequent_pairs(30), oracle.frequent_pairs(soff, stids, 30))
+
+
+# ---------------------------------------------------------------- structure
+
+def test_exported_batmaps_pass_the_structural_check(ctx):
+    m, n = 30_000, 50
+    off, tids = instance(31, m, n, 0.0, 0.3, empty_every=7)
+    perms = datagen.hash_permutations(m, 4)
+    for ml in (64, 1):
+        idx = bm.Index.from_sets(ctx, m, off, tids, perms=perms, max_loop=ml)
+        ex = idx.export()
+        st = ex["stats"]
+        assert st["shift"] == oracle.shift(m)
+        np.testing.assert_array_equal(ex["perms"], np.stack(perms))
+        invs = oracle.inverse_perms(perms)
+        failed = ex["failed"]
+        pos = 0
+        for item, r in zip(ex["sorted_items"], ex["r"]):
+            S = tids[off[item]:off[item + 1]]
+            assert r == oracle.r_for(S.size, st["r0"])
+            F = failed[failed[:, 0] == item, 1] if failed.size else np.zeros(0, np.uint32)
+            B = ex["bytes"][pos:pos + 3 * r]
+            pos += 3 * r
+            assert oracle.batmap_check(m, st["shift"], st["r0"], int(r), perms, invs, S, F, B) == 0
+        assert pos == ex["bytes"].size
+        # maps sorted by size, then id
+        sizes = np.diff(off)[ex["sorted_items"]]
+        assert np.all(np.diff(sizes.astype(np.int64)) >= 0)
+
+
+def test_generated_permutations_are_bijections(ctx):
+    m = 1_234_567
+    off = np.array([0, 3], dtype=np.uint64)
+    tids = np.array([0, 5, m - 1], dtype=np.uint32)
+    idx = bm.Index.from_sets(ctx, m, off, tids, seed=99)
+    P = idx.export()["perms"]
+    for t in range(3):
+        assert np.array_equal(np.sort(P[t]), np.arange(m, dtype=np.uint32))
+    assert not np.array_equal(P[0], P[1])
+
+
+# ------------------------------------------------------------------ subsets
+
+def test_subset_queries(ctx):
+    m, n = 8000, 300
+    off, tids = instance(41, m, n, 0.0, 0.25)
+    idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=3)
+    rng = np.random.default_rng(0)
+    for k in (2, 3, 17, 64, 255, 300):
+        q = rng.choice(n, size=k, replace=False).astype(np.uint32)
+        got = idx.subset_pair_supports(q)[:bm.n_pairs(k)]
+        np.testing.assert_array_equal(got, oracle.subset_pairs(off, tids, q))
+    # device input and output
+    q = rng.choice(n, size=100, replace=False).astype(np.uint32)
+    out = torch.zeros(bm.n_pairs(100), dtype=torch.int32, device="cuda:0")
+    idx.subset_pair_supports(dev(q), out)
+    ctx.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.subset_pairs(off, tids, q))
+
+
+# ------------------------------------------------------------------- dense
+
+@pytest.mark.parametrize("seed,m,n", [(51, 3000, 130), (52, 10_000, 257), (53, 700, 20)])
+def test_dense_comparator(ctx, seed, m, n):
+    off, tids = instance(seed, m, n, 0.0, 0.5)
+    idx = bm.Index.from_sets(ctx, m, off, tids)
+    got = idx.all_pair_supports_dense()[:bm.n_pairs(n)]
+    np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+
+
+# ------------------------------------------------------------------- batched
+
+def test_batched_equals_each_instance(ctx):
+    ws = datagen.batch_instances(count=6, seed=77, m_lo=2e3, m_hi=2e4, n_lo=20, n_hi=150)
+    idxs, outs, refs = [], [], []
+    for w in ws:
+        off, tids = w.sets()
+        idxs.append(bm.Index.from_sets(ctx, w.m, off, tids))
+        outs.append(torch.full((max(bm.n_pairs(w.n), 1),), 7, dtype=torch.int32, device="cuda:0"))
+        refs.append(oracle.all_pairs(off, tids))
+    bm.batch_all_pair_supports(ctx, idxs, outs)
+    for o, r, w in zip(outs, refs, ws):
+        np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)], r)
+
+
+# -------------------------------------------------------------------- errors
+
+def test_error_codes(ctx):
+    off = np.array([0, 3, 5], dtype=np.uint64)
+    with pytest.raises(bm.BatmapError) as e:
+        bm.Index.from_sets(ctx, 10, off, np.array([1, 3, 2, 4, 5], dtype=np.uint32))
+    assert e.value.status == bm.BM_EUNSORTED
+    with pytest.raises(bm.BatmapError) as e:
+        bm.Index.from_sets(ctx, 10, off, np.array([1, 2, 3, 4, 10], dtype=np.uint32))
+    assert e.value.status == bm.BM_ERANGE
+    with pytest.raises(bm.BatmapError) as e:
+        bm.Index.from_sets(ctx, 10, off, np.array([1, 2, 2, 4, 5], dtype=np.uint32))
+    assert e.value.status == bm.BM_EUNSORTED
+    with pytest.raises(bm.BatmapError) as e:
+        bm.Index.from_transactions(ctx, 3, np.array([0, 2], dtype=np.uint64), np.array([0, 3], dtype=np.uint32))
+    assert e.value.status == bm.BM_ERANGE
+    bad = [np.arange(10, dtype=np.uint32)] * 3
+    bad[1] = bad[1].copy()
+    bad[1][0] = 1
+    with pytest.raises(bm.BatmapError) as e:
+        bm.Index.from_sets(ctx, 10, off, np.array([1, 2, 3, 4, 5], dtype=np.uint32), perms=bad)
+    assert e.value.status == bm.BM_EINVAL
+    idx = bm.Index.from_sets(ctx, 10, off, np.array([1, 2, 3, 4, 5], dtype=np.uint32), min_support=3)
+    with pytest.raises(bm.BatmapError) as e:
+        idx.all_pair_supports()
+    assert e.value.status == bm.BM_EINVAL
+    with pytest.raises(bm.BatmapError) as e:
+        idx.frequent_pairs(2)
+    assert e.value.status == bm.BM_EINVAL
+    assert len(idx.frequent_pairs(3)) == 0
+    with pytest.raises(bm.BatmapError) as e:
+        idx.subset_pair_supports(np.array([0, 0], dtype=np.uint32))
+    assert e.value.status == bm.BM_EINVAL
+
+
+def test_pruned_build_frequent_pairs(ctx):
+    m, n = 6000, 200
+    off, tids = instance(61, m, n, 0.0, 0.1)
+    for min_sup in (0, 150, 400):
+        idx = bm.Index.from_sets(ctx, m, off, tids, min_support=min_sup)
+        for sigma in (max(min_sup, 20), max(min_sup, 60)):
+            np.testing.assert_array_equal(idx.frequent_pairs(sigma), oracle.frequent_pairs(off, tids, sigma))
