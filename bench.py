@@ -46,7 +46,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and has no multi-GPU mode "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+              "; the work would shard as independent pair tiles across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch
