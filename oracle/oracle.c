@@ -22,7 +22,7 @@
  *   - the failed-insertion correction (Sec. III-C, "Failed insertions").
  *   It also holds a structural checker for BatMaps in canonical byte form.
  *
- * Readings where the paper is silent or loose (numbered as in the design doc):
+ * Readings where the paper is silent or loose:
  *   C1 indicator bit = 1 on the copy whose other copy sits in the cyclically
  *      preceding table (Fig. 3);
  *   C3 the empty slot is the byte 0x7F (code 127, indicator 0), and
