@@ -29,16 +29,20 @@ struct Status {
 };
 
 // One unit of compare work: a tile of row maps (narrower width class) against
-// a tile of column maps (wider or equal class) over column groups [c0, c1).
+// a tile of column maps (wider or equal class).  Two loop orders exist:
+//  - staged tiles walk column groups c in [c0, c1) and meet row group c mod G_row;
+//  - row-resident tiles walk row groups h in [c0, c1) and, for each, every
+//    column group h + u G_row, u = 0 .. G_col / G_row - 1 (the Fig. 1 wrap).
 struct WorkItem {
-    uint32_t row0;       // first sorted index of the row tile
-    uint32_t col0;       // first sorted index of the column tile
-    uint16_t nrow;       // valid rows
-    uint16_t ncol;       // valid columns
-    uint32_t c0, c1;     // column-group range, multiples of kStageGroups (c1 may be the map end)
-    uint32_t row_blocks; // r_row / r_0 (power of two): row group = block & (row_blocks-1)
-    uint32_t inst;       // instance (descriptor index)
-    uint32_t flags;      // bit 0: same width class and overlapping tiles -> emit only row < col
+    uint32_t row0;        // first sorted index of the row tile
+    uint32_t col0;        // first sorted index of the column tile
+    uint16_t nrow;        // valid rows
+    uint16_t ncol;        // valid columns
+    uint32_t c0, c1;      // group range (see above)
+    uint32_t row_groups;  // G_row = 3 r_row / 32
+    uint32_t col_groups;  // G_col = 3 r_col / 32
+    uint16_t inst;        // instance (descriptor index)
+    uint16_t flags;       // bit 0: same width class -> emit only row < col; bit 1: row-resident
 };
 static_assert(sizeof(WorkItem) == 32, "work item layout");
 
@@ -120,7 +124,12 @@ hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, co
                                      const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
                                      hipStream_t s);
 int compare_variant_count();
+// Tile shape of variant v and its loop order (true: row-resident).
 void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj);
+bool compare_variant_row_resident(int v);
+// Shapes the planner picks from by default (the others are tuning alternatives).
+bool compare_variant_default(int v);
+float compare_variant_speed(int v);
 
 // Threshold + compaction.
 hipError_t launch_threshold_count(const uint32_t *sup, uint64_t n_pairs, uint32_t sigma, uint32_t *block_counts,

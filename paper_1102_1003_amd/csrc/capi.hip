@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -264,6 +265,12 @@ bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
 // shape) is chosen per class pair to minimise padded work, and every tile's
 // column-group range is cut into pieces of about `piece` groups.
 
+// Column groups an item visits (longest first gives a better tail).
+uint64_t item_cost(const WorkItem &w)
+{
+    return (w.flags & 2u) ? (uint64_t)(w.c1 - w.c0) * (w.col_groups / w.row_groups) : (uint64_t)(w.c1 - w.c0);
+}
+
 struct Plan {
     std::vector<std::vector<WorkItem>> by_variant;
     double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
@@ -289,9 +296,20 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
     *count = c;
 }
 
+// BM_COMPARE_VARIANT=<v> pins every class pair to tile shape v (tuning aid).
+int forced_variant()
+{
+    const char *e = getenv("BM_COMPARE_VARIANT");
+    if (!e || !*e)
+        return -1;
+    int v = atoi(e);
+    return (v >= 0 && v < compare_variant_count()) ? v : -1;
+}
+
 void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan)
 {
     int nv = compare_variant_count();
+    const int pinned = forced_variant();
     plan.by_variant.assign(nv, {});
     plan.slot_pairs = 0;
     struct Choice {
@@ -306,19 +324,19 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
             if (same && cls[a].count < 2)
                 continue;
             int best = 0;
-            uint64_t best_cost = UINT64_MAX;
+            double best_cost = 1e300;
             for (int v = 0; v < nv; v++) {
+                if (pinned >= 0 ? v != pinned : !compare_variant_default(v))
+                    continue;
                 uint32_t bi, bj;
                 compare_variant_shape(v, &bi, &bj);
                 uint64_t cnt;
                 tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
-                uint64_t cost = cnt * bi * bj;
+                double cost = (double)cnt * bi * bj / compare_variant_speed(v);
                 // prefer larger tiles on ties (more reuse per loaded group)
-                if (cost < best_cost || (cost == best_cost && bi * bj > 0)) {
-                    if (cost < best_cost) {
-                        best_cost = cost;
-                        best = v;
-                    }
+                if (cost < best_cost) {  // variants are listed largest tile first
+                    best_cost = cost;
+                    best = v;
                 }
             }
             uint32_t bi, bj;
@@ -343,13 +361,21 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
         tiles.clear();
         uint64_t cnt;
         tiles_for(A, B, same, bi, bj, &tiles, &cnt);
-        uint32_t G = (uint32_t)(3ull * B.r / kSlotsPerGroup);
-        uint32_t pieces = (uint32_t)((G + piece - 1) / piece);
+        const uint32_t Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+        const uint32_t Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
+        const bool rows = compare_variant_row_resident(ch.v);
+        // row-resident items walk row groups (each meeting Gb / Ga column
+        // groups); staged items walk column groups in stages of kStageGroups
+        const uint32_t span = rows ? Ga : Gb;
+        const uint64_t unit = rows ? (uint64_t)(Gb / Ga) : 1;
+        uint32_t pieces = (uint32_t)std::max<uint64_t>(1, ((uint64_t)span * unit + piece - 1) / piece);
+        const uint32_t align = rows ? 1 : kStageGroups;
+        pieces = std::min<uint32_t>(pieces, span / align);
         for (auto &t : tiles) {
             for (uint32_t k = 0; k < pieces; k++) {
-                uint64_t c0 = (uint64_t)G * k / pieces, c1 = (uint64_t)G * (k + 1) / pieces;
-                c0 = c0 / kStageGroups * kStageGroups;
-                c1 = (k + 1 == pieces) ? G : c1 / kStageGroups * kStageGroups;
+                uint64_t c0 = (uint64_t)span * k / pieces, c1 = (uint64_t)span * (k + 1) / pieces;
+                c0 = c0 / align * align;
+                c1 = (k + 1 == pieces) ? span : c1 / align * align;
                 if (c1 <= c0)
                     continue;
                 WorkItem w;
@@ -359,16 +385,16 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
                 w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
                 w.c0 = (uint32_t)c0;
                 w.c1 = (uint32_t)c1;
-                w.row_blocks = A.r / r0;
-                w.inst = inst;
-                w.flags = same ? 1u : 0u;
+                w.row_groups = Ga;
+                w.col_groups = Gb;
+                w.inst = (uint16_t)inst;
+                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u));
                 plan.by_variant[ch.v].push_back(w);
             }
         }
     }
     for (auto &v : plan.by_variant)
-        std::stable_sort(v.begin(), v.end(),
-                         [](const WorkItem &x, const WorkItem &y) { return (x.c1 - x.c0) > (y.c1 - y.c0); });
+        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
 }
 
 // Classes restricted to sorted indices >= first.
@@ -420,7 +446,7 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
     return BM_OK;
 }
 
-uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 32; }
+uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
 
 // ------------------------------------------------------------- build steps
 
@@ -1326,8 +1352,7 @@ bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uin
             all.by_variant[v].insert(all.by_variant[v].end(), one.by_variant[v].begin(), one.by_variant[v].end());
     }
     for (auto &v : all.by_variant)
-        std::stable_sort(v.begin(), v.end(),
-                         [](const WorkItem &x, const WorkItem &y) { return (x.c1 - x.c0) > (y.c1 - y.c0); });
+        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
     DevBuf<InstDesc> d_desc;
     DevBuf<WorkItem> d_work;
     HIPC(ctx, d_desc.alloc(count));

@@ -62,6 +62,12 @@ __device__ inline uint32_t group_hits(const uint32_t (&x)[8], const uint32_t (&y
     return __builtin_popcount(hit) + acc;
 }
 
+__device__ inline void unpack(const uint4 &a, const uint4 &b, uint32_t (&v)[8])
+{
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
 __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
 {
     return i * n - i * (i + 1) / 2 + (j - i - 1);
@@ -91,11 +97,8 @@ __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, 
         for (int j = 0; j < MJ; j++)
             acc[i][j] = 0;
 
-    const uint32_t gb = d.gb;
     for (uint32_t c = w.c0; c < w.c1; c += KG) {
-        uint32_t blk = c / gb;
-        uint32_t within = c - blk * gb;
-        uint32_t rg = (blk & (w.row_blocks - 1)) * gb + within;
+        uint32_t rg = c % w.row_groups;
         // global -> LDS: every map contributes KG consecutive groups (KG*32 bytes)
         for (int u = tid; u < S::BI * KG * 2; u += 256) {
             int rho = u / (KG * 2), rem = u % (KG * 2);
@@ -183,21 +186,167 @@ __global__ __launch_bounds__(256) void compare_persistent_kernel(const WorkItem 
     }
 }
 
+// Row-resident form, one wavefront per workgroup and no LDS.  Each lane holds
+// R row maps' current group in registers; the MJ column maps are the same for
+// the whole wavefront, so their groups come through scalar loads (one 32-byte
+// s_load per group, read by every lane as an SGPR operand of v_bitop3).  The
+// loop walks each row group h once and, while it stays in registers, every
+// column group that wraps onto it (h + u G_row), so a narrow row map is read
+// once however wide its partners are.
+// Pointers in the global address space: uniform loads through them can be
+// scalar loads (generic pointers force vector flat loads).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 GlobalU4;
+typedef __attribute__((address_space(1))) const uint64_t GlobalU64;
+
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
+{
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+template <int R, int MJ>
+__device__ void process_rows(const WorkItem &w, const InstDesc &d)
+{
+    const int lane = threadIdx.x & 63;
+    GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
+    uint64_t rbase[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+        uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
+        rbase[r] = goff[w.row0 + rr] * 2;
+    }
+    // column maps' first groups (arena group indices fit 32 bits: < 128 GB)
+    uint32_t cbase[MJ];
+#pragma unroll
+    for (int j = 0; j < MJ; j++) {
+        uint32_t cc = j < w.ncol ? j : w.ncol - 1;
+        cbase[j] = __builtin_amdgcn_readfirstlane((uint32_t)goff[w.col0 + cc]);
+    }
+    uint32_t acc[R][MJ];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[r][j] = 0;
+    const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
+    const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
+    const uint32_t h0 = __builtin_amdgcn_readfirstlane(w.c0), h1 = __builtin_amdgcn_readfirstlane(w.c1);
+    // row groups for h are fetched one step ahead
+    u32x4 na[R], nb[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        na[r] = arena[rbase[r] + 2 * (uint64_t)h0];
+        nb[r] = arena[rbase[r] + 2 * (uint64_t)h0 + 1];
+    }
+    for (uint32_t h = h0; h < h1; h++) {
+        uint32_t x[R][8];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            unpack4(na[r], nb[r], x[r]);
+        if (h + 1 < h1) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                na[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1)];
+                nb[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1) + 1];
+            }
+        }
+        for (uint32_t u = 0; u < wraps; u++) {
+            const uint32_t c = h + u * row_groups;
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                uint32_t y[8];
+                const uint64_t g2 = 2 * (uint64_t)(cbase[j] + c);
+                const u32x4 a = arena[g2], b = arena[g2 + 1];
+                unpack4(a, b, y);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r][j] = group_hits(x[r], y, acc[r][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            if (rho < w.nrow && j < w.ncol && acc[r][j] != 0) {
+                uint32_t p = w.row0 + rho, q = w.col0 + j;
+                if ((w.flags & 1u) && p >= q)
+                    continue;
+                uint32_t a = d.outpos[p], b = d.outpos[q];
+                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[r][j]);
+            }
+        }
+    }
+}
+
+template <int R, int MJ>
+__global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__restrict__ items,
+                                                          const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_rows<R, MJ>(w, d);
+}
+
+template <int R, int MJ>
+__global__ __launch_bounds__(64) void compare_rows_persistent_kernel(const WorkItem *__restrict__ items,
+                                                                     uint32_t n_items,
+                                                                     const InstDesc *__restrict__ descs,
+                                                                     InstDesc d0, uint32_t *counter)
+{
+    for (;;) {
+        uint32_t it = 0;
+        if ((threadIdx.x & 63) == 0)
+            it = atomicAdd(counter, 1u);
+        it = __shfl(it, 0, 64);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        const InstDesc d = descs ? descs[w.inst] : d0;
+        process_rows<R, MJ>(w, d);
+    }
+}
+
 struct Variant {
     uint32_t bi, bj;
+    bool row_resident;
+    uint32_t block;
     void (*grid_fn)(const WorkItem *, const InstDesc *, InstDesc);
     void (*pers_fn)(const WorkItem *, uint32_t, const InstDesc *, InstDesc, uint32_t *);
+    bool default_choice;  // offered to the planner unless a variant is pinned
+    float speed;          // relative group-pair rate of an unpadded tile (planner cost weight)
 };
 
 #define BM_VARIANT(MI, MJ, TX)                                                                          \
-    Variant{Shape<MI, MJ, TX>::BI, Shape<MI, MJ, TX>::BJ, compare_kernel<MI, MJ, TX>,                  \
-            compare_persistent_kernel<MI, MJ, TX>}
+    Variant{Shape<MI, MJ, TX>::BI, Shape<MI, MJ, TX>::BJ, false, 256, compare_kernel<MI, MJ, TX>,      \
+            compare_persistent_kernel<MI, MJ, TX>, false, 0.6f}
+#define BM_ROWS_VARIANT(R, MJ, SPEED)                                                                   \
+    Variant{64 * R, MJ, true, 64, compare_rows_kernel<R, MJ>, compare_rows_persistent_kernel<R, MJ>, R == 2, SPEED}
 
 const Variant kVariants[] = {
     BM_VARIANT(4, 4, 16),  // 64 x 64
     BM_VARIANT(4, 4, 32),  // 128 x 32
     BM_VARIANT(4, 4, 64),  // 256 x 16
     BM_VARIANT(2, 4, 128), // 256 x 8
+    // speeds: group pairs per unit time relative to 128 x 16, measured on MI355X
+    BM_ROWS_VARIANT(2, 16, 1.00f),  // 128 x 16, row-resident
+    BM_ROWS_VARIANT(2, 12, 1.00f),  // 128 x 12, row-resident
+    BM_ROWS_VARIANT(2, 8, 0.92f),   // 128 x 8, row-resident
+    BM_ROWS_VARIANT(2, 4, 0.60f),   // 128 x 4, row-resident
+    BM_ROWS_VARIANT(4, 8, 0.85f),   // 256 x 8, row-resident
+    BM_ROWS_VARIANT(1, 16, 0.65f),  // 64 x 16, row-resident
 };
 
 }  // namespace
@@ -210,12 +359,19 @@ void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj)
     *bj = kVariants[v].bj;
 }
 
+bool compare_variant_row_resident(int v) { return kVariants[v].row_resident; }
+
+bool compare_variant_default(int v) { return kVariants[v].default_choice; }
+
+float compare_variant_speed(int v) { return kVariants[v].speed; }
+
 hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
                           int variant, hipStream_t s)
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(kVariants[variant].grid_fn, dim3(n_items), dim3(256), 0, s, items, descs, d0);
+    hipLaunchKernelGGL(kVariants[variant].grid_fn, dim3(n_items), dim3(kVariants[variant].block), 0, s, items, descs,
+                       d0);
     return hipGetLastError();
 }
 
@@ -225,7 +381,9 @@ hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, co
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(kVariants[variant].pers_fn, dim3(grid), dim3(256), 0, s, items, n_items, descs, d0, counter);
+    uint32_t g = kVariants[variant].row_resident ? grid * 4 : grid;
+    hipLaunchKernelGGL(kVariants[variant].pers_fn, dim3(g), dim3(kVariants[variant].block), 0, s, items, n_items, descs,
+                       d0, counter);
     return hipGetLastError();
 }
 
