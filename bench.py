@@ -73,6 +73,9 @@ def main():
     fp_cap = n_pairs_total
     d_fp = torch.empty(3 * fp_cap, dtype=torch.int32, device=dev)
     ctx = bm.Context(0, stream)
+    t_tune = time.time()
+    speeds = ctx.autotune(3)   # tile-shape speeds for the planner (once per process, untimed)
+    log(f"autotuned {speeds.shape[0]} tile shapes in {time.time() - t_tune:.2f}s")
     sigma = w.sigma
 
     sizes = np.diff(off)

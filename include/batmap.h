@@ -113,6 +113,18 @@ void bm_context_destroy(bm_context *ctx);
 const char *bm_last_error(const bm_context *ctx);
 /* Waits for all work queued on the context's stream. */
 bm_status bm_synchronize(bm_context *ctx);
+/* Tile-shape autotuner.  The compare kernel has several tile shapes; the
+ * planner picks one per pair of width classes by padded work divided by the
+ * shape's speed.  bm_context_autotune times every shape on synthetic,
+ * unpadded tiles at three ratios of column to row width (1, 4, 64), `reps`
+ * times each, and keeps the measured rates (group pairs per microsecond) in
+ * the context; plans made afterwards use them.  The table can be read and
+ * restored (n = shapes x 3 floats) to skip the measurement in later runs.
+ * Without a table the planner uses built-in relative speeds. */
+bm_status bm_context_autotune(bm_context *ctx, uint32_t reps);
+bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capacity, uint32_t *n_out);
+bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint32_t n);
+
 /* Turns per-phase event timing on (enable != 0) or off; off by default. */
 bm_status bm_context_set_profiling(bm_context *ctx, int enable);
 /* Waits for the recorded events and fills *out (phases never run read 0). */

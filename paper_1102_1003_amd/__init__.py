@@ -77,6 +77,7 @@ EXPORTED = [
     "bm_index_build_sets", "bm_index_build_transactions", "bm_index_stats_get", "bm_index_destroy",
     "bm_all_pair_supports", "bm_frequent_pairs", "bm_subset_pair_supports", "bm_batch_all_pair_supports",
     "bm_all_pair_supports_dense", "bm_index_export", "bm_context_set_profiling", "bm_context_timings",
+    "bm_context_autotune", "bm_context_tile_speeds", "bm_context_set_tile_speeds",
 ]
 
 _lib = None
@@ -137,6 +138,12 @@ def load_library(path: str = LIB_PATH):
     L.bm_context_set_profiling.argtypes = [vp, i32]
     L.bm_context_timings.restype = i32
     L.bm_context_timings.argtypes = [vp, ctypes.POINTER(bm_timings)]
+    L.bm_context_autotune.restype = i32
+    L.bm_context_autotune.argtypes = [vp, u32]
+    L.bm_context_tile_speeds.restype = i32
+    L.bm_context_tile_speeds.argtypes = [vp, vp, u32, ctypes.POINTER(ctypes.c_uint32)]
+    L.bm_context_set_tile_speeds.restype = i32
+    L.bm_context_set_tile_speeds.argtypes = [vp, vp, u32]
     _lib = L
     return L
 
@@ -196,6 +203,29 @@ class Context:
 
     def set_profiling(self, enable: bool = True):
         self.check(load_library().bm_context_set_profiling(self._h, 1 if enable else 0))
+
+    def autotune(self, reps: int = 3) -> np.ndarray:
+        """Times every compare tile shape and keeps the speeds for planning; returns them
+        as an array [shape, wrap bucket] (group pairs per microsecond)."""
+        self.check(load_library().bm_context_autotune(self._h, reps))
+        return self.tile_speeds()
+
+    def tile_speeds(self) -> np.ndarray:
+        L = load_library()
+        n = ctypes.c_uint32(0)
+        self.check(L.bm_context_tile_speeds(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float32)
+        self.check(L.bm_context_tile_speeds(self._h, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out.reshape(-1, 3)
+
+    def set_tile_speeds(self, speeds):
+        """Restores a table from tile_speeds()/autotune() (None: back to built-in speeds)."""
+        L = load_library()
+        if speeds is None:
+            self.check(L.bm_context_set_tile_speeds(self._h, None, 0))
+            return
+        a = np.ascontiguousarray(speeds, dtype=np.float32).reshape(-1)
+        self.check(L.bm_context_set_tile_speeds(self._h, a.ctypes.data, a.size))
 
     def timings(self) -> dict:
         t = bm_timings()

@@ -57,6 +57,50 @@ struct InstDesc {
     uint32_t pad;
 };
 
+// The three permutations pi_t of [0, m) (Sec. III-A).  Either a table of 3m
+// values given by the caller, or a keyed bijection evaluated on the fly: on
+// [0, 2^b) it is a chain of invertible steps (odd multiply, add, xor with a
+// right shift), and cycle walking (Black and Rogaway, "Ciphers with arbitrary
+// finite domains", 2002) restricts it to [0, m): apply until the value falls
+// below m, which ends because the chain permutes [0, 2^b).
+struct PermSpec {
+    const uint32_t *table;  // pi_t(x) = table[t m + x] when not null
+    uint32_t m, mask, h1, h2;
+    uint32_t mul1[3], add1[3], mul2[3], mul3[3], add3[3];
+};
+
+__host__ __device__ inline uint32_t perm_chain(const PermSpec &P, int t, uint32_t v)
+{
+    v = (v * P.mul1[t] + P.add1[t]) & P.mask;
+    v ^= v >> P.h1;
+    v = (v * P.mul2[t]) & P.mask;
+    v ^= v >> P.h2;
+    v = (v * P.mul3[t] + P.add3[t]) & P.mask;
+    v ^= v >> P.h1;
+    return v;
+}
+
+__host__ __device__ inline uint32_t perm_eval(const PermSpec &P, int t, uint32_t x)
+{
+    if (P.table)
+        return P.table[(uint64_t)t * P.m + x];
+    uint32_t y = perm_chain(P, t, x);
+    while (y >= P.m)  // a cycle of the chain through [0, 2^b) returns below m
+        y = perm_chain(P, t, y);
+    return y;
+}
+
+// The value held by the first active lane, as a wavefront-uniform scalar.
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Keys for the generated permutations, derived from a seed (host).
+PermSpec make_perm_spec(uint32_t m, uint64_t seed);
+
 // ------------------------------------------------------------------ device
 // Host-side launchers.  All take a stream; none synchronises.
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
@@ -85,7 +129,8 @@ hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint3
                                 uint32_t *flags, hipStream_t s);
 
 // Construction.
-hipError_t launch_gen_perms(uint32_t m, const uint64_t keys[3][5], uint32_t *pi, hipStream_t s);
+// Materialises pi_0, pi_1, pi_2 into out[3m].
+hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s);
 hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, uint32_t *flag, hipStream_t s);
 hipError_t launch_size_keys(const uint64_t *off, uint32_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_map_layout(const uint32_t *sorted_items, const uint64_t *off, uint32_t n, uint32_t first_built,
@@ -96,14 +141,16 @@ struct BuildBatch {
 };
 hipError_t launch_insert(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
                          const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, BuildBatch b,
-                         uint64_t n_elems, const uint32_t *pi, uint32_t m, uint32_t max_loop, uint32_t *stage,
+                         uint64_t n_elems, const PermSpec &P, uint32_t max_loop, uint32_t *stage,
                          uint32_t *cand, uint32_t cand_cap, uint32_t *cand_count, hipStream_t s);
-hipError_t launch_resolve(const uint32_t *cand, uint32_t n_cand, const uint32_t *tids, const uint64_t *off,
-                          const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                          const uint32_t *pi, uint32_t m, uint32_t *stage, uint32_t *failed_bits, uint32_t *failed,
-                          uint32_t *n_failed, hipStream_t s);
+// Resolves the candidates counted in *count (at most cap); failures beyond
+// fail_cap are counted but not written; *max_count keeps the largest count.
+hipError_t launch_resolve(const uint32_t *cand, const uint32_t *count, uint32_t cap, const uint32_t *tids,
+                          const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                          const uint64_t *goff, BuildBatch b, const PermSpec &P, uint32_t *stage, uint32_t *failed_bits,
+                          uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *max_count, hipStream_t s);
 hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                         uint64_t n_groups, const uint32_t *pi, uint32_t m, uint32_t shift, uint32_t r0,
+                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0,
                          uint32_t *arena, hipStream_t s);
 hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
 

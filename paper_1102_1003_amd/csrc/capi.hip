@@ -82,14 +82,6 @@ PtrKind ptr_kind(const void *p)
     return PTR_HOST;
 }
 
-uint64_t splitmix64(uint64_t &x)
-{
-    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 int bits_for(uint64_t v)  // bits needed to hold values 0..v
 {
     int b = 0;
@@ -101,6 +93,9 @@ int bits_for(uint64_t v)  // bits needed to hold values 0..v
 uint64_t n_pairs(uint64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 
 }  // namespace
+
+constexpr int kWrapBuckets = 3;  // G_col / G_row: 1 | 2..8 | >= 16
+inline int wrap_bucket(uint32_t ratio) { return ratio <= 1 ? 0 : (ratio <= 8 ? 1 : 2); }
 
 enum Phase { PH_INGEST, PH_LAYOUT, PH_CONSTRUCT, PH_ENCODE, PH_CORRECT, PH_FILL, PH_COMPARE, PH_APPLY,
              PH_THRESHOLD, PH_COUNT };
@@ -118,6 +113,9 @@ struct bm_context {
     std::vector<hipEvent_t> event_pool;
     double slot_pairs = 0;
     uint64_t launches = 0;
+    // autotuned tile speeds, [variant * kWrapBuckets + bucket], group pairs per us
+    std::vector<float> speeds;
+    uint32_t tune_gen = 0;
 };
 
 namespace {
@@ -200,7 +198,8 @@ struct bm_index {
 
     DevBuf<uint64_t> off;
     DevBuf<uint32_t> tids;
-    DevBuf<uint32_t> pi;            // 3 m
+    DevBuf<uint32_t> pi;            // 3 m, only for caller-given permutations
+    PermSpec perm;                  // pi_t: table (caller's) or keyed bijection
     DevBuf<uint32_t> sorted_items;  // n
     DevBuf<uint32_t> r_sorted;      // n
     DevBuf<uint64_t> goff;          // n + 1
@@ -219,6 +218,7 @@ struct bm_index {
     DevBuf<WorkItem> work;
     std::vector<std::pair<int, uint32_t>> work_ranges;  // (variant, count) in order
     uint32_t planned_first = UINT32_MAX;
+    uint32_t planned_gen = 0;
     double planned_slot_pairs = 0;
     DevBuf<uint32_t> thr_counts;
     DevBuf<uint64_t> thr_off;
@@ -306,7 +306,8 @@ int forced_variant()
     return (v >= 0 && v < compare_variant_count()) ? v : -1;
 }
 
-void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan)
+void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan,
+                  const std::vector<float> *speeds = nullptr)
 {
     int nv = compare_variant_count();
     const int pinned = forced_variant();
@@ -325,14 +326,22 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
                 continue;
             int best = 0;
             double best_cost = 1e300;
+            const int bucket = wrap_bucket(cls[b].r / cls[a].r);
+            const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
             for (int v = 0; v < nv; v++) {
+                // measured speeds weigh the default shapes against each other; the
+                // staged-tile shapes time well on uniform synthetic tiles but lose on
+                // skewed instances, so they are used only when pinned
                 if (pinned >= 0 ? v != pinned : !compare_variant_default(v))
+                    continue;
+                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : compare_variant_speed(v);
+                if (!(speed > 0))
                     continue;
                 uint32_t bi, bj;
                 compare_variant_shape(v, &bi, &bj);
                 uint64_t cnt;
                 tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
-                double cost = (double)cnt * bi * bj / compare_variant_speed(v);
+                double cost = (double)cnt * bi * bj / speed;
                 // prefer larger tiles on ties (more reuse per loaded group)
                 if (cost < best_cost) {  // variants are listed largest tile first
                     best_cost = cost;
@@ -497,22 +506,13 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
 
     // permutations pi_t
     Span span_layout(ctx, PH_LAYOUT);
-    HIPC(ctx, idx->pi.alloc(3ull * m));
     if (o->perm[0]) {
+        HIPC(ctx, idx->pi.alloc(3ull * m));
         for (int t = 0; t < 3; t++) {
             bm_status st = copy_in(ctx, idx->pi.p + (uint64_t)t * m, o->perm[t], (uint64_t)m * 4);
             if (st != BM_OK)
                 return st;
         }
-    } else {
-        uint64_t sm = o->seed ^ 0xB47A5EEDull;
-        uint64_t keys[3][5];
-        for (int t = 0; t < 3; t++)
-            for (int k = 0; k < 5; k++)
-                keys[t][k] = splitmix64(sm);
-        HIPC(ctx, launch_gen_perms(m, keys, idx->pi.p, s));
-    }
-    {
         DevBuf<uint32_t> bits, flag;
         uint64_t words = ((uint64_t)m + 31) / 32;
         HIPC(ctx, bits.alloc(3 * words));
@@ -526,6 +526,10 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             return st;
         if (h)
             return fail(ctx, BM_EINVAL, "bm_build_opts.perm: not three permutations of 0..m-1");
+        idx->perm = make_perm_spec(m, o->seed);
+        idx->perm.table = idx->pi.p;
+    } else {
+        idx->perm = make_perm_spec(m, o->seed);
     }
 
     // size order (Sec. III-C: sort by increasing width; ties by size then id)
@@ -607,84 +611,83 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
     size_t free_b = 0, total_b = 0;
     HIPC(ctx, hipMemGetInfo(&free_b, &total_b));
-    uint64_t stage_budget_groups = std::max<uint64_t>((uint64_t)(free_b / 4) / (kSlotsPerGroup * 4), 1);
-    stage_budget_groups = std::min<uint64_t>(stage_budget_groups, idx->total_groups);
-    DevBuf<uint32_t> stage, cand, counters, ebase_d;
-    DevBuf<uint64_t> ebase;
-    HIPC(ctx, stage.alloc(std::max<uint64_t>(stage_budget_groups, 1) * kSlotsPerGroup));
-    HIPC(ctx, counters.alloc(2));
-    uint32_t fail_cap = 1024;
-    HIPC(ctx, idx->failed.alloc(2ull * fail_cap));
-    uint64_t n_failed_total = 0;
-    uint32_t cand_cap = 4096;
-    HIPC(ctx, cand.alloc(2ull * cand_cap));
-
-    uint32_t p = first_built;
-    while (p < n) {
-        // batch [p, q): at least one map
+    // Maps are built in batches whose staging (128 B per group) fits a quarter
+    // of free device memory; BM_STAGE_MB caps it lower.  A batch holds at
+    // least one map.
+    uint64_t budget_bytes = ~0ull;
+    if (const char *e = getenv("BM_STAGE_MB"))
+        if (atoll(e) > 0)
+            budget_bytes = (uint64_t)atoll(e) << 20;
+    budget_bytes = std::min<uint64_t>(budget_bytes, (uint64_t)free_b / 4);
+    const uint64_t budget_groups = std::max<uint64_t>(budget_bytes / (kSlotsPerGroup * 4), 1);
+    struct Batch {
+        uint32_t p, q;
+        uint64_t groups, n_elems, eoff;  // eoff: offset of this batch's element bases
+    };
+    std::vector<Batch> batches;
+    std::vector<uint64_t> eb_all;
+    uint64_t max_groups = 0;
+    for (uint32_t p = first_built; p < n;) {
         uint32_t q = p + 1;
-        while (q < n && h_goff[q + 1] - h_goff[p] <= stage_budget_groups)
+        while (q < n && h_goff[q + 1] - h_goff[p] <= budget_groups)
             q++;
-        uint64_t groups = h_goff[q] - h_goff[p];
-        if (groups > stage_budget_groups) {
-            HIPC(ctx, stage.alloc(groups * kSlotsPerGroup));
-            stage_budget_groups = groups;
-        }
-        std::vector<uint64_t> eb(q - p + 1, 0);
+        Batch b{p, q, h_goff[q] - h_goff[p], 0, eb_all.size()};
+        eb_all.push_back(0);
         for (uint32_t k = p; k < q; k++)
-            eb[k - p + 1] = eb[k - p] + idx->h_sizes_sorted[k];
-        uint64_t n_elems = eb.back();
-        HIPC(ctx, ebase.alloc(eb.size()));
-        HIPC(ctx, hipMemcpyAsync(ebase.p, eb.data(), eb.size() * 8, hipMemcpyHostToDevice, s));
-        BuildBatch bb{p, q, h_goff[p]};
-        Span span_construct(ctx, PH_CONSTRUCT);
-        for (;;) {
-            HIPC(ctx, fill_u32(stage.p, groups * kSlotsPerGroup, kEmpty, s));
-            HIPC(ctx, fill_u32(counters.p, 2, 0, s));
-            HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
-                                    ebase.p, bb, n_elems, idx->pi.p, m, o->max_loop, stage.p, cand.p, cand_cap,
-                                    counters.p, s));
-            uint32_t nc = 0;
-            st = read_back(ctx, &nc, counters.p, 4);
-            if (st != BM_OK)
-                return st;
-            if (nc <= cand_cap) {
-                // room for the failures of this batch in the index list
-                if (n_failed_total + nc > fail_cap) {
-                    uint64_t want = std::max<uint64_t>(2ull * fail_cap, n_failed_total + nc);
-                    DevBuf<uint32_t> bigger;
-                    HIPC(ctx, bigger.alloc(2 * want));
-                    if (n_failed_total)
-                        HIPC(ctx, hipMemcpyAsync(bigger.p, idx->failed.p, n_failed_total * 8, hipMemcpyDeviceToDevice,
-                                                 s));
-                    HIPC(ctx, hipStreamSynchronize(s));
-                    std::swap(bigger.p, idx->failed.p);
-                    std::swap(bigger.n, idx->failed.n);
-                    fail_cap = (uint32_t)want;
-                }
-                HIPC(ctx, fill_u32(counters.p + 1, 1, (uint32_t)n_failed_total, s));
-                HIPC(ctx, launch_resolve(cand.p, nc, idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
-                                         idx->goff.p, bb, idx->pi.p, m, stage.p, failed_bits.p, idx->failed.p,
-                                         counters.p + 1, s));
-                uint32_t nf = 0;
-                st = read_back(ctx, &nf, counters.p + 1, 4);
-                if (st != BM_OK)
-                    return st;
-                n_failed_total = nf;
-                break;
-            }
-            cand_cap = nc + nc / 2 + 1024;
-            HIPC(ctx, cand.alloc(2ull * cand_cap));
-        }
-        span_construct.end();
-        {
-            Span span_encode(ctx, PH_ENCODE);
-            HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, groups, idx->pi.p, m, shift, idx->r0,
-                                    idx->arena.p, s));
-        }
+            eb_all.push_back(eb_all.back() + idx->h_sizes_sorted[k]);
+        b.n_elems = eb_all.back();
+        max_groups = std::max(max_groups, b.groups);
+        batches.push_back(b);
         p = q;
     }
-    HIPC(ctx, hipStreamSynchronize(s));
+    DevBuf<uint32_t> stage, cand, counters;
+    DevBuf<uint64_t> ebase;
+    HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
+    HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
+    if (!eb_all.empty())
+        HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
+    HIPC(ctx, counters.alloc(4));
+    // counters: [0] candidates of the running batch, [1] failures so far,
+    // [2] largest candidate count of any batch.  Capacities are checked once
+    // at the end; on overflow the whole construction runs again, larger.
+    uint64_t cand_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
+    uint64_t fail_cap = cand_cap;
+    uint64_t n_failed_total = 0;
+    for (int attempt = 0;; attempt++) {
+        HIPC(ctx, cand.alloc(2 * cand_cap));
+        HIPC(ctx, idx->failed.alloc(2 * fail_cap));
+        HIPC(ctx, fill_u32(counters.p, 4, 0, s));
+        if (attempt)
+            HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+        for (const Batch &b : batches) {
+            BuildBatch bb{b.p, b.q, h_goff[b.p]};
+            {
+                Span span_construct(ctx, PH_CONSTRUCT);
+                HIPC(ctx, fill_u32(stage.p, b.groups * kSlotsPerGroup, kEmpty, s));
+                HIPC(ctx, fill_u32(counters.p, 1, 0, s));
+                HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
+                                        ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop, stage.p, cand.p,
+                                        (uint32_t)cand_cap, counters.p, s));
+                HIPC(ctx, launch_resolve(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
+                                         idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm, stage.p,
+                                         failed_bits.p, idx->failed.p, counters.p + 1, (uint32_t)fail_cap,
+                                         counters.p + 2, s));
+            }
+            Span span_encode(ctx, PH_ENCODE);
+            HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift, idx->r0,
+                                    idx->arena.p, s));
+        }
+        uint32_t h[4] = {0, 0, 0, 0};
+        st = read_back(ctx, h, counters.p, 16);
+        if (st != BM_OK)
+            return st;
+        if (h[2] <= cand_cap && h[1] <= fail_cap) {
+            n_failed_total = h[1];
+            break;
+        }
+        cand_cap = std::max<uint64_t>(cand_cap, (uint64_t)h[2] + h[2] / 2 + 1024);
+        fail_cap = std::max<uint64_t>(fail_cap, (uint64_t)h[1] + h[1] / 2 + 1024);
+    }
     stage.reset();
     cand.reset();
     idx->n_failed = n_failed_total;
@@ -741,13 +744,14 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
         Span sp(ctx, PH_FILL);
         HIPC(ctx, fill_u32(out, n_pairs(idx->n), 0, ctx->stream));
     }
-    if (idx->planned_first != first) {
+    if (idx->planned_first != first || idx->planned_gen != ctx->tune_gen) {
         Plan plan;
-        plan_classes(classes_from(idx->classes, first), idx->r0, 0, target_items(ctx), plan);
+        plan_classes(classes_from(idx->classes, first), idx->r0, 0, target_items(ctx), plan, &ctx->speeds);
         bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
         if (st != BM_OK)
             return st;
         idx->planned_first = first;
+        idx->planned_gen = ctx->tune_gen;
         idx->planned_slot_pairs = plan.slot_pairs;
     }
     ctx->slot_pairs = idx->planned_slot_pairs;
@@ -763,6 +767,120 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ autotuner
+// Synthetic instance: 4096 row maps of 768 groups (r = 8192) and, per wrap
+// ratio U in {1, 4, 64}, 384 / 96 / 48 column maps of 768 U groups (about
+// 10^9 - 10^10 group pairs each, so launch overhead is negligible).  The
+// column counts are multiples of every column tile width and 4096 of every
+// row tile height, so the tiles carry no padding.  Group contents are
+// arbitrary bits: the compare's cost does not depend on them.
+bm_status autotune(bm_context *ctx, uint32_t reps)
+{
+    hipStream_t s = ctx->stream;
+    const uint32_t nrow = 4096, grow = 768, gb = 768;
+    const uint32_t ratios[kWrapBuckets] = {1, 4, 64};
+    const uint32_t ncols[kWrapBuckets] = {384, 96, 48};
+    std::vector<uint64_t> h_goff;
+    uint64_t g = 0;
+    for (uint32_t i = 0; i < nrow; i++, g += grow)
+        h_goff.push_back(g);
+    uint64_t col_first[kWrapBuckets];
+    for (int b = 0; b < kWrapBuckets; b++) {
+        col_first[b] = h_goff.size();
+        for (uint32_t j = 0; j < ncols[b]; j++, g += (uint64_t)grow * ratios[b])
+            h_goff.push_back(g);
+    }
+    h_goff.push_back(g);
+    const uint64_t total_groups = g;
+    DevBuf<uint32_t> arena, outpos, out;
+    DevBuf<uint64_t> goff;
+    DevBuf<WorkItem> items;
+    HIPC(ctx, arena.alloc(total_groups * kWordsPerGroup));
+    HIPC(ctx, fill_u32(arena.p, total_groups * kWordsPerGroup, 0x5A5A5A5Au, s));
+    HIPC(ctx, goff.alloc(h_goff.size()));
+    HIPC(ctx, hipMemcpyAsync(goff.p, h_goff.data(), h_goff.size() * 8, hipMemcpyHostToDevice, s));
+    const uint32_t n_pos = (uint32_t)h_goff.size() - 1;
+    std::vector<uint32_t> h_pos(n_pos);
+    for (uint32_t i = 0; i < n_pos; i++)
+        h_pos[i] = i;
+    HIPC(ctx, outpos.alloc(n_pos));
+    HIPC(ctx, hipMemcpyAsync(outpos.p, h_pos.data(), (uint64_t)n_pos * 4, hipMemcpyHostToDevice, s));
+    HIPC(ctx, out.alloc(n_pairs(n_pos)));
+    HIPC(ctx, hipStreamSynchronize(s));
+    InstDesc d;
+    d.arena = reinterpret_cast<const uint4 *>(arena.p);
+    d.goff = goff.p;
+    d.outpos = outpos.p;
+    d.out = out.p;
+    d.n_out = n_pos;
+    d.gb = gb;
+    d.pad = 0;
+    hipEvent_t e0, e1;
+    HIPC(ctx, hipEventCreate(&e0));
+    HIPC(ctx, hipEventCreate(&e1));
+    const int nv = compare_variant_count();
+    std::vector<float> speeds((size_t)nv * kWrapBuckets, 0.f);
+    bm_status result = BM_OK;
+    for (int b = 0; b < kWrapBuckets && result == BM_OK; b++) {
+        const uint32_t ncol = ncols[b];
+        Cls A{8192, 0, nrow}, B{8192 * ratios[b], (uint32_t)col_first[b], ncol};
+        for (int v = 0; v < nv; v++) {
+            // force variant v on this one class pair
+            Plan plan;
+            plan.by_variant.assign(nv, {});
+            uint32_t bi, bj;
+            compare_variant_shape(v, &bi, &bj);
+            std::vector<std::pair<uint32_t, uint32_t>> tiles;
+            uint64_t cnt;
+            tiles_for(A, B, false, bi, bj, &tiles, &cnt);
+            const uint32_t Ga = grow, Gb = grow * ratios[b];
+            const bool rows = compare_variant_row_resident(v);
+            const uint32_t span = rows ? Ga : Gb, align = rows ? 1 : kStageGroups;
+            const uint64_t want = (uint64_t)ctx->n_cu * 16;
+            uint32_t pieces = (uint32_t)std::max<uint64_t>(1, (want + tiles.size() - 1) / tiles.size());
+            pieces = std::min<uint32_t>(pieces, span / align);
+            std::vector<WorkItem> list;
+            for (auto &t : tiles) {
+                for (uint32_t k = 0; k < pieces; k++) {
+                    uint64_t c0 = (uint64_t)span * k / pieces / align * align;
+                    uint64_t c1 = (k + 1 == pieces) ? span : (uint64_t)span * (k + 1) / pieces / align * align;
+                    if (c1 <= c0)
+                        continue;
+                    WorkItem w;
+                    w.row0 = A.start + t.first * bi;
+                    w.col0 = B.start + t.second * bj;
+                    w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
+                    w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
+                    w.c0 = (uint32_t)c0;
+                    w.c1 = (uint32_t)c1;
+                    w.row_groups = Ga;
+                    w.col_groups = Gb;
+                    w.inst = 0;
+                    w.flags = rows ? 2u : 0u;
+                    list.push_back(w);
+                }
+            }
+            HIPC(ctx, items.ensure(list.size()));
+            HIPC(ctx, hipMemcpyAsync(items.p, list.data(), list.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+            HIPC(ctx, launch_compare(items.p, (uint32_t)list.size(), nullptr, d, v, s));  // warm
+            HIPC(ctx, hipEventRecord(e0, s));
+            for (uint32_t rp = 0; rp < std::max(reps, 1u); rp++)
+                HIPC(ctx, launch_compare(items.p, (uint32_t)list.size(), nullptr, d, v, s));
+            HIPC(ctx, hipEventRecord(e1, s));
+            HIPC(ctx, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
+            double group_pairs = (double)nrow * ncol * Gb * std::max(reps, 1u);
+            speeds[(size_t)v * kWrapBuckets + b] = ms > 0 ? (float)(group_pairs / (ms * 1e3)) : 0.f;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->speeds = speeds;
+    ctx->tune_gen++;
+    return result;
+}
 
 // =================================================================== C ABI
 
@@ -861,6 +979,46 @@ bm_status bm_context_timings(bm_context *ctx, bm_timings *out)
     out->threshold_ms = ms[PH_THRESHOLD];
     out->compare_slot_pairs = ctx->slot_pairs;
     out->compare_launches = ctx->spans[PH_COMPARE].size();
+    return BM_OK;
+}
+
+bm_status bm_context_autotune(bm_context *ctx, uint32_t reps)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    ctx->err.clear();
+    HIPC(ctx, hipSetDevice(ctx->device));
+    return autotune(ctx, reps);
+}
+
+bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capacity, uint32_t *n_out)
+{
+    if (!ctx || !n_out)
+        return BM_EINVAL;
+    uint32_t n = (uint32_t)compare_variant_count() * kWrapBuckets;
+    *n_out = n;
+    if (!speeds)
+        return BM_OK;
+    if (capacity < n)
+        return fail(ctx, BM_ECAPACITY, "need %u floats", n);
+    for (uint32_t i = 0; i < n; i++)
+        speeds[i] = ctx->speeds.size() == n ? ctx->speeds[i] : 0.f;
+    return BM_OK;
+}
+
+bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint32_t n)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    if (n == 0) {  // back to the built-in speeds
+        ctx->speeds.clear();
+        ctx->tune_gen++;
+        return BM_OK;
+    }
+    if (!speeds || n != (uint32_t)compare_variant_count() * kWrapBuckets)
+        return fail(ctx, BM_EINVAL, "expected %u speeds", (uint32_t)compare_variant_count() * kWrapBuckets);
+    ctx->speeds.assign(speeds, speeds + n);
+    ctx->tune_gen++;
     return BM_OK;
 }
 
@@ -1285,7 +1443,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.gb = idx->gb;
     d.pad = 0;
     Plan plan;
-    plan_classes(cls, idx->r0, 0, target_items(ctx), plan);
+    plan_classes(cls, idx->r0, 0, target_items(ctx), plan, &ctx->speeds);
     std::vector<std::pair<int, uint32_t>> ranges;
     st = upload_plan(idx, plan, idx->sub_work, ranges);
     if (st != BM_OK)
@@ -1346,7 +1504,7 @@ bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uin
         d.gb = idx->gb;
         d.pad = 0;
         Plan one;
-        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one);
+        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one, &ctx->speeds);
         ctx->slot_pairs += one.slot_pairs;
         for (size_t v = 0; v < one.by_variant.size(); v++)
             all.by_variant[v].insert(all.by_variant[v].end(), one.by_variant[v].begin(), one.by_variant[v].end());
@@ -1474,7 +1632,14 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
             return st;
     }
     if (perms) {
-        bm_status st = read_back(ctx, perms, idx->pi.p, 3ull * idx->m * 4);
+        DevBuf<uint32_t> tmp;
+        const uint32_t *src = idx->pi.p;
+        if (!src) {
+            HIPC(ctx, tmp.alloc(3ull * idx->m));
+            HIPC(ctx, launch_gen_perms(idx->perm, tmp.p, ctx->stream));
+            src = tmp.p;
+        }
+        bm_status st = read_back(ctx, perms, src, 3ull * idx->m * 4);
         if (st != BM_OK)
             return st;
     }

@@ -62,12 +62,6 @@ __device__ inline uint32_t group_hits(const uint32_t (&x)[8], const uint32_t (&y
     return __builtin_popcount(hit) + acc;
 }
 
-__device__ inline void unpack(const uint4 &a, const uint4 &b, uint32_t (&v)[8])
-{
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-
 __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
 {
     return i * n - i * (i + 1) / 2 + (j - i - 1);
@@ -199,12 +193,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 GlobalU4;
 typedef __attribute__((address_space(1))) const uint64_t GlobalU64;
 
-__device__ inline uint64_t uniform_u64(uint64_t v)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
 {

@@ -20,6 +20,8 @@
 // q = r_0 floor(v / 3r_0) + v mod r_0 (the Fig. 4 layout).  The bytes are
 // stored bit-sliced: 32 consecutive slots form a group of 8 uint32 planes,
 // plane b holding bit b of the 32 bytes.
+#include <cstring>
+
 #include "bm_internal.h"
 
 namespace bm {
@@ -37,42 +39,14 @@ uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 22)
 }
 
 // --------------------------------------------------------------- permutations
-// A bijection on [0, 2^b) built from invertible steps (odd multiply, add,
-// xor with a right shift), restricted to [0, m) by cycle walking (Black and
-// Rogaway, "Ciphers with arbitrary finite domains", 2002): apply until the
-// value falls below m.  The walk ends because the map permutes [0, 2^b).
-struct PermKey {
-    uint64_t mul1, add1, mul2, mul3, add3;
-};
 
-__device__ inline uint32_t mix_bits(uint32_t x, const PermKey &k, uint32_t bits, uint64_t mask)
+__global__ void gen_perms_kernel(PermSpec P, uint32_t *out)
 {
-    uint64_t v = x;
-    uint32_t h1 = bits / 2 + 1, h2 = bits / 3 + 1;
-    v = (v * k.mul1 + k.add1) & mask;
-    v ^= v >> h1;
-    v = (v * k.mul2) & mask;
-    v ^= v >> h2;
-    v = (v * k.mul3 + k.add3) & mask;
-    v ^= v >> h1;
-    return (uint32_t)v;
-}
-
-__global__ void gen_perms_kernel(uint32_t m, uint32_t bits, PermKey k0, PermKey k1, PermKey k2, uint32_t *pi)
-{
-    uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += stride) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.m; x += stride)
 #pragma unroll
-        for (int t = 0; t < 3; t++) {
-            const PermKey &k = t == 0 ? k0 : (t == 1 ? k1 : k2);
-            uint32_t y = mix_bits((uint32_t)x, k, bits, mask);
-            // bounded by the cycle length through [0, 2^b); never reached in practice
-            for (uint64_t guard = 0; y >= m && guard <= mask; guard++)
-                y = mix_bits(y, k, bits, mask);
-            pi[(uint64_t)t * m + x] = y;
-        }
-    }
+        for (int t = 0; t < 3; t++)
+            out[(uint64_t)t * P.m + x] = perm_eval(P, t, (uint32_t)x);
 }
 
 // Each value must hit a distinct slot of a bitmap: flag on a repeat or out of range.
@@ -140,40 +114,57 @@ __device__ inline uint32_t find_segment(const uint64_t *base, uint32_t count, ui
     return lo;
 }
 
+// One thread per element.  The two copies are two INSERT chains run side by
+// side (their atomics overlap): copy 0 enters at A_1, copy 1 at A_2, each then
+// cycling through the tables.  Starting the second chain at A_2 skips the
+// exchange with the element's own first copy that a start at A_1 would
+// usually make; any valid 2-of-3 placement counts the same.
 __global__ void insert_kernel(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
                               const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, uint32_t p0,
-                              uint32_t np, uint64_t g0, uint64_t n_elems, const uint32_t *pi, uint32_t m,
+                              uint32_t np, uint64_t g0, uint64_t n_elems, PermSpec P,
                               uint32_t max_loop, uint32_t *stage, uint32_t *cand, uint32_t cand_cap,
                               uint32_t *cand_count)
 {
-    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_elems)
+    const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);  // lane 0's element
+    if (e0 >= n_elems)
         return;
-    uint32_t j = find_segment(ebase, np, e);
+    const uint64_t e = e0 + (threadIdx.x & 63u);
+    // the wavefront's first element locates its set once (scalar loads);
+    // lanes past that set's end step forward
+    uint32_t j = __builtin_amdgcn_readfirstlane(find_segment(ebase, np, uniform_u64(e0)));
+    const bool live = e < n_elems;
+    if (live)
+        while (j + 1 < np && ebase[j + 1] <= e)
+            j++;
     uint32_t p = p0 + j;
     uint32_t item = sorted_items[p];
-    uint32_t x = tids[off[item] + (e - ebase[j])];
+    uint32_t x = live ? tids[off[item] + (e - ebase[j])] : 0;
     uint32_t r = r_sorted[p];
     uint32_t mask = r - 1;
     uint32_t *T = stage + (goff[p] - g0) * kSlotsPerGroup;
-    for (int copy = 0; copy < 2; copy++) {
-        uint32_t tau = x;
-        bool placed = false;
-        for (uint32_t loop = 0; loop < max_loop && !placed; loop++) {
+    uint32_t tau[2] = {x, x};
+    bool done[2] = {!live, !live};
+    int table[2] = {0, 1};
+    const uint32_t steps = 3 * max_loop;  // MaxLoop rounds of the three tables
+    for (uint32_t k = 0; k < steps && !(done[0] && done[1]); k++) {
 #pragma unroll
-            for (int t = 0; t < 3; t++) {
-                if (!placed) {
-                    uint32_t q = pi[(uint64_t)t * m + tau] & mask;
-                    tau = atomicExch(&T[(uint64_t)t * r + q], tau);
-                    placed = tau == kEmpty;
-                }
+        for (int c = 0; c < 2; c++) {
+            if (!done[c]) {
+                const int t = table[c];
+                uint32_t q = perm_eval(P, t, tau[c]) & mask;
+                tau[c] = atomicExch(&T[(uint64_t)t * r + q], tau[c]);
+                done[c] = tau[c] == kEmpty;
+                table[c] = t == 2 ? 0 : t + 1;
             }
         }
-        if (!placed) {
+    }
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        if (!done[c]) {
             uint32_t slot = atomicAdd(cand_count, 1u);
             if (slot < cand_cap) {
                 cand[2 * (uint64_t)slot] = p;
-                cand[2 * (uint64_t)slot + 1] = tau;
+                cand[2 * (uint64_t)slot + 1] = tau[c];
             }
         }
     }
@@ -192,32 +183,41 @@ __device__ inline int64_t find_tid(const uint32_t *a, uint64_t n, uint32_t x)
     return (lo < n && a[lo] == x) ? (int64_t)lo : -1;
 }
 
-__global__ void resolve_kernel(const uint32_t *cand, uint32_t n_cand, const uint32_t *tids, const uint64_t *off,
-                               const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff,
-                               uint64_t g0, const uint32_t *pi, uint32_t m, uint32_t *stage, uint32_t *failed_bits,
-                               uint32_t *failed, uint32_t *n_failed)
+// Candidates (map, nestless element) of the batch just inserted: delete the
+// element's remaining copy, then record it once as failed.  Grid-stride over
+// the device-side count (no host round trip); the largest count seen is kept
+// so the host can check the capacity afterwards.
+__global__ void resolve_kernel(const uint32_t *cand, const uint32_t *count, uint32_t cap, const uint32_t *tids,
+                               const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                               const uint64_t *goff, uint64_t g0, PermSpec P, uint32_t *stage, uint32_t *failed_bits,
+                               uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *max_count)
 {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cand)
-        return;
-    uint32_t p = cand[2 * (uint64_t)c], tau = cand[2 * (uint64_t)c + 1];
-    uint32_t r = r_sorted[p];
-    uint32_t *T = stage + (goff[p] - g0) * kSlotsPerGroup;
-    for (int t = 0; t < 3; t++) {
-        uint32_t q = pi[(uint64_t)t * m + tau] & (r - 1);
-        atomicCAS(&T[(uint64_t)t * r + q], tau, kEmpty);
-    }
-    uint32_t item = sorted_items[p];
-    int64_t k = find_tid(tids + off[item], off[item + 1] - off[item], tau);
-    if (k < 0)
-        return;  // cannot happen: tau came from this set
-    uint64_t kk = off[item] + (uint64_t)k;
-    uint32_t bit = 1u << (kk % 32);
-    uint32_t old = atomicOr(&failed_bits[kk / 32], bit);
-    if (!(old & bit)) {
-        uint32_t slot = atomicAdd(n_failed, 1u);
-        failed[2 * (uint64_t)slot] = item;
-        failed[2 * (uint64_t)slot + 1] = tau;
+    const uint32_t total = *count;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicMax(max_count, total);
+    const uint32_t nc = total < cap ? total : cap;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        uint32_t p = cand[2 * (uint64_t)c], tau = cand[2 * (uint64_t)c + 1];
+        uint32_t r = r_sorted[p];
+        uint32_t *T = stage + (goff[p] - g0) * kSlotsPerGroup;
+        for (int t = 0; t < 3; t++) {
+            uint32_t q = perm_eval(P, t, tau) & (r - 1);
+            atomicCAS(&T[(uint64_t)t * r + q], tau, kEmpty);
+        }
+        uint32_t item = sorted_items[p];
+        int64_t k = find_tid(tids + off[item], off[item + 1] - off[item], tau);
+        if (k < 0)
+            continue;  // cannot happen: tau came from this set
+        uint64_t kk = off[item] + (uint64_t)k;
+        uint32_t bit = 1u << (kk % 32);
+        uint32_t old = atomicOr(&failed_bits[kk / 32], bit);
+        if (!(old & bit)) {
+            uint32_t slot = atomicAdd(n_failed, 1u);
+            if (slot < fail_cap) {
+                failed[2 * (uint64_t)slot] = item;
+                failed[2 * (uint64_t)slot + 1] = tau;
+            }
+        }
     }
 }
 
@@ -225,14 +225,16 @@ __global__ void resolve_kernel(const uint32_t *cand, uint32_t n_cand, const uint
 // One thread per slot; a wavefront covers 64 consecutive slots (two groups),
 // always inside one map because every map holds a multiple of 384 slots.
 __global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
-                              uint32_t np, uint64_t g0, uint64_t n_slots, const uint32_t *pi, uint32_t m,
+                              uint32_t np, uint64_t g0, uint64_t n_slots, PermSpec P,
                               uint32_t shift, uint32_t r0, uint32_t *arena)
 {
     uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // slot index within the batch
     if (sl >= n_slots)
         return;  // n_slots is a multiple of 64: whole wavefronts leave together
     uint64_t g = g0 + sl / kSlotsPerGroup;
-    uint32_t j = find_segment(goff + p0, np, g);
+    // every lane of the wavefront is in the same map: search once, as scalars
+    uint32_t j = find_segment(goff + p0, np, uniform_u64(g));
+    j = __builtin_amdgcn_readfirstlane(j);
     uint32_t p = p0 + j;
     uint32_t r = r_sorted[p];
     uint64_t v = (g - goff[p]) * kSlotsPerGroup + (sl % kSlotsPerGroup);
@@ -244,9 +246,9 @@ __global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, c
     uint32_t x = T[(uint64_t)t * r + q];
     uint32_t byte = 0x7Fu;
     if (x != kEmpty) {
-        uint32_t code = pi[(uint64_t)t * m + x] >> shift;
+        uint32_t code = perm_eval(P, t, x) >> shift;
         uint32_t pt = (t + 2) % 3;
-        uint32_t qp = pi[(uint64_t)pt * m + x] & (r - 1);
+        uint32_t qp = perm_eval(P, pt, x) & (r - 1);
         uint32_t bit = T[(uint64_t)pt * r + qp] == x ? 1u : 0u;
         byte = (bit << 7) | code;
     }
@@ -280,35 +282,45 @@ __global__ void decode_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t 
     }
 }
 
-PermKey to_key(const uint64_t k[5])
-{
-    PermKey p;
-    p.mul1 = k[0] | 1;
-    p.add1 = k[1];
-    p.mul2 = k[2] | 1;
-    p.mul3 = k[3] | 1;
-    p.add3 = k[4];
-    return p;
-}
-
 }  // namespace
 
-hipError_t launch_gen_perms(uint32_t m, const uint64_t keys[3][5], uint32_t *pi, hipStream_t s)
+PermSpec make_perm_spec(uint32_t m, uint64_t seed)
 {
+    PermSpec P;
+    memset(&P, 0, sizeof(P));
+    P.table = nullptr;
+    P.m = m;
     uint32_t bits = 1;
     while (bits < 32 && (1ull << bits) < m)
         bits++;
-    PermKey k0 = to_key(keys[0]), k1 = to_key(keys[1]), k2 = to_key(keys[2]);
-    uint64_t mask = (1ull << bits) - 1;
-    k0.mul1 &= mask; k0.mul2 &= mask; k0.mul3 &= mask; k0.add1 &= mask; k0.add3 &= mask;
-    k1.mul1 &= mask; k1.mul2 &= mask; k1.mul3 &= mask; k1.add1 &= mask; k1.add3 &= mask;
-    k2.mul1 &= mask; k2.mul2 &= mask; k2.mul3 &= mask; k2.add1 &= mask; k2.add3 &= mask;
-    k0.mul1 |= 1; k0.mul2 |= 1; k0.mul3 |= 1;
-    k1.mul1 |= 1; k1.mul2 |= 1; k1.mul3 |= 1;
-    k2.mul1 |= 1; k2.mul2 |= 1; k2.mul3 |= 1;
-    gen_perms_kernel<<<blocks_for(m, 65536), kBlock, 0, s>>>(m, bits, k0, k1, k2, pi);
+    P.mask = bits >= 32 ? 0xFFFFFFFFu : (uint32_t)((1ull << bits) - 1);
+    P.h1 = bits / 2 + 1;
+    P.h2 = bits / 3 + 1;
+    uint64_t x = seed ^ 0xB47A5EEDull;
+    auto next = [&x]() {  // splitmix64
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (int t = 0; t < 3; t++) {
+        P.mul1[t] = ((uint32_t)next() & P.mask) | 1u;
+        P.add1[t] = (uint32_t)next() & P.mask;
+        P.mul2[t] = ((uint32_t)next() & P.mask) | 1u;
+        P.mul3[t] = ((uint32_t)next() & P.mask) | 1u;
+        P.add3[t] = (uint32_t)next() & P.mask;
+    }
+    return P;
+}
+
+hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s)
+{
+    gen_perms_kernel<<<blocks_for(P.m, 65536), kBlock, 0, s>>>(P, out);
     return hipGetLastError();
 }
+
+namespace {
+}  // namespace
 
 hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, uint32_t *flag, hipStream_t s)
 {
@@ -331,40 +343,40 @@ hipError_t launch_map_layout(const uint32_t *sorted_items, const uint64_t *off, 
 
 hipError_t launch_insert(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
                          const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, BuildBatch b,
-                         uint64_t n_elems, const uint32_t *pi, uint32_t m, uint32_t max_loop, uint32_t *stage,
+                         uint64_t n_elems, const PermSpec &P, uint32_t max_loop, uint32_t *stage,
                          uint32_t *cand, uint32_t cand_cap, uint32_t *cand_count, hipStream_t s)
 {
     if (n_elems == 0)
         return hipSuccess;
     uint64_t blocks = (n_elems + kBlock - 1) / kBlock;
     insert_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(tids, off, sorted_items, r_sorted, goff, ebase, b.p0,
-                                                      b.p1 - b.p0, b.g0, n_elems, pi, m, max_loop, stage, cand,
+                                                      b.p1 - b.p0, b.g0, n_elems, P, max_loop, stage, cand,
                                                       cand_cap, cand_count);
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const uint32_t *cand, uint32_t n_cand, const uint32_t *tids, const uint64_t *off,
-                          const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                          const uint32_t *pi, uint32_t m, uint32_t *stage, uint32_t *failed_bits, uint32_t *failed,
-                          uint32_t *n_failed, hipStream_t s)
+hipError_t launch_resolve(const uint32_t *cand, const uint32_t *count, uint32_t cap, const uint32_t *tids,
+                          const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                          const uint64_t *goff, BuildBatch b, const PermSpec &P, uint32_t *stage, uint32_t *failed_bits,
+                          uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *max_count, hipStream_t s)
 {
-    if (n_cand == 0)
-        return hipSuccess;
-    resolve_kernel<<<(n_cand + kBlock - 1) / kBlock, kBlock, 0, s>>>(cand, n_cand, tids, off, sorted_items, r_sorted,
-                                                                      goff, b.g0, pi, m, stage, failed_bits, failed,
-                                                                      n_failed);
+    uint32_t blocks = (cap + kBlock - 1) / kBlock;
+    if (blocks > 1024)
+        blocks = 1024;
+    resolve_kernel<<<blocks, kBlock, 0, s>>>(cand, count, cap, tids, off, sorted_items, r_sorted, goff, b.g0, P, stage,
+                                             failed_bits, failed, n_failed, fail_cap, max_count);
     return hipGetLastError();
 }
 
 hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                         uint64_t n_groups, const uint32_t *pi, uint32_t m, uint32_t shift, uint32_t r0,
+                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0,
                          uint32_t *arena, hipStream_t s)
 {
     uint64_t n_slots = n_groups * kSlotsPerGroup;
     if (n_slots == 0)
         return hipSuccess;
     uint64_t blocks = (n_slots + kBlock - 1) / kBlock;
-    encode_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_slots, pi, m,
+    encode_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_slots, P,
                                                       shift, r0, arena);
     return hipGetLastError();
 }
