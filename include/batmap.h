@@ -172,8 +172,22 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
  * BM_ERANGE on an id >= n. */
 bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t k, uint32_t *out);
 
-/* Many instances at once: all pairs of count indexes (same context) in one
- * persistent launch.  outs[q] (device) sized n_q(n_q-1)/2. */
+/* Many instances at once.  A batch plans all pairs of `count` indexes
+ * (same context, built with min_support 0) as one work list, longest items
+ * first, run by ONE persistent compare launch, and captures the whole
+ * sequence (counter reset, output zeroing, compare, corrections) as a HIP
+ * graph on the context's stream.  outs[q]: device, n_q(n_q-1)/2 uint32,
+ * bound to the batch until bm_batch_destroy; the indexes must outlive it.
+ * bm_batch_run replays the graph (asynchronously); when the stream cannot be
+ * captured the same kernels are enqueued eagerly. */
+typedef struct bm_batch bm_batch;
+bm_status bm_batch_create(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs,
+                          bm_batch **out);
+bm_status bm_batch_run(bm_batch *batch);
+/* 1 when the batch replays a captured graph, 0 when it runs eagerly. */
+int bm_batch_is_graph(const bm_batch *batch);
+void bm_batch_destroy(bm_batch *batch);
+/* create + run + synchronize + destroy. */
 bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs);
 
 /* Same result as bm_all_pair_supports by the plain bitmap route (Sec. I-A,

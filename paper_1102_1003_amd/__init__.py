@@ -78,16 +78,20 @@ EXPORTED = [
     "bm_all_pair_supports", "bm_frequent_pairs", "bm_subset_pair_supports", "bm_batch_all_pair_supports",
     "bm_all_pair_supports_dense", "bm_index_export", "bm_context_set_profiling", "bm_context_timings",
     "bm_context_autotune", "bm_context_tile_speeds", "bm_context_set_tile_speeds",
+    "bm_batch_create", "bm_batch_run", "bm_batch_is_graph", "bm_batch_destroy",
 ]
 
 _lib = None
 _live_indexes = weakref.WeakSet()
+_live_batches = weakref.WeakSet()
 _live_contexts = weakref.WeakSet()
 
 
 @atexit.register
 def _release_all():
     # Free device memory before the HIP runtime tears itself down.
+    for b in list(_live_batches):
+        b.close()
     for ix in list(_live_indexes):
         ix.close()
     for c in list(_live_contexts):
@@ -130,6 +134,14 @@ def load_library(path: str = LIB_PATH):
     L.bm_subset_pair_supports.argtypes = [vp, vp, u32, vp]
     L.bm_batch_all_pair_supports.restype = i32
     L.bm_batch_all_pair_supports.argtypes = [vp, ctypes.POINTER(vp), u32, ctypes.POINTER(vp)]
+    L.bm_batch_create.restype = i32
+    L.bm_batch_create.argtypes = [vp, ctypes.POINTER(vp), u32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.bm_batch_run.restype = i32
+    L.bm_batch_run.argtypes = [vp]
+    L.bm_batch_is_graph.restype = i32
+    L.bm_batch_is_graph.argtypes = [vp]
+    L.bm_batch_destroy.restype = None
+    L.bm_batch_destroy.argtypes = [vp]
     L.bm_all_pair_supports_dense.restype = i32
     L.bm_all_pair_supports_dense.argtypes = [vp, vp, u64]
     L.bm_index_export.restype = i32
@@ -382,3 +394,37 @@ def batch_all_pair_supports(ctx: Context, indexes, outs):
     hs = (ctypes.c_void_p * len(indexes))(*[ix.handle.value for ix in indexes])
     os_ = (ctypes.c_void_p * len(outs))(*[_ptr(o) for o in outs])
     ctx.check(L.bm_batch_all_pair_supports(ctx.handle, hs, len(indexes), os_))
+
+
+class Batch:
+    """All pairs of many indexes as one persistent launch, captured as a HIP graph and replayed by run()."""
+
+    def __init__(self, ctx: Context, indexes, outs):
+        L = load_library()
+        self.ctx = ctx
+        self._indexes = list(indexes)
+        self._outs = list(outs)
+        hs = (ctypes.c_void_p * len(indexes))(*[ix.handle.value for ix in indexes])
+        os_ = (ctypes.c_void_p * len(outs))(*[_ptr(o) for o in outs])
+        h = ctypes.c_void_p()
+        ctx.check(L.bm_batch_create(ctx.handle, hs, len(indexes), os_, ctypes.byref(h)))
+        self._h = h
+        _live_batches.add(self)
+
+    @property
+    def is_graph(self) -> bool:
+        return bool(load_library().bm_batch_is_graph(self._h))
+
+    def run(self):
+        self.ctx.check(load_library().bm_batch_run(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

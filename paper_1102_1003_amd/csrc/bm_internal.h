@@ -170,6 +170,11 @@ hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDes
 hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
                                      const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
                                      hipStream_t s);
+// Code of variant v for the single-launch persistent kernel (flags bits 2..3),
+// or -1 when that kernel cannot run it.
+int compare_multi_code(int v);
+hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
+                                           uint32_t *counter, uint32_t grid, hipStream_t s);
 int compare_variant_count();
 // Tile shape of variant v and its loop order (true: row-resident).
 void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj);

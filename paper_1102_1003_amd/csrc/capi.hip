@@ -234,6 +234,20 @@ struct bm_index {
     uint64_t dense_ld = 0;
 };
 
+struct bm_batch {
+    bm_context *ctx = nullptr;
+    std::vector<bm_index *> idx;
+    std::vector<uint32_t *> outs;
+    DevBuf<InstDesc> descs;
+    DevBuf<WorkItem> items;
+    DevBuf<uint32_t> counter;
+    uint32_t n_items = 0, grid = 0;
+    double slot_pairs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t enqueue(hipStream_t s);
+};
+
 namespace {
 
 bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
@@ -307,7 +321,7 @@ int forced_variant()
 }
 
 void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds = nullptr)
+                  const std::vector<float> *speeds = nullptr, bool multi_only = false)
 {
     int nv = compare_variant_count();
     const int pinned = forced_variant();
@@ -332,7 +346,8 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
                 // measured speeds weigh the default shapes against each other; the
                 // staged-tile shapes time well on uniform synthetic tiles but lose on
                 // skewed instances, so they are used only when pinned
-                if (pinned >= 0 ? v != pinned : !compare_variant_default(v))
+                if (multi_only ? compare_multi_code(v) < 0
+                               : (pinned >= 0 ? v != pinned : !compare_variant_default(v)))
                     continue;
                 const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : compare_variant_speed(v);
                 if (!(speed > 0))
@@ -397,7 +412,8 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint6
                 w.row_groups = Ga;
                 w.col_groups = Gb;
                 w.inst = (uint16_t)inst;
-                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u));
+                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u) |
+                                     (compare_multi_code(ch.v) >= 0 ? (uint32_t)compare_multi_code(ch.v) << 2 : 0u));
                 plan.by_variant[ch.v].push_back(w);
             }
         }
@@ -768,6 +784,21 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
 
 }  // namespace
 
+hipError_t bm_batch::enqueue(hipStream_t s)
+{
+    hipError_t e = fill_u32(counter.p, 1, 0, s);
+    for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
+        if (n_pairs(idx[q]->n))
+            e = fill_u32(outs[q], n_pairs(idx[q]->n), 0, s);
+    if (e == hipSuccess)
+        e = launch_compare_multi_persistent(items.p, n_items, descs.p, counter.p, grid, s);
+    for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
+        e = launch_apply_corrections(idx[q]->corr.p, idx[q]->n_corr, outs[q], idx[q]->n, s);
+    return e;
+}
+
+namespace {
+
 // ------------------------------------------------------------------ autotuner
 // Synthetic instance: 4096 row maps of 768 groups (r = 8192) and, per wrap
 // ratio U in {1, 4, 64}, 384 / 96 / 48 column maps of 768 U groups (about
@@ -881,6 +912,8 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
     ctx->tune_gen++;
     return result;
 }
+
+}  // namespace
 
 // =================================================================== C ABI
 
@@ -1470,21 +1503,25 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     return BM_OK;
 }
 
-bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs)
+bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs,
+                          bm_batch **out)
 {
     if (!ctx)
         return BM_EINVAL;
     ctx->err.clear();
-    begin_query(ctx);
-    if (count == 0)
-        return BM_OK;
-    if (!idxs || !outs)
-        return fail(ctx, BM_EINVAL, "null pointer");
+    if (!out || !idxs || !outs || count == 0)
+        return fail(ctx, BM_EINVAL, "null pointer or empty batch");
+    if (count > 65535)
+        return fail(ctx, BM_EINVAL, "at most 65535 instances per batch");
+    *out = nullptr;
     HIPC(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
+    std::unique_ptr<bm_batch> b(new (std::nothrow) bm_batch());
+    if (!b)
+        return fail(ctx, BM_ENOMEM, "host allocation");
+    b->ctx = ctx;
     std::vector<InstDesc> descs(count);
-    Plan all;
-    all.by_variant.assign(compare_variant_count(), {});
+    std::vector<WorkItem> flat;
     for (uint32_t q = 0; q < count; q++) {
         bm_index *idx = idxs[q];
         if (!idx || idx->ctx != ctx)
@@ -1495,62 +1532,94 @@ bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uin
             return fail(ctx, BM_EINVAL, "outs[%u] is null", q);
         if (n_pairs(idx->n) && ptr_kind(outs[q]) != PTR_DEVICE)
             return fail(ctx, BM_EINVAL, "outs[%u] must be device memory", q);
-        InstDesc &d = descs[q];
-        d.arena = reinterpret_cast<const uint4 *>(idx->arena.p);
-        d.goff = idx->goff.p;
-        d.outpos = idx->sorted_items.p;
-        d.out = outs[q];
-        d.n_out = idx->n;
-        d.gb = idx->gb;
-        d.pad = 0;
+        descs[q] = whole_desc(idx, outs[q]);
         Plan one;
-        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one, &ctx->speeds);
-        ctx->slot_pairs += one.slot_pairs;
-        for (size_t v = 0; v < one.by_variant.size(); v++)
-            all.by_variant[v].insert(all.by_variant[v].end(), one.by_variant[v].begin(), one.by_variant[v].end());
+        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one, &ctx->speeds, true);
+        b->slot_pairs += one.slot_pairs;
+        for (auto &v : one.by_variant)
+            flat.insert(flat.end(), v.begin(), v.end());
+        b->idx.push_back(idx);
+        b->outs.push_back(outs[q]);
     }
-    for (auto &v : all.by_variant)
-        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
-    DevBuf<InstDesc> d_desc;
-    DevBuf<WorkItem> d_work;
-    HIPC(ctx, d_desc.alloc(count));
-    HIPC(ctx, hipMemcpyAsync(d_desc.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    // longest items first across all instances
+    std::stable_sort(flat.begin(), flat.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+    b->n_items = (uint32_t)flat.size();
+    HIPC(ctx, b->descs.alloc(count));
+    HIPC(ctx, b->items.alloc(std::max<uint64_t>(flat.size(), 1)));
+    HIPC(ctx, b->counter.alloc(1));
+    HIPC(ctx, hipMemcpyAsync(b->descs.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    if (!flat.empty())
+        HIPC(ctx, hipMemcpyAsync(b->items.p, flat.data(), flat.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
     HIPC(ctx, hipStreamSynchronize(s));
-    for (uint32_t q = 0; q < count; q++)
-        if (n_pairs(idxs[q]->n))
-            HIPC(ctx, fill_u32(outs[q], n_pairs(idxs[q]->n), 0, s));
-    std::vector<std::pair<int, uint32_t>> ranges;
-    uint64_t total = 0;
-    std::vector<WorkItem> flat;
-    for (size_t v = 0; v < all.by_variant.size(); v++) {
-        if (all.by_variant[v].empty())
-            continue;
-        ranges.push_back({(int)v, (uint32_t)all.by_variant[v].size()});
-        flat.insert(flat.end(), all.by_variant[v].begin(), all.by_variant[v].end());
+    // the whole sequence as one graph: counter reset, output fills (kernels,
+    // not memsets), one persistent compare launch, corrections
+    b->grid = (uint32_t)ctx->n_cu * 16;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        hipError_t e = b->enqueue(s);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e == hipSuccess && e2 == hipSuccess && g) {
+            if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess)
+                b->graph = g;
+            else
+                (void)hipGraphDestroy(g);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+    } else {
+        (void)hipGetLastError();  // stream not capturable: the batch runs eagerly
     }
-    total = flat.size();
-    HIPC(ctx, d_work.alloc(std::max<uint64_t>(total, 1)));
-    if (total) {
-        HIPC(ctx, hipMemcpyAsync(d_work.p, flat.data(), total * sizeof(WorkItem), hipMemcpyHostToDevice, s));
-        HIPC(ctx, hipStreamSynchronize(s));
-    }
-    HIPC(ctx, ctx->counter.ensure(64));
-    uint64_t at = 0;
-    uint32_t grid = (uint32_t)ctx->n_cu * 4;
-    Span span_cmp(ctx, PH_COMPARE);
-    for (size_t r = 0; r < ranges.size(); r++) {
-        HIPC(ctx, fill_u32(ctx->counter.p + r, 1, 0, s));
-        HIPC(ctx, launch_compare_persistent(d_work.p + at, ranges[r].second, d_desc.p, descs[0], ranges[r].first,
-                                            ctx->counter.p + r, grid, s));
-        at += ranges[r].second;
-    }
-    span_cmp.end();
-    Span span_apply(ctx, PH_APPLY);
-    for (uint32_t q = 0; q < count; q++)
-        HIPC(ctx, launch_apply_corrections(idxs[q]->corr.p, idxs[q]->n_corr, outs[q], idxs[q]->n, s));
-    span_apply.end();
-    HIPC(ctx, hipStreamSynchronize(s));
+    *out = b.release();
     return BM_OK;
+}
+
+bm_status bm_batch_run(bm_batch *b)
+{
+    if (!b)
+        return BM_EINVAL;
+    bm_context *ctx = b->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    ctx->slot_pairs = b->slot_pairs;
+    Span sp(ctx, PH_COMPARE);
+    if (b->exec)
+        HIPC(ctx, hipGraphLaunch(b->exec, ctx->stream));
+    else
+        HIPC(ctx, b->enqueue(ctx->stream));
+    return BM_OK;
+}
+
+int bm_batch_is_graph(const bm_batch *b) { return b && b->exec ? 1 : 0; }
+
+void bm_batch_destroy(bm_batch *b)
+{
+    if (!b)
+        return;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    delete b;
+}
+
+bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs)
+{
+    bm_batch *b = nullptr;
+    bm_status st = bm_batch_create(ctx, idxs, count, outs, &b);
+    if (st != BM_OK)
+        return st;
+    st = bm_batch_run(b);
+    if (st == BM_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess)
+            st = fail(ctx, BM_EDEVICE, "batch: %s", hipGetErrorString(e));
+    }
+    bm_batch_destroy(b);
+    return st;
 }
 
 bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_len)

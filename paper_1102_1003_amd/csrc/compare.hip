@@ -307,6 +307,32 @@ __global__ __launch_bounds__(64) void compare_rows_persistent_kernel(const WorkI
     }
 }
 
+// One persistent launch for items of every default row-resident shape
+// (128 rows x 16 / 12 / 8 / 4 columns): the shape travels in the item's
+// flags (bits 2..3) and selects the specialised body.
+__global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
+                                                                           uint32_t n_items,
+                                                                           const InstDesc *__restrict__ descs,
+                                                                           uint32_t *counter)
+{
+    for (;;) {
+        uint32_t it = 0;
+        if ((threadIdx.x & 63) == 0)
+            it = atomicAdd(counter, 1u);
+        it = __shfl(it, 0, 64);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        const InstDesc d = descs[w.inst];
+        switch ((w.flags >> 2) & 3u) {
+        case 0: process_rows<2, 16>(w, d); break;
+        case 1: process_rows<2, 12>(w, d); break;
+        case 2: process_rows<2, 8>(w, d); break;
+        default: process_rows<2, 4>(w, d); break;
+        }
+    }
+}
+
 struct Variant {
     uint32_t bi, bj;
     bool row_resident;
@@ -360,6 +386,28 @@ hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDes
         return hipSuccess;
     hipLaunchKernelGGL(kVariants[variant].grid_fn, dim3(n_items), dim3(kVariants[variant].block), 0, s, items, descs,
                        d0);
+    return hipGetLastError();
+}
+
+int compare_multi_code(int v)
+{
+    if (!kVariants[v].row_resident || kVariants[v].bi != 128)
+        return -1;
+    switch (kVariants[v].bj) {
+    case 16: return 0;
+    case 12: return 1;
+    case 8: return 2;
+    case 4: return 3;
+    default: return -1;
+    }
+}
+
+hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
+                                           uint32_t *counter, uint32_t grid, hipStream_t s)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, n_items, descs, counter);
     return hipGetLastError();
 }
 

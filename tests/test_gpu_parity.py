@@ -269,3 +269,45 @@ def test_pruned_build_frequent_pairs(ctx):
         idx = bm.Index.from_sets(ctx, m, off, tids, min_support=min_sup)
         for sigma in (max(min_sup, 20), max(min_sup, 60)):
             np.testing.assert_array_equal(idx.frequent_pairs(sigma), oracle.frequent_pairs(off, tids, sigma))
+
+
+def test_batch_graph_replays(ctx):
+    """One captured graph replayed several times, with eager work between replays."""
+    ws = datagen.batch_instances(count=12, seed=880, m_lo=2e3, m_hi=5e4, n_lo=10, n_hi=260)
+    idxs, outs, refs = [], [], []
+    for w in ws:
+        off, tids = w.sets()
+        idxs.append(bm.Index.from_sets(ctx, w.m, off, tids))
+        outs.append(torch.zeros(max(bm.n_pairs(w.n), 1), dtype=torch.int32, device="cuda:0"))
+        refs.append(oracle.all_pairs(off, tids))
+    batch = bm.Batch(ctx, idxs, outs)
+    assert batch.is_graph
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1)
+        batch.run()
+        ctx.synchronize()
+        for o, r, w in zip(outs, refs, ws):
+            np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)], r)
+        # eager work on the same stream between replays
+        single = idxs[rep].all_pair_supports()
+        np.testing.assert_array_equal(single[:bm.n_pairs(ws[rep].n)], refs[rep])
+    batch.close()
+
+
+def test_batch_of_64_uneven_instances(ctx):
+    """64 instances of uneven m, n and density in one launch equal each instance alone."""
+    ws = datagen.batch_instances(count=64, seed=3000, m_lo=1e3, m_hi=3e4, n_lo=20, n_hi=300)
+    idxs, outs, refs, alone = [], [], [], []
+    for w in ws:
+        off, tids = w.sets()
+        ix = bm.Index.from_sets(ctx, w.m, off, tids, max_loop=8)
+        idxs.append(ix)
+        outs.append(torch.zeros(max(bm.n_pairs(w.n), 1), dtype=torch.int32, device="cuda:0"))
+        refs.append(oracle.all_pairs(off, tids))
+        alone.append(ix.all_pair_supports()[:bm.n_pairs(w.n)])
+    bm.batch_all_pair_supports(ctx, idxs, outs)
+    for o, r, a, w in zip(outs, refs, alone, ws):
+        got = o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)]
+        np.testing.assert_array_equal(got, r)
+        np.testing.assert_array_equal(a, r)
