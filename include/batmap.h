@@ -190,6 +190,54 @@ void bm_batch_destroy(bm_batch *batch);
 /* create + run + synchronize + destroy. */
 bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs);
 
+/* Serving: subset queries (as bm_subset_pair_supports) against one resident
+ * index, with continuous batching.  bm_server_submit copies the query and
+ * returns at once.  A pump thread admits queued queries in arrival order
+ * whenever one of `streams` launch slots is free and the query's device
+ * memory (result k(k-1)/2 uint32, plus 16 k + 4 n bytes of gather data)
+ * fits in what is left of `memory_budget`; everything admitted in one pass
+ * runs as one persistent compare launch on its own stream, so queries that
+ * arrive while others are on the GPU start as soon as a slot and memory
+ * free up, overlapping those still running.  Results land in pinned host
+ * memory; bm_server_wait copies one into the caller's buffer and releases
+ * its memory.  Results are identical to bm_subset_pair_supports.
+ * The index must stay alive and must not be destroyed while the server
+ * runs; other calls on the index may run from the thread that owns the
+ * context.  A server's calls are thread-safe among themselves. */
+typedef struct bm_server bm_server;
+typedef struct {
+    uint32_t streams;        /* concurrent launch slots (default 4) */
+    uint32_t max_queue;      /* submits beyond this many waiting queries get BM_EBUSY (default 1 << 16) */
+    uint32_t max_batch;      /* queries admitted into one launch at most (default 64) */
+    uint32_t flags;          /* reserved, 0 */
+    uint64_t memory_budget;  /* device bytes for in-flight queries (default 1 GiB) */
+} bm_server_opts;
+typedef struct {
+    double queued_s;   /* submit -> admitted */
+    double run_s;      /* admitted -> completion seen */
+    double total_s;    /* submit -> completion seen */
+    uint32_t batch;    /* queries in the launch that carried it */
+    uint32_t k;
+} bm_request_info;
+typedef struct {
+    uint64_t submitted, completed, launches, rejected_busy;
+    uint64_t admission_waits;   /* pump passes where the queue head did not fit in memory */
+    uint64_t peak_bytes;        /* largest device memory held by in-flight queries */
+} bm_server_stats;
+void bm_server_opts_init(bm_server_opts *o);
+bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server **out);
+/* items: host, k >= 2 distinct ids with BatMaps.  *request_id identifies it for bm_server_wait.
+ * BM_EBUSY when the queue is full, BM_ENOMEM when it can never fit the budget. */
+bm_status bm_server_submit(bm_server *srv, const uint32_t *items, uint32_t k, uint64_t *request_id);
+/* Blocks until the request is done (timeout_s < 0: no limit; on timeout BM_EBUSY, request kept),
+ * copies k(k-1)/2 supports into out (host, out_len entries) and releases the request.
+ * info may be NULL.  BM_ENOTFOUND for an unknown or already collected id. */
+bm_status bm_server_wait(bm_server *srv, uint64_t request_id, uint32_t *out, uint64_t out_len, double timeout_s,
+                         bm_request_info *info);
+bm_status bm_server_stats_get(bm_server *srv, bm_server_stats *out);
+/* Waits for in-flight launches, drops queued requests, frees everything. */
+void bm_server_destroy(bm_server *srv);
+
 /* Same result as bm_all_pair_supports by the plain bitmap route (Sec. I-A,
  * bitmaps: AND and count): a 0/1 int8 item x transaction matrix A and the
  * product A A^T on the int8 matrix cores with int32 accumulation. */

@@ -72,6 +72,21 @@ class bm_timings(ctypes.Structure):
         "threshold_ms", "compare_slot_pairs")] + [("compare_launches", ctypes.c_uint64)]
 
 
+class bm_server_opts(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_uint32), ("max_queue", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("memory_budget", ctypes.c_uint64)]
+
+
+class bm_request_info(ctypes.Structure):
+    _fields_ = [("queued_s", ctypes.c_double), ("run_s", ctypes.c_double), ("total_s", ctypes.c_double),
+                ("batch", ctypes.c_uint32), ("k", ctypes.c_uint32)]
+
+
+class bm_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "launches", "rejected_busy",
+                                                "admission_waits", "peak_bytes")]
+
+
 EXPORTED = [
     "bm_build_opts_init", "bm_context_create", "bm_context_destroy", "bm_last_error", "bm_synchronize",
     "bm_index_build_sets", "bm_index_build_transactions", "bm_index_stats_get", "bm_index_destroy",
@@ -79,17 +94,22 @@ EXPORTED = [
     "bm_all_pair_supports_dense", "bm_index_export", "bm_context_set_profiling", "bm_context_timings",
     "bm_context_autotune", "bm_context_tile_speeds", "bm_context_set_tile_speeds",
     "bm_batch_create", "bm_batch_run", "bm_batch_is_graph", "bm_batch_destroy",
+    "bm_server_opts_init", "bm_server_create", "bm_server_submit", "bm_server_wait", "bm_server_stats_get",
+    "bm_server_destroy",
 ]
 
 _lib = None
 _live_indexes = weakref.WeakSet()
 _live_batches = weakref.WeakSet()
+_live_servers = weakref.WeakSet()
 _live_contexts = weakref.WeakSet()
 
 
 @atexit.register
 def _release_all():
     # Free device memory before the HIP runtime tears itself down.
+    for sv in list(_live_servers):
+        sv.close()
     for b in list(_live_batches):
         b.close()
     for ix in list(_live_indexes):
@@ -142,6 +162,18 @@ def load_library(path: str = LIB_PATH):
     L.bm_batch_is_graph.argtypes = [vp]
     L.bm_batch_destroy.restype = None
     L.bm_batch_destroy.argtypes = [vp]
+    L.bm_server_opts_init.restype = None
+    L.bm_server_opts_init.argtypes = [ctypes.POINTER(bm_server_opts)]
+    L.bm_server_create.restype = i32
+    L.bm_server_create.argtypes = [vp, ctypes.POINTER(bm_server_opts), ctypes.POINTER(vp)]
+    L.bm_server_submit.restype = i32
+    L.bm_server_submit.argtypes = [vp, vp, u32, ctypes.POINTER(ctypes.c_uint64)]
+    L.bm_server_wait.restype = i32
+    L.bm_server_wait.argtypes = [vp, u64, vp, u64, ctypes.c_double, ctypes.POINTER(bm_request_info)]
+    L.bm_server_stats_get.restype = i32
+    L.bm_server_stats_get.argtypes = [vp, ctypes.POINTER(bm_server_stats)]
+    L.bm_server_destroy.restype = None
+    L.bm_server_destroy.argtypes = [vp]
     L.bm_all_pair_supports_dense.restype = i32
     L.bm_all_pair_supports_dense.argtypes = [vp, vp, u64]
     L.bm_index_export.restype = i32
@@ -279,6 +311,7 @@ class Index:
         self.n = n
         self.m = m
         self._keep = keep
+        self._servers = weakref.WeakSet()
         ctx._indexes.add(self)
         _live_indexes.add(self)
 
@@ -378,6 +411,8 @@ class Index:
 
     def close(self):
         if getattr(self, "_h", None):
+            for sv in list(getattr(self, "_servers", ())):
+                sv.close()
             load_library().bm_index_destroy(self._h)
             self._h = None
 
@@ -421,6 +456,66 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load_library().bm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching subset-query server over one resident index (see bm_server_* in batmap.h)."""
+
+    def __init__(self, index: Index, streams: int = 4, memory_budget: int = 1 << 30, max_batch: int = 64,
+                 max_queue: int = 1 << 16):
+        L = load_library()
+        o = bm_server_opts()
+        L.bm_server_opts_init(ctypes.byref(o))
+        o.streams = streams
+        o.memory_budget = memory_budget
+        o.max_batch = max_batch
+        o.max_queue = max_queue
+        h = ctypes.c_void_p()
+        index.ctx.check(L.bm_server_create(index.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.index = index
+        self._k = {}
+        index._servers.add(self)
+        _live_servers.add(self)
+
+    def submit(self, items) -> int:
+        items = np.ascontiguousarray(items, dtype=np.uint32)
+        rid = ctypes.c_uint64(0)
+        st = load_library().bm_server_submit(self._h, items.ctypes.data, items.size, ctypes.byref(rid))
+        if st != BM_OK:
+            raise BatmapError(st, "bm_server_submit")
+        self._k[rid.value] = items.size
+        return rid.value
+
+    def wait(self, request_id: int, timeout_s: float = -1.0):
+        """(supports as packed upper triangle over the query order, info dict)."""
+        k = self._k[request_id]
+        out = np.zeros(max(n_pairs(k), 1), dtype=np.uint32)
+        info = bm_request_info()
+        st = load_library().bm_server_wait(self._h, request_id, out.ctypes.data, out.size, timeout_s,
+                                           ctypes.byref(info))
+        if st != BM_OK:
+            raise BatmapError(st, "bm_server_wait")
+        del self._k[request_id]
+        return out[:n_pairs(k)], {f: getattr(info, f) for f, _ in info._fields_}
+
+    def stats(self) -> dict:
+        s = bm_server_stats()
+        st = load_library().bm_server_stats_get(self._h, ctypes.byref(s))
+        if st != BM_OK:
+            raise BatmapError(st, "bm_server_stats_get")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bm_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

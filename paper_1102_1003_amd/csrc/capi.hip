@@ -1716,3 +1716,510 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
 }
 
 }  // extern "C"
+
+// ==================================================================== serving
+// Continuous batching of subset queries against one resident index.
+//
+// Memory: one device pool and a pinned host mirror of the same size.  A query
+// admitted at offset o owns [o, o + need) in both: its result, the gathered
+// group offsets and output positions of its maps (written on the host side,
+// copied up) and the item -> position table for the corrections.  The result
+// comes back down into the host mirror; bm_server_wait copies it out and
+// frees the range.  A pump thread retires finished launches, then admits
+// queued queries (first come, first served, while a launch slot is free and
+// the next query fits) into one new persistent launch on a free stream.
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+struct SrvRequest {
+    std::vector<uint32_t> items;
+    uint32_t k = 0;
+    uint64_t off = 0, need = 0;
+    uint64_t o_res = 0, o_goff = 0, o_pos = 0, o_item = 0;  // offsets inside the request's range
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 failed
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    uint32_t batch = 0;
+};
+
+struct SrvLaunch {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool active = false;
+    std::vector<uint64_t> reqs;
+    DevBuf<WorkItem> items;
+    DevBuf<InstDesc> descs;
+    DevBuf<uint32_t> counter, flag;
+    WorkItem *h_items = nullptr;  // pinned staging
+    InstDesc *h_descs = nullptr;
+    uint64_t cap_items = 0, cap_descs = 0;
+};
+
+}  // namespace
+
+struct bm_server {
+    bm_index *idx = nullptr;
+    bm_server_opts opts;
+    uint8_t *dpool = nullptr, *hpool = nullptr;
+    uint64_t pool_bytes = 0, held = 0;
+    std::map<uint64_t, uint64_t> free_ranges;  // offset -> size
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, SrvRequest> reqs;
+    std::vector<std::unique_ptr<SrvLaunch>> launches;
+    std::vector<int32_t> sorted_pos;  // item -> sorted index (host copy)
+    std::mutex mu;
+    std::condition_variable cv_pump, cv_done;
+    std::thread pump;
+    bool stop = false;
+    uint64_t next_id = 1;
+    bm_server_stats stats{};
+    std::string err;
+
+    bool alloc(uint64_t need, uint64_t *off)
+    {
+        for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+            if (it->second >= need) {
+                *off = it->first;
+                uint64_t rest = it->second - need;
+                uint64_t start = it->first + need;
+                free_ranges.erase(it);
+                if (rest)
+                    free_ranges[start] = rest;
+                held += need;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t need)
+    {
+        held -= need;
+        auto it = free_ranges.emplace(off, need).first;
+        auto next = std::next(it);
+        if (next != free_ranges.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_ranges.erase(next);
+        }
+        if (it != free_ranges.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_ranges.erase(it);
+            }
+        }
+    }
+    uint64_t need_for(uint32_t k) const
+    {
+        // result | group offsets (8k) + output positions (4k) + item ids (4k) | item -> position (4n)
+        return align256((uint64_t)k * (k - 1) / 2 * 4) + align256(16ull * k) + align256(4ull * idx->n);
+    }
+    hipError_t launch_group(SrvLaunch &L, const std::vector<uint64_t> &ids);
+    void retire();
+    void admit();
+    void loop();
+};
+
+hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &ids)
+{
+    bm_index *ix = idx;
+    const uint32_t nq = (uint32_t)ids.size();
+    std::vector<WorkItem> flat;
+    if (L.cap_descs < nq) {
+        if (L.h_descs)
+            (void)hipHostFree(L.h_descs);
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&L.h_descs), nq * sizeof(InstDesc));
+        if (e != hipSuccess)
+            return e;
+        e = L.descs.alloc(nq);
+        if (e != hipSuccess)
+            return e;
+        L.cap_descs = nq;
+    }
+    for (uint32_t j = 0; j < nq; j++) {
+        SrvRequest &r = reqs[ids[j]];
+        const uint32_t k = r.k;
+        // the query's maps in width order; output positions are query positions
+        std::vector<uint32_t> ord(k);
+        for (uint32_t p = 0; p < k; p++)
+            ord[p] = p;
+        std::sort(ord.begin(), ord.end(),
+                  [&](uint32_t a, uint32_t b) { return sorted_pos[r.items[a]] < sorted_pos[r.items[b]]; });
+        uint64_t *hg = reinterpret_cast<uint64_t *>(hpool + r.off + r.o_goff);
+        uint32_t *ho = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_pos);
+        uint32_t *hi = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_item);
+        std::vector<Cls> cls;
+        for (uint32_t t = 0; t < k; t++) {
+            uint32_t p = ord[t];
+            int32_t sp = sorted_pos[r.items[p]];
+            uint32_t rr = ix->h_r_sorted[sp];
+            hg[t] = ix->h_goff[sp];
+            ho[t] = p;
+            if (cls.empty() || cls.back().r != rr)
+                cls.push_back({rr, t, 0});
+            cls.back().count++;
+        }
+        for (uint32_t p = 0; p < k; p++)
+            hi[p] = r.items[p];
+        Plan plan;
+        plan_classes(cls, ix->r0, j, (uint64_t)ix->ctx->n_cu * 16 / nq + 32, plan, &ix->ctx->speeds, true);
+        for (auto &v : plan.by_variant)
+            flat.insert(flat.end(), v.begin(), v.end());
+        InstDesc &d = L.h_descs[j];
+        d.arena = reinterpret_cast<const uint4 *>(ix->arena.p);
+        d.goff = reinterpret_cast<const uint64_t *>(dpool + r.off + r.o_goff);
+        d.outpos = reinterpret_cast<const uint32_t *>(dpool + r.off + r.o_pos);
+        d.out = reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res);
+        d.n_out = k;
+        d.gb = ix->gb;
+        d.pad = 0;
+    }
+    std::stable_sort(flat.begin(), flat.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+    if (L.cap_items < flat.size()) {
+        if (L.h_items)
+            (void)hipHostFree(L.h_items);
+        uint64_t cap = std::max<uint64_t>(flat.size(), 1024);
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&L.h_items), cap * sizeof(WorkItem));
+        if (e != hipSuccess)
+            return e;
+        e = L.items.alloc(cap);
+        if (e != hipSuccess)
+            return e;
+        L.cap_items = cap;
+    }
+    if (!flat.empty())
+        memcpy(L.h_items, flat.data(), flat.size() * sizeof(WorkItem));
+    hipStream_t s = L.stream;
+    hipError_t e = hipMemcpyAsync(L.descs.p, L.h_descs, nq * sizeof(InstDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !flat.empty())
+        e = hipMemcpyAsync(L.items.p, L.h_items, flat.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
+        SrvRequest &r = reqs[ids[j]];
+        // goff, outpos and items are contiguous in the range: one upload
+        e = hipMemcpyAsync(dpool + r.off + r.o_goff, hpool + r.off + r.o_goff, r.o_item + 4ull * r.k - r.o_goff,
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = fill_u32(reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), (uint64_t)r.k * (r.k - 1) / 2, 0, s);
+    }
+    if (e == hipSuccess)
+        e = fill_u32(L.counter.p, 1, 0, s);
+    if (e == hipSuccess)
+        e = launch_compare_multi_persistent(L.items.p, (uint32_t)flat.size(), L.descs.p, L.counter.p,
+                                            (uint32_t)ix->ctx->n_cu * 8, s);
+    for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
+        SrvRequest &r = reqs[ids[j]];
+        if (ix->n_corr == 0)
+            break;
+        // item -> query position, then the index's corrections that fall inside the query
+        uint32_t *pos_of_item = reinterpret_cast<uint32_t *>(dpool + r.off + r.need - align256(4ull * ix->n));
+        e = fill_u32(pos_of_item, ix->n, kEmpty, s);
+        if (e == hipSuccess)
+            e = launch_subset_prepare(reinterpret_cast<const uint32_t *>(dpool + r.off + r.o_item), r.k, ix->n,
+                                      ix->sorted_pos.p, pos_of_item, L.flag.p, s);
+        if (e == hipSuccess)
+            e = launch_apply_corrections_subset(ix->corr.p, ix->n_corr, pos_of_item,
+                                                reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), r.k, s);
+    }
+    for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
+        SrvRequest &r = reqs[ids[j]];
+        e = hipMemcpyAsync(hpool + r.off + r.o_res, dpool + r.off + r.o_res, (uint64_t)r.k * (r.k - 1) / 2 * 4,
+                           hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(L.done, s);
+    return e;
+}
+
+void bm_server::retire()
+{
+    for (auto &Lp : launches) {
+        SrvLaunch &L = *Lp;
+        if (!L.active)
+            continue;
+        hipError_t q = hipEventQuery(L.done);
+        if (q == hipErrorNotReady)
+            continue;
+        (void)hipGetLastError();
+        double t = now_s();
+        for (uint64_t id : L.reqs) {
+            SrvRequest &r = reqs[id];
+            r.state = q == hipSuccess ? 2 : 3;
+            r.t_done = t;
+            stats.completed++;
+        }
+        L.reqs.clear();
+        L.active = false;
+        cv_done.notify_all();
+    }
+}
+
+void bm_server::admit()
+{
+    while (!queue.empty()) {
+        SrvLaunch *L = nullptr;
+        for (auto &c : launches)
+            if (!c->active) {
+                L = c.get();
+                break;
+            }
+        if (!L)
+            return;
+        std::vector<uint64_t> ids;
+        while (!queue.empty() && ids.size() < opts.max_batch) {
+            SrvRequest &r = reqs[queue.front()];
+            uint64_t off;
+            if (!alloc(r.need, &off)) {
+                stats.admission_waits++;
+                break;
+            }
+            r.off = off;
+            r.state = 1;
+            r.t_admit = now_s();
+            ids.push_back(queue.front());
+            queue.pop_front();
+        }
+        if (ids.empty())
+            return;
+        stats.peak_bytes = std::max(stats.peak_bytes, held);
+        for (uint64_t id : ids)
+            reqs[id].batch = (uint32_t)ids.size();
+        hipError_t e = launch_group(*L, ids);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            err = std::string("launch failed: ") + hipGetErrorString(e);
+            // surfaced by bm_server_wait as BM_EDEVICE
+            double t = now_s();
+            for (uint64_t id : ids) {
+                SrvRequest &r = reqs[id];
+                r.state = 3;
+                r.t_done = t;
+            }
+            cv_done.notify_all();
+            continue;
+        }
+        L->reqs = ids;
+        L->active = true;
+        stats.launches++;
+    }
+}
+
+void bm_server::loop()
+{
+    (void)hipSetDevice(idx->device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        retire();
+        if (stop) {
+            bool busy = false;
+            for (auto &L : launches)
+                busy |= L->active;
+            if (!busy)
+                break;
+        } else {
+            admit();
+        }
+        bool running = false;
+        for (auto &L : launches)
+            running |= L->active;
+        // poll the in-flight launches every few microseconds; sleep when idle
+        if (running)
+            cv_pump.wait_for(lk, std::chrono::microseconds(20));
+        else if (!stop)
+            cv_pump.wait_for(lk, std::chrono::milliseconds(5));
+    }
+}
+
+extern "C" {
+
+void bm_server_opts_init(bm_server_opts *o)
+{
+    if (!o)
+        return;
+    memset(o, 0, sizeof(*o));
+    o->streams = 4;
+    o->max_queue = 1u << 16;
+    o->max_batch = 64;
+    o->memory_budget = 1ull << 30;
+}
+
+bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server **out)
+{
+    if (!idx || !out)
+        return BM_EINVAL;
+    *out = nullptr;
+    bm_context *ctx = idx->ctx;
+    bm_server_opts o;
+    bm_server_opts_init(&o);
+    if (opts)
+        o = *opts;
+    if (o.streams == 0 || o.streams > 16 || o.max_batch == 0 || o.memory_budget < 4096 || o.flags != 0)
+        return fail(ctx, BM_EINVAL, "bad server options");
+    HIPC(ctx, hipSetDevice(idx->device));
+    std::unique_ptr<bm_server> srv(new (std::nothrow) bm_server());
+    if (!srv)
+        return fail(ctx, BM_ENOMEM, "host allocation");
+    srv->idx = idx;
+    srv->opts = o;
+    srv->pool_bytes = align256(o.memory_budget);
+    HIPC(ctx, hipMalloc(reinterpret_cast<void **>(&srv->dpool), srv->pool_bytes));
+    if (hipHostMalloc(reinterpret_cast<void **>(&srv->hpool), srv->pool_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(srv->dpool);
+        return fail(ctx, BM_ENOMEM, "pinned host pool of %llu bytes", (unsigned long long)srv->pool_bytes);
+    }
+    srv->free_ranges[0] = srv->pool_bytes;
+    srv->sorted_pos.assign(idx->n, -1);
+    for (uint32_t p = idx->first_built; p < idx->n; p++)
+        srv->sorted_pos[idx->h_sorted_items[p]] = (int32_t)p;
+    for (uint32_t i = 0; i < o.streams; i++) {
+        srv->launches.emplace_back(new SrvLaunch());
+        SrvLaunch &L = *srv->launches.back();
+        HIPC(ctx, hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+        HIPC(ctx, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+        HIPC(ctx, L.counter.alloc(1));
+        HIPC(ctx, L.flag.alloc(1));
+    }
+    bm_server *raw = srv.get();
+    raw->pump = std::thread([raw]() { raw->loop(); });
+    *out = srv.release();
+    return BM_OK;
+}
+
+bm_status bm_server_submit(bm_server *srv, const uint32_t *items, uint32_t k, uint64_t *request_id)
+{
+    if (!srv || !items || !request_id || k < 2)
+        return BM_EINVAL;
+    bm_index *ix = srv->idx;
+    // validate on the host: ids in range, distinct, each with a BatMap
+    std::vector<uint32_t> q(items, items + k);
+    {
+        std::vector<uint32_t> sorted(q);
+        std::sort(sorted.begin(), sorted.end());
+        if (sorted.back() >= ix->n)
+            return BM_ERANGE;
+        for (uint32_t p = 1; p < k; p++)
+            if (sorted[p] == sorted[p - 1])
+                return BM_EINVAL;
+    }
+    for (uint32_t p = 0; p < k; p++)
+        if (srv->sorted_pos[q[p]] < 0)
+            return BM_EINVAL;
+    SrvRequest r;
+    r.k = k;
+    r.items = std::move(q);
+    r.o_res = 0;
+    r.o_goff = align256((uint64_t)k * (k - 1) / 2 * 4);
+    r.o_pos = r.o_goff + 8ull * k;
+    r.o_item = r.o_pos + 4ull * k;
+    r.need = srv->need_for(k);
+    if (r.need > srv->pool_bytes)
+        return BM_ENOMEM;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->queue.size() >= srv->opts.max_queue) {
+        srv->stats.rejected_busy++;
+        return BM_EBUSY;
+    }
+    r.t_submit = now_s();
+    uint64_t id = srv->next_id++;
+    srv->reqs.emplace(id, std::move(r));
+    srv->queue.push_back(id);
+    srv->stats.submitted++;
+    *request_id = id;
+    srv->cv_pump.notify_one();
+    return BM_OK;
+}
+
+bm_status bm_server_wait(bm_server *srv, uint64_t request_id, uint32_t *out, uint64_t out_len, double timeout_s,
+                         bm_request_info *info)
+{
+    if (!srv)
+        return BM_EINVAL;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(request_id);
+    if (it == srv->reqs.end())
+        return BM_ENOTFOUND;
+    auto ready = [&]() { return srv->reqs[request_id].state >= 2; };
+    if (timeout_s < 0)
+        srv->cv_done.wait(lk, ready);
+    else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready))
+        return BM_EBUSY;
+    SrvRequest &r = srv->reqs[request_id];
+    uint64_t np = (uint64_t)r.k * (r.k - 1) / 2;
+    if (r.state == 3) {
+        srv->release(r.off, r.need);
+        srv->reqs.erase(request_id);
+        return BM_EDEVICE;
+    }
+    if (out) {
+        if (out_len < np)
+            return BM_ECAPACITY;
+        memcpy(out, srv->hpool + r.off + r.o_res, np * 4);
+    }
+    if (info) {
+        info->queued_s = r.t_admit - r.t_submit;
+        info->run_s = r.t_done - r.t_admit;
+        info->total_s = r.t_done - r.t_submit;
+        info->batch = r.batch;
+        info->k = r.k;
+    }
+    srv->release(r.off, r.need);
+    srv->reqs.erase(request_id);
+    srv->cv_pump.notify_one();
+    return BM_OK;
+}
+
+bm_status bm_server_stats_get(bm_server *srv, bm_server_stats *out)
+{
+    if (!srv || !out)
+        return BM_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->stats;
+    return BM_OK;
+}
+
+void bm_server_destroy(bm_server *srv)
+{
+    if (!srv)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->queue.clear();
+        srv->cv_pump.notify_one();
+    }
+    if (srv->pump.joinable())
+        srv->pump.join();
+    (void)hipSetDevice(srv->idx->device);
+    for (auto &Lp : srv->launches) {
+        SrvLaunch &L = *Lp;
+        if (L.stream) {
+            (void)hipStreamSynchronize(L.stream);
+            (void)hipStreamDestroy(L.stream);
+        }
+        if (L.done)
+            (void)hipEventDestroy(L.done);
+        if (L.h_items)
+            (void)hipHostFree(L.h_items);
+        if (L.h_descs)
+            (void)hipHostFree(L.h_descs);
+    }
+    srv->launches.clear();
+    (void)hipFree(srv->dpool);
+    (void)hipHostFree(srv->hpool);
+    delete srv;
+}
+
+}  // extern "C"

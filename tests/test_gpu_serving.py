@@ -1,0 +1,90 @@
+"""Serving: continuous batching of subset queries; every result equals the query run alone."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+bm = pytest.importorskip("paper_1102_1003_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = bm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def data():
+    probs, _ = datagen.zipf_probs(500, 1.1, 0.05, seed=17)
+    off, tids = datagen.sets_from_probs(30_000, probs, seed=17)
+    return 30_000, 500, off, tids
+
+
+def test_mixed_stream_equals_alone(ctx, data):
+    m, n, off, tids = data
+    idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=3)   # some failures: corrections take part
+    assert idx.stats()["n_corrections"] > 0
+    rng = np.random.default_rng(5)
+    ks = [int(round(np.exp(rng.uniform(np.log(2), np.log(500))))) for _ in range(60)]
+    queries = [rng.choice(n, size=k, replace=False).astype(np.uint32) for k in ks]
+    srv = bm.Server(idx, streams=3, memory_budget=32 << 20, max_batch=6)
+    ids = [None] * len(queries)
+
+    def producer():
+        for i, q in enumerate(queries):
+            ids[i] = srv.submit(q)
+            if i % 7 == 0:
+                time.sleep(0.002)   # arrivals while earlier launches are on the GPU
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    results = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    assert st["completed"] == len(queries) and st["launches"] >= 2
+    assert max(info["batch"] for _, info in results) > 1   # queries were batched together
+    for q, (got, info) in zip(queries, results):
+        alone = idx.subset_pair_supports(q)[:bm.n_pairs(q.size)]
+        np.testing.assert_array_equal(got, alone)
+        if q.size <= 120:
+            np.testing.assert_array_equal(got, oracle.subset_pairs(off, tids, q))
+        assert info["k"] == q.size and info["total_s"] >= info["run_s"] >= 0
+    srv.close()
+
+
+def test_tight_memory_admission(ctx, data):
+    m, n, off, tids = data
+    idx = bm.Index.from_sets(ctx, m, off, tids)
+    rng = np.random.default_rng(9)
+    queries = [rng.choice(n, size=300, replace=False).astype(np.uint32) for _ in range(10)]
+    one = 300 * 299 // 2 * 4 + 300 * 16 + 4 * n + 4096
+    srv = bm.Server(idx, streams=4, memory_budget=one + one // 2, max_batch=4)
+    ids = [srv.submit(q) for q in queries]
+    for q, i in zip(queries, ids):
+        got, info = srv.wait(i)
+        np.testing.assert_array_equal(got, oracle.subset_pairs(off, tids, q))
+        assert info["batch"] == 1
+    st = srv.stats()
+    assert st["admission_waits"] > 0 and st["peak_bytes"] <= one + one // 2
+    srv.close()
+
+
+def test_rejected_queries(ctx, data):
+    m, n, off, tids = data
+    idx = bm.Index.from_sets(ctx, m, off, tids)
+    srv = bm.Server(idx)
+    for bad, status in ((np.array([1, 1], np.uint32), bm.BM_EINVAL), (np.array([0, n], np.uint32), bm.BM_ERANGE),
+                        (np.array([3], np.uint32), bm.BM_EINVAL)):
+        with pytest.raises(bm.BatmapError) as e:
+            srv.submit(bad)
+        assert e.value.status == status
+    srv.close()
