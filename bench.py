@@ -43,6 +43,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--compare-reps", type=int, default=5)
+    ap.add_argument("--mode", default="step", choices=["step", "serving", "dense-sweep"],
+                    help="step: the path on one instance (default); serving: subset-query stream against the "
+                         "resident serving instance; dense-sweep: BatMap vs int8-MFMA bitmap across densities")
+    ap.add_argument("--queries", type=int, default=240, help="serving: queries per arrival rate")
+    ap.add_argument("--densities", default="0.0001,0.0005,0.001,0.002,0.005,0.01,0.02,0.05,0.10,0.20")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path runs on a single MI355X and has no multi-GPU mode "
@@ -55,6 +60,10 @@ def main():
     import paper_1102_1003_amd as bm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mode == "serving":
+        return serving_mode(args)
+    if args.mode == "dense-sweep":
+        return dense_sweep_mode(args)
     w = {"large-zipf": datagen.LARGE, "tiny-bernoulli": datagen.TINY, "paper-replica": datagen.PAPER_REPLICA}[
         args.workload]
     t0 = time.time()
@@ -226,6 +235,161 @@ def main():
     }
     ctx.close()
     print(json.dumps(result))
+
+
+def serving_mode(args):
+    """Subset queries against the resident serving instance (m=4e6, n=16384, capped Zipf(1.1) at 1%).
+    First the saturation rate (all queries submitted at once), then Poisson arrivals at fractions of
+    it; latency is submit -> completion seen by the server, per query."""
+    import threading
+
+    import torch
+
+    import datagen
+    import paper_1102_1003_amd as bm
+
+    w = datagen.SERVING
+    t0 = time.time()
+    off, tids = w.sets()
+    log(f"generated {w.name}: m={w.m} n={w.n} nnz={tids.size} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    d_off = torch.from_numpy(off.view(np.int64)).to(dev)
+    d_tids = torch.from_numpy(tids.view(np.int32)).to(dev)
+    ctx = bm.Context(0)
+    ctx.autotune(3)
+    tb = time.time()
+    idx = bm.Index.from_sets(ctx, w.m, d_off, d_tids)
+    torch.cuda.synchronize()
+    build_s = time.time() - tb
+    stats = idx.stats()
+    log(f"index built in {build_s:.2f}s: {stats['batmap_bytes'] / 2**30:.2f} GiB of BatMaps, {stats['n_classes']} widths")
+    del d_tids
+
+    def make_queries(count, seed):
+        return [q for _, q in datagen.query_stream(w.n, count, seed)]
+
+    srv = bm.Server(idx, streams=4, memory_budget=2 << 30, max_batch=32)
+    # warm-up and the alone-vs-mix check on a few queries
+    check = make_queries(12, 66)
+    ids = [srv.submit(q) for q in check]
+    mixed = [srv.wait(i)[0] for i in ids]
+    mix_ok = all(np.array_equal(g, idx.subset_pair_supports(q)[:bm.n_pairs(q.size)]) for g, q in zip(mixed, check))
+    small = [q for q in check if q.size <= 200][:3]
+    import oracle
+    oracle_ok = all(np.array_equal(idx.subset_pair_supports(q)[:bm.n_pairs(q.size)], oracle.subset_pairs(off, tids, q))
+                    for q in small)
+    log(f"alone-vs-mix equal={mix_ok}, oracle on {len(small)} small queries equal={oracle_ok}")
+
+    def run_stream(queries, gaps):
+        infos = [None] * len(queries)
+        ids = [None] * len(queries)
+
+        def producer():
+            t_start = time.perf_counter()
+            due = 0.0
+            for i, q in enumerate(queries):
+                due += gaps[i]
+                while time.perf_counter() - t_start < due:
+                    time.sleep(min(0.0005, max(0.0, due - (time.perf_counter() - t_start))))
+                ids[i] = srv.submit(q)
+        th = threading.Thread(target=producer)
+        t = time.perf_counter()
+        th.start()
+        th.join()
+        for i in range(len(queries)):
+            infos[i] = srv.wait(ids[i])[1]
+        span = time.perf_counter() - t
+        lat = np.array([x["total_s"] for x in infos]) * 1e3
+        pairs = sum(bm.n_pairs(q.size) for q in queries)
+        return {"queries": len(queries), "seconds": span, "queries_per_s": len(queries) / span,
+                "pairs_per_s": pairs / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([x["batch"] for x in infos]))}
+
+    qs = make_queries(args.queries, 6)
+    sat = run_stream(qs, [0.0] * len(qs))
+    log(f"saturation: {sat['queries_per_s']:.1f} q/s, {sat['pairs_per_s']:.3e} pairs/s, p50 {sat['p50_ms']:.1f} ms")
+    rates = {}
+    for frac in (0.5, 0.8):
+        lam = frac * sat["queries_per_s"]
+        rng = np.random.default_rng(int(frac * 100))
+        gaps = list(rng.exponential(1.0 / lam, size=args.queries))
+        r = run_stream(make_queries(args.queries, 60 + int(frac * 10)), gaps)
+        r["arrival_rate_per_s"] = lam
+        rates[f"{frac:.1f}x"] = r
+        log(f"poisson {frac:.1f}x ({lam:.1f} q/s): p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+    st = srv.stats()
+    srv.close()
+    idx.close()
+    ctx.close()
+    print(json.dumps({
+        "metric": "serving: subset pair-support queries, p50/p99 latency and throughput",
+        "value": sat["pairs_per_s"], "unit": "item-pair supports/s at saturation", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: m={w.m}, n={w.n}, capped Zipf({w.alpha}) at {w.density:.0%}; queries k "
+                               f"log-uniform in [16, 4096], items uniform without replacement",
+                   "nnz": int(tids.size), "streams": 4, "memory_budget_bytes": 2 << 30, "max_batch": 32},
+        "index_build_s": build_s, "saturation": sat, "poisson": rates, "server": st,
+        "exact": {"alone_vs_mix": mix_ok, "oracle_small_queries": oracle_ok}}))
+
+
+def dense_sweep_mode(args):
+    """BatMap all pairs vs the int8-MFMA bitmap product on m=2^20, n=8192 Bernoulli instances of rising
+    density (inputs drawn on the GPU); both exact, compared element by element."""
+    import torch
+
+    import datagen
+    import paper_1102_1003_amd as bm
+
+    m, n = 1 << 20, 8192
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+    ctx = bm.Context(0, stream)
+    ctx.autotune(3)
+    ctx.set_profiling(True)
+    out_b = torch.empty(bm.n_pairs(n), dtype=torch.int32, device=dev)
+    out_d = torch.empty_like(out_b)
+    rows = []
+    for k, dens in enumerate(float(x) for x in args.densities.split(",")):
+        d_off, d_tids = datagen.bernoulli_sets_device(m, n, dens, seed=4000 + k)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        idx = bm.Index.from_sets(ctx, m, d_off, d_tids)
+        build_ms = (time.perf_counter() - tb) * 1e3
+        bt = []
+        for _ in range(2):
+            idx.all_pair_supports(out_b)
+            bt.append(ctx.timings()["compare_ms"])
+        slot_pairs = ctx.timings()["compare_slot_pairs"]
+        idx.all_pair_supports_dense(out_d)
+        enc_ms = ctx.timings()["encode_ms"]
+        dt = []
+        for _ in range(2):
+            idx.all_pair_supports_dense(out_d)
+            dt.append(ctx.timings()["compare_ms"])
+        torch.cuda.synchronize()
+        equal = bool(torch.equal(out_b, out_d))
+        # closed form: sum over pairs = sum over transactions of C(|T_b|, 2)
+        tl = torch.bincount(d_tids.long(), minlength=m).double()
+        closed = bool(abs(out_b.double().sum().item() - (tl * (tl - 1) / 2).sum().item()) < 0.5)
+        st = idx.stats()
+        b_ms, d_ms = min(bt), min(dt)
+        row = {"density": dens, "nnz": int(d_tids.numel()), "shift": st["shift"], "batmap_bytes": st["batmap_bytes"],
+               "build_ms": build_ms, "batmap_compare_ms": b_ms,
+               "batmap_tops": slot_pairs / 32 * OPS_PER_GROUP_PAIR / (b_ms * 1e-3) / 1e12,
+               "dense_bitmap_build_ms": enc_ms, "dense_gemm_ms": d_ms,
+               "dense_tops": 2.0 * m * bm.n_pairs(n) / (d_ms * 1e-3) / 1e12,
+               "batmap_pairs_per_s": bm.n_pairs(n) / (b_ms * 1e-3), "dense_pairs_per_s": bm.n_pairs(n) / (d_ms * 1e-3),
+               "faster": "batmap" if b_ms < d_ms else "dense_mfma", "equal": equal, "closed_form_sum": closed}
+        rows.append(row)
+        log(f"density {dens:.4f}: BatMap {b_ms:8.2f} ms  MFMA {d_ms:8.2f} ms  equal={equal} closed={closed}")
+        idx.close()
+        del d_off, d_tids, tl
+        torch.cuda.empty_cache()
+    cross = [r["density"] for r in rows if r["faster"] == "dense_mfma"]
+    print(json.dumps({"metric": "BatMap vs int8-MFMA bitmap all-pairs time across density (exact both)",
+                      "config": {"workload": f"Bernoulli m={m}, n={n}", "densities": [r["density"] for r in rows]},
+                      "rows": rows, "dense_wins_from_density": min(cross) if cross else None}))
 
 
 if __name__ == "__main__":

@@ -184,3 +184,25 @@ def query_stream(n_items: int, count: int, seed: int, k_lo: int = 16, k_hi: int 
         items = rng.choice(n_items, size=k, replace=False).astype(np.uint32)
         qs.append((float(a), items))
     return qs
+
+
+def bernoulli_sets_device(m: int, n: int, p: float, seed: int, device="cuda:0", chunk_bytes: int = 1 << 30):
+    """Bernoulli(p) tidlists drawn on the GPU with torch's seeded generator (for instances too large
+    to draw on the host).  Returns (offsets int64[n+1], tids int32[nnz]) on `device`, sorted per item.
+    Same model as bernoulli_sets; a different random stream."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    rows_per_chunk = max(1, chunk_bytes // (4 * max(m, 1)))
+    sizes, parts = [], []
+    for i0 in range(0, n, rows_per_chunk):
+        i1 = min(n, i0 + rows_per_chunk)
+        hit = torch.rand((i1 - i0, m), generator=g, device=device) < p
+        sizes.append(hit.sum(dim=1))
+        parts.append(torch.nonzero(hit, as_tuple=True)[1].to(torch.int32))   # row-major: sorted per item
+        del hit
+    sizes = torch.cat(sizes)
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offsets[1:] = torch.cumsum(sizes, 0)
+    tids = torch.cat(parts) if parts else torch.zeros(0, dtype=torch.int32, device=device)
+    return offsets, tids

@@ -134,8 +134,9 @@ bm_status bm_context_timings(bm_context *ctx, bm_timings *out);
  * offsets: n_sets+1 uint64, host or device, offsets[0] = 0, non-decreasing;
  * tids: offsets[n_sets] uint32, host or device; set i is
  * tids[offsets[i] .. offsets[i+1]) and must be strictly increasing with every
- * tid < m.  Errors: BM_EINVAL (null, n_sets = 0, m = 0, bad offsets, bad
- * options), BM_ERANGE (tid >= m), BM_EUNSORTED, BM_ENOMEM, BM_EDEVICE.
+ * tid < m; fewer than 2^32 tids in all.  Errors: BM_EINVAL (null, n_sets = 0,
+ * m = 0, bad offsets, too many tids, bad options), BM_ERANGE (tid >= m),
+ * BM_EUNSORTED, BM_ENOMEM, BM_EDEVICE.
  * Returns when the index is complete. */
 bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, const uint64_t *offsets,
                               const uint32_t *tids, const bm_build_opts *opts, bm_index **out);

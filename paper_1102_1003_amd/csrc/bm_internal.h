@@ -173,6 +173,7 @@ hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, co
 // Code of variant v for the single-launch persistent kernel (flags bits 2..3),
 // or -1 when that kernel cannot run it.
 int compare_multi_code(int v);
+uint32_t multi_persistent_grid(uint32_t n_cu);
 hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
                                            uint32_t *counter, uint32_t grid, hipStream_t s);
 int compare_variant_count();

@@ -1105,6 +1105,8 @@ bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, cons
         if (idx->h_off[i + 1] < idx->h_off[i])
             return fail(ctx, BM_EINVAL, "offsets decrease at set %u", i);
     idx->nnz = idx->h_off[n_sets];
+    if (idx->nnz >= (1ull << 32))
+        return fail(ctx, BM_EINVAL, "2^32 or more incidences");
     if (idx->nnz && !tids)
         return fail(ctx, BM_EINVAL, "tids is null");
     for (uint32_t i = 0; i < n_sets; i++)
@@ -1183,8 +1185,8 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     uint64_t nnz_in = roff[m_txn];
     if (nnz_in && !items)
         return fail(ctx, BM_EINVAL, "items is null");
-    if (nnz_in > 0xFFFFFFFFull)
-        return fail(ctx, BM_EINVAL, "more than 2^32-1 incidences");
+    if (nnz_in >= (1ull << 32))
+        return fail(ctx, BM_EINVAL, "2^32 or more incidences");
 
     Span span_ingest(ctx, PH_INGEST);
     DevBuf<uint64_t> d_roff;
@@ -1553,7 +1555,7 @@ bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count
     HIPC(ctx, hipStreamSynchronize(s));
     // the whole sequence as one graph: counter reset, output fills (kernels,
     // not memsets), one persistent compare launch, corrections
-    b->grid = (uint32_t)ctx->n_cu * 16;
+    b->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         hipError_t e = b->enqueue(s);
         hipGraph_t g = nullptr;
@@ -1788,6 +1790,7 @@ struct bm_server {
     uint64_t next_id = 1;
     bm_server_stats stats{};
     std::string err;
+    uint32_t grid = 0;  // persistent workgroups per launch
 
     bool alloc(uint64_t need, uint64_t *off)
     {
@@ -1918,7 +1921,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         e = fill_u32(L.counter.p, 1, 0, s);
     if (e == hipSuccess)
         e = launch_compare_multi_persistent(L.items.p, (uint32_t)flat.size(), L.descs.p, L.counter.p,
-                                            (uint32_t)ix->ctx->n_cu * 8, s);
+                                            grid, s);
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];
         if (ix->n_corr == 0)
@@ -2081,6 +2084,7 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         return fail(ctx, BM_ENOMEM, "pinned host pool of %llu bytes", (unsigned long long)srv->pool_bytes);
     }
     srv->free_ranges[0] = srv->pool_bytes;
+    srv->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     srv->sorted_pos.assign(idx->n, -1);
     for (uint32_t p = idx->first_built; p < idx->n; p++)
         srv->sorted_pos[idx->h_sorted_items[p]] = (int32_t)p;

@@ -192,6 +192,12 @@ __global__ __launch_bounds__(256) void compare_persistent_kernel(const WorkItem 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 GlobalU4;
 typedef __attribute__((address_space(1))) const uint64_t GlobalU64;
+// The arena is read-only while a compare runs.  Reading the column groups
+// through the constant address space keeps them scalar loads even in the
+// persistent kernels, whose atomics inside the work loop would otherwise stop
+// the compiler from proving that the arena is unchanged between iterations.
+typedef __attribute__((address_space(4))) const u32x4 ConstU4;
+typedef __attribute__((address_space(4))) const uint64_t ConstU64;
 
 
 __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
@@ -205,7 +211,9 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.arena);
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
+    ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -218,7 +226,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 #pragma unroll
     for (int j = 0; j < MJ; j++) {
         uint32_t cc = j < w.ncol ? j : w.ncol - 1;
-        cbase[j] = __builtin_amdgcn_readfirstlane((uint32_t)goff[w.col0 + cc]);
+        cbase[j] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.col0 + cc)]);
     }
     uint32_t acc[R][MJ];
 #pragma unroll
@@ -254,7 +262,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
             for (int j = 0; j < MJ; j++) {
                 uint32_t y[8];
                 const uint64_t g2 = 2 * (uint64_t)(cbase[j] + c);
-                const u32x4 a = arena[g2], b = arena[g2 + 1];
+                const u32x4 a = carena[g2], b = carena[g2 + 1];
                 unpack4(a, b, y);
 #pragma unroll
                 for (int r = 0; r < R; r++)
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(64) void compare_rows_persistent_kernel(const WorkI
         uint32_t it = 0;
         if ((threadIdx.x & 63) == 0)
             it = atomicAdd(counter, 1u);
-        it = __shfl(it, 0, 64);
+        it = __builtin_amdgcn_readfirstlane(it);
         if (it >= n_items)
             break;
         const WorkItem w = items[it];
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
         uint32_t it = 0;
         if ((threadIdx.x & 63) == 0)
             it = atomicAdd(counter, 1u);
-        it = __shfl(it, 0, 64);
+        it = __builtin_amdgcn_readfirstlane(it);
         if (it >= n_items)
             break;
         const WorkItem w = items[it];
@@ -400,6 +408,20 @@ int compare_multi_code(int v)
     case 4: return 3;
     default: return -1;
     }
+}
+
+// Workgroups that fill every CU of the current device at the multi-shape
+// kernel's occupancy (its one-wave workgroups are register-bound).
+uint32_t multi_persistent_grid(uint32_t n_cu)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, compare_rows_multi_persistent_kernel, 64, 0) !=
+            hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 16;
+    }
+    return n_cu * (uint32_t)per_cu;
 }
 
 hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,

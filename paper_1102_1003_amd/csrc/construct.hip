@@ -119,15 +119,12 @@ __device__ inline uint32_t find_segment(const uint64_t *base, uint32_t count, ui
 // cycling through the tables.  Starting the second chain at A_2 skips the
 // exchange with the element's own first copy that a start at A_1 would
 // usually make; any valid 2-of-3 placement counts the same.
-__global__ void insert_kernel(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
-                              const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, uint32_t p0,
-                              uint32_t np, uint64_t g0, uint64_t n_elems, PermSpec P,
-                              uint32_t max_loop, uint32_t *stage, uint32_t *cand, uint32_t cand_cap,
-                              uint32_t *cand_count)
+__device__ inline void insert_wave(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                                   const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, uint32_t p0,
+                                   uint32_t np, uint64_t g0, uint64_t n_elems, const PermSpec &P, uint32_t max_loop,
+                                   uint32_t *stage, uint32_t *cand, uint32_t cand_cap, uint32_t *cand_count,
+                                   uint64_t e0)
 {
-    const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);  // lane 0's element
-    if (e0 >= n_elems)
-        return;
     const uint64_t e = e0 + (threadIdx.x & 63u);
     // the wavefront's first element locates its set once (scalar loads);
     // lanes past that set's end step forward
@@ -168,6 +165,24 @@ __global__ void insert_kernel(const uint32_t *tids, const uint64_t *off, const u
             }
         }
     }
+}
+
+// One thread per element.  The two copies are two INSERT chains run side by
+// side (their atomics overlap): copy 0 enters at A_1, copy 1 at A_2, each then
+// cycling through the tables.  Starting the second chain at A_2 skips the
+// exchange with the element's own first copy that a start at A_1 would
+// usually make; any valid 2-of-3 placement counts the same.  Grid-stride over
+// whole wavefronts of elements.
+__global__ void insert_kernel(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                              const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, uint32_t p0,
+                              uint32_t np, uint64_t g0, uint64_t n_elems, PermSpec P,
+                              uint32_t max_loop, uint32_t *stage, uint32_t *cand, uint32_t cand_cap,
+                              uint32_t *cand_count)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); e0 < n_elems; e0 += stride)
+        insert_wave(tids, off, sorted_items, r_sorted, goff, ebase, p0, np, g0, n_elems, P, max_loop, stage, cand,
+                    cand_cap, cand_count, e0);
 }
 
 __device__ inline int64_t find_tid(const uint32_t *a, uint64_t n, uint32_t x)
@@ -224,13 +239,10 @@ __global__ void resolve_kernel(const uint32_t *cand, const uint32_t *count, uint
 // -------------------------------------------------------------- encoding
 // One thread per slot; a wavefront covers 64 consecutive slots (two groups),
 // always inside one map because every map holds a multiple of 384 slots.
-__global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
-                              uint32_t np, uint64_t g0, uint64_t n_slots, PermSpec P,
-                              uint32_t shift, uint32_t r0, uint32_t *arena)
+__device__ inline void encode_slot(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
+                                   uint32_t np, uint64_t g0, uint64_t sl, const PermSpec &P, uint32_t shift,
+                                   uint32_t r0, uint32_t *arena)
 {
-    uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // slot index within the batch
-    if (sl >= n_slots)
-        return;  // n_slots is a multiple of 64: whole wavefronts leave together
     uint64_t g = g0 + sl / kSlotsPerGroup;
     // every lane of the wavefront is in the same map: search once, as scalars
     uint32_t j = find_segment(goff + p0, np, uniform_u64(g));
@@ -265,6 +277,18 @@ __global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, c
     uint64_t g_first = g0 + (sl - lane) / kSlotsPerGroup;  // group of lane 0 (even)
     if (lane < 16)
         arena[g_first * kWordsPerGroup + lane] = word;
+}
+
+
+__global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
+                              uint32_t np, uint64_t g0, uint64_t n_slots, PermSpec P,
+                              uint32_t shift, uint32_t r0, uint32_t *arena)
+{
+    // grid-stride over slots (a batch may hold more than 2^32 of them); the
+    // stride is a multiple of 64 and n_slots too, so wavefronts stay whole
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_slots; sl += stride)
+        encode_slot(stage, r_sorted, goff, p0, np, g0, sl, P, shift, r0, arena);
 }
 
 __global__ void decode_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes)
@@ -349,6 +373,8 @@ hipError_t launch_insert(const uint32_t *tids, const uint64_t *off, const uint32
     if (n_elems == 0)
         return hipSuccess;
     uint64_t blocks = (n_elems + kBlock - 1) / kBlock;
+    if (blocks > (1u << 20))
+        blocks = 1u << 20;  // grid-stride beyond ~2.7e8 threads
     insert_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(tids, off, sorted_items, r_sorted, goff, ebase, b.p0,
                                                       b.p1 - b.p0, b.g0, n_elems, P, max_loop, stage, cand,
                                                       cand_cap, cand_count);
@@ -376,6 +402,8 @@ hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const 
     if (n_slots == 0)
         return hipSuccess;
     uint64_t blocks = (n_slots + kBlock - 1) / kBlock;
+    if (blocks > (1u << 20))
+        blocks = 1u << 20;  // grid-stride beyond ~2.7e8 threads
     encode_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_slots, P,
                                                       shift, r0, arena);
     return hipGetLastError();

@@ -311,3 +311,29 @@ def test_batch_of_64_uneven_instances(ctx):
         got = o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)]
         np.testing.assert_array_equal(got, r)
         np.testing.assert_array_equal(a, r)
+
+
+def test_more_than_2_32_slots(ctx):
+    """One construction batch of more than 2^32 slots (1400 maps of 3 * 2^20 slots): every grid
+    stays within launch limits and the result is exact (closed form + sampled rows vs the oracle)."""
+    m, n = 8_000_000, 1400
+    d_off, d_tids = datagen.bernoulli_sets_device(m, n, 0.06, seed=123)
+    idx = bm.Index.from_sets(ctx, m, d_off, d_tids)
+    st = idx.stats()
+    assert st["batmap_bytes"] > (1 << 32)
+    out = torch.zeros(bm.n_pairs(n), dtype=torch.int32, device="cuda:0")
+    idx.all_pair_supports(out)
+    ctx.synchronize()
+    tl = torch.bincount(d_tids.long(), minlength=m).double()
+    assert abs(out.double().sum().item() - (tl * (tl - 1) / 2).sum().item()) < 0.5
+    off = d_off.cpu().numpy().astype(np.uint64)
+    tids = d_tids.cpu().numpy().view(np.uint32)
+    got = out.cpu().numpy().view(np.uint32)
+    rows = np.array([0, 1, 700, 1398, 1399], dtype=np.uint32)
+    ref = oracle.pair_rows(off, tids, rows)
+    for r_i, i in enumerate(rows):
+        for j in range(n):
+            if j == i:
+                continue
+            lo, hi = min(i, j), max(i, j)
+            assert got[int(oracle.packed_index(n, lo, hi))] == ref[r_i, j]
