@@ -1,6 +1,6 @@
 """Compile the HIP sources of the BatMap library into libbatmap.so (gfx950).
 
-Each .hip file is compiled to an object in parallel, then linked into one
+Each .hip / .cpp file is compiled to an object in parallel, then linked into one
 shared library next to this file.  Used by ``__graft_entry__.build()``.
 """
 from __future__ import annotations
@@ -30,7 +30,8 @@ COMMON = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    # .hip: kernels and their launchers; .cpp: host-only code (the planner)
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:

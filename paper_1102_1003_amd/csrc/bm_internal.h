@@ -8,19 +8,14 @@
 #include <vector>
 
 #include "../../include/batmap.h"
+#include "plan.h"
 
 namespace bm {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-// Slots are stored bit-sliced: a "group" is 32 consecutive slots held as
-// 8 uint32 planes (planes 0..6: code bits, plane 7: indicator bits).
-constexpr uint32_t kSlotsPerGroup = 32;
-constexpr uint32_t kWordsPerGroup = 8;
 // Smallest hash domain: r_0 = max(kMinR0, 2^s).  128 keeps 3 r_0 a multiple
 // of 64 slots (one wavefront of the encoder) and of 4 groups (one compare stage).
 constexpr uint32_t kMinR0 = 128;
-// Compare kernel: groups staged per step.
-constexpr uint32_t kStageGroups = 4;
 
 struct Status {
     bm_status code = BM_OK;
@@ -28,23 +23,6 @@ struct Status {
     bool ok() const { return code == BM_OK; }
 };
 
-// One unit of compare work: a tile of row maps (narrower width class) against
-// a tile of column maps (wider or equal class).  Two loop orders exist:
-//  - staged tiles walk column groups c in [c0, c1) and meet row group c mod G_row;
-//  - row-resident tiles walk row groups h in [c0, c1) and, for each, every
-//    column group h + u G_row, u = 0 .. G_col / G_row - 1 (the Fig. 1 wrap).
-struct WorkItem {
-    uint32_t row0;        // first sorted index of the row tile
-    uint32_t col0;        // first sorted index of the column tile
-    uint16_t nrow;        // valid rows
-    uint16_t ncol;        // valid columns
-    uint32_t c0, c1;      // group range (see above)
-    uint32_t row_groups;  // G_row = 3 r_row / 32
-    uint32_t col_groups;  // G_col = 3 r_col / 32
-    uint16_t inst;        // instance (descriptor index)
-    uint16_t flags;       // bit 0: same width class -> emit only row < col; bit 1: row-resident
-};
-static_assert(sizeof(WorkItem) == 32, "work item layout");
 
 // Per-instance view used by the compare kernel.
 struct InstDesc {
@@ -167,22 +145,13 @@ hipError_t launch_apply_corrections_subset(const uint32_t *pairs, uint64_t n_cor
 // descs == nullptr: every item uses d0 (passed by value).
 hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
                           int variant, hipStream_t s);
-hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                     const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
-                                     hipStream_t s);
-// Code of variant v for the single-launch persistent kernel (flags bits 2..3),
-// or -1 when that kernel cannot run it.
-int compare_multi_code(int v);
 uint32_t multi_persistent_grid(uint32_t n_cu);
+// Items of the row-resident single-launch shapes (body codes 0..3) as one
+// persistent launch on s; *counter must be zero.  descs == nullptr: every
+// item uses d0.
 hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                           uint32_t *counter, uint32_t grid, hipStream_t s);
-int compare_variant_count();
-// Tile shape of variant v and its loop order (true: row-resident).
-void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj);
-bool compare_variant_row_resident(int v);
-// Shapes the planner picks from by default (the others are tuning alternatives).
-bool compare_variant_default(int v);
-float compare_variant_speed(int v);
+                                           const InstDesc &d0, uint32_t *counter, uint32_t grid, hipStream_t s);
+
 
 // Threshold + compaction.
 hipError_t launch_threshold_count(const uint32_t *sup, uint64_t n_pairs, uint32_t sigma, uint32_t *block_counts,

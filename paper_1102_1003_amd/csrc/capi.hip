@@ -22,22 +22,54 @@
 
 using namespace bm;
 
+// Freed device memory the stream-ordered pool keeps for reuse.
+static constexpr uint64_t kPoolKeepBytes = 8ull << 30;
+
 // ----------------------------------------------------------------- helpers
 
 namespace {
+
+// Stream of a context for stream-ordered allocation.  A context and every
+// buffer allocated on its stream share one of these; when the context goes
+// away it is switched to the null stream, so buffers that outlive the
+// context (an index's) are still released in order.
+struct AllocStream {
+    hipStream_t s = nullptr;
+};
+
+// Set for the duration of a call that enqueues all its work on one context's
+// stream: buffers allocated meanwhile come from the device's memory pool in
+// stream order (hipMallocAsync / hipFreeAsync), so building and querying
+// repeatedly neither maps nor unmaps device memory nor waits on a free.
+thread_local const std::shared_ptr<AllocStream> *t_alloc_scope = nullptr;
+
+struct AllocScope {
+    const std::shared_ptr<AllocStream> *prev;
+    explicit AllocScope(const std::shared_ptr<AllocStream> &as) : prev(t_alloc_scope)
+    {
+        t_alloc_scope = as ? &as : nullptr;
+    }
+    ~AllocScope() { t_alloc_scope = prev; }
+};
 
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
     uint64_t n = 0;
+    std::shared_ptr<AllocStream> as;  // set when p came from the stream-ordered pool
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { reset(); }
     void reset()
     {
-        if (p)
-            (void)hipFree(p);
+        if (p) {
+            if (as)
+                (void)hipFreeAsync(p, as->s);
+            else
+                (void)hipFree(p);
+        }
+        as.reset();
         p = nullptr;
         n = 0;
     }
@@ -46,7 +78,14 @@ struct DevBuf {
         reset();
         if (count == 0)
             count = 1;
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+        hipError_t e;
+        if (t_alloc_scope && *t_alloc_scope) {
+            e = hipMallocAsync(reinterpret_cast<void **>(&p), count * sizeof(T), (*t_alloc_scope)->s);
+            if (e == hipSuccess)
+                as = *t_alloc_scope;
+        } else {
+            e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+        }
         if (e != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
@@ -63,9 +102,6 @@ struct DevBuf {
     }
 };
 
-struct Cls {
-    uint32_t r, start, count;  // width r; sorted-index range [start, start + count)
-};
 
 enum PtrKind { PTR_HOST, PTR_DEVICE };
 
@@ -94,8 +130,6 @@ uint64_t n_pairs(uint64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 
 }  // namespace
 
-constexpr int kWrapBuckets = 3;  // G_col / G_row: 1 | 2..8 | >= 16
-inline int wrap_bucket(uint32_t ratio) { return ratio <= 1 ? 0 : (ratio <= 8 ? 1 : 2); }
 
 enum Phase { PH_INGEST, PH_LAYOUT, PH_CONSTRUCT, PH_ENCODE, PH_CORRECT, PH_FILL, PH_COMPARE, PH_APPLY,
              PH_THRESHOLD, PH_COUNT };
@@ -107,6 +141,10 @@ struct bm_context {
     int n_cu = 256;
     std::string err;
     DevBuf<uint32_t> counter;  // persistent-kernel work counter
+    std::shared_ptr<AllocStream> as;  // stream-ordered allocation on `stream` (null: plain hipMalloc)
+    // one persistent multi-shape launch per compare (else one launch per tile shape)
+    bool persistent = false;
+    uint32_t grid = 0;  // its workgroups
     // profiling: event spans per phase of the last build / last query
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[PH_COUNT];
@@ -279,36 +317,8 @@ bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
 // shape) is chosen per class pair to minimise padded work, and every tile's
 // column-group range is cut into pieces of about `piece` groups.
 
-// Column groups an item visits (longest first gives a better tail).
-uint64_t item_cost(const WorkItem &w)
-{
-    return (w.flags & 2u) ? (uint64_t)(w.c1 - w.c0) * (w.col_groups / w.row_groups) : (uint64_t)(w.c1 - w.c0);
-}
 
-struct Plan {
-    std::vector<std::vector<WorkItem>> by_variant;
-    double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
-};
 
-void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
-               std::vector<std::pair<uint32_t, uint32_t>> *out, uint64_t *count)
-{
-    uint64_t c = 0;
-    for (uint32_t I = 0; I * bi < A.count; I++) {
-        for (uint32_t J = 0; J * bj < B.count; J++) {
-            if (same) {
-                uint32_t row_start = I * bi;
-                uint32_t col_end = std::min(B.count, (J + 1) * bj);
-                if (!(row_start + 1 < col_end))
-                    continue;  // no row < column in this tile
-            }
-            c++;
-            if (out)
-                out->push_back({I, J});
-        }
-    }
-    *count = c;
-}
 
 // BM_COMPARE_VARIANT=<v> pins every class pair to tile shape v (tuning aid).
 int forced_variant()
@@ -317,124 +327,15 @@ int forced_variant()
     if (!e || !*e)
         return -1;
     int v = atoi(e);
-    return (v >= 0 && v < compare_variant_count()) ? v : -1;
+    return (v >= 0 && v < kVariantCount) ? v : -1;
 }
 
-void plan_classes(const std::vector<Cls> &cls, uint32_t r0, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds = nullptr, bool multi_only = false)
-{
-    int nv = compare_variant_count();
-    const int pinned = forced_variant();
-    plan.by_variant.assign(nv, {});
-    plan.slot_pairs = 0;
-    struct Choice {
-        size_t a, b;
-        int v;
-    };
-    std::vector<Choice> choices;
-    uint64_t total_groups = 0;
-    for (size_t a = 0; a < cls.size(); a++) {
-        for (size_t b = a; b < cls.size(); b++) {
-            bool same = a == b;
-            if (same && cls[a].count < 2)
-                continue;
-            int best = 0;
-            double best_cost = 1e300;
-            const int bucket = wrap_bucket(cls[b].r / cls[a].r);
-            const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
-            for (int v = 0; v < nv; v++) {
-                // measured speeds weigh the default shapes against each other; the
-                // staged-tile shapes time well on uniform synthetic tiles but lose on
-                // skewed instances, so they are used only when pinned
-                if (multi_only ? compare_multi_code(v) < 0
-                               : (pinned >= 0 ? v != pinned : !compare_variant_default(v)))
-                    continue;
-                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : compare_variant_speed(v);
-                if (!(speed > 0))
-                    continue;
-                uint32_t bi, bj;
-                compare_variant_shape(v, &bi, &bj);
-                uint64_t cnt;
-                tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
-                double cost = (double)cnt * bi * bj / speed;
-                // prefer larger tiles on ties (more reuse per loaded group)
-                if (cost < best_cost) {  // variants are listed largest tile first
-                    best_cost = cost;
-                    best = v;
-                }
-            }
-            uint32_t bi, bj;
-            compare_variant_shape(best, &bi, &bj);
-            uint64_t cnt;
-            tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
-            double pairs = same ? 0.5 * cls[a].count * (cls[a].count - 1.0) : (double)cls[a].count * cls[b].count;
-            plan.slot_pairs += pairs * 3.0 * cls[b].r;
-            total_groups += cnt * (3ull * cls[b].r / kSlotsPerGroup);
-            choices.push_back({a, b, best});
-        }
-    }
-    uint64_t piece = (total_groups + target_items - 1) / std::max<uint64_t>(target_items, 1);
-    piece = std::max<uint64_t>(piece, 16 * kStageGroups);
-    piece = (piece + kStageGroups - 1) / kStageGroups * kStageGroups;
-    std::vector<std::pair<uint32_t, uint32_t>> tiles;
-    for (const Choice &ch : choices) {
-        const Cls &A = cls[ch.a], &B = cls[ch.b];
-        bool same = ch.a == ch.b;
-        uint32_t bi, bj;
-        compare_variant_shape(ch.v, &bi, &bj);
-        tiles.clear();
-        uint64_t cnt;
-        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
-        const uint32_t Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
-        const uint32_t Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
-        const bool rows = compare_variant_row_resident(ch.v);
-        // row-resident items walk row groups (each meeting Gb / Ga column
-        // groups); staged items walk column groups in stages of kStageGroups
-        const uint32_t span = rows ? Ga : Gb;
-        const uint64_t unit = rows ? (uint64_t)(Gb / Ga) : 1;
-        uint32_t pieces = (uint32_t)std::max<uint64_t>(1, ((uint64_t)span * unit + piece - 1) / piece);
-        const uint32_t align = rows ? 1 : kStageGroups;
-        pieces = std::min<uint32_t>(pieces, span / align);
-        for (auto &t : tiles) {
-            for (uint32_t k = 0; k < pieces; k++) {
-                uint64_t c0 = (uint64_t)span * k / pieces, c1 = (uint64_t)span * (k + 1) / pieces;
-                c0 = c0 / align * align;
-                c1 = (k + 1 == pieces) ? span : c1 / align * align;
-                if (c1 <= c0)
-                    continue;
-                WorkItem w;
-                w.row0 = A.start + t.first * bi;
-                w.col0 = B.start + t.second * bj;
-                w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
-                w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
-                w.c0 = (uint32_t)c0;
-                w.c1 = (uint32_t)c1;
-                w.row_groups = Ga;
-                w.col_groups = Gb;
-                w.inst = (uint16_t)inst;
-                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u) |
-                                     (compare_multi_code(ch.v) >= 0 ? (uint32_t)compare_multi_code(ch.v) << 2 : 0u));
-                plan.by_variant[ch.v].push_back(w);
-            }
-        }
-    }
-    for (auto &v : plan.by_variant)
-        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
-}
 
-// Classes restricted to sorted indices >= first.
-std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first)
-{
-    std::vector<Cls> out;
-    for (const Cls &c : cls) {
-        uint32_t e = c.start + c.count;
-        if (e <= first)
-            continue;
-        uint32_t s = std::max(c.start, first);
-        out.push_back({c.r, s, e - s});
-    }
-    return out;
-}
+
+// Persistent plans run as one single-launch list: range (-1, all items),
+// longest first.
+bool use_persistent(const bm_context *ctx) { return ctx->persistent && forced_variant() < 0; }
+
 
 bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
                       std::vector<std::pair<int, uint32_t>> &ranges)
@@ -452,6 +353,11 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
         ranges.push_back({(int)v, (uint32_t)plan.by_variant[v].size()});
         flat.insert(flat.end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
     }
+    if (use_persistent(ctx) && total) {
+        std::stable_sort(flat.begin(), flat.end(),
+                         [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+        ranges.assign(1, {-1, (uint32_t)total});
+    }
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total) {
         HIPC(ctx, hipMemcpyAsync(dst.p, flat.data(), total * sizeof(WorkItem), hipMemcpyHostToDevice, ctx->stream));
@@ -463,6 +369,12 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
 bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<std::pair<int, uint32_t>> &ranges,
                       const InstDesc &d0)
 {
+    if (!ranges.empty() && ranges[0].first == -1) {
+        HIPC(ctx, fill_u32(ctx->counter.p, 1, 0, ctx->stream));
+        HIPC(ctx, launch_compare_multi_persistent(items, ranges[0].second, nullptr, d0, ctx->counter.p,
+                                                  ctx->grid, ctx->stream));
+        return BM_OK;
+    }
     uint64_t at = 0;
     for (auto &r : ranges) {
         HIPC(ctx, launch_compare(items + at, r.second, nullptr, d0, r.first, ctx->stream));
@@ -762,7 +674,8 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
     }
     if (idx->planned_first != first || idx->planned_gen != ctx->tune_gen) {
         Plan plan;
-        plan_classes(classes_from(idx->classes, first), idx->r0, 0, target_items(ctx), plan, &ctx->speeds);
+        plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, &ctx->speeds,
+                     use_persistent(ctx) ? 1 : 0, forced_variant());
         bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
         if (st != BM_OK)
             return st;
@@ -791,7 +704,7 @@ hipError_t bm_batch::enqueue(hipStream_t s)
         if (n_pairs(idx[q]->n))
             e = fill_u32(outs[q], n_pairs(idx[q]->n), 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(items.p, n_items, descs.p, counter.p, grid, s);
+        e = launch_compare_multi_persistent(items.p, n_items, descs.p, InstDesc{}, counter.p, grid, s);
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         e = launch_apply_corrections(idx[q]->corr.p, idx[q]->n_corr, outs[q], idx[q]->n, s);
     return e;
@@ -850,7 +763,7 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
     hipEvent_t e0, e1;
     HIPC(ctx, hipEventCreate(&e0));
     HIPC(ctx, hipEventCreate(&e1));
-    const int nv = compare_variant_count();
+    const int nv = kVariantCount;
     std::vector<float> speeds((size_t)nv * kWrapBuckets, 0.f);
     bm_status result = BM_OK;
     for (int b = 0; b < kWrapBuckets && result == BM_OK; b++) {
@@ -860,14 +773,13 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
             // force variant v on this one class pair
             Plan plan;
             plan.by_variant.assign(nv, {});
-            uint32_t bi, bj;
-            compare_variant_shape(v, &bi, &bj);
+            const uint32_t bi = variant_info(v).bi, bj = variant_info(v).bj;
             std::vector<std::pair<uint32_t, uint32_t>> tiles;
             uint64_t cnt;
             tiles_for(A, B, false, bi, bj, &tiles, &cnt);
             const uint32_t Ga = grow, Gb = grow * ratios[b];
-            const bool rows = compare_variant_row_resident(v);
-            const uint32_t span = rows ? Ga : Gb, align = rows ? 1 : kStageGroups;
+            const bool rows = variant_info(v).row_resident;
+            const uint32_t span = rows ? Ga : Gb, align = variant_info(v).step;
             const uint64_t want = (uint64_t)ctx->n_cu * 16;
             uint32_t pieces = (uint32_t)std::max<uint64_t>(1, (want + tiles.size() - 1) / tiles.size());
             pieces = std::min<uint32_t>(pieces, span / align);
@@ -957,6 +869,36 @@ bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess)
         ctx->n_cu = prop.multiProcessorCount;
+    // BM_COMPARE_PERSISTENT=1 runs single-call compares as one multi-shape
+    // persistent launch (tuning aid).  The default, one launch per tile shape,
+    // is faster there: each shape's kernel keeps its own, higher occupancy.
+    const char *pe = getenv("BM_COMPARE_PERSISTENT");
+    ctx->persistent = pe && pe[0] == '1';
+    ctx->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
+    // stream-ordered allocations from the device's default pool, which keeps
+    // up to kPoolKeepBytes of freed memory for reuse instead of unmapping it
+    // (BM_STREAM_ALLOC=0 turns this off)
+    const char *sa = getenv("BM_STREAM_ALLOC");
+    if (!(sa && sa[0] == '0')) {
+        hipMemPool_t pool = nullptr;
+        uint64_t keep = kPoolKeepBytes;
+        int supported = 0;
+        if (hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess &&
+            supported && hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess &&
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess) {
+            ctx->as = std::make_shared<AllocStream>();
+            ctx->as->s = ctx->stream;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    if (ctx->counter.alloc(1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->own_stream)
+            (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return BM_ENOMEM;
+    }
     *out = ctx;
     return BM_OK;
 }
@@ -969,6 +911,8 @@ void bm_context_destroy(bm_context *ctx)
     if (ctx->stream)
         (void)hipStreamSynchronize(ctx->stream);
     ctx->counter.reset();
+    if (ctx->as)
+        ctx->as->s = nullptr;  // indexes built here release their buffers on the null stream from now on
     clear_phases(ctx, 0, PH_COUNT - 1);
     for (hipEvent_t e : ctx->event_pool)
         (void)hipEventDestroy(e);
@@ -1020,6 +964,7 @@ bm_status bm_context_autotune(bm_context *ctx, uint32_t reps)
     if (!ctx)
         return BM_EINVAL;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     HIPC(ctx, hipSetDevice(ctx->device));
     return autotune(ctx, reps);
 }
@@ -1028,7 +973,7 @@ bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capaci
 {
     if (!ctx || !n_out)
         return BM_EINVAL;
-    uint32_t n = (uint32_t)compare_variant_count() * kWrapBuckets;
+    uint32_t n = (uint32_t)kVariantCount * kWrapBuckets;
     *n_out = n;
     if (!speeds)
         return BM_OK;
@@ -1048,8 +993,8 @@ bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint3
         ctx->tune_gen++;
         return BM_OK;
     }
-    if (!speeds || n != (uint32_t)compare_variant_count() * kWrapBuckets)
-        return fail(ctx, BM_EINVAL, "expected %u speeds", (uint32_t)compare_variant_count() * kWrapBuckets);
+    if (!speeds || n != (uint32_t)kVariantCount * kWrapBuckets)
+        return fail(ctx, BM_EINVAL, "expected %u speeds", (uint32_t)kVariantCount * kWrapBuckets);
     ctx->speeds.assign(speeds, speeds + n);
     ctx->tune_gen++;
     return BM_OK;
@@ -1070,6 +1015,7 @@ bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, cons
     if (!ctx)
         return BM_EINVAL;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_build(ctx);
     if (!out || !offsets || m == 0 || n_sets == 0)
         return fail(ctx, BM_EINVAL, "bm_index_build_sets: null pointer or zero size");
@@ -1148,6 +1094,7 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     if (!ctx)
         return BM_EINVAL;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_build(ctx);
     if (!out || !offsets || m_txn == 0 || n_items == 0)
         return fail(ctx, BM_EINVAL, "bm_index_build_transactions: null pointer or zero size");
@@ -1280,7 +1227,9 @@ bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
 void bm_index_destroy(bm_index *idx)
 {
     // Uses only the index's own device id, so it stays valid after the
-    // context is gone; hipFree waits for outstanding work on the buffers.
+    // context is gone.  Buffers are released in the order of the context's
+    // stream (or, once the context is gone, the null stream), after the work
+    // already queued there.
     if (!idx)
         return;
     (void)hipSetDevice(idx->device);
@@ -1293,6 +1242,7 @@ bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len)
         return BM_EINVAL;
     bm_context *ctx = idx->ctx;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_query(ctx);
     uint64_t np = n_pairs(idx->n);
     if (np == 0)
@@ -1327,6 +1277,7 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
         return BM_EINVAL;
     bm_context *ctx = idx->ctx;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_query(ctx);
     if (!n_out)
         return fail(ctx, BM_EINVAL, "n_out is null");
@@ -1391,6 +1342,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
         return BM_EINVAL;
     bm_context *ctx = idx->ctx;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_query(ctx);
     uint64_t np = n_pairs(k);
     if (k == 0)
@@ -1478,7 +1430,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.gb = idx->gb;
     d.pad = 0;
     Plan plan;
-    plan_classes(cls, idx->r0, 0, target_items(ctx), plan, &ctx->speeds);
+    plan_classes(cls, 0, target_items(ctx), plan, &ctx->speeds, use_persistent(ctx) ? 1 : 0, forced_variant());
     std::vector<std::pair<int, uint32_t>> ranges;
     st = upload_plan(idx, plan, idx->sub_work, ranges);
     if (st != BM_OK)
@@ -1536,7 +1488,7 @@ bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count
             return fail(ctx, BM_EINVAL, "outs[%u] must be device memory", q);
         descs[q] = whole_desc(idx, outs[q]);
         Plan one;
-        plan_classes(idx->classes, idx->r0, q, target_items(ctx) / count + 64, one, &ctx->speeds, true);
+        plan_classes(idx->classes, q, target_items(ctx) / count + 64, one, &ctx->speeds, 1, -1);
         b->slot_pairs += one.slot_pairs;
         for (auto &v : one.by_variant)
             flat.insert(flat.end(), v.begin(), v.end());
@@ -1630,6 +1582,7 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
         return BM_EINVAL;
     bm_context *ctx = idx->ctx;
     ctx->err.clear();
+    AllocScope scope(ctx->as);
     begin_query(ctx);
     uint64_t np = n_pairs(idx->n);
     if (np == 0)
@@ -1878,7 +1831,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         for (uint32_t p = 0; p < k; p++)
             hi[p] = r.items[p];
         Plan plan;
-        plan_classes(cls, ix->r0, j, (uint64_t)ix->ctx->n_cu * 16 / nq + 32, plan, &ix->ctx->speeds, true);
+        plan_classes(cls, j, target_items(ix->ctx) / nq + 64, plan, &ix->ctx->speeds, 1, -1);
         for (auto &v : plan.by_variant)
             flat.insert(flat.end(), v.begin(), v.end());
         InstDesc &d = L.h_descs[j];
@@ -1920,7 +1873,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
     if (e == hipSuccess)
         e = fill_u32(L.counter.p, 1, 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(L.items.p, (uint32_t)flat.size(), L.descs.p, L.counter.p,
+        e = launch_compare_multi_persistent(L.items.p, (uint32_t)flat.size(), L.descs.p, InstDesc{}, L.counter.p,
                                             grid, s);
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];

@@ -159,26 +159,6 @@ __global__ __launch_bounds__(256) void compare_kernel(const WorkItem *__restrict
 
 // Persistent form: a fixed grid pulls work items from a counter until the
 // list is exhausted (every workgroup exits once the counter passes n_items).
-template <int MI, int MJ, int TX>
-__global__ __launch_bounds__(256) void compare_persistent_kernel(const WorkItem *__restrict__ items,
-                                                                 uint32_t n_items,
-                                                                 const InstDesc *__restrict__ descs,
-                                                                 InstDesc d0, uint32_t *counter)
-{
-    __shared__ Smem<MI, MJ, TX> sm;
-    for (;;) {
-        if (threadIdx.x == 0)
-            sm.item = atomicAdd(counter, 1u);
-        __syncthreads();
-        uint32_t it = sm.item;
-        __syncthreads();
-        if (it >= n_items)
-            break;
-        const WorkItem w = items[it];
-        const InstDesc d = descs ? descs[w.inst] : d0;
-        process_item<MI, MJ, TX>(w, d, sm);
-    }
-}
 
 // Row-resident form, one wavefront per workgroup and no LDS.  Each lane holds
 // R row maps' current group in registers; the MJ column maps are the same for
@@ -206,7 +186,11 @@ __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
-template <int R, int MJ>
+// H > 1: each step takes H consecutive row groups h .. h+H-1 (ranges are
+// multiples of H; every width's group count 3r/32 is even), so the column
+// groups they meet are consecutive too and arrive in one wider scalar load.
+// That doubles the VALU work per scalar-load wait without widening the tile.
+template <int R, int MJ, int H = 1>
 __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
@@ -237,36 +221,45 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
     const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
     const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
     const uint32_t h0 = __builtin_amdgcn_readfirstlane(w.c0), h1 = __builtin_amdgcn_readfirstlane(w.c1);
-    // row groups for h are fetched one step ahead
-    u32x4 na[R], nb[R];
+    // row groups for the next step are fetched one step ahead
+    u32x4 na[H][R], nb[H][R];
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        na[r] = arena[rbase[r] + 2 * (uint64_t)h0];
-        nb[r] = arena[rbase[r] + 2 * (uint64_t)h0 + 1];
-    }
-    for (uint32_t h = h0; h < h1; h++) {
-        uint32_t x[R][8];
+    for (int e = 0; e < H; e++)
 #pragma unroll
-        for (int r = 0; r < R; r++)
-            unpack4(na[r], nb[r], x[r]);
-        if (h + 1 < h1) {
+        for (int r = 0; r < R; r++) {
+            na[e][r] = arena[rbase[r] + 2 * (uint64_t)(h0 + e)];
+            nb[e][r] = arena[rbase[r] + 2 * (uint64_t)(h0 + e) + 1];
+        }
+    for (uint32_t h = h0; h < h1; h += H) {
+        uint32_t x[H][R][8];
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                na[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1)];
-                nb[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1) + 1];
-            }
+        for (int e = 0; e < H; e++)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                unpack4(na[e][r], nb[e][r], x[e][r]);
+        if (h + H < h1) {
+#pragma unroll
+            for (int e = 0; e < H; e++)
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    na[e][r] = arena[rbase[r] + 2 * (uint64_t)(h + H + e)];
+                    nb[e][r] = arena[rbase[r] + 2 * (uint64_t)(h + H + e) + 1];
+                }
         }
         for (uint32_t u = 0; u < wraps; u++) {
             const uint32_t c = h + u * row_groups;
 #pragma unroll
             for (int j = 0; j < MJ; j++) {
-                uint32_t y[8];
                 const uint64_t g2 = 2 * (uint64_t)(cbase[j] + c);
-                const u32x4 a = carena[g2], b = carena[g2 + 1];
-                unpack4(a, b, y);
 #pragma unroll
-                for (int r = 0; r < R; r++)
-                    acc[r][j] = group_hits(x[r], y, acc[r][j]);
+                for (int e = 0; e < H; e++) {
+                    uint32_t y[8];
+                    const u32x4 a = carena[g2 + 2 * e], b = carena[g2 + 2 * e + 1];
+                    unpack4(a, b, y);
+#pragma unroll
+                    for (int r = 0; r < R; r++)
+                        acc[r][j] = group_hits(x[e][r], y, acc[r][j]);
+                }
             }
         }
     }
@@ -287,20 +280,243 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
     }
 }
 
-template <int R, int MJ>
+// Software-pipelined form of the row-resident loop.  Column groups arrive in
+// chunks of CH maps, double-buffered in SGPRs.  Scalar loads complete out of
+// order, so a wait on them waits for all of them; the order below therefore
+// makes the wait for chunk k come before the loads of chunk k+1 are issued
+// (the first use of chunk k triggers it), and the rest of chunk k's compare
+// then runs while chunk k+1 is in flight.  Scheduling barriers keep that order.
+template <int R, int MJ, int CH>
+__device__ void process_rows_pipe(const WorkItem &w, const InstDesc &d)
+{
+    static_assert(MJ % CH == 0 && (MJ / CH) % 2 == 0, "chunks alternate between two buffers");
+    constexpr int NK = MJ / CH;
+    const int lane = threadIdx.x & 63;
+    GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.arena);
+    GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
+    ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
+    uint64_t rbase[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+        uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
+        rbase[r] = goff[w.row0 + rr] * 2;
+    }
+    uint32_t cbase[MJ];
+#pragma unroll
+    for (int j = 0; j < MJ; j++) {
+        uint32_t cc = j < w.ncol ? j : w.ncol - 1;
+        cbase[j] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.col0 + cc)]);
+    }
+    uint32_t acc[R][MJ];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[r][j] = 0;
+    const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
+    const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
+    const uint32_t h0 = __builtin_amdgcn_readfirstlane(w.c0), h1 = __builtin_amdgcn_readfirstlane(w.c1);
+    u32x4 na[R], nb[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        na[r] = arena[rbase[r] + 2 * (uint64_t)h0];
+        nb[r] = arena[rbase[r] + 2 * (uint64_t)h0 + 1];
+    }
+    uint32_t Y[2][CH][8];
+#define BM_LOAD_CHUNK(BUF, K, C)                                                   \
+    _Pragma("unroll") for (int jj = 0; jj < CH; jj++)                              \
+    {                                                                              \
+        const uint64_t g2 = 2 * (uint64_t)(cbase[(K) * CH + jj] + (C));           \
+        const u32x4 a = carena[g2], b = carena[g2 + 1];                            \
+        unpack4(a, b, Y[BUF][jj]);                                                 \
+    }
+    BM_LOAD_CHUNK(0, 0, h0);
+    for (uint32_t h = h0; h < h1; h++) {
+        uint32_t x[R][8];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            unpack4(na[r], nb[r], x[r]);
+        if (h + 1 < h1) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                na[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1)];
+                nb[r] = arena[rbase[r] + 2 * (uint64_t)(h + 1) + 1];
+            }
+        }
+        for (uint32_t u = 0; u < wraps; u++) {
+            const uint32_t c = h + u * row_groups;
+            // column group of the next step's first chunk (a valid group is
+            // re-read after the last step)
+            const uint32_t nc = u + 1 < wraps ? c + row_groups : (h + 1 < h1 ? h + 1 : c);
+#pragma unroll
+            for (int k = 0; k < NK; k++) {
+                const int buf = k & 1;
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r][k * CH] = group_hits(x[r], Y[buf][0], acc[r][k * CH]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (k + 1 < NK) {
+                    BM_LOAD_CHUNK(buf ^ 1, k + 1, c);
+                } else {
+                    BM_LOAD_CHUNK(buf ^ 1, 0, nc);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 1; jj < CH; jj++)
+#pragma unroll
+                    for (int r = 0; r < R; r++)
+                        acc[r][k * CH + jj] = group_hits(x[r], Y[buf][jj], acc[r][k * CH + jj]);
+            }
+        }
+    }
+#undef BM_LOAD_CHUNK
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            if (rho < w.nrow && j < w.ncol && acc[r][j] != 0) {
+                uint32_t p = w.row0 + rho, q = w.col0 + j;
+                if ((w.flags & 1u) && p >= q)
+                    continue;
+                uint32_t a = d.outpos[p], b = d.outpos[q];
+                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[r][j]);
+            }
+        }
+    }
+}
+
+template <int R, int MJ, int CH>
+__global__ __launch_bounds__(64) void compare_pipe_kernel(const WorkItem *__restrict__ items,
+                                                          const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_rows_pipe<R, MJ, CH>(w, d);
+}
+
+
+// Group-parallel form for classes with few maps: one wavefront takes an
+// MI x MJ tile and spreads its lanes over row-group positions (lane l takes
+// h = c0 + l, c0 + l + 64, ...), so a tile of a handful of maps keeps every
+// lane busy instead of padding 64 R rows.  Each lane loads its row groups
+// once and meets the column groups h + u G_row of every wrap u; the counts
+// are summed over the lanes at the end.  Loads are coalesced: neighbouring
+// lanes read neighbouring groups of the same map.
+template <int MI, int MJ>
+__device__ void process_gp(const WorkItem &w, const InstDesc &d)
+{
+    const int lane = threadIdx.x & 63;
+    GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
+    uint32_t rb[MI], cb[MJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++) {
+        uint32_t ii = i < w.nrow ? i : w.nrow - 1;
+        rb[i] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.row0 + ii)]);
+    }
+#pragma unroll
+    for (int j = 0; j < MJ; j++) {
+        uint32_t jj = j < w.ncol ? j : w.ncol - 1;
+        cb[j] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.col0 + jj)]);
+    }
+    uint32_t acc[MI][MJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[i][j] = 0;
+    const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
+    const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
+    const uint32_t h1 = __builtin_amdgcn_readfirstlane(w.c1);
+    for (uint32_t h = __builtin_amdgcn_readfirstlane(w.c0) + lane; h < h1; h += 64) {
+        uint32_t x[MI][8];
+#pragma unroll
+        for (int i = 0; i < MI; i++) {
+            const uint64_t g2 = 2 * (uint64_t)(rb[i] + h);
+            const u32x4 a = arena[g2], b = arena[g2 + 1];
+            unpack4(a, b, x[i]);
+        }
+        for (uint32_t u = 0; u < wraps; u++) {
+            const uint32_t c = h + u * row_groups;
+            // one column group in flight ahead of the one compared (the
+            // barriers stop the compiler from hoisting all MJ loads, which
+            // would cost registers the single-launch kernel cannot spare)
+            u32x4 na = arena[2 * (uint64_t)(cb[0] + c)], nb = arena[2 * (uint64_t)(cb[0] + c) + 1];
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                uint32_t y[8];
+                unpack4(na, nb, y);
+                if (j + 1 < MJ) {
+                    const uint64_t g2 = 2 * (uint64_t)(cb[j + 1] + c);
+                    na = arena[g2];
+                    nb = arena[g2 + 1];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < MI; i++)
+                    acc[i][j] = group_hits(x[i], y, acc[i][j]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            uint32_t v = acc[i][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                v += __shfl_xor(v, o, 64);
+            acc[i][j] = v;
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                if (i < w.nrow && j < w.ncol && acc[i][j] != 0) {
+                    uint32_t p = w.row0 + i, q = w.col0 + j;
+                    if ((w.flags & 1u) && p >= q)
+                        continue;
+                    uint32_t a = d.outpos[p], b = d.outpos[q];
+                    uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[i][j]);
+                }
+            }
+    }
+}
+
+template <int MI, int MJ>
+__global__ __launch_bounds__(64) void compare_gp_kernel(const WorkItem *__restrict__ items,
+                                                        const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_gp<MI, MJ>(w, d);
+}
+
+
+template <int R, int MJ, int H>
 __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__restrict__ items,
                                                           const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_rows<R, MJ>(w, d);
+    process_rows<R, MJ, H>(w, d);
 }
 
-template <int R, int MJ>
-__global__ __launch_bounds__(64) void compare_rows_persistent_kernel(const WorkItem *__restrict__ items,
-                                                                     uint32_t n_items,
-                                                                     const InstDesc *__restrict__ descs,
-                                                                     InstDesc d0, uint32_t *counter)
+
+// One persistent launch for items of every shape the single-launch forms use
+// (row-resident 128 x 16 / 12 / 8 / 4, body codes 0..3): the shape travels in
+// the item's flags (bits 2..4) and selects the specialised body.
+__global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
+                                                                           uint32_t n_items,
+                                                                           const InstDesc *__restrict__ descs,
+                                                                           InstDesc d0, uint32_t *counter)
 {
     for (;;) {
         uint32_t it = 0;
@@ -311,28 +527,7 @@ __global__ __launch_bounds__(64) void compare_rows_persistent_kernel(const WorkI
             break;
         const WorkItem w = items[it];
         const InstDesc d = descs ? descs[w.inst] : d0;
-        process_rows<R, MJ>(w, d);
-    }
-}
-
-// One persistent launch for items of every default row-resident shape
-// (128 rows x 16 / 12 / 8 / 4 columns): the shape travels in the item's
-// flags (bits 2..3) and selects the specialised body.
-__global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
-                                                                           uint32_t n_items,
-                                                                           const InstDesc *__restrict__ descs,
-                                                                           uint32_t *counter)
-{
-    for (;;) {
-        uint32_t it = 0;
-        if ((threadIdx.x & 63) == 0)
-            it = atomicAdd(counter, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if (it >= n_items)
-            break;
-        const WorkItem w = items[it];
-        const InstDesc d = descs[w.inst];
-        switch ((w.flags >> 2) & 3u) {
+        switch ((w.flags >> 2) & 7u) {
         case 0: process_rows<2, 16>(w, d); break;
         case 1: process_rows<2, 12>(w, d); break;
         case 2: process_rows<2, 8>(w, d); break;
@@ -341,74 +536,47 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
     }
 }
 
-struct Variant {
-    uint32_t bi, bj;
-    bool row_resident;
+
+// Kernel of each tile shape, in the order of the shape catalogue (plan.cpp).
+struct Kernels {
     uint32_t block;
     void (*grid_fn)(const WorkItem *, const InstDesc *, InstDesc);
-    void (*pers_fn)(const WorkItem *, uint32_t, const InstDesc *, InstDesc, uint32_t *);
-    bool default_choice;  // offered to the planner unless a variant is pinned
-    float speed;          // relative group-pair rate of an unpadded tile (planner cost weight)
 };
 
-#define BM_VARIANT(MI, MJ, TX)                                                                          \
-    Variant{Shape<MI, MJ, TX>::BI, Shape<MI, MJ, TX>::BJ, false, 256, compare_kernel<MI, MJ, TX>,      \
-            compare_persistent_kernel<MI, MJ, TX>, false, 0.6f}
-#define BM_ROWS_VARIANT(R, MJ, SPEED)                                                                   \
-    Variant{64 * R, MJ, true, 64, compare_rows_kernel<R, MJ>, compare_rows_persistent_kernel<R, MJ>, R == 2, SPEED}
+#define BM_STAGED(MI, MJ, TX) Kernels{256, compare_kernel<MI, MJ, TX>}
+#define BM_ROWS(R, MJ, H) Kernels{64, compare_rows_kernel<R, MJ, H>}
+#define BM_PIPE(R, MJ, CH) Kernels{64, compare_pipe_kernel<R, MJ, CH>}
+#define BM_GP(MI, MJ) Kernels{64, compare_gp_kernel<MI, MJ>}
 
-const Variant kVariants[] = {
-    BM_VARIANT(4, 4, 16),  // 64 x 64
-    BM_VARIANT(4, 4, 32),  // 128 x 32
-    BM_VARIANT(4, 4, 64),  // 256 x 16
-    BM_VARIANT(2, 4, 128), // 256 x 8
-    // speeds: group pairs per unit time relative to 128 x 16, measured on MI355X
-    BM_ROWS_VARIANT(2, 16, 1.00f),  // 128 x 16, row-resident
-    BM_ROWS_VARIANT(2, 12, 1.00f),  // 128 x 12, row-resident
-    BM_ROWS_VARIANT(2, 8, 0.92f),   // 128 x 8, row-resident
-    BM_ROWS_VARIANT(2, 4, 0.60f),   // 128 x 4, row-resident
-    BM_ROWS_VARIANT(4, 8, 0.85f),   // 256 x 8, row-resident
-    BM_ROWS_VARIANT(1, 16, 0.65f),  // 64 x 16, row-resident
+const Kernels kKernels[] = {
+    BM_STAGED(4, 4, 16), BM_STAGED(4, 4, 32), BM_STAGED(4, 4, 64), BM_STAGED(2, 4, 128),
+    BM_ROWS(2, 16, 1),   BM_ROWS(2, 12, 1),   BM_ROWS(2, 8, 1),    BM_ROWS(2, 4, 1),
+    BM_ROWS(4, 8, 1),    BM_ROWS(1, 16, 1),
+    BM_ROWS(2, 12, 2),   BM_ROWS(2, 8, 2),    BM_ROWS(1, 16, 2),
+    BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),
+    BM_GP(4, 4),         BM_GP(2, 8),
 };
+static_assert(sizeof(kKernels) / sizeof(kKernels[0]) == kVariantCount, "one kernel entry per tile shape");
+
 
 }  // namespace
 
-int compare_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
-void compare_variant_shape(int v, uint32_t *bi, uint32_t *bj)
-{
-    *bi = kVariants[v].bi;
-    *bj = kVariants[v].bj;
-}
 
-bool compare_variant_row_resident(int v) { return kVariants[v].row_resident; }
 
-bool compare_variant_default(int v) { return kVariants[v].default_choice; }
 
-float compare_variant_speed(int v) { return kVariants[v].speed; }
+
 
 hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
                           int variant, hipStream_t s)
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(kVariants[variant].grid_fn, dim3(n_items), dim3(kVariants[variant].block), 0, s, items, descs,
+    hipLaunchKernelGGL(kKernels[variant].grid_fn, dim3(n_items), dim3(kKernels[variant].block), 0, s, items, descs,
                        d0);
     return hipGetLastError();
 }
 
-int compare_multi_code(int v)
-{
-    if (!kVariants[v].row_resident || kVariants[v].bi != 128)
-        return -1;
-    switch (kVariants[v].bj) {
-    case 16: return 0;
-    case 12: return 1;
-    case 8: return 2;
-    case 4: return 3;
-    default: return -1;
-    }
-}
 
 // Workgroups that fill every CU of the current device at the multi-shape
 // kernel's occupancy (its one-wave workgroups are register-bound).
@@ -425,24 +593,12 @@ uint32_t multi_persistent_grid(uint32_t n_cu)
 }
 
 hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                           uint32_t *counter, uint32_t grid, hipStream_t s)
+                                           const InstDesc &d0, uint32_t *counter, uint32_t grid, hipStream_t s)
 {
-    if (n_items == 0)
-        return hipSuccess;
-    compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, n_items, descs, counter);
+    if (n_items)
+        compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, n_items, descs, d0, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_compare_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                     const InstDesc &d0, int variant, uint32_t *counter, uint32_t grid,
-                                     hipStream_t s)
-{
-    if (n_items == 0)
-        return hipSuccess;
-    uint32_t g = kVariants[variant].row_resident ? grid * 4 : grid;
-    hipLaunchKernelGGL(kVariants[variant].pers_fn, dim3(g), dim3(kVariants[variant].block), 0, s, items, n_items, descs,
-                       d0, counter);
-    return hipGetLastError();
-}
 
 }  // namespace bm

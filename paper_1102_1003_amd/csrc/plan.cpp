@@ -1,0 +1,200 @@
+// Compare work planning (host only): tile-shape catalogue and planner.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace bm {
+
+namespace {
+
+// Tile shapes, in the order of the compare kernel table.  Speeds are group
+// pairs per unit time relative to 128 x 16, measured on MI355X; the planner
+// uses them until the autotuner has measured the device.
+const VariantInfo kInfo[kVariantCount] = {
+    // staged LDS tiles (64 x 64, 128 x 32, 256 x 16, 256 x 8): only when pinned
+    {64, 64, false, kStageGroups, -1, false, 0.60f},
+    {128, 32, false, kStageGroups, -1, false, 0.60f},
+    {256, 16, false, kStageGroups, -1, false, 0.60f},
+    {256, 8, false, kStageGroups, -1, false, 0.60f},
+    // row-resident, 64 R rows x MJ columns
+    {128, 16, true, 1, 0, true, 1.00f},
+    {128, 12, true, 1, 1, true, 1.00f},
+    {128, 8, true, 1, 2, true, 0.92f},
+    {128, 4, true, 1, 3, true, 0.60f},
+    {256, 8, true, 1, -1, false, 0.85f},
+    {64, 16, true, 1, -1, false, 0.65f},
+    // row-resident, two row groups per step
+    {128, 12, true, 2, -1, false, 1.00f},
+    {128, 8, true, 2, -1, false, 0.95f},
+    {64, 16, true, 2, -1, false, 0.70f},
+    // row-resident, software-pipelined column chunks
+    {128, 8, true, 1, -1, false, 0.95f},
+    {128, 16, true, 1, -1, false, 1.00f},
+    {64, 16, true, 1, -1, false, 0.70f},
+    {128, 4, true, 1, -1, false, 0.65f},
+    // group-parallel small tiles (lanes over group positions)
+    {4, 4, true, 64, -1, true, 0.30f},
+    {2, 8, true, 64, -1, true, 0.30f},
+};
+
+}  // namespace
+
+const VariantInfo &variant_info(int v) { return kInfo[v]; }
+
+uint64_t item_cost(const WorkItem &w)
+{
+    return (w.flags & 2u) ? (uint64_t)(w.c1 - w.c0) * (w.col_groups / w.row_groups) : (uint64_t)(w.c1 - w.c0);
+}
+
+void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
+               std::vector<std::pair<uint32_t, uint32_t>> *out, uint64_t *count)
+{
+    uint64_t c = 0;
+    for (uint32_t I = 0; I * bi < A.count; I++) {
+        for (uint32_t J = 0; J * bj < B.count; J++) {
+            if (same) {
+                uint32_t row_start = I * bi;
+                uint32_t col_end = std::min(B.count, (J + 1) * bj);
+                if (!(row_start + 1 < col_end))
+                    continue;  // no row < column in this tile
+            }
+            c++;
+            if (out)
+                out->push_back({I, J});
+        }
+    }
+    *count = c;
+}
+
+void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
+                  const std::vector<float> *speeds, int single, int pinned)
+{
+    const int nv = kVariantCount;
+    plan.by_variant.assign(nv, {});
+    plan.slot_pairs = 0;
+    struct Choice {
+        size_t a, b;
+        int v;
+        double speed;
+    };
+    std::vector<Choice> choices;
+    double total_work = 0;  // padded pair-groups over speed: wave time, arbitrary unit
+    for (size_t a = 0; a < cls.size(); a++) {
+        for (size_t b = a; b < cls.size(); b++) {
+            bool same = a == b;
+            if (same && cls[a].count < 2)
+                continue;
+            int best = 0;
+            double best_cost = 1e300, best_speed = 1;
+            const int bucket = wrap_bucket(cls[b].r / cls[a].r);
+            const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
+            for (int v = 0; v < nv; v++) {
+                // measured speeds weigh the default shapes against each other; the
+                // staged-tile shapes time well on uniform synthetic tiles but lose on
+                // skewed instances, so they are used only when pinned
+                const VariantInfo &V = variant_info(v);
+                if (single ? V.multi < 0
+                           : (pinned >= 0 ? v != pinned : !V.default_choice))
+                    continue;
+                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : V.speed;
+                if (!(speed > 0))
+                    continue;
+                const uint32_t bi = V.bi, bj = V.bj;
+                uint64_t cnt;
+                tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
+                double cost = (double)cnt * bi * bj / speed;
+                // prefer larger tiles on ties (more reuse per loaded group)
+                if (cost < best_cost) {  // variants are listed largest tile first
+                    best_cost = cost;
+                    best = v;
+                    best_speed = speed;
+                }
+            }
+            const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
+            uint64_t cnt;
+            tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
+            double pairs = same ? 0.5 * cls[a].count * (cls[a].count - 1.0) : (double)cls[a].count * cls[b].count;
+            plan.slot_pairs += pairs * 3.0 * cls[b].r;
+            total_work += (double)cnt * bi * bj * (3.0 * cls[b].r / kSlotsPerGroup) / best_speed;
+            choices.push_back({a, b, best, best_speed});
+        }
+    }
+    // every item should take about the same time: work_per_item of wave time
+    const double work_per_item = total_work / (double)std::max<uint64_t>(target_items, 1);
+    std::vector<std::pair<uint32_t, uint32_t>> tiles;
+    for (const Choice &ch : choices) {
+        const Cls &A = cls[ch.a], &B = cls[ch.b];
+        bool same = ch.a == ch.b;
+        const VariantInfo &V = variant_info(ch.v);
+        const uint32_t bi = V.bi, bj = V.bj;
+        tiles.clear();
+        uint64_t cnt;
+        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
+        const uint32_t Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+        const uint32_t Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
+        const bool rows = V.row_resident;
+        // row-resident items walk row groups (each meeting Gb / Ga column
+        // groups); staged items walk column groups in stages of kStageGroups
+        const uint32_t span = rows ? Ga : Gb;
+        const uint64_t unit = rows ? (uint64_t)(Gb / Ga) : 1;
+        // an item visits plen * unit groups of each of its tile's pairs; it
+        // should hold about work_per_item, and at least min_steps groups
+        const uint32_t align = V.step;
+        const double min_steps = (double)std::max<uint32_t>(8 * align, kMinPieceGroups);
+        const double steps = std::max(work_per_item / ((double)bi * bj / ch.speed), min_steps);
+        double pieces_d = std::ceil((double)span * unit / steps);
+        // Locality: one range of every map of the class pair should stay in
+        // the last-level caches while the tiles that share it run, so ranges
+        // shrink until that working set is at most kLocalityBytes.
+        const double ws = 32.0 * span * ((double)A.count + (double)B.count * unit);
+        pieces_d = std::max(pieces_d, std::ceil(ws / kLocalityBytes));
+        // ranges of at least one step of the shape and min_steps groups of work
+        pieces_d = std::min(pieces_d, std::floor((double)span / align));
+        pieces_d = std::min(pieces_d, std::floor((double)span * unit / min_steps));
+        uint32_t pieces = (uint32_t)std::max(1.0, pieces_d);
+        // equal range lengths (a multiple of `align`), the last one shorter
+        uint32_t plen = (span + pieces - 1) / pieces;
+        plen = (plen + align - 1) / align * align;
+        pieces = (span + plen - 1) / plen;
+        // range-major order: all tiles of range k before range k + 1, so the
+        // waves running at one time share one range of the maps
+        for (uint32_t k = 0; k < pieces; k++) {
+            for (auto &t : tiles) {
+                uint64_t c0 = (uint64_t)k * plen, c1 = std::min<uint64_t>(span, c0 + plen);
+                if (c1 <= c0)
+                    continue;
+                WorkItem w;
+                w.row0 = A.start + t.first * bi;
+                w.col0 = B.start + t.second * bj;
+                w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
+                w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
+                w.c0 = (uint32_t)c0;
+                w.c1 = (uint32_t)c1;
+                w.row_groups = Ga;
+                w.col_groups = Gb;
+                w.inst = (uint16_t)inst;
+                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u) | (V.multi >= 0 ? (uint32_t)V.multi << 2 : 0u));
+                plan.by_variant[ch.v].push_back(w);
+            }
+        }
+    }
+    for (auto &v : plan.by_variant)
+        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+}
+
+std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first)
+{
+    std::vector<Cls> out;
+    for (const Cls &c : cls) {
+        uint32_t e = c.start + c.count;
+        if (e <= first)
+            continue;
+        uint32_t s = std::max(c.start, first);
+        out.push_back({c.r, s, e - s});
+    }
+    return out;
+}
+
+
+}  // namespace bm

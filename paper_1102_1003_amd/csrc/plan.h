@@ -1,0 +1,93 @@
+// Compare work planning (host only, no HIP): the work-item layout the compare
+// kernels read, the catalogue of tile shapes, and the planner that cuts the
+// pairs of width classes into tiles and group ranges (Sec. III-B, III-C).
+#pragma once
+
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+namespace bm {
+
+// Slots are stored bit-sliced: a "group" is 32 consecutive slots held as
+// 8 uint32 planes (planes 0..6: code bits, plane 7: indicator bits).
+constexpr uint32_t kSlotsPerGroup = 32;
+constexpr uint32_t kWordsPerGroup = 8;
+// Staged compare kernels: groups staged per step.
+constexpr uint32_t kStageGroups = 4;
+
+// One unit of compare work: a tile of row maps (narrower width class) against
+// a tile of column maps (wider or equal class).  Two loop orders exist:
+//  - staged tiles walk column groups c in [c0, c1) and meet row group c mod G_row;
+//  - the other shapes walk row groups h in [c0, c1) and, for each, every
+//    column group h + u G_row, u = 0 .. G_col / G_row - 1 (the Fig. 1 wrap).
+struct WorkItem {
+    uint32_t row0;        // first sorted index of the row tile
+    uint32_t col0;        // first sorted index of the column tile
+    uint16_t nrow;        // valid rows
+    uint16_t ncol;        // valid columns
+    uint32_t c0, c1;      // group range (see above)
+    uint32_t row_groups;  // G_row = 3 r_row / 32
+    uint32_t col_groups;  // G_col = 3 r_col / 32
+    uint16_t inst;        // instance (descriptor index)
+    uint16_t flags;       // bit 0: same width class -> emit only row < col; bit 1: walks row groups;
+                          // bits 2..4: body of the single-launch kernel
+};
+static_assert(sizeof(WorkItem) == 32, "work item layout");
+
+// A compare tile shape.  The kernels for shape v are listed in the same order
+// in the compare kernel table.
+struct VariantInfo {
+    uint32_t bi, bj;      // rows x columns of a tile
+    bool row_resident;    // walks row groups (else staged column groups)
+    uint32_t step;        // group ranges of its items start and end at multiples of this
+    int multi;            // body code in the single-launch kernel (0..3), -1 if it has none
+    bool default_choice;  // offered to the planner unless a shape is pinned
+    float speed;          // relative group-pair rate of an unpadded tile (planner weight)
+};
+constexpr int kVariantCount = 19;
+const VariantInfo &variant_info(int v);
+
+// Measured speeds are kept per wrap ratio G_col / G_row: 1 | 2..8 | >= 16.
+constexpr int kWrapBuckets = 3;
+inline int wrap_bucket(uint32_t ratio) { return ratio <= 1 ? 0 : (ratio <= 8 ? 1 : 2); }
+
+// Compare work is split into group ranges whose working set (that range of
+// every map of a class pair) fits in the last-level caches (256 MB Infinity
+// Cache, 8 x 4 MB L2).
+constexpr double kLocalityBytes = 64.0 * (1 << 20);
+// Shortest range, in steps of the shape (at least kMinPieceGroups groups).
+constexpr uint32_t kMinPieceGroups = 64;
+
+struct Cls {
+    uint32_t r, start, count;  // width r; sorted-index range [start, start + count)
+};
+
+struct Plan {
+    std::vector<std::vector<WorkItem>> by_variant;
+    double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
+};
+
+// Groups an item visits (longest first gives a better tail).
+uint64_t item_cost(const WorkItem &w);
+
+// Tiles (I, J) of bi x bj over classes A (rows) and B (columns); within one
+// class only tiles holding some row < column.
+void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
+               std::vector<std::pair<uint32_t, uint32_t>> *out, uint64_t *count);
+
+// Plans every pair of the classes `cls` (sorted by width): one shape per class
+// pair, chosen to minimise padded work over speed (measured `speeds`
+// [v * kWrapBuckets + bucket] when given, else the catalogue's); each tile's
+// group range is cut into ranges sized for balance (about `target_items`
+// items in all) and for cache locality, emitted range-major, longest first.
+// single: 0 = any default shape (one launch per shape); 1 = shapes of the
+// single-launch kernel only.  pinned >= 0 forces that shape (single == 0 only).
+void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
+                  const std::vector<float> *speeds, int single, int pinned);
+
+// Classes restricted to sorted indices >= first.
+std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first);
+
+
+}  // namespace bm

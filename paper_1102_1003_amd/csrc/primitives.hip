@@ -9,7 +9,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kScanItems = 8;
 constexpr uint64_t kScanTile = kBlock * kScanItems;  // 2048 elements per block
-constexpr int kRadixTile = 4096;                    // elements per wave tile (64 rounds of 64)
+constexpr int kRadixTile = 4096;                    // elements per workgroup tile
 
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
 {
@@ -148,68 +148,125 @@ hipError_t scan_rec(const In *in, Out *out, uint64_t n, char *tmp, hipStream_t s
 }
 
 // ---------------------------------------------------------------- radix sort
+// One tile of kRadixTile consecutive elements per workgroup; each of its four
+// wavefronts owns a quarter of the tile.  The digit of a pass has `bits` bits
+// (at most 8), so a pass has 2^bits buckets.
 
-__global__ void radix_hist_kernel(const uint32_t *keys, uint64_t n, int shift, uint32_t *hist, uint32_t tiles)
+__global__ __launch_bounds__(256) void radix_hist_kernel(const uint32_t *keys, uint64_t n, int shift, int bits,
+                                                         uint32_t *hist, uint32_t tiles)
 {
-    __shared__ uint32_t h[4][256];
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = lane; i < 256; i += 64)
-        h[w][i] = 0;
+    __shared__ uint32_t h[256];
+    const uint32_t nb = 1u << bits, mask = nb - 1u;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        h[i] = 0;
     __syncthreads();
-    uint32_t t = blockIdx.x * 4 + w;
-    if (t < tiles) {
-        uint64_t base = (uint64_t)t * kRadixTile;
-        for (int r = 0; r < kRadixTile / 64; r++) {
-            uint64_t idx = base + (uint64_t)r * 64 + lane;
-            if (idx < n)
-                atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
-        }
+    const uint32_t t = blockIdx.x;
+    const uint64_t base = (uint64_t)t * kRadixTile;
+    for (int r = 0; r < kRadixTile / 256; r++) {
+        uint64_t idx = base + (uint64_t)r * 256 + threadIdx.x;
+        if (idx < n)
+            atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    if (t < tiles)
-        for (int i = lane; i < 256; i += 64)
-            hist[(uint64_t)i * tiles + t] = h[w][i];
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        hist[(uint64_t)i * tiles + t] = h[i];
 }
 
-// Each wavefront re-reads its tile in order and scatters every element to
-// (bucket offset of its tile) + (rank among equal digits seen so far), which
-// keeps the sort stable.  Ranks within 64 lanes come from 8 ballots.
-__global__ void radix_scatter_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t n, int shift,
-                                     const uint32_t *hoff, uint32_t tiles, uint32_t *ko, uint32_t *vo)
+// Stable scatter of one tile.  (1) Every wavefront ranks its quarter in input
+// order: within 64 lanes by `bits` ballots, across rounds by a running count
+// per digit.  (2) The block turns the per-wave counts into the tile's bucket
+// starts.  (3) Elements go to LDS in (digit, input order) order.  (4) Threads
+// write consecutive LDS positions, so each bucket's run of the tile leaves
+// as contiguous stores at (global offset of the tile's bucket) + (position in
+// the run).
+__global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t n,
+                                                            int shift, int bits, const uint32_t *hoff, uint32_t tiles,
+                                                            uint32_t *ko, uint32_t *vo)
 {
-    __shared__ uint32_t cnt[4][256];
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t t = blockIdx.x * 4 + w;
-    if (t < tiles)
-        for (int i = lane; i < 256; i += 64)
-            cnt[w][i] = hoff[(uint64_t)i * tiles + t];
+    constexpr int kQuarter = kRadixTile / 4;
+    constexpr int kRounds = kQuarter / 64;
+    __shared__ uint32_t sk[kRadixTile], sv[kRadixTile];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t lstart[256], gbase[256];
+    const uint32_t nb = 1u << bits, mask = nb - 1u;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < 4 * 256; i += blockDim.x)
+        (&wcnt[0][0])[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        gbase[i] = hoff[(uint64_t)i * tiles + t];
     __syncthreads();
-    if (t >= tiles)
-        return;
-    uint64_t base = (uint64_t)t * kRadixTile;
-    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kRadixTile / 64; r++) {
+    const uint64_t base = (uint64_t)t * kRadixTile + (uint64_t)w * kQuarter;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t kk[kRounds], vv[kRounds], rk[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
         uint64_t idx = base + (uint64_t)r * 64 + lane;
         bool valid = idx < n;
         uint32_t k = valid ? keys[idx] : 0u;
-        uint32_t v = valid ? vals[idx] : 0u;
-        uint32_t d = (k >> shift) & 255u;
+        kk[r] = k;
+        vv[r] = valid ? vals[idx] : 0u;
+        uint32_t d = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
+        for (int b = 0; b < bits; b++) {
             uint64_t bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        uint32_t rank = __popcll(peers & lt);
-        uint32_t start = cnt[w][d];
-        if (valid) {
-            ko[start + rank] = k;
-            vo[start + rank] = v;
+        uint32_t start = wcnt[w][d];
+        rk[r] = valid ? start + (uint32_t)__popcll(peers & lt) : 0xFFFFFFFFu;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && __popcll(peers & lt) == 0)
+            wcnt[w][d] = start + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // bucket starts of the tile (exclusive scan over digits of the tile's
+    // counts) and, per digit, the offset of each wavefront inside its bucket
+    if (threadIdx.x < 64) {
+        uint32_t carry = 0;
+        for (uint32_t d0 = 0; d0 < nb; d0 += 64) {
+            uint32_t d = d0 + lane;
+            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+            if (d < nb) {
+                c0 = wcnt[0][d]; c1 = wcnt[1][d]; c2 = wcnt[2][d]; c3 = wcnt[3][d];
+            }
+            uint32_t tot = c0 + c1 + c2 + c3;
+            uint32_t incl = tot;
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o)
+                    incl += y;
+            }
+            if (d < nb) {
+                uint32_t st = carry + incl - tot;
+                lstart[d] = st;
+                wcnt[0][d] = st;
+                wcnt[1][d] = st + c0;
+                wcnt[2][d] = st + c0 + c1;
+                wcnt[3][d] = st + c0 + c1 + c2;
+            }
+            carry += __shfl(incl, 63, 64);
         }
-        __builtin_amdgcn_wave_barrier();
-        if (valid && rank == 0)
-            cnt[w][d] = start + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; r++) {
+        if (rk[r] != 0xFFFFFFFFu) {
+            uint32_t d = (kk[r] >> shift) & mask;
+            uint32_t pos = wcnt[w][d] + rk[r];
+            sk[pos] = kk[r];
+            sv[pos] = vv[r];
+        }
+    }
+    __syncthreads();
+    const uint64_t tile0 = (uint64_t)t * kRadixTile;
+    const uint32_t cnt = (uint32_t)((n - tile0) < (uint64_t)kRadixTile ? (n - tile0) : (uint64_t)kRadixTile);
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        uint32_t k = sk[i];
+        uint32_t d = (k >> shift) & mask;
+        uint32_t o = gbase[d] + (i - lstart[d]);
+        ko[o] = k;
+        vo[o] = sv[i];
     }
 }
 
@@ -264,29 +321,33 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32
     if (n <= 1 || key_bits <= 0)
         return hipSuccess;
     uint32_t tiles = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
-    uint64_t h = (uint64_t)tiles * 256;
     char *base = reinterpret_cast<char *>(tmp);
     uint32_t *hist = reinterpret_cast<uint32_t *>(base);
-    uint32_t *hoff = reinterpret_cast<uint32_t *>(base + align256(h * sizeof(uint32_t)));
-    char *stmp = base + 2 * align256(h * sizeof(uint32_t));
-    uint32_t blocks = (tiles + 3) / 4;
+    uint32_t *hoff = reinterpret_cast<uint32_t *>(base + align256((uint64_t)tiles * 256 * sizeof(uint32_t)));
+    char *stmp = base + 2 * align256((uint64_t)tiles * 256 * sizeof(uint32_t));
     uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
-    int passes = 0;
-    for (int shift = 0; shift < key_bits; shift += 8, passes++) {
-        radix_hist_kernel<<<blocks, kBlock, 0, s>>>(ka, n, shift, hist, tiles);
+    // as few passes as 8-bit digits need, with the bits spread evenly over
+    // them: fewer buckets per pass give longer contiguous runs per tile
+    const int passes = (key_bits + 7) / 8;
+    int shift = 0;
+    for (int p = 0; p < passes; p++) {
+        const int bits = (key_bits - shift + (passes - p) - 1) / (passes - p);
+        const uint64_t h = (uint64_t)tiles << bits;
+        radix_hist_kernel<<<tiles, kBlock, 0, s>>>(ka, n, shift, bits, hist, tiles);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
         e = exclusive_scan_u32(hist, hoff, h, stmp, s);
         if (e != hipSuccess)
             return e;
-        radix_scatter_kernel<<<blocks, kBlock, 0, s>>>(ka, va, n, shift, hoff, tiles, kb, vb);
+        radix_scatter_kernel<<<tiles, kBlock, 0, s>>>(ka, va, n, shift, bits, hoff, tiles, kb, vb);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
         uint32_t *t;
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
+        shift += bits;
     }
     if (passes & 1) {
         hipError_t e = hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);

@@ -1,0 +1,106 @@
+// Host-side checker of the compare work planner (built with g++ by
+// tests/test_planner.py; no GPU).  It plans the pairs of a list of width
+// classes and verifies every work item against the shape catalogue, then that
+// the items together visit every pair i < j over all 3 max(r_i, r_j) / 32
+// groups of the wider map exactly once (the Fig. 1 wrap included).
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../paper_1102_1003_amd/csrc/plan.h"
+
+using namespace bm;
+
+namespace {
+
+int fail(char *msg, uint32_t len, int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, len, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+}  // namespace
+
+extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *count, uint64_t target, int single,
+                          int pinned, uint32_t inst, char *msg, uint32_t msg_len, uint64_t *n_items)
+{
+    std::vector<Cls> cls;
+    uint32_t n = 0;
+    for (uint32_t c = 0; c < n_cls; c++) {
+        cls.push_back({r[c], n, count[c]});
+        n += count[c];
+    }
+    std::vector<uint32_t> cls_of(n);
+    for (uint32_t c = 0; c < n_cls; c++)
+        for (uint32_t i = 0; i < count[c]; i++)
+            cls_of[cls[c].start + i] = c;
+    Plan plan;
+    plan_classes(cls, inst, target, plan, nullptr, single, pinned);
+    if ((int)plan.by_variant.size() != kVariantCount)
+        return fail(msg, msg_len, 1, "plan has %zu shape lists", plan.by_variant.size());
+    std::vector<uint64_t> cov((uint64_t)n * (n ? n - 1 : 0) / 2, 0);
+    auto pidx = [&](uint64_t i, uint64_t j) { return i * n - i * (i + 1) / 2 + (j - i - 1); };
+    uint64_t items = 0;
+    for (int v = 0; v < kVariantCount; v++) {
+        const VariantInfo &V = variant_info(v);
+        for (const WorkItem &w : plan.by_variant[v]) {
+            items++;
+            if (single && V.multi < 0)
+                return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
+            if (!single && pinned >= 0 && v != pinned)
+                return fail(msg, msg_len, 3, "shape %d while %d is pinned", v, pinned);
+            if (w.inst != inst)
+                return fail(msg, msg_len, 4, "instance %u", w.inst);
+            if (w.nrow < 1 || w.nrow > V.bi || w.ncol < 1 || w.ncol > V.bj)
+                return fail(msg, msg_len, 5, "shape %d tile %u x %u", v, w.nrow, w.ncol);
+            if ((uint64_t)w.row0 + w.nrow > n || (uint64_t)w.col0 + w.ncol > n)
+                return fail(msg, msg_len, 6, "tile outside the maps");
+            const uint32_t a = cls_of[w.row0], b = cls_of[w.col0];
+            if (cls_of[w.row0 + w.nrow - 1] != a || cls_of[w.col0 + w.ncol - 1] != b || a > b)
+                return fail(msg, msg_len, 7, "tile spans classes or rows wider than columns");
+            const bool same = a == b;
+            if (((w.flags & 1u) != 0) != same || ((w.flags & 2u) != 0) != V.row_resident)
+                return fail(msg, msg_len, 8, "flags 0x%x for shape %d", w.flags, v);
+            const uint32_t code = (w.flags >> 2) & 7u;
+            if (code != (V.multi >= 0 ? (uint32_t)V.multi : 0u) || (w.flags >> 5) != 0)
+                return fail(msg, msg_len, 9, "body code %u for shape %d", code, v);
+            const uint32_t Ga = 3 * r[a] / kSlotsPerGroup, Gb = 3 * r[b] / kSlotsPerGroup;
+            if (w.row_groups != Ga || w.col_groups != Gb || Gb % Ga != 0)
+                return fail(msg, msg_len, 10, "group counts %u / %u", w.row_groups, w.col_groups);
+            const uint32_t span = V.row_resident ? Ga : Gb;
+            if (!(w.c0 < w.c1 && w.c1 <= span) || w.c0 % V.step != 0 || (w.c1 % V.step != 0 && w.c1 != span))
+                return fail(msg, msg_len, 11, "range [%u, %u) of %u, step %u", w.c0, w.c1, span, V.step);
+            const uint64_t unit = V.row_resident ? Gb / Ga : 1;
+            for (uint32_t i = 0; i < w.nrow; i++)
+                for (uint32_t j = 0; j < w.ncol; j++) {
+                    const uint32_t p = w.row0 + i, q = w.col0 + j;
+                    if (same && p >= q)
+                        continue;
+                    if (p >= q)
+                        return fail(msg, msg_len, 12, "pair (%u, %u) out of order", p, q);
+                    cov[pidx(p, q)] += (uint64_t)(w.c1 - w.c0) * unit;
+                }
+        }
+    }
+    for (uint32_t p = 0; p < n; p++)
+        for (uint32_t q = p + 1; q < n; q++) {
+            const uint64_t want = 3ull * r[cls_of[q]] / kSlotsPerGroup;
+            if (cov[pidx(p, q)] != want)
+                return fail(msg, msg_len, 13, "pair (%u, %u) visits %llu groups, not %llu", p, q,
+                            (unsigned long long)cov[pidx(p, q)], (unsigned long long)want);
+        }
+    double sp = 0;
+    for (uint32_t a = 0; a < n_cls; a++)
+        for (uint32_t b = a; b < n_cls; b++) {
+            double pairs = a == b ? 0.5 * count[a] * (count[a] - 1.0) : (double)count[a] * count[b];
+            sp += pairs * 3.0 * r[b];
+        }
+    if (sp != plan.slot_pairs)
+        return fail(msg, msg_len, 14, "slot pairs %.0f, expected %.0f", plan.slot_pairs, sp);
+    *n_items = items;
+    return 0;
+}

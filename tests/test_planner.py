@@ -1,0 +1,111 @@
+"""The compare work planner, checked on the CPU: every work item fits its tile
+shape and the kernels' range rules, and the items of a plan visit every pair
+over all groups of the wider map exactly once (Fig. 1's wrap included)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import datagen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1102_1003_amd", "csrc")
+N_SHAPES = 19
+CU64 = 256 * 64     # items a full MI355X plan aims at
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("plan") / "libplancheck.so")
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", os.path.join(CSRC, "plan.cpp"),
+           os.path.join(ROOT, "tests", "planner_check.cpp"), "-o", out]
+    subprocess.run(cmd, check=True)
+    lib = ctypes.CDLL(out)
+    lib.plan_check.restype = ctypes.c_int
+    lib.plan_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_uint32,
+                               ctypes.POINTER(ctypes.c_uint64)]
+
+    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0):
+        r = np.ascontiguousarray(widths, dtype=np.uint32)
+        c = np.ascontiguousarray(counts, dtype=np.uint32)
+        msg = ctypes.create_string_buffer(256)
+        n_items = ctypes.c_uint64(0)
+        st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst, msg, 256,
+                            ctypes.byref(n_items))
+        assert st == 0, f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned})"
+        return n_items.value
+    return check
+
+
+def widths_of(m, sizes):
+    """r_i = max(r_0, 2^ceil(log2 2|S_i|)), r_0 = max(128, 2^s), s = min{s : m <= 127 2^s}."""
+    s = 0
+    while m > 127 * (1 << s):
+        s += 1
+    r0 = max(128, 1 << s)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    r = np.full(sizes.size, r0, dtype=np.int64)
+    big = sizes > 0
+    r[big] = np.maximum(r0, 1 << np.ceil(np.log2(2 * sizes[big])).astype(np.int64))
+    return r
+
+
+def classes(r):
+    vals, counts = np.unique(np.sort(r), return_counts=True)
+    return vals, counts
+
+
+def test_large_instance_all_pairs(checker):
+    off, _ = datagen.LARGE.sets()
+    vals, counts = classes(widths_of(datagen.LARGE.m, np.diff(off.astype(np.int64))))
+    for single in (0, 1):
+        assert checker(vals, counts, single=single) > 0
+
+
+def test_serving_test_queries(checker):
+    # the queries of the continuous-batching test, planned as the server does
+    probs, _ = datagen.zipf_probs(500, 1.1, 0.05, seed=17)
+    off, _ = datagen.sets_from_probs(30_000, probs, seed=17)
+    r = widths_of(30_000, np.diff(off.astype(np.int64)))
+    rng = np.random.default_rng(5)
+    ks = [int(round(np.exp(rng.uniform(np.log(2), np.log(500))))) for _ in range(60)]
+    queries = [rng.choice(500, size=k, replace=False) for k in ks]
+    for nq in (1, 3, 6):
+        for j, q in enumerate(queries):
+            vals, counts = classes(r[q])
+            checker(vals, counts, target=CU64 // nq + 64, single=1, inst=j)
+
+
+def test_serving_instance_queries(checker):
+    w = datagen.SERVING
+    probs, _ = datagen.zipf_probs(w.n, w.alpha, w.density, w.seed)
+    r = widths_of(w.m, np.round(probs * w.m))       # expected sizes: widths as the build would pick
+    rng = np.random.default_rng(1)
+    for k in (2, 16, 64, 256):
+        q = rng.choice(w.n, size=k, replace=False)
+        vals, counts = classes(r[q])
+        for single in (0, 1):
+            checker(vals, counts, single=single)
+
+
+@pytest.mark.parametrize("pinned", range(N_SHAPES))
+def test_every_shape_pinned(checker, pinned):
+    rng = np.random.default_rng(100 + pinned)
+    for _ in range(4):
+        n_cls = int(rng.integers(1, 5))
+        vals = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536], size=n_cls, replace=False))
+        counts = rng.integers(1, 300, size=n_cls)
+        checker(vals, counts, target=int(rng.integers(64, 20000)), pinned=pinned)
+
+
+def test_edge_class_lists(checker):
+    checker([128], [2])                     # one pair
+    checker([128], [1])                     # no pair
+    checker([128, 1 << 20], [1, 1])         # extreme wrap
+    checker([128, 256], [300, 1], single=1)
+    checker([1 << 16], [129], single=1)     # ragged 128-row tiles
+    for single in (0, 1):
+        checker([128, 512, 4096, 1 << 17], [1000, 37, 5, 2], single=single, target=17)
