@@ -27,6 +27,40 @@ PEAK_HBM_GBS = 8.0e3
 OPS_PER_GROUP_PAIR = 9                        # bit-sliced compare of 32 slot pairs
 SLOTS_PER_GROUP = 32
 METRIC = "item-pair supports/sec + achieved HBM GB/s, BatMap vs bitmap/MFMA, exact"
+COPY_BYTES = 1 << 30
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "compare_large-zipf_counters.md")
+# sources whose change invalidates measured counters of the compare
+TRAFFIC_SOURCES = ["paper_1102_1003_amd/csrc/compare.hip", "paper_1102_1003_amd/csrc/plan.cpp",
+                   "paper_1102_1003_amd/csrc/plan.h"]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes of one all-pairs compare call from the committed counter summary, or None when the
+    summary is missing or was taken on other compare sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources digest") != sources_digest():
+        return None
+    try:
+        return float(vals["HBM bytes per compare call"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -48,6 +82,8 @@ def main():
                          "resident serving instance; dense-sweep: BatMap vs int8-MFMA bitmap across densities; "
                          "batch: 64 uneven instances in one graph-captured launch vs one call per instance")
     ap.add_argument("--instances", type=int, default=64, help="batch: number of uneven instances")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first (the reference dispatch of a counter run)")
     ap.add_argument("--queries", type=int, default=240, help="serving: queries per arrival rate")
     ap.add_argument("--densities", default="0.0001,0.0005,0.001,0.002,0.005,0.01,0.02,0.05,0.10,0.20")
     args = ap.parse_args()
@@ -78,6 +114,14 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     torch.cuda.set_stream(stream)
+    if args.calibrate_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE scale the counters of the compare
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     d_rows = torch.from_numpy(rows.view(np.int64)).to(dev)
     d_items = torch.from_numpy(items.view(np.int32)).to(dev)
     d_off = torch.from_numpy(off.view(np.int64)).to(dev)
@@ -221,7 +265,7 @@ def main():
                                f"{w.density:.0%} mean density, sigma={sigma}, transactions resident in HBM",
                    "m": w.m, "n": w.n, "nnz": int(tids.size), "sigma": sigma, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
+                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": measured_traffic(),
                      "kernel": "compare_kernel (all tile variants of one all-pairs call)",
                      "algorithmic_ops_per_call": ops},
         "cpu_baseline": cpu,

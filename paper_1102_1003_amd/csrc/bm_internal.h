@@ -97,7 +97,10 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32
 
 // Ingest.
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s);
+// Sets bit 0 of *flag when an item id is >= n.
 hipError_t launch_check_items(const uint32_t *items, uint64_t nnz, uint32_t n, uint32_t *flag, hipStream_t s);
+// Sets bit 1 of *flag when off[0] != 0, bit 2 when off[0..m] decreases.
+hipError_t launch_check_offsets(const uint64_t *off, uint32_t m, uint32_t *flag, hipStream_t s);
 hipError_t launch_mark_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t *keep,
                             uint32_t *n_dup, hipStream_t s);
 hipError_t launch_compact_pairs(const uint32_t *keys, const uint32_t *vals, const uint32_t *keep,

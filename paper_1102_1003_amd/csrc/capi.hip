@@ -142,6 +142,11 @@ struct bm_context {
     std::string err;
     DevBuf<uint32_t> counter;  // persistent-kernel work counter
     std::shared_ptr<AllocStream> as;  // stream-ordered allocation on `stream` (null: plain hipMalloc)
+    // pinned staging of work lists: uploads are asynchronous; `staged` marks
+    // the end of the last upload, before which the buffer is not rewritten
+    void *h_stage = nullptr;
+    uint64_t h_stage_bytes = 0;
+    hipEvent_t staged = nullptr;
     // one persistent multi-shape launch per compare (else one launch per tile shape)
     bool persistent = false;
     uint32_t grid = 0;  // its workgroups
@@ -337,6 +342,12 @@ int forced_variant()
 bool use_persistent(const bm_context *ctx) { return ctx->persistent && forced_variant() < 0; }
 
 
+// Largest index whose all-pairs plan is made during its build.
+constexpr uint32_t kPlanAtBuild = 4096;
+
+// Items a plan aims at: about 64 per CU.
+uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
+
 bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
                       std::vector<std::pair<int, uint32_t>> &ranges)
 {
@@ -360,9 +371,43 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
     }
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total) {
-        HIPC(ctx, hipMemcpyAsync(dst.p, flat.data(), total * sizeof(WorkItem), hipMemcpyHostToDevice, ctx->stream));
-        HIPC(ctx, hipStreamSynchronize(ctx->stream));  // `flat` is released on return
+        const uint64_t bytes = total * sizeof(WorkItem);
+        if (ctx->staged)
+            HIPC(ctx, hipEventSynchronize(ctx->staged));  // the previous upload has left the buffer
+        else
+            HIPC(ctx, hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+        if (ctx->h_stage_bytes < bytes) {
+            if (ctx->h_stage)
+                HIPC(ctx, hipHostFree(ctx->h_stage));
+            ctx->h_stage = nullptr;
+            ctx->h_stage_bytes = 0;
+            const uint64_t want = std::max<uint64_t>(bytes + bytes / 2, 1 << 20);
+            HIPC(ctx, hipHostMalloc(&ctx->h_stage, want));
+            ctx->h_stage_bytes = want;
+        }
+        memcpy(ctx->h_stage, flat.data(), bytes);
+        HIPC(ctx, hipMemcpyAsync(dst.p, ctx->h_stage, bytes, hipMemcpyHostToDevice, ctx->stream));
+        HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
     }
+    return BM_OK;
+}
+
+// The all-pairs plan of an index over sorted indices >= first, made unless
+// the index holds it for the context's current tile speeds.
+bm_status ensure_plan(bm_index *idx, uint32_t first)
+{
+    bm_context *ctx = idx->ctx;
+    if (idx->planned_first == first && idx->planned_gen == ctx->tune_gen)
+        return BM_OK;
+    Plan plan;
+    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, &ctx->speeds,
+                 use_persistent(ctx) ? 1 : 0, forced_variant());
+    bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
+    if (st != BM_OK)
+        return st;
+    idx->planned_first = first;
+    idx->planned_gen = ctx->tune_gen;
+    idx->planned_slot_pairs = plan.slot_pairs;
     return BM_OK;
 }
 
@@ -383,7 +428,6 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
     return BM_OK;
 }
 
-uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
 
 // ------------------------------------------------------------- build steps
 
@@ -605,6 +649,15 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift, idx->r0,
                                     idx->arena.p, s));
         }
+        // the all-pairs plan depends only on the width classes: make and
+        // upload it on the host while the construction kernels run (indexes of
+        // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
+        // and planning all their pairs takes longer than building them)
+        if (attempt == 0 && n - idx->first_built <= kPlanAtBuild) {
+            st = ensure_plan(idx, idx->first_built);
+            if (st != BM_OK)
+                return st;
+        }
         uint32_t h[4] = {0, 0, 0, 0};
         st = read_back(ctx, h, counters.p, 16);
         if (st != BM_OK)
@@ -672,16 +725,10 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
         Span sp(ctx, PH_FILL);
         HIPC(ctx, fill_u32(out, n_pairs(idx->n), 0, ctx->stream));
     }
-    if (idx->planned_first != first || idx->planned_gen != ctx->tune_gen) {
-        Plan plan;
-        plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, &ctx->speeds,
-                     use_persistent(ctx) ? 1 : 0, forced_variant());
-        bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
+    {
+        bm_status st = ensure_plan(idx, first);
         if (st != BM_OK)
             return st;
-        idx->planned_first = first;
-        idx->planned_gen = ctx->tune_gen;
-        idx->planned_slot_pairs = plan.slot_pairs;
     }
     ctx->slot_pairs = idx->planned_slot_pairs;
     {
@@ -713,16 +760,17 @@ hipError_t bm_batch::enqueue(hipStream_t s)
 namespace {
 
 // ------------------------------------------------------------------ autotuner
-// Synthetic instance: 4096 row maps of 768 groups (r = 8192) and, per wrap
-// ratio U in {1, 4, 64}, 384 / 96 / 48 column maps of 768 U groups (about
-// 10^9 - 10^10 group pairs each, so launch overhead is negligible).  The
-// column counts are multiples of every column tile width and 4096 of every
-// row tile height, so the tiles carry no padding.  Group contents are
-// arbitrary bits: the compare's cost does not depend on them.
+// Synthetic instance: 4096 row maps of 3072 groups (r = 32768; 400 MB, more
+// than the Infinity Cache holds, like the instances the shapes are picked
+// for) and, per wrap ratio U in {1, 4, 64}, 384 / 96 / 48 column maps of
+// 3072 U groups (5 10^9 - 4 10^10 group pairs each, so launch overhead is
+// negligible).  The column counts are multiples of every column tile width
+// and 4096 of every row tile height, so the tiles carry no padding.  Group
+// contents are arbitrary bits: the compare's cost does not depend on them.
 bm_status autotune(bm_context *ctx, uint32_t reps)
 {
     hipStream_t s = ctx->stream;
-    const uint32_t nrow = 4096, grow = 768, gb = 768;
+    const uint32_t nrow = 4096, grow = 3072, gb = 3072;
     const uint32_t ratios[kWrapBuckets] = {1, 4, 64};
     const uint32_t ncols[kWrapBuckets] = {384, 96, 48};
     std::vector<uint64_t> h_goff;
@@ -768,42 +816,15 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
     bm_status result = BM_OK;
     for (int b = 0; b < kWrapBuckets && result == BM_OK; b++) {
         const uint32_t ncol = ncols[b];
-        Cls A{8192, 0, nrow}, B{8192 * ratios[b], (uint32_t)col_first[b], ncol};
+        Cls A{32768, 0, nrow}, B{32768 * ratios[b], (uint32_t)col_first[b], ncol};
         for (int v = 0; v < nv; v++) {
-            // force variant v on this one class pair
+            // variant v on this one class pair, cut and ordered by the planner
+            // exactly as in a real plan
             Plan plan;
-            plan.by_variant.assign(nv, {});
-            const uint32_t bi = variant_info(v).bi, bj = variant_info(v).bj;
-            std::vector<std::pair<uint32_t, uint32_t>> tiles;
-            uint64_t cnt;
-            tiles_for(A, B, false, bi, bj, &tiles, &cnt);
-            const uint32_t Ga = grow, Gb = grow * ratios[b];
-            const bool rows = variant_info(v).row_resident;
-            const uint32_t span = rows ? Ga : Gb, align = variant_info(v).step;
-            const uint64_t want = (uint64_t)ctx->n_cu * 16;
-            uint32_t pieces = (uint32_t)std::max<uint64_t>(1, (want + tiles.size() - 1) / tiles.size());
-            pieces = std::min<uint32_t>(pieces, span / align);
-            std::vector<WorkItem> list;
-            for (auto &t : tiles) {
-                for (uint32_t k = 0; k < pieces; k++) {
-                    uint64_t c0 = (uint64_t)span * k / pieces / align * align;
-                    uint64_t c1 = (k + 1 == pieces) ? span : (uint64_t)span * (k + 1) / pieces / align * align;
-                    if (c1 <= c0)
-                        continue;
-                    WorkItem w;
-                    w.row0 = A.start + t.first * bi;
-                    w.col0 = B.start + t.second * bj;
-                    w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
-                    w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
-                    w.c0 = (uint32_t)c0;
-                    w.c1 = (uint32_t)c1;
-                    w.row_groups = Ga;
-                    w.col_groups = Gb;
-                    w.inst = 0;
-                    w.flags = rows ? 2u : 0u;
-                    list.push_back(w);
-                }
-            }
+            // (four times the usual item count: no launch tail in the timing)
+            plan_classes({A, B}, 0, 4 * target_items(ctx), plan, nullptr, 0, v, true);
+            const std::vector<WorkItem> &list = plan.by_variant[v];
+            const uint32_t Gb = grow * ratios[b];
             HIPC(ctx, items.ensure(list.size()));
             HIPC(ctx, hipMemcpyAsync(items.p, list.data(), list.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
             HIPC(ctx, launch_compare(items.p, (uint32_t)list.size(), nullptr, d, v, s));  // warm
@@ -913,6 +934,10 @@ void bm_context_destroy(bm_context *ctx)
     ctx->counter.reset();
     if (ctx->as)
         ctx->as->s = nullptr;  // indexes built here release their buffers on the null stream from now on
+    if (ctx->h_stage)
+        (void)hipHostFree(ctx->h_stage);
+    if (ctx->staged)
+        (void)hipEventDestroy(ctx->staged);
     clear_phases(ctx, 0, PH_COUNT - 1);
     for (hipEvent_t e : ctx->event_pool)
         (void)hipEventDestroy(e);
@@ -1116,20 +1141,25 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     idx->n = n_items;
     hipStream_t s = ctx->stream;
 
-    std::vector<uint64_t> roff((size_t)m_txn + 1);
-    if (ptr_kind(offsets) == PTR_DEVICE) {
-        st = read_back(ctx, roff.data(), offsets, ((uint64_t)m_txn + 1) * 8);
+    // Offsets in device memory are used in place and checked by a kernel (only
+    // their last entry, the incidence count, comes back first); host offsets
+    // are checked here and copied in.
+    const bool dev_off = ptr_kind(offsets) == PTR_DEVICE;
+    uint64_t nnz_in = 0;
+    std::vector<uint64_t> roff;
+    if (dev_off) {
+        st = read_back(ctx, &nnz_in, offsets + m_txn, 8);
         if (st != BM_OK)
             return st;
     } else {
-        memcpy(roff.data(), offsets, ((size_t)m_txn + 1) * 8);
+        roff.assign(offsets, offsets + (size_t)m_txn + 1);
+        if (roff[0] != 0)
+            return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+        for (uint32_t b = 0; b < m_txn; b++)
+            if (roff[b + 1] < roff[b])
+                return fail(ctx, BM_EINVAL, "offsets decrease at transaction %u", b);
+        nnz_in = roff[m_txn];
     }
-    if (roff[0] != 0)
-        return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
-    for (uint32_t b = 0; b < m_txn; b++)
-        if (roff[b + 1] < roff[b])
-            return fail(ctx, BM_EINVAL, "offsets decrease at transaction %u", b);
-    uint64_t nnz_in = roff[m_txn];
     if (nnz_in && !items)
         return fail(ctx, BM_EINVAL, "items is null");
     if (nnz_in >= (1ull << 32))
@@ -1140,25 +1170,35 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     DevBuf<uint32_t> keys, vals, k2, v2, flag;
     DevBuf<char> tmp;
     uint64_t N = std::max<uint64_t>(nnz_in, 1);
-    HIPC(ctx, d_roff.alloc((uint64_t)m_txn + 1));
+    const uint64_t *row_off = offsets;
+    if (!dev_off) {
+        HIPC(ctx, d_roff.alloc((uint64_t)m_txn + 1));
+        HIPC(ctx, hipMemcpyAsync(d_roff.p, roff.data(), ((uint64_t)m_txn + 1) * 8, hipMemcpyHostToDevice, s));
+        row_off = d_roff.p;
+    }
     HIPC(ctx, keys.alloc(N));
     HIPC(ctx, vals.alloc(N));
     HIPC(ctx, k2.alloc(N));
     HIPC(ctx, v2.alloc(N));
     HIPC(ctx, flag.alloc(1));
-    HIPC(ctx, hipMemcpyAsync(d_roff.p, roff.data(), ((uint64_t)m_txn + 1) * 8, hipMemcpyHostToDevice, s));
     st = copy_in(ctx, keys.p, items, nnz_in * 4);
     if (st != BM_OK)
         return st;
     HIPC(ctx, fill_u32(flag.p, 1, 0, s));
+    if (dev_off)
+        HIPC(ctx, launch_check_offsets(row_off, m_txn, flag.p, s));
     HIPC(ctx, launch_check_items(keys.p, nnz_in, n_items, flag.p, s));
     uint32_t hflag = 0;
     st = read_back(ctx, &hflag, flag.p, 4);
     if (st != BM_OK)
         return st;
+    if (hflag & 2u)
+        return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+    if (hflag & 4u)
+        return fail(ctx, BM_EINVAL, "offsets decrease");
     if (hflag)
         return fail(ctx, BM_ERANGE, "an item id is >= n_items");
-    HIPC(ctx, launch_expand_rows(d_roff.p, m_txn, vals.p, s));
+    HIPC(ctx, launch_expand_rows(row_off, m_txn, vals.p, s));
     HIPC(ctx, tmp.alloc(std::max(radix_tmp_bytes(N), scan_tmp_bytes(N))));
     HIPC(ctx, radix_sort_pairs(keys.p, vals.p, k2.p, v2.p, nnz_in, bits_for(n_items - 1), tmp.p, s));
     // drop an item repeated within one transaction (now adjacent equal pairs)

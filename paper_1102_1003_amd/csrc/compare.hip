@@ -511,8 +511,9 @@ __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__rest
 
 
 // One persistent launch for items of every shape the single-launch forms use
-// (row-resident 128 x 16 / 12 / 8 / 4, body codes 0..3): the shape travels in
-// the item's flags (bits 2..4) and selects the specialised body.
+// (row-resident 128 x 16, 128 x 12 and 128 x 8 two row groups per step,
+// 128 x 4; body codes 0..3): the shape travels in the item's flags (bits
+// 2..4) and selects the specialised body.
 __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
                                                                            uint32_t n_items,
                                                                            const InstDesc *__restrict__ descs,
@@ -529,8 +530,8 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
         const InstDesc d = descs ? descs[w.inst] : d0;
         switch ((w.flags >> 2) & 7u) {
         case 0: process_rows<2, 16>(w, d); break;
-        case 1: process_rows<2, 12>(w, d); break;
-        case 2: process_rows<2, 8>(w, d); break;
+        case 1: process_rows<2, 12, 2>(w, d); break;
+        case 2: process_rows<2, 8, 2>(w, d); break;
         default: process_rows<2, 4>(w, d); break;
         }
     }
@@ -555,6 +556,7 @@ const Kernels kKernels[] = {
     BM_ROWS(2, 12, 2),   BM_ROWS(2, 8, 2),    BM_ROWS(1, 16, 2),
     BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),
     BM_GP(4, 4),         BM_GP(2, 8),
+    BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),
 };
 static_assert(sizeof(kKernels) / sizeof(kKernels[0]) == kVariantCount, "one kernel entry per tile shape");
 

@@ -39,6 +39,20 @@ __global__ void check_items_kernel(const uint32_t *items, uint64_t nnz, uint32_t
         atomicOr(flag, 1u);
 }
 
+// Row offsets of a transactions CSR: bit 1 when offsets[0] != 0, bit 2 when
+// they decrease somewhere.
+__global__ void check_offsets_kernel(const uint64_t *off, uint32_t m, uint32_t *flag)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool down = false;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += stride)
+        down |= off[b + 1] < off[b];
+    if (down)
+        atomicOr(flag, 4u);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && off[0] != 0)
+        atomicOr(flag, 2u);
+}
+
 __global__ void mark_dups_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t *keep,
                                  uint32_t *n_dup)
 {
@@ -102,6 +116,12 @@ __global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, 
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s)
 {
     expand_rows_kernel<<<blocks_for(m), kBlock, 0, s>>>(row_off, m, row_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_offsets(const uint64_t *off, uint32_t m, uint32_t *flag, hipStream_t s)
+{
+    check_offsets_kernel<<<blocks_for(m, 4096), kBlock, 0, s>>>(off, m, flag);
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <unordered_map>
 
 namespace bm {
 
@@ -17,16 +18,18 @@ const VariantInfo kInfo[kVariantCount] = {
     {128, 32, false, kStageGroups, -1, false, 0.60f},
     {256, 16, false, kStageGroups, -1, false, 0.60f},
     {256, 8, false, kStageGroups, -1, false, 0.60f},
-    // row-resident, 64 R rows x MJ columns
+    // row-resident, 64 R rows x MJ columns, one row group per step
     {128, 16, true, 1, 0, true, 1.00f},
-    {128, 12, true, 1, 1, true, 1.00f},
-    {128, 8, true, 1, 2, true, 0.92f},
+    {128, 12, true, 1, -1, false, 1.00f},
+    {128, 8, true, 1, -1, false, 0.92f},
     {128, 4, true, 1, 3, true, 0.60f},
     {256, 8, true, 1, -1, false, 0.85f},
     {64, 16, true, 1, -1, false, 0.65f},
-    // row-resident, two row groups per step
-    {128, 12, true, 2, -1, false, 1.00f},
-    {128, 8, true, 2, -1, false, 0.95f},
+    // row-resident, two row groups per step (one 64-byte scalar load per
+    // column for both): 128 x 12 and 128 x 8 run at 62 % / 55 % of the VALU
+    // peak on the large Zipf instance against 47 % / 42 % with one
+    {128, 12, true, 2, 1, true, 1.30f},
+    {128, 8, true, 2, 2, true, 1.10f},
     {64, 16, true, 2, -1, false, 0.70f},
     // row-resident, software-pipelined column chunks
     {128, 8, true, 1, -1, false, 0.95f},
@@ -36,6 +39,9 @@ const VariantInfo kInfo[kVariantCount] = {
     // group-parallel small tiles (lanes over group positions)
     {4, 4, true, 64, -1, true, 0.30f},
     {2, 8, true, 64, -1, true, 0.30f},
+    // row-resident, two row groups per step, 16 and 4 columns
+    {128, 16, true, 2, -1, false, 1.20f},
+    {128, 4, true, 2, -1, false, 0.70f},
 };
 
 }  // namespace
@@ -67,8 +73,57 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
     *count = c;
 }
 
+namespace {
+
+// Workgroup b of a launch runs on XCD b mod kXcds, and each XCD has its own
+// L2.  Within each run of equal-cost items, the items of one (range, row
+// tile) group go to one XCD's queue (groups dealt round-robin), and position
+// p of the run takes the next item of queue p mod kXcds; so the column tiles
+// that share a row tile's range run on the XCD that holds those rows.  When a
+// queue runs dry its positions take items from the fullest queue.
+constexpr uint32_t kXcds = 8;
+
+void xcd_order(std::vector<WorkItem> &v)
+{
+    std::vector<WorkItem> out(v.size());
+    std::vector<std::vector<uint32_t>> q(kXcds);
+    std::unordered_map<uint64_t, uint32_t> group_of;
+    size_t s = 0;
+    while (s < v.size()) {
+        size_t e = s + 1;
+        const uint64_t c = item_cost(v[s]);
+        while (e < v.size() && item_cost(v[e]) == c)
+            e++;
+        for (auto &x : q)
+            x.clear();
+        group_of.clear();
+        for (size_t t = s; t < e; t++) {
+            const uint64_t key = ((uint64_t)v[t].c0 << 32) | v[t].row0;
+            auto it = group_of.emplace(key, (uint32_t)group_of.size()).first;
+            q[it->second % kXcds].push_back((uint32_t)t);
+        }
+        std::vector<size_t> head(kXcds, 0);
+        for (size_t p = s; p < e; p++) {
+            uint32_t x = (uint32_t)(p % kXcds);
+            if (head[x] == q[x].size()) {
+                size_t best = 0;
+                for (uint32_t y = 0; y < kXcds; y++)
+                    if (q[y].size() - head[y] > best) {
+                        best = q[y].size() - head[y];
+                        x = y;
+                    }
+            }
+            out[p] = v[q[x][head[x]++]];
+        }
+        s = e;
+    }
+    v.swap(out);
+}
+
+}  // namespace
+
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds, int single, int pinned)
+                  const std::vector<float> *speeds, int single, int pinned, bool cross_only)
 {
     const int nv = kVariantCount;
     plan.by_variant.assign(nv, {});
@@ -83,7 +138,7 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
     for (size_t a = 0; a < cls.size(); a++) {
         for (size_t b = a; b < cls.size(); b++) {
             bool same = a == b;
-            if (same && cls[a].count < 2)
+            if (same && (cls[a].count < 2 || cross_only))
                 continue;
             int best = 0;
             double best_cost = 1e300, best_speed = 1;
@@ -179,8 +234,41 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
             }
         }
     }
-    for (auto &v : plan.by_variant)
-        std::stable_sort(v.begin(), v.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+    // longest first, ties in emission order (range-major).  A plan has few
+    // distinct costs (about one per class pair), so this is a bucket sort.
+    std::vector<WorkItem> sorted;
+    std::vector<uint64_t> costs, item_bucket;
+    std::unordered_map<uint64_t, uint32_t> bucket_of;
+    for (auto &v : plan.by_variant) {
+        if (v.empty())
+            continue;
+        costs.clear();
+        bucket_of.clear();
+        item_bucket.resize(v.size());
+        for (size_t t = 0; t < v.size(); t++) {
+            const uint64_t c = item_cost(v[t]);
+            auto it = bucket_of.emplace(c, (uint32_t)costs.size()).first;
+            if (it->second == costs.size())
+                costs.push_back(c);
+            item_bucket[t] = it->second;
+        }
+        std::vector<uint32_t> order(costs.size()), start(costs.size() + 1, 0);
+        for (uint32_t b = 0; b < costs.size(); b++)
+            order[b] = b;
+        std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return costs[x] > costs[y]; });
+        std::vector<uint32_t> rank(costs.size());
+        for (uint32_t i = 0; i < order.size(); i++)
+            rank[order[i]] = i;
+        for (size_t t = 0; t < v.size(); t++)
+            start[rank[item_bucket[t]] + 1]++;
+        for (size_t b = 0; b < costs.size(); b++)
+            start[b + 1] += start[b];
+        sorted.resize(v.size());
+        for (size_t t = 0; t < v.size(); t++)
+            sorted[start[rank[item_bucket[t]]]++] = v[t];
+        v.swap(sorted);
+        xcd_order(v);
+    }
 }
 
 std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first)

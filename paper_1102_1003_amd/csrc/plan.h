@@ -45,7 +45,7 @@ struct VariantInfo {
     bool default_choice;  // offered to the planner unless a shape is pinned
     float speed;          // relative group-pair rate of an unpadded tile (planner weight)
 };
-constexpr int kVariantCount = 19;
+constexpr int kVariantCount = 21;
 const VariantInfo &variant_info(int v);
 
 // Measured speeds are kept per wrap ratio G_col / G_row: 1 | 2..8 | >= 16.
@@ -83,8 +83,9 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
 // items in all) and for cache locality, emitted range-major, longest first.
 // single: 0 = any default shape (one launch per shape); 1 = shapes of the
 // single-launch kernel only.  pinned >= 0 forces that shape (single == 0 only).
+// cross_only: only pairs of different classes.
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds, int single, int pinned);
+                  const std::vector<float> *speeds, int single, int pinned, bool cross_only = false);
 
 // Classes restricted to sorted indices >= first.
 std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first);
