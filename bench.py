@@ -494,7 +494,8 @@ def batch_mode(args):
             ix.all_pair_supports(o)
     alone()
     alone_s = timed(alone, 5)
-    batch = bm.Batch(ctx, idxs, outs_b)
+    batch = bm.Batch(ctx, idxs, outs_b)      # tries built-in vs autotuned tile speeds on the batch itself
+    trial = batch.plan_trial
     batch.run()
     batch_s = timed(batch.run, 5)
     torch.cuda.synchronize()
@@ -534,6 +535,8 @@ def batch_mode(args):
         "index_build_s": build_s,
         "batch_ms": batch_s * 1e3, "alone_sum_ms": alone_s * 1e3, "speedup_vs_alone": alone_s / batch_s,
         "graph": batch.is_graph,
+        "autotune_trial_ms": {"builtin_speeds": trial[0], "measured_speeds": trial[1],
+                              "kept": "measured" if 0 < trial[1] < trial[0] else "builtin"},
         "batch_tops": ops / batch_s / 1e12, "alone_tops": ops / alone_s / 1e12,
         "frac_of_valu_peak": ops / batch_s / 1e12 / PEAK_VALU_TOPS,
         "exact": {"batch_equals_alone": equal, "closed_form_sum_all": all(closed), "oracle_rows_3_instances": rows_ok},

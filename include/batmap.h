@@ -117,10 +117,13 @@ bm_status bm_synchronize(bm_context *ctx);
  * planner picks one per pair of width classes by padded work divided by the
  * shape's speed.  bm_context_autotune times every shape on synthetic,
  * unpadded tiles at three ratios of column to row width (1, 4, 64), `reps`
- * times each, and keeps the measured rates (group pairs per microsecond) in
- * the context; plans made afterwards use them.  The table can be read and
- * restored (n = shapes x 3 floats) to skip the measurement in later runs.
- * Without a table the planner uses built-in relative speeds. */
+ * times each, through the same planner that cuts real work, and keeps the
+ * measured rates (group pairs per microsecond) in the context.  A batch
+ * created afterwards (bm_batch_create) tries both its plan from these rates
+ * and its plan from the built-in speeds on itself, once each, and keeps the
+ * faster.  Single-index calls and the server plan with the built-in speeds
+ * (relative rates measured on MI355X over real instances).  The table can be
+ * read and restored (n = shapes x 3 floats) to skip the measurement later. */
 bm_status bm_context_autotune(bm_context *ctx, uint32_t reps);
 bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capacity, uint32_t *n_out);
 bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint32_t n);
@@ -177,18 +180,24 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
  * (same context, built with min_support 0) as one work list, longest items
  * first, run by ONE persistent compare launch, and captures the whole
  * sequence (counter reset, output zeroing, compare, corrections) as a HIP
- * graph on the context's stream.  outs[q]: device, n_q(n_q-1)/2 uint32,
- * bound to the batch until bm_batch_destroy; the indexes must outlive it.
- * bm_batch_run replays the graph (asynchronously); when the stream cannot be
- * captured the same kernels are enqueued eagerly. */
+ * graph on the context's stream.  When the context holds autotuned tile
+ * speeds, creation runs the batch twice (plans from built-in and from
+ * measured speeds) and keeps the faster plan; outs then already hold the
+ * result.  outs[q]: device, n_q(n_q-1)/2 uint32, bound to the batch until
+ * bm_batch_destroy; the indexes must outlive it.  bm_batch_run replays the
+ * graph (asynchronously); when the stream cannot be captured the same
+ * kernels are enqueued eagerly. */
 typedef struct bm_batch bm_batch;
 bm_status bm_batch_create(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs,
                           bm_batch **out);
 bm_status bm_batch_run(bm_batch *batch);
 /* 1 when the batch replays a captured graph, 0 when it runs eagerly. */
 int bm_batch_is_graph(const bm_batch *batch);
+/* Times (ms) of the creation trial: the batch with built-in and with measured
+ * tile speeds; both 0 when no trial ran.  The smaller one's plan was kept. */
+bm_status bm_batch_plan_trial(const bm_batch *batch, float *builtin_ms, float *measured_ms);
 void bm_batch_destroy(bm_batch *batch);
-/* create + run + synchronize + destroy. */
+/* create (without the plan trial) + run + synchronize + destroy. */
 bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint32_t count, uint32_t *const *outs);
 
 /* Serving: subset queries (as bm_subset_pair_supports) against one resident

@@ -93,7 +93,7 @@ EXPORTED = [
     "bm_all_pair_supports", "bm_frequent_pairs", "bm_subset_pair_supports", "bm_batch_all_pair_supports",
     "bm_all_pair_supports_dense", "bm_index_export", "bm_context_set_profiling", "bm_context_timings",
     "bm_context_autotune", "bm_context_tile_speeds", "bm_context_set_tile_speeds",
-    "bm_batch_create", "bm_batch_run", "bm_batch_is_graph", "bm_batch_destroy",
+    "bm_batch_create", "bm_batch_run", "bm_batch_is_graph", "bm_batch_plan_trial", "bm_batch_destroy",
     "bm_server_opts_init", "bm_server_create", "bm_server_submit", "bm_server_wait", "bm_server_stats_get",
     "bm_server_destroy",
 ]
@@ -160,6 +160,8 @@ def load_library(path: str = LIB_PATH):
     L.bm_batch_run.argtypes = [vp]
     L.bm_batch_is_graph.restype = i32
     L.bm_batch_is_graph.argtypes = [vp]
+    L.bm_batch_plan_trial.restype = i32
+    L.bm_batch_plan_trial.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.bm_batch_destroy.restype = None
     L.bm_batch_destroy.argtypes = [vp]
     L.bm_server_opts_init.restype = None
@@ -449,6 +451,13 @@ class Batch:
     @property
     def is_graph(self) -> bool:
         return bool(load_library().bm_batch_is_graph(self._h))
+
+    @property
+    def plan_trial(self):
+        """(ms with built-in tile speeds, ms with measured ones) of the creation trial; (0, 0) if none ran."""
+        a, b = ctypes.c_float(0), ctypes.c_float(0)
+        self.ctx.check(load_library().bm_batch_plan_trial(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def run(self):
         self.ctx.check(load_library().bm_batch_run(self._h))

@@ -149,11 +149,16 @@ hipError_t launch_apply_corrections_subset(const uint32_t *pairs, uint64_t n_cor
 hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDesc *descs, const InstDesc &d0,
                           int variant, hipStream_t s);
 uint32_t multi_persistent_grid(uint32_t n_cu);
+// Per-XCD queues of a single-launch work list (see xcd_queues).
+struct XcdQueues {
+    uint32_t off[kXcds + 1];
+};
 // Items of the row-resident single-launch shapes (body codes 0..3) as one
-// persistent launch on s; *counter must be zero.  descs == nullptr: every
-// item uses d0.
-hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                           const InstDesc &d0, uint32_t *counter, uint32_t grid, hipStream_t s);
+// persistent launch on s.  Workgroups drain the queue of their own XCD, then
+// take what is left in the others.  counters[0..kXcds) must be zero.
+// descs == nullptr: every item uses d0.
+hipError_t launch_compare_multi_persistent(const WorkItem *items, const XcdQueues &q, const InstDesc *descs,
+                                           const InstDesc &d0, uint32_t *counters, uint32_t grid, hipStream_t s);
 
 
 // Threshold + compaction.

@@ -285,7 +285,9 @@ struct bm_batch {
     DevBuf<WorkItem> items;
     DevBuf<uint32_t> counter;
     uint32_t n_items = 0, grid = 0;
+    XcdQueues queues{};  // per-XCD queues of `items`
     double slot_pairs = 0;
+    float tuned_ms[2] = {0, 0};  // batch time with catalogue / measured tile speeds (0: not tried)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t enqueue(hipStream_t s);
@@ -365,9 +367,12 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
         flat.insert(flat.end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
     }
     if (use_persistent(ctx) && total) {
-        std::stable_sort(flat.begin(), flat.end(),
-                         [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
-        ranges.assign(1, {-1, (uint32_t)total});
+        // one single launch: ranges hold the per-XCD queue offsets, tagged -1
+        uint32_t off[kXcds + 1];
+        xcd_queues(flat, off);
+        ranges.clear();
+        for (uint32_t x = 0; x <= kXcds; x++)
+            ranges.push_back({-1, off[x]});
     }
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total) {
@@ -400,7 +405,7 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
     if (idx->planned_first == first && idx->planned_gen == ctx->tune_gen)
         return BM_OK;
     Plan plan;
-    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, &ctx->speeds,
+    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
                  use_persistent(ctx) ? 1 : 0, forced_variant());
     bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
     if (st != BM_OK)
@@ -415,9 +420,11 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
                       const InstDesc &d0)
 {
     if (!ranges.empty() && ranges[0].first == -1) {
-        HIPC(ctx, fill_u32(ctx->counter.p, 1, 0, ctx->stream));
-        HIPC(ctx, launch_compare_multi_persistent(items, ranges[0].second, nullptr, d0, ctx->counter.p,
-                                                  ctx->grid, ctx->stream));
+        XcdQueues q;
+        for (uint32_t x = 0; x <= kXcds; x++)
+            q.off[x] = ranges[x].second;
+        HIPC(ctx, fill_u32(ctx->counter.p, kXcds, 0, ctx->stream));
+        HIPC(ctx, launch_compare_multi_persistent(items, q, nullptr, d0, ctx->counter.p, ctx->grid, ctx->stream));
         return BM_OK;
     }
     uint64_t at = 0;
@@ -746,12 +753,12 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
 
 hipError_t bm_batch::enqueue(hipStream_t s)
 {
-    hipError_t e = fill_u32(counter.p, 1, 0, s);
+    hipError_t e = fill_u32(counter.p, kXcds, 0, s);
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         if (n_pairs(idx[q]->n))
             e = fill_u32(outs[q], n_pairs(idx[q]->n), 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(items.p, n_items, descs.p, InstDesc{}, counter.p, grid, s);
+        e = launch_compare_multi_persistent(items.p, queues, descs.p, InstDesc{}, counter.p, grid, s);
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         e = launch_apply_corrections(idx[q]->corr.p, idx[q]->n_corr, outs[q], idx[q]->n, s);
     return e;
@@ -913,7 +920,7 @@ bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
             (void)hipGetLastError();
         }
     }
-    if (ctx->counter.alloc(1) != hipSuccess) {
+    if (ctx->counter.alloc(kXcds) != hipSuccess) {
         (void)hipGetLastError();
         if (ctx->own_stream)
             (void)hipStreamDestroy(ctx->stream);
@@ -1470,7 +1477,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.gb = idx->gb;
     d.pad = 0;
     Plan plan;
-    plan_classes(cls, 0, target_items(ctx), plan, &ctx->speeds, use_persistent(ctx) ? 1 : 0, forced_variant());
+    plan_classes(cls, 0, target_items(ctx), plan, nullptr, use_persistent(ctx) ? 1 : 0, forced_variant());
     std::vector<std::pair<int, uint32_t>> ranges;
     st = upload_plan(idx, plan, idx->sub_work, ranges);
     if (st != BM_OK)
@@ -1497,8 +1504,12 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     return BM_OK;
 }
 
-bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs,
-                          bm_batch **out)
+}  // extern "C"
+
+namespace {
+
+bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs,
+                       bm_batch **out, bool trial)
 {
     if (!ctx)
         return BM_EINVAL;
@@ -1515,7 +1526,6 @@ bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count
         return fail(ctx, BM_ENOMEM, "host allocation");
     b->ctx = ctx;
     std::vector<InstDesc> descs(count);
-    std::vector<WorkItem> flat;
     for (uint32_t q = 0; q < count; q++) {
         bm_index *idx = idxs[q];
         if (!idx || idx->ctx != ctx)
@@ -1527,27 +1537,83 @@ bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count
         if (n_pairs(idx->n) && ptr_kind(outs[q]) != PTR_DEVICE)
             return fail(ctx, BM_EINVAL, "outs[%u] must be device memory", q);
         descs[q] = whole_desc(idx, outs[q]);
-        Plan one;
-        plan_classes(idx->classes, q, target_items(ctx) / count + 64, one, &ctx->speeds, 1, -1);
-        b->slot_pairs += one.slot_pairs;
-        for (auto &v : one.by_variant)
-            flat.insert(flat.end(), v.begin(), v.end());
         b->idx.push_back(idx);
         b->outs.push_back(outs[q]);
     }
-    // longest items first across all instances
-    std::stable_sort(flat.begin(), flat.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
-    b->n_items = (uint32_t)flat.size();
+    // one work list over all instances, longest items first
+    auto make_list = [&](const std::vector<float> *speeds, std::vector<WorkItem> &flat, double &slot_pairs) {
+        flat.clear();
+        slot_pairs = 0;
+        for (uint32_t q = 0; q < count; q++) {
+            Plan one;
+            plan_classes(idxs[q]->classes, q, target_items(ctx) / count + 64, one, speeds, 1, -1);
+            slot_pairs += one.slot_pairs;
+            for (auto &v : one.by_variant)
+                flat.insert(flat.end(), v.begin(), v.end());
+        }
+    };
+    // Candidate tile-shape choices: the catalogue speeds and, after
+    // bm_context_autotune, the measured ones.  Each candidate list is timed
+    // once on the batch itself and the faster one is kept.
+    std::vector<WorkItem> flat, cand;
+    double sp = 0, sp2 = 0;
+    XcdQueues q_flat{}, q_cand{};
+    make_list(nullptr, flat, sp);
+    xcd_queues(flat, q_flat.off);
+    const bool tuned = trial && (int)ctx->speeds.size() == kVariantCount * kWrapBuckets;
+    if (tuned) {
+        make_list(&ctx->speeds, cand, sp2);
+        xcd_queues(cand, q_cand.off);
+    }
+    b->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     HIPC(ctx, b->descs.alloc(count));
-    HIPC(ctx, b->items.alloc(std::max<uint64_t>(flat.size(), 1)));
-    HIPC(ctx, b->counter.alloc(1));
+    HIPC(ctx, b->items.alloc(std::max<uint64_t>(std::max(flat.size(), cand.size()), 1)));
+    HIPC(ctx, b->counter.alloc(kXcds));
     HIPC(ctx, hipMemcpyAsync(b->descs.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    if (tuned) {
+        hipEvent_t e0, e1;
+        HIPC(ctx, hipEventCreate(&e0));
+        HIPC(ctx, hipEventCreate(&e1));
+        float ms[2] = {0, 0};
+        std::vector<WorkItem> *lists[2] = {&flat, &cand};
+        const XcdQueues *qs[2] = {&q_flat, &q_cand};
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < 2 && e == hipSuccess; c++) {
+            b->n_items = (uint32_t)lists[c]->size();
+            b->queues = *qs[c];
+            if (b->n_items)
+                e = hipMemcpyAsync(b->items.p, lists[c]->data(), b->n_items * sizeof(WorkItem),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                e = b->enqueue(s);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms[c], e0, e1);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPC(ctx, e);
+        if (ms[1] < ms[0]) {
+            flat.swap(cand);
+            sp = sp2;
+            q_flat = q_cand;
+        }
+        b->tuned_ms[0] = ms[0];
+        b->tuned_ms[1] = ms[1];
+    }
+    b->slot_pairs = sp;
+    b->n_items = (uint32_t)flat.size();
+    b->queues = q_flat;
     if (!flat.empty())
         HIPC(ctx, hipMemcpyAsync(b->items.p, flat.data(), flat.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
     HIPC(ctx, hipStreamSynchronize(s));
     // the whole sequence as one graph: counter reset, output fills (kernels,
     // not memsets), one persistent compare launch, corrections
-    b->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         hipError_t e = b->enqueue(s);
         hipGraph_t g = nullptr;
@@ -1566,6 +1632,16 @@ bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count
     }
     *out = b.release();
     return BM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bm_status bm_batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs,
+                          bm_batch **out)
+{
+    return batch_create(ctx, idxs, count, outs, out, true);
 }
 
 bm_status bm_batch_run(bm_batch *b)
@@ -1600,10 +1676,19 @@ void bm_batch_destroy(bm_batch *b)
     delete b;
 }
 
+bm_status bm_batch_plan_trial(const bm_batch *b, float *builtin_ms, float *measured_ms)
+{
+    if (!b || !builtin_ms || !measured_ms)
+        return BM_EINVAL;
+    *builtin_ms = b->tuned_ms[0];
+    *measured_ms = b->tuned_ms[1];
+    return BM_OK;
+}
+
 bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idxs, uint32_t count, uint32_t *const *outs)
 {
     bm_batch *b = nullptr;
-    bm_status st = bm_batch_create(ctx, idxs, count, outs, &b);
+    bm_status st = batch_create(ctx, idxs, count, outs, &b, false);
     if (st != BM_OK)
         return st;
     st = bm_batch_run(b);
@@ -1871,7 +1956,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         for (uint32_t p = 0; p < k; p++)
             hi[p] = r.items[p];
         Plan plan;
-        plan_classes(cls, j, target_items(ix->ctx) / nq + 64, plan, &ix->ctx->speeds, 1, -1);
+        plan_classes(cls, j, target_items(ix->ctx) / nq + 64, plan, nullptr, 1, -1);
         for (auto &v : plan.by_variant)
             flat.insert(flat.end(), v.begin(), v.end());
         InstDesc &d = L.h_descs[j];
@@ -1883,7 +1968,8 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         d.gb = ix->gb;
         d.pad = 0;
     }
-    std::stable_sort(flat.begin(), flat.end(), [](const WorkItem &x, const WorkItem &y) { return item_cost(x) > item_cost(y); });
+    XcdQueues queues;
+    xcd_queues(flat, queues.off);
     if (L.cap_items < flat.size()) {
         if (L.h_items)
             (void)hipHostFree(L.h_items);
@@ -1911,9 +1997,9 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
             e = fill_u32(reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), (uint64_t)r.k * (r.k - 1) / 2, 0, s);
     }
     if (e == hipSuccess)
-        e = fill_u32(L.counter.p, 1, 0, s);
+        e = fill_u32(L.counter.p, kXcds, 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(L.items.p, (uint32_t)flat.size(), L.descs.p, InstDesc{}, L.counter.p,
+        e = launch_compare_multi_persistent(L.items.p, queues, L.descs.p, InstDesc{}, L.counter.p,
                                             grid, s);
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];
@@ -2086,7 +2172,7 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         SrvLaunch &L = *srv->launches.back();
         HIPC(ctx, hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
         HIPC(ctx, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
-        HIPC(ctx, L.counter.alloc(1));
+        HIPC(ctx, L.counter.alloc(kXcds));
         HIPC(ctx, L.flag.alloc(1));
     }
     bm_server *raw = srv.get();

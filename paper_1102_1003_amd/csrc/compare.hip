@@ -515,24 +515,31 @@ __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__rest
 // 128 x 4; body codes 0..3): the shape travels in the item's flags (bits
 // 2..4) and selects the specialised body.
 __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
-                                                                           uint32_t n_items,
+                                                                           XcdQueues q,
                                                                            const InstDesc *__restrict__ descs,
-                                                                           InstDesc d0, uint32_t *counter)
+                                                                           InstDesc d0, uint32_t *counters)
 {
-    for (;;) {
-        uint32_t it = 0;
-        if ((threadIdx.x & 63) == 0)
-            it = atomicAdd(counter, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if (it >= n_items)
-            break;
-        const WorkItem w = items[it];
-        const InstDesc d = descs ? descs[w.inst] : d0;
-        switch ((w.flags >> 2) & 7u) {
-        case 0: process_rows<2, 16>(w, d); break;
-        case 1: process_rows<2, 12, 2>(w, d); break;
-        case 2: process_rows<2, 8, 2>(w, d); break;
-        default: process_rows<2, 4>(w, d); break;
+    // workgroup b runs on XCD b mod kXcds: its own queue first (the items
+    // whose row tiles that XCD's L2 holds), then the rest of the others
+    const uint32_t home = blockIdx.x % kXcds;
+    for (uint32_t k = 0; k < kXcds; k++) {
+        const uint32_t x = (home + k) % kXcds;
+        const uint32_t base = q.off[x], size = q.off[x + 1] - q.off[x];
+        for (;;) {
+            uint32_t it = 0;
+            if ((threadIdx.x & 63) == 0)
+                it = atomicAdd(&counters[x], 1u);
+            it = __builtin_amdgcn_readfirstlane(it);
+            if (it >= size)
+                break;
+            const WorkItem w = items[base + it];
+            const InstDesc d = descs ? descs[w.inst] : d0;
+            switch ((w.flags >> 2) & 7u) {
+            case 0: process_rows<2, 16>(w, d); break;
+            case 1: process_rows<2, 12, 2>(w, d); break;
+            case 2: process_rows<2, 8, 2>(w, d); break;
+            default: process_rows<2, 4>(w, d); break;
+            }
         }
     }
 }
@@ -594,11 +601,11 @@ uint32_t multi_persistent_grid(uint32_t n_cu)
     return n_cu * (uint32_t)per_cu;
 }
 
-hipError_t launch_compare_multi_persistent(const WorkItem *items, uint32_t n_items, const InstDesc *descs,
-                                           const InstDesc &d0, uint32_t *counter, uint32_t grid, hipStream_t s)
+hipError_t launch_compare_multi_persistent(const WorkItem *items, const XcdQueues &q, const InstDesc *descs,
+                                           const InstDesc &d0, uint32_t *counters, uint32_t grid, hipStream_t s)
 {
-    if (n_items)
-        compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, n_items, descs, d0, counter);
+    if (q.off[kXcds] > q.off[0])
+        compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, q, descs, d0, counters);
     return hipGetLastError();
 }
 

@@ -81,7 +81,6 @@ namespace {
 // p of the run takes the next item of queue p mod kXcds; so the column tiles
 // that share a row tile's range run on the XCD that holds those rows.  When a
 // queue runs dry its positions take items from the fullest queue.
-constexpr uint32_t kXcds = 8;
 
 void xcd_order(std::vector<WorkItem> &v)
 {
@@ -268,6 +267,49 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
             sorted[start[rank[item_bucket[t]]]++] = v[t];
         v.swap(sorted);
         xcd_order(v);
+    }
+}
+
+void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1])
+{
+    // groups: items sharing instance, range and row tile (a key collision
+    // only merges two groups, which costs locality, not correctness)
+    std::unordered_map<uint64_t, uint32_t> group_of;
+    std::vector<uint32_t> item_group(flat.size());
+    std::vector<uint64_t> group_cost;
+    for (size_t t = 0; t < flat.size(); t++) {
+        const WorkItem &w = flat[t];
+        const uint64_t key = (((uint64_t)w.row0 << 32) | w.c0) ^ ((uint64_t)w.inst * 0x9E3779B97F4A7C15ull);
+        auto it = group_of.emplace(key, (uint32_t)group_cost.size()).first;
+        if (it->second == group_cost.size())
+            group_cost.push_back(0);
+        item_group[t] = it->second;
+        group_cost[it->second] += item_cost(w) * (uint64_t)std::max<uint32_t>(w.ncol, 1);
+    }
+    std::vector<uint32_t> order(group_cost.size());
+    for (uint32_t g = 0; g < order.size(); g++)
+        order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return group_cost[a] > group_cost[b]; });
+    std::vector<uint32_t> queue_of(group_cost.size());
+    uint64_t load[kXcds] = {};
+    for (uint32_t g : order) {
+        uint32_t best = 0;
+        for (uint32_t x = 1; x < kXcds; x++)
+            if (load[x] < load[best])
+                best = x;
+        queue_of[g] = best;
+        load[best] += group_cost[g];
+    }
+    std::vector<std::vector<WorkItem>> q(kXcds);
+    for (size_t t = 0; t < flat.size(); t++)
+        q[queue_of[item_group[t]]].push_back(flat[t]);
+    flat.clear();
+    off[0] = 0;
+    for (uint32_t x = 0; x < kXcds; x++) {
+        std::stable_sort(q[x].begin(), q[x].end(),
+                         [](const WorkItem &a, const WorkItem &b) { return item_cost(a) > item_cost(b); });
+        flat.insert(flat.end(), q[x].begin(), q[x].end());
+        off[x + 1] = (uint32_t)flat.size();
     }
 }
 

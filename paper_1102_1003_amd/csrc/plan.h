@@ -90,5 +90,15 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
 // Classes restricted to sorted indices >= first.
 std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first);
 
+// XCDs of the GPU (each with its own L2); workgroup b of a launch runs on
+// XCD b mod kXcds.
+constexpr uint32_t kXcds = 8;
+
+// Work list of a single persistent launch, split into one queue per XCD:
+// items of one (instance, range, row tile) group share a queue (groups dealt
+// greedily to the least-loaded queue, largest first), each queue longest
+// first.  Queue x is items [off[x], off[x+1]) of the reordered list.
+void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1]);
+
 
 }  // namespace bm

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <vector>
 
 #include "../paper_1102_1003_amd/csrc/plan.h"
@@ -102,5 +103,57 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
     if (sp != plan.slot_pairs)
         return fail(msg, msg_len, 14, "slot pairs %.0f, expected %.0f", plan.slot_pairs, sp);
     *n_items = items;
+    return 0;
+}
+
+// xcd_queues on the flattened plan: a permutation of the items, queues
+// contiguous and longest first, every (range, row tile) group in one queue.
+extern "C" int queues_check(uint32_t n_cls, const uint32_t *r, const uint32_t *count, uint64_t target, int single,
+                            char *msg, uint32_t msg_len)
+{
+    std::vector<Cls> cls;
+    uint32_t n = 0;
+    for (uint32_t c = 0; c < n_cls; c++) {
+        cls.push_back({r[c], n, count[c]});
+        n += count[c];
+    }
+    Plan plan;
+    plan_classes(cls, 0, target, plan, nullptr, single, -1);
+    std::vector<WorkItem> flat;
+    for (auto &v : plan.by_variant)
+        flat.insert(flat.end(), v.begin(), v.end());
+    auto key = [](const WorkItem &w) {
+        return std::vector<uint64_t>{w.row0, w.col0, w.c0, w.c1, w.flags, w.inst};
+    };
+    std::vector<std::vector<uint64_t>> before, after;
+    for (auto &w : flat)
+        before.push_back(key(w));
+    uint32_t off[kXcds + 1];
+    xcd_queues(flat, off);
+    for (auto &w : flat)
+        after.push_back(key(w));
+    std::sort(before.begin(), before.end());
+    std::sort(after.begin(), after.end());
+    if (before != after)
+        return fail(msg, msg_len, 1, "queues are not a permutation of the plan");
+    if (off[0] != 0 || off[kXcds] != flat.size())
+        return fail(msg, msg_len, 2, "queue offsets %u .. %u for %zu items", off[0], off[kXcds], flat.size());
+    std::vector<int> queue_of(flat.size());
+    for (uint32_t x = 0; x < kXcds; x++) {
+        if (off[x + 1] < off[x])
+            return fail(msg, msg_len, 3, "queue %u ends before it starts", x);
+        for (uint32_t t = off[x]; t < off[x + 1]; t++) {
+            queue_of[t] = (int)x;
+            if (t > off[x] && item_cost(flat[t]) > item_cost(flat[t - 1]))
+                return fail(msg, msg_len, 4, "queue %u not longest first at %u", x, t);
+        }
+    }
+    std::vector<std::pair<std::pair<uint64_t, uint64_t>, int>> g;
+    for (size_t t = 0; t < flat.size(); t++)
+        g.push_back({{((uint64_t)flat[t].inst << 32) | flat[t].row0, flat[t].c0}, queue_of[t]});
+    std::sort(g.begin(), g.end());
+    for (size_t t = 1; t < g.size(); t++)
+        if (g[t].first == g[t - 1].first && g[t].second != g[t - 1].second)
+            return fail(msg, msg_len, 5, "a (range, row tile) group spans two queues");
     return 0;
 }

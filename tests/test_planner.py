@@ -23,6 +23,9 @@ def checker(tmp_path_factory):
            os.path.join(ROOT, "tests", "planner_check.cpp"), "-o", out]
     subprocess.run(cmd, check=True)
     lib = ctypes.CDLL(out)
+    lib.queues_check.restype = ctypes.c_int
+    lib.queues_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_char_p, ctypes.c_uint32]
     lib.plan_check.restype = ctypes.c_int
     lib.plan_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                ctypes.c_int, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_uint32,
@@ -36,6 +39,9 @@ def checker(tmp_path_factory):
         st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst, msg, 256,
                             ctypes.byref(n_items))
         assert st == 0, f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned})"
+        if single:
+            st = lib.queues_check(r.size, r.ctypes.data, c.ctypes.data, target, single, msg, 256)
+            assert st == 0, f"{msg.value.decode()} (queues; widths {list(r)}, counts {list(c)})"
         return n_items.value
     return check
 
