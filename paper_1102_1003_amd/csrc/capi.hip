@@ -13,7 +13,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,6 +37,46 @@ namespace {
 // context (an index's) are still released in order.
 struct AllocStream {
     hipStream_t s = nullptr;
+    // Blocks freed by the context's buffers, kept for reuse in the order of
+    // s (a block handed out again is only touched by work queued after its
+    // last use).  Up to kPoolKeepBytes; released when the context goes.
+    std::mutex mu;
+    std::multimap<uint64_t, void *> spare;  // bytes -> block
+    uint64_t spare_bytes = 0;
+
+    // A spare block of at least `bytes` and at most 1.25x that, or null.
+    void *take(uint64_t bytes, uint64_t *got)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = spare.lower_bound(bytes);
+        if (it == spare.end() || it->first > bytes + bytes / 4)
+            return nullptr;
+        void *p = it->second;
+        *got = it->first;
+        spare_bytes -= it->first;
+        spare.erase(it);
+        return p;
+    }
+    // Keeps the block for reuse; false when the cache is full or the
+    // context is gone (the caller then frees it).
+    bool give(void *p, uint64_t bytes)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!s || spare_bytes + bytes > kPoolKeepBytes)
+            return false;
+        spare.emplace(bytes, p);
+        spare_bytes += bytes;
+        return true;
+    }
+    void release()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : spare)
+            (void)hipFreeAsync(kv.second, s);
+        spare.clear();
+        spare_bytes = 0;
+    }
+    ~AllocStream() { release(); }
 };
 
 // Set for the duration of a call that enqueues all its work on one context's
@@ -56,6 +98,7 @@ template <typename T>
 struct DevBuf {
     T *p = nullptr;
     uint64_t n = 0;
+    uint64_t bytes = 0;               // size of the block behind p
     std::shared_ptr<AllocStream> as;  // set when p came from the stream-ordered pool
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
@@ -64,14 +107,17 @@ struct DevBuf {
     void reset()
     {
         if (p) {
-            if (as)
-                (void)hipFreeAsync(p, as->s);
-            else
+            if (as) {
+                if (!as->give(p, bytes))
+                    (void)hipFreeAsync(p, as->s);
+            } else {
                 (void)hipFree(p);
+            }
         }
         as.reset();
         p = nullptr;
         n = 0;
+        bytes = 0;
     }
     hipError_t alloc(uint64_t count)
     {
@@ -79,10 +125,20 @@ struct DevBuf {
         if (count == 0)
             count = 1;
         hipError_t e;
+        const uint64_t want = count * sizeof(T);
+        bytes = want;
         if (t_alloc_scope && *t_alloc_scope) {
-            e = hipMallocAsync(reinterpret_cast<void **>(&p), count * sizeof(T), (*t_alloc_scope)->s);
+            const std::shared_ptr<AllocStream> &a = *t_alloc_scope;
+            void *q = a->take(want, &bytes);
+            if (q) {
+                p = reinterpret_cast<T *>(q);
+                e = hipSuccess;
+            } else {
+                bytes = want;
+                e = hipMallocAsync(reinterpret_cast<void **>(&p), want, a->s);
+            }
             if (e == hipSuccess)
-                as = *t_alloc_scope;
+                as = a;
         } else {
             e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
         }
@@ -939,8 +995,11 @@ void bm_context_destroy(bm_context *ctx)
     if (ctx->stream)
         (void)hipStreamSynchronize(ctx->stream);
     ctx->counter.reset();
-    if (ctx->as)
+    if (ctx->as) {
+        ctx->as->release();
+        std::lock_guard<std::mutex> lk(ctx->as->mu);
         ctx->as->s = nullptr;  // indexes built here release their buffers on the null stream from now on
+    }
     if (ctx->h_stage)
         (void)hipHostFree(ctx->h_stage);
     if (ctx->staged)
