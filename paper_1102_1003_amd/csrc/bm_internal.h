@@ -175,6 +175,8 @@ hipError_t launch_subset_prepare(const uint32_t *items, uint32_t k, uint32_t n, 
 // Dense comparator.
 hipError_t launch_bitmap_build(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t ld, int8_t *A,
                                hipStream_t s);
+// Rows of the dense bitmap are padded to a multiple of this.
+uint32_t dense_row_pad();
 hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t k_len, uint32_t *out,
                              uint32_t k_split, hipStream_t s);
 

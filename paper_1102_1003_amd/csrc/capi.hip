@@ -1781,7 +1781,8 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
     if (!idx->dense_A.p) {
         Span sp(ctx, PH_ENCODE);
         uint64_t ld = ((uint64_t)idx->m + 127) / 128 * 128;
-        uint64_t rows = ((uint64_t)idx->n + 127) / 128 * 128;
+        const uint64_t pad = dense_row_pad();
+        uint64_t rows = ((uint64_t)idx->n + pad - 1) / pad * pad;
         HIPC(ctx, idx->dense_A.alloc(rows * ld));
         HIPC(ctx, fill_u8(reinterpret_cast<uint8_t *>(idx->dense_A.p), rows * ld, 0, s));
         HIPC(ctx, launch_bitmap_build(idx->off.p, idx->tids.p, idx->n, ld, idx->dense_A.p, s));
@@ -1797,7 +1798,9 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
         Span sp(ctx, PH_FILL);
         HIPC(ctx, fill_u32(dst, np, 0, s));
     }
-    uint64_t T = ((uint64_t)idx->n + 127) / 128;
+    // one workgroup per CU at a time: about four rounds of them (a short
+    // tail), the contraction split as far as that needs
+    uint64_t T = ((uint64_t)idx->n + dense_row_pad() - 1) / dense_row_pad();
     uint64_t tiles = T * (T + 1) / 2;
     uint64_t want = (uint64_t)ctx->n_cu * 4;
     uint32_t ksplit = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want / std::max<uint64_t>(tiles, 1),
