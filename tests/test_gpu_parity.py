@@ -202,6 +202,27 @@ def test_subset_queries(ctx):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.subset_pairs(off, tids, q))
 
 
+def test_single_launch_and_every_default_shape(monkeypatch):
+    # the single persistent launch (per-XCD queues) for ordinary calls, and each
+    # default tile shape pinned for a whole plan, all equal to the definition
+    m, n = 9000, 280
+    off, tids = instance(44, m, n, 0.0, 0.3)
+    ref = oracle.all_pairs(off, tids)
+    rng = np.random.default_rng(44)
+    q = rng.choice(n, size=150, replace=False).astype(np.uint32)
+    ref_q = oracle.subset_pairs(off, tids, q)
+    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in (4, 7, 10, 11, 17, 18)]
+    for key, val in settings:
+        monkeypatch.setenv(key, val)
+        c = bm.Context(0)
+        idx = bm.Index.from_sets(c, m, off, tids, max_loop=3)
+        np.testing.assert_array_equal(idx.all_pair_supports(), ref, err_msg=f"{key}={val}")
+        np.testing.assert_array_equal(idx.subset_pair_supports(q)[:bm.n_pairs(q.size)], ref_q, err_msg=f"{key}={val}")
+        idx.close()
+        c.close()
+        monkeypatch.delenv(key)
+
+
 # ------------------------------------------------------------------- dense
 
 @pytest.mark.parametrize("seed,m,n", [(51, 3000, 130), (52, 10_000, 257), (53, 700, 20)])

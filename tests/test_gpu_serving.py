@@ -64,6 +64,36 @@ def test_mixed_stream_equals_alone(ctx, data):
     srv.close()
 
 
+def test_concurrent_queries_equal_single_calls(ctx):
+    # Bernoulli instance with forced failures (corrections take part); queries arrive from a
+    # producer thread while earlier launches run on several streams
+    off, tids = datagen.bernoulli_sets(20_000, 400, 0.03, seed=23)
+    idx = bm.Index.from_sets(ctx, 20_000, off, tids, max_loop=2)
+    assert idx.stats()["n_corrections"] > 0
+    rng = np.random.default_rng(24)
+    ks = [int(rng.integers(2, 400)) for _ in range(40)]
+    queries = [rng.choice(400, size=k, replace=False).astype(np.uint32) for k in ks]
+    srv = bm.Server(idx, streams=4, memory_budget=16 << 20, max_batch=8)
+    ids = [None] * len(queries)
+
+    def producer():
+        for i, q in enumerate(queries):
+            ids[i] = srv.submit(q)
+            if i % 5 == 0:
+                time.sleep(0.001)
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    results = [srv.wait(i, timeout_s=60.0) for i in ids]
+    st = srv.stats()
+    assert st["completed"] == len(queries)
+    for q, (got, info) in zip(queries, results):
+        np.testing.assert_array_equal(got, idx.subset_pair_supports(q)[:bm.n_pairs(q.size)])
+        if q.size <= 60:
+            np.testing.assert_array_equal(got, oracle.subset_pairs(off, tids, q))
+    srv.close()
+
+
 def test_tight_memory_admission(ctx, data):
     m, n, off, tids = data
     idx = bm.Index.from_sets(ctx, m, off, tids)
