@@ -232,9 +232,25 @@ def main():
         ref_rows = oracle.pair_rows(off, tids, sample, threads=threads)
         cpu_s = time.perf_counter() - tc
         cpu_pairs = sample.size * (w.n - 1)
+        # one core: a smaller sample of the same rows
+        t1 = time.perf_counter()
+        oracle.pair_rows(off, tids, sample[:16], threads=1)
+        one_s = time.perf_counter() - t1
+        # calibration: the merge on two sorted 2^24-element arrays, one core (the microbenchmark of
+        # Sec. IV-B, 2.25e8 elements/s on the paper's Xeon 5462)
+        crng = np.random.default_rng(24)
+        ca = np.sort(crng.integers(0, 1 << 31, size=1 << 24, dtype=np.uint32))
+        cb = np.sort(crng.integers(0, 1 << 31, size=1 << 24, dtype=np.uint32))
+        t2 = time.perf_counter()
+        for _ in range(3):
+            oracle.merge_count(ca, cb)
+        merge_rate = 3 * 2 * (1 << 24) / (time.perf_counter() - t2)
         cpu = {"value": cpu_pairs / cpu_s, "unit": "item-pair supports/s", "cores": threads, "kind": "oracle",
                "sample": f"{sample.size} random items x all {w.n} partners of {w.name} by sorted-tidlist merge "
-                         f"({cpu_pairs} pairs, {cpu_s:.1f} s)"}
+                         f"({cpu_pairs} pairs, {cpu_s:.1f} s)",
+               "single_core_value": 16 * (w.n - 1) / one_s,
+               "merge_elements_per_s_one_core": merge_rate,
+               "paper_merge_elements_per_s_one_core": 2.25e8}
         # the same rows from the GPU's packed output
         i_idx = sample.astype(np.int64)[:, None]
         j_idx = np.arange(w.n, dtype=np.int64)[None, :]
@@ -242,7 +258,8 @@ def main():
         pk = lo * w.n - lo * (lo + 1) // 2 + (hi - lo - 1)
         mask = i_idx != j_idx
         rows_ok = bool(np.array_equal(gpu_all[pk[mask]], ref_rows[mask]))
-        log(f"oracle: {cpu['value']:.3e} pairs/s on {threads} threads; sampled rows equal={rows_ok}")
+        log(f"oracle: {cpu['value']:.3e} pairs/s on {threads} threads, {cpu['single_core_value']:.3e} on one; "
+            f"merge {merge_rate:.3e} elements/s on one core (paper 2.25e8); sampled rows equal={rows_ok}")
 
     result = {
         "metric": METRIC,
