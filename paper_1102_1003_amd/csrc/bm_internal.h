@@ -68,6 +68,36 @@ __host__ __device__ inline uint32_t perm_eval(const PermSpec &P, int t, uint32_t
     return y;
 }
 
+// perm_eval for a table index that differs between lanes: the keys are
+// picked by selects instead of an indexed load from the argument block.
+__device__ inline uint32_t perm_eval_lane(const PermSpec &P, int t, uint32_t x)
+{
+    if (P.table)
+        return P.table[(uint64_t)t * P.m + x];
+    // the keys as scalars first: a select between loads would otherwise be
+    // turned into a per-lane load from the argument block
+    auto pick = [t](uint32_t a, uint32_t b, uint32_t c) {
+        a = __builtin_amdgcn_readfirstlane(a);
+        b = __builtin_amdgcn_readfirstlane(b);
+        c = __builtin_amdgcn_readfirstlane(c);
+        return t == 0 ? a : (t == 1 ? b : c);
+    };
+    PermSpec Q;
+    Q.m = P.m;
+    Q.mask = P.mask;
+    Q.h1 = P.h1;
+    Q.h2 = P.h2;
+    Q.mul1[0] = pick(P.mul1[0], P.mul1[1], P.mul1[2]);
+    Q.add1[0] = pick(P.add1[0], P.add1[1], P.add1[2]);
+    Q.mul2[0] = pick(P.mul2[0], P.mul2[1], P.mul2[2]);
+    Q.mul3[0] = pick(P.mul3[0], P.mul3[1], P.mul3[2]);
+    Q.add3[0] = pick(P.add3[0], P.add3[1], P.add3[2]);
+    uint32_t y = perm_chain(Q, 0, x);
+    while (y >= Q.m)
+        y = perm_chain(Q, 0, y);
+    return y;
+}
+
 // The value held by the first active lane, as a wavefront-uniform scalar.
 __device__ inline uint64_t uniform_u64(uint64_t v)
 {
@@ -130,8 +160,10 @@ hipError_t launch_resolve(const uint32_t *cand, const uint32_t *count, uint32_t 
                           const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
                           const uint64_t *goff, BuildBatch b, const PermSpec &P, uint32_t *stage, uint32_t *failed_bits,
                           uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *max_count, hipStream_t s);
+// `scratch` holds encode_scratch_bytes(n_groups) bytes.
+size_t encode_scratch_bytes(uint64_t n_groups);
 hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0,
+                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint8_t *scratch,
                          uint32_t *arena, hipStream_t s);
 hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
 

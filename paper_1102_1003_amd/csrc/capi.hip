@@ -646,15 +646,15 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
     size_t free_b = 0, total_b = 0;
     HIPC(ctx, hipMemGetInfo(&free_b, &total_b));
-    // Maps are built in batches whose staging (128 B per group) fits a quarter
-    // of free device memory; BM_STAGE_MB caps it lower.  A batch holds at
-    // least one map.
+    // Maps are built in batches whose staging (128 B per group, plus 32 B of
+    // codes) fits a quarter of free device memory; BM_STAGE_MB caps it lower.
+    // A batch holds at least one map.
     uint64_t budget_bytes = ~0ull;
     if (const char *e = getenv("BM_STAGE_MB"))
         if (atoll(e) > 0)
             budget_bytes = (uint64_t)atoll(e) << 20;
     budget_bytes = std::min<uint64_t>(budget_bytes, (uint64_t)free_b / 4);
-    const uint64_t budget_groups = std::max<uint64_t>(budget_bytes / (kSlotsPerGroup * 4), 1);
+    const uint64_t budget_groups = std::max<uint64_t>(budget_bytes / (kSlotsPerGroup * 5), 1);
     struct Batch {
         uint32_t p, q;
         uint64_t groups, n_elems, eoff;  // eoff: offset of this batch's element bases
@@ -676,8 +676,10 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         p = q;
     }
     DevBuf<uint32_t> stage, cand, counters;
+    DevBuf<uint8_t> codes;
     DevBuf<uint64_t> ebase;
     HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
+    HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
     HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
     if (!eb_all.empty())
         HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
@@ -710,7 +712,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             }
             Span span_encode(ctx, PH_ENCODE);
             HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift, idx->r0,
-                                    idx->arena.p, s));
+                                    codes.p, idx->arena.p, s));
         }
         // the all-pairs plan depends only on the width classes: make and
         // upload it on the host while the construction kernels run (indexes of
@@ -733,6 +735,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         fail_cap = std::max<uint64_t>(fail_cap, (uint64_t)h[1] + h[1] / 2 + 1024);
     }
     stage.reset();
+    codes.reset();
     cand.reset();
     idx->n_failed = n_failed_total;
 

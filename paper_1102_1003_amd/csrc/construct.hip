@@ -19,7 +19,10 @@
 // Slot v of the map is table t = (v / r_0) mod 3, hash value
 // q = r_0 floor(v / 3r_0) + v mod r_0 (the Fig. 4 layout).  The bytes are
 // stored bit-sliced: 32 consecutive slots form a group of 8 uint32 planes,
-// plane b holding bit b of the 32 bytes.
+// plane b holding bit b of the 32 bytes.  Codes are written first (one byte
+// per staging slot) so that the indicator test reads a byte of a table that
+// stays cache-resident instead of a staging word.
+#include <algorithm>
 #include <cstring>
 
 #include "bm_internal.h"
@@ -148,7 +151,7 @@ __device__ inline void insert_wave(const uint32_t *tids, const uint64_t *off, co
         for (int c = 0; c < 2; c++) {
             if (!done[c]) {
                 const int t = table[c];
-                uint32_t q = perm_eval(P, t, tau[c]) & mask;
+                uint32_t q = perm_eval_lane(P, t, tau[c]) & mask;
                 tau[c] = atomicExch(&T[(uint64_t)t * r + q], tau[c]);
                 done[c] = tau[c] == kEmpty;
                 table[c] = t == 2 ? 0 : t + 1;
@@ -216,7 +219,7 @@ __global__ void resolve_kernel(const uint32_t *cand, const uint32_t *count, uint
         uint32_t r = r_sorted[p];
         uint32_t *T = stage + (goff[p] - g0) * kSlotsPerGroup;
         for (int t = 0; t < 3; t++) {
-            uint32_t q = perm_eval(P, t, tau) & (r - 1);
+            uint32_t q = perm_eval_lane(P, t, tau) & (r - 1);
             atomicCAS(&T[(uint64_t)t * r + q], tau, kEmpty);
         }
         uint32_t item = sorted_items[p];
@@ -237,58 +240,305 @@ __global__ void resolve_kernel(const uint32_t *cand, const uint32_t *count, uint
 }
 
 // -------------------------------------------------------------- encoding
-// One thread per slot; a wavefront covers 64 consecutive slots (two groups),
-// always inside one map because every map holds a multiple of 384 slots.
-__device__ inline void encode_slot(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
-                                   uint32_t np, uint64_t g0, uint64_t sl, const PermSpec &P, uint32_t shift,
-                                   uint32_t r0, uint32_t *arena)
+// Two passes over a batch's staging, in staging order (table-major within each
+// map), by chunks of 64 staging slots.  A chunk lies inside one table of one
+// map (tables hold a multiple of 128 slots and maps start at multiples of 384
+// from the batch start), so its map and table are wavefront-uniform.  Chunks
+// are taken kEncChunks at a time (a "span" of 64 kEncChunks slots); span_map
+// holds, for every span, the map of its first slot.  The spans are cut into
+// kXcds contiguous parts, part x walked by the workgroups b with b mod kXcds
+// = x (the XCD that runs them), their wavefronts interleaved span by span, so
+// the maps an XCD is encoding at any moment stay few and in its L2.
+constexpr int kEncChunks = 8;
+constexpr uint32_t kEncSpan = 64u * kEncChunks;
+
+struct EncChunk {
+    uint32_t p;      // sorted map index
+    uint32_t r, lr;  // table width and its log2
+    uint32_t t;      // table
+    uint64_t base;   // staging index of the map's first slot
+    uint64_t q0;     // hash value of the chunk's first slot
+};
+
+// The map a wavefront is walking through: reloaded only when a chunk starts
+// past its end (chunks come in increasing order).
+struct MapCursor {
+    uint32_t p;      // sorted map index
+    uint32_t r, lr;  // table width and its log2
+    uint64_t base;   // staging index of the map's first slot
+    uint64_t end;    // staging index one past its last slot
+};
+
+__device__ inline void cursor_load(MapCursor &m, const uint32_t *r_sorted, const uint64_t *goff, uint64_t g0,
+                                   uint32_t p)
 {
-    uint64_t g = g0 + sl / kSlotsPerGroup;
-    // every lane of the wavefront is in the same map: search once, as scalars
-    uint32_t j = find_segment(goff + p0, np, uniform_u64(g));
-    j = __builtin_amdgcn_readfirstlane(j);
-    uint32_t p = p0 + j;
-    uint32_t r = r_sorted[p];
-    uint64_t v = (g - goff[p]) * kSlotsPerGroup + (sl % kSlotsPerGroup);
-    uint64_t blk = v / (3ull * r0);
-    uint32_t within = (uint32_t)(v - blk * 3ull * r0);
-    uint32_t t = within / r0;
-    uint32_t q = (uint32_t)(blk * r0) + within % r0;
-    const uint32_t *T = stage + (goff[p] - g0) * kSlotsPerGroup;
-    uint32_t x = T[(uint64_t)t * r + q];
-    uint32_t byte = 0x7Fu;
-    if (x != kEmpty) {
-        uint32_t code = perm_eval(P, t, x) >> shift;
-        uint32_t pt = (t + 2) % 3;
-        uint32_t qp = perm_eval(P, pt, x) & (r - 1);
-        uint32_t bit = T[(uint64_t)pt * r + qp] == x ? 1u : 0u;
-        byte = (bit << 7) | code;
+    m.p = p;
+    m.r = r_sorted[p];
+    m.lr = 31u - (uint32_t)__builtin_clz(m.r);
+    m.base = (goff[p] - g0) * kSlotsPerGroup;
+    m.end = (goff[p + 1] - g0) * kSlotsPerGroup;
+}
+
+// Chunk starting at staging index i0 (< n_slots).
+__device__ inline EncChunk locate_chunk(MapCursor &m, const uint32_t *r_sorted, const uint64_t *goff, uint64_t g0,
+                                        uint64_t i0)
+{
+    while (i0 >= m.end)
+        cursor_load(m, r_sorted, goff, g0, m.p + 1);
+    EncChunk c;
+    c.p = m.p;
+    c.r = m.r;
+    c.lr = m.lr;
+    c.base = m.base;
+    const uint64_t local = i0 - m.base;
+    c.t = (uint32_t)(local >> m.lr);
+    c.q0 = local - ((uint64_t)c.t << m.lr);
+    return c;
+}
+
+__global__ void span_map_kernel(const uint64_t *goff, uint32_t p0, uint32_t np, uint64_t g0, uint64_t n_spans,
+                                uint32_t *span_map)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_spans;
+         k += (uint64_t)gridDim.x * blockDim.x)
+        span_map[k] = find_segment(goff + p0, np, g0 + k * (kEncSpan / kSlotsPerGroup));
+}
+
+// The spans of this wavefront: span0, span0 + stride, ... below end.
+struct EncWalk {
+    uint64_t span0, stride, end;
+};
+
+__device__ inline EncWalk enc_walk(uint64_t n_spans)
+{
+    const uint32_t x = blockIdx.x % kXcds;
+    const uint64_t lo = n_spans * x / kXcds, hi = n_spans * (x + 1) / kXcds;
+    const uint32_t waves_per_block = blockDim.x / 64u;
+    // wavefront-uniform (the compiler cannot see that threadIdx.x / 64 is):
+    // keeps the walk, the map search and the table index in scalar registers
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
+    const uint64_t w = (uint64_t)(blockIdx.x / kXcds) * waves_per_block + wave;
+    return {lo + w, (uint64_t)(gridDim.x / kXcds) * waves_per_block, hi};
+}
+
+// Wavefront-private LDS of the compaction below: the element (then the
+// result) and the table of each occupied slot of a span, in slot order.
+struct EncLds {
+    uint32_t v[kEncSpan];
+    uint8_t t[kEncSpan];
+};
+
+// Order of LDS accesses between the lanes of one wavefront.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lanes below `lane` whose bit is set in `bal`.
+__device__ inline uint32_t lanes_below(uint64_t bal)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+// A quarter or so of the slots are occupied, and the permutation costs three
+// quarter-rate multiplies and a cycle walk: when a span lies inside one map,
+// its occupied slots are packed into as few rows of 64 lanes as they fill
+// (in LDS, in slot order) and permuted there.  Its position in the packing is
+// *pos.  Returns the number of packed slots.
+__device__ inline uint32_t pack_span(EncLds &L, const uint32_t (&x)[kEncChunks], const MapCursor &m, uint64_t first,
+                                     uint32_t (&pos)[kEncChunks])
+{
+    uint32_t n = 0;
+#pragma unroll
+    for (int u = 0; u < kEncChunks; u++) {
+        const bool occ = x[u] != kEmpty;
+        const uint64_t bal = __ballot(occ);
+        pos[u] = n + lanes_below(bal);
+        if (occ) {
+            L.v[pos[u]] = x[u];
+            L.t[pos[u]] = (uint8_t)((first + 64u * u - m.base) >> m.lr);
+        }
+        n += (uint32_t)__popcll(bal);
     }
-    int lane = threadIdx.x & 63;
+    wave_lds_sync();
+    return n;
+}
+
+// Pass 1: byte i of `codes` is 0x7F for an empty staging slot, else
+// pi_t(x) >> s for the element x held in table t (Sec. III-A).  Codes never
+// reach 0x7F because m <= 127 2^s.
+__global__ void __launch_bounds__(kBlock) codes_kernel(const uint32_t *__restrict__ stage,
+                                                       const uint32_t *__restrict__ r_sorted,
+                                                       const uint64_t *__restrict__ goff,
+                                                       const uint32_t *__restrict__ span_map, uint32_t p0, uint64_t g0,
+                                                       uint64_t n_slots, PermSpec P, uint32_t shift,
+                                                       uint8_t *__restrict__ codes)
+{
+    __shared__ EncLds lds[kBlock / 64];
+    const uint32_t lane = threadIdx.x & 63u;
+    EncLds &L = lds[__builtin_amdgcn_readfirstlane(threadIdx.x / 64u)];
+    const uint64_t n_spans = (n_slots + kEncSpan - 1) / kEncSpan;
+    const EncWalk wk = enc_walk(n_spans);
+    for (uint64_t sp = wk.span0; sp < wk.end; sp += wk.stride) {
+        const uint64_t first = sp * kEncSpan;
+        MapCursor m;
+        cursor_load(m, r_sorted, goff, g0, p0 + span_map[sp]);
+        const uint32_t *xs = stage + first;
+        uint8_t *cs = codes + first;
+        uint32_t x[kEncChunks];
+#pragma unroll
+        for (int u = 0; u < kEncChunks; u++)
+            x[u] = first + 64u * u < n_slots ? xs[64u * u + lane] : kEmpty;
+        if (first + kEncSpan <= m.end) {
+            uint32_t pos[kEncChunks];
+            const uint32_t n = pack_span(L, x, m, first, pos);
+            for (uint32_t k = lane; k < n; k += 64u)
+                L.v[k] = perm_eval_lane(P, L.t[k], L.v[k]) >> shift;
+            wave_lds_sync();
+#pragma unroll
+            for (int u = 0; u < kEncChunks; u++)
+                cs[64u * u + lane] = (uint8_t)(x[u] == kEmpty ? 0x7Fu : L.v[pos[u]]);
+            wave_lds_sync();  // the next span's packing overwrites L
+        } else {
+#pragma unroll
+            for (int u = 0; u < kEncChunks; u++) {
+                const uint64_t i0 = first + 64u * u;
+                if (i0 >= n_slots)
+                    break;
+                const EncChunk c = locate_chunk(m, r_sorted, goff, g0, i0);
+                codes[i0 + lane] = (uint8_t)(x[u] == kEmpty ? 0x7Fu : perm_eval(P, (int)c.t, x[u]) >> shift);
+            }
+        }
+    }
+}
+
+// Slot bytes of one chunk (lane = slot) into two bit-sliced groups at gdst.
+__device__ inline void store_chunk(uint32_t byte, uint64_t gdst, uint32_t *__restrict__ arena)
+{
+    const uint32_t lane = threadIdx.x & 63u;
     uint32_t word = 0;
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-        uint64_t plane = __ballot((byte >> b) & 1u);
-        if (lane == b)
-            word = (uint32_t)plane;
-        if (lane == 8 + b)
-            word = (uint32_t)(plane >> 32);
+        const uint64_t plane = __ballot((byte >> b) & 1u);
+        // lane b takes the low half of the plane, lane 8 + b the high half
+        word = lane == (uint32_t)b ? (uint32_t)plane : word;
+        word = lane == 8u + b ? (uint32_t)(plane >> 32) : word;
     }
-    uint64_t g_first = g0 + (sl - lane) / kSlotsPerGroup;  // group of lane 0 (even)
-    if (lane < 16)
-        arena[g_first * kWordsPerGroup + lane] = word;
+    if (lane < 16u)
+        (arena + gdst * kWordsPerGroup)[lane] = word;
 }
 
-
-__global__ void encode_kernel(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, uint32_t p0,
-                              uint32_t np, uint64_t g0, uint64_t n_slots, PermSpec P,
-                              uint32_t shift, uint32_t r0, uint32_t *arena)
+// First group (arena index) of the Fig. 4 layout holding the chunk whose
+// first slot is hash value q0 of table t; r_0 = 2^lr0.
+__device__ inline uint64_t chunk_group(uint64_t g0, uint64_t base, uint64_t q0, uint32_t t, uint32_t lr0)
 {
-    // grid-stride over slots (a batch may hold more than 2^32 of them); the
-    // stride is a multiple of 64 and n_slots too, so wavefronts stay whole
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_slots; sl += stride)
-        encode_slot(stage, r_sorted, goff, p0, np, g0, sl, P, shift, r0, arena);
+    const uint64_t v0 = (((q0 >> lr0) * 3ull + t) << lr0) | (q0 & ((1ull << lr0) - 1));
+    return g0 + base / kSlotsPerGroup + v0 / kSlotsPerGroup;
+}
+
+// Pass 2: the slot bytes, bit-sliced into the arena.  The indicator of x in
+// table t is set when its other copy sits in the cyclically preceding table
+// t' (Fig. 3).  The slot of table t' that x would take, pi_t'(x) mod r, holds
+// x exactly when its occupant's pi_t' agrees with pi_t'(x) above the low
+// log2 r bits (the permutation is a bijection), and those bits are the
+// occupant's code shifted right by log2 r - s: so the test reads one code byte
+// of the pass-1 output instead of a staging word.  Each chunk of 64 slots of
+// table t becomes two consecutive groups of the Fig. 4 layout, where slot v
+// holds table t = (v / r_0) mod 3 and hash value r_0 floor(v / 3r_0) + v mod r_0.
+__global__ void __launch_bounds__(kBlock) bits_kernel(const uint32_t *__restrict__ stage,
+                                                      const uint8_t *__restrict__ codes,
+                                                      const uint32_t *__restrict__ r_sorted,
+                                                      const uint64_t *__restrict__ goff,
+                                                      const uint32_t *__restrict__ span_map, uint32_t p0, uint64_t g0,
+                                                      uint64_t n_slots, PermSpec P, uint32_t shift, uint32_t lr0,
+                                                      uint32_t *__restrict__ arena)
+{
+    __shared__ EncLds lds[kBlock / 64];
+    const uint32_t lane = threadIdx.x & 63u;
+    EncLds &L = lds[__builtin_amdgcn_readfirstlane(threadIdx.x / 64u)];
+    const uint64_t n_spans = (n_slots + kEncSpan - 1) / kEncSpan;
+    const EncWalk wk = enc_walk(n_spans);
+    for (uint64_t sp = wk.span0; sp < wk.end; sp += wk.stride) {
+        const uint64_t first = sp * kEncSpan;
+        MapCursor m;
+        cursor_load(m, r_sorted, goff, g0, p0 + span_map[sp]);
+        const uint32_t *xs = stage + first;
+        const uint8_t *cs = codes + first;
+        uint32_t x[kEncChunks], code[kEncChunks];
+#pragma unroll
+        for (int u = 0; u < kEncChunks; u++) {
+            const bool in = first + 64u * u < n_slots;
+            x[u] = in ? xs[64u * u + lane] : kEmpty;
+            code[u] = in ? cs[64u * u + lane] : 0x7Fu;
+        }
+        if (first + kEncSpan <= m.end) {
+            uint32_t pos[kEncChunks];
+            const uint32_t n = pack_span(L, x, m, first, pos);
+            const uint32_t dsh = m.lr - shift;
+            const uint8_t *cm = codes + m.base;  // the map's codes, table-major
+            // the packed rows: every partner code load issued before any is used
+            uint32_t want[kEncChunks], occ[kEncChunks];
+#pragma unroll
+            for (int k = 0; k < kEncChunks; k++) {
+                const uint32_t idx = 64u * k + lane;
+                want[k] = 0;
+                occ[k] = 0x7Fu;
+                if (64u * k < n && idx < n) {
+                    const uint32_t t = L.t[idx];
+                    const uint32_t pt = t == 0 ? 2u : t - 1u;
+                    const uint32_t y = perm_eval_lane(P, (int)pt, L.v[idx]);
+                    want[k] = y >> m.lr;
+                    occ[k] = cm[(pt << m.lr) + (y & (m.r - 1u))];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kEncChunks; k++) {
+                const uint32_t idx = 64u * k + lane;
+                if (64u * k < n && idx < n)
+                    L.v[idx] = occ[k] != 0x7Fu && (occ[k] >> dsh) == want[k] ? 0x80u : 0u;
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int u = 0; u < kEncChunks; u++) {
+                const uint64_t local = first + 64u * u - m.base;
+                const uint32_t t = (uint32_t)(local >> m.lr);
+                const uint64_t q0 = local - ((uint64_t)t << m.lr);
+                const uint32_t ind = x[u] == kEmpty ? 0u : L.v[pos[u]];
+                store_chunk(ind | code[u], chunk_group(g0, m.base, q0, t, lr0), arena);
+            }
+            wave_lds_sync();  // the next span's packing overwrites L
+        } else {
+            uint32_t want[kEncChunks], occ[kEncChunks], dsh[kEncChunks];
+            uint64_t gdst[kEncChunks];
+#pragma unroll
+            for (int u = 0; u < kEncChunks; u++) {
+                const uint64_t i0 = first + 64u * u;
+                occ[u] = 0x7Fu;
+                want[u] = 0;
+                if (i0 >= n_slots)
+                    continue;
+                const EncChunk c = locate_chunk(m, r_sorted, goff, g0, i0);
+                gdst[u] = chunk_group(g0, c.base, c.q0, c.t, lr0);
+                dsh[u] = c.lr - shift;
+                if (code[u] != 0x7Fu) {
+                    const uint32_t pt = c.t == 0 ? 2u : c.t - 1u;
+                    const uint32_t y = perm_eval(P, (int)pt, x[u]);
+                    want[u] = y >> c.lr;
+                    occ[u] = codes[c.base + ((pt << c.lr) + (y & (c.r - 1u)))];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kEncChunks; u++) {
+                const uint64_t i0 = first + 64u * u;
+                if (i0 >= n_slots)
+                    break;
+                const bool ind = occ[u] != 0x7Fu && (occ[u] >> dsh[u]) == want[u];
+                store_chunk((ind ? 0x80u : 0u) | code[u], gdst[u], arena);
+            }
+        }
+    }
 }
 
 __global__ void decode_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes)
@@ -394,18 +644,45 @@ hipError_t launch_resolve(const uint32_t *cand, const uint32_t *count, uint32_t 
     return hipGetLastError();
 }
 
+size_t encode_scratch_bytes(uint64_t n_groups)
+{
+    return n_groups * kSlotsPerGroup + ((n_groups * kSlotsPerGroup + kEncSpan - 1) / kEncSpan) * 4 + 256;
+}
+
 hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
-                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0,
+                         uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint8_t *scratch,
                          uint32_t *arena, hipStream_t s)
 {
-    uint64_t n_slots = n_groups * kSlotsPerGroup;
+    const uint64_t n_slots = n_groups * kSlotsPerGroup;
     if (n_slots == 0)
         return hipSuccess;
-    uint64_t blocks = (n_slots + kBlock - 1) / kBlock;
-    if (blocks > (1u << 20))
-        blocks = 1u << 20;  // grid-stride beyond ~2.7e8 threads
-    encode_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_slots, P,
-                                                      shift, r0, arena);
+    const uint64_t n_spans = (n_slots + kEncSpan - 1) / kEncSpan;
+    uint8_t *codes = scratch;
+    uint32_t *span_map = reinterpret_cast<uint32_t *>(scratch + (n_slots + 255) / 256 * 256);
+    span_map_kernel<<<blocks_for(n_spans, 65536), kBlock, 0, s>>>(goff, b.p0, b.p1 - b.p0, b.g0, n_spans, span_map);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // one resident wave of workgroups per kernel, a multiple of kXcds
+    static uint32_t grid[2] = {0, 0};
+    if (!grid[0]) {
+        int dev = 0, n_cu = 0, occ0 = 0, occ1 = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess ||
+            (e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+            (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ0, codes_kernel, kBlock, 0)) != hipSuccess ||
+            (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, bits_kernel, kBlock, 0)) != hipSuccess)
+            return e;
+        grid[1] = (uint32_t)std::max(1, occ1 * n_cu) / kXcds * kXcds;
+        grid[0] = (uint32_t)std::max(1, occ0 * n_cu) / kXcds * kXcds;
+        if (!grid[0] || !grid[1])
+            grid[0] = grid[1] = kXcds;
+    }
+    codes_kernel<<<grid[0], kBlock, 0, s>>>(stage, r_sorted, goff, span_map, b.p0, b.g0, n_slots, P, shift, codes);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    bits_kernel<<<grid[1], kBlock, 0, s>>>(stage, codes, r_sorted, goff, span_map, b.p0, b.g0, n_slots, P, shift,
+                                           31u - (uint32_t)__builtin_clz(r0), arena);
     return hipGetLastError();
 }
 
