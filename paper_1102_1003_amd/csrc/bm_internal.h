@@ -42,9 +42,11 @@ struct InstDesc {
 // finite domains", 2002) restricts it to [0, m): apply until the value falls
 // below m, which ends because the chain permutes [0, 2^b).
 struct PermSpec {
-    const uint32_t *table;  // pi_t(x) = table[t m + x] when not null
+    const uint32_t *table;      // pi_t(x) = table[t m + x] when not null
+    const uint32_t *inv_table;  // pi_t^-1(y) = inv_table[t m + y] (with table), when not null
     uint32_t m, mask, h1, h2;
     uint32_t mul1[3], add1[3], mul2[3], mul3[3], add3[3];
+    uint32_t inv1[3], inv2[3], inv3[3];  // inverses of the multipliers mod 2^32
 };
 
 __host__ __device__ inline uint32_t perm_chain(const PermSpec &P, int t, uint32_t v)
@@ -96,6 +98,36 @@ __device__ inline uint32_t perm_eval_lane(const PermSpec &P, int t, uint32_t x)
     while (y >= Q.m)
         y = perm_chain(Q, 0, y);
     return y;
+}
+
+// pi_t^-1 for a table index that differs between lanes: the chain's steps
+// undone in reverse order (an odd multiply by its inverse, an add by a
+// subtract, v ^= v >> h by v ^ (v >> h) ^ (v >> 2h) ..., which ends after
+// two terms because 3 h2 >= b and 2 h1 > b), cycle-walked back into [0, m).
+__device__ inline uint32_t perm_inverse_lane(const PermSpec &P, int t, uint32_t y)
+{
+    if (P.table)
+        return P.inv_table[(uint64_t)t * P.m + y];
+    auto pick = [t](uint32_t a, uint32_t b, uint32_t c) {
+        a = __builtin_amdgcn_readfirstlane(a);
+        b = __builtin_amdgcn_readfirstlane(b);
+        c = __builtin_amdgcn_readfirstlane(c);
+        return t == 0 ? a : (t == 1 ? b : c);
+    };
+    const uint32_t add1 = pick(P.add1[0], P.add1[1], P.add1[2]), add3 = pick(P.add3[0], P.add3[1], P.add3[2]);
+    const uint32_t inv1 = pick(P.inv1[0], P.inv1[1], P.inv1[2]), inv2 = pick(P.inv2[0], P.inv2[1], P.inv2[2]);
+    const uint32_t inv3 = pick(P.inv3[0], P.inv3[1], P.inv3[2]);
+    const uint32_t mask = P.mask, h1 = P.h1, h2 = P.h2;
+    uint32_t v = y;
+    do {
+        v ^= v >> h1;
+        v = ((v - add3) * inv3) & mask;
+        v ^= (v >> h2) ^ (v >> (2 * h2));
+        v = (v * inv2) & mask;
+        v ^= v >> h1;
+        v = ((v - add1) * inv1) & mask;
+    } while (v >= P.m);
+    return v;
 }
 
 // The value held by the first active lane, as a wavefront-uniform scalar.
@@ -166,6 +198,19 @@ hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const 
                          uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint8_t *scratch,
                          uint32_t *arena, hipStream_t s);
 hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
+// Maps of width r <= lds_build_max_r() (0 when LDS cannot hold any) can be
+// built whole in LDS: insertion, failures (recorded as the staged path
+// does) and encoding.  One launch builds the `count` maps of width r from
+// sorted index p_first on; *overflow is set when a map leaves more nestless
+// elements than the kernel can resolve (that map is then left unbuilt).
+uint32_t lds_build_max_r();
+hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                            const uint32_t *r_sorted, const uint64_t *goff, uint32_t p_first, uint32_t count, uint32_t r,
+                            const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t max_loop, uint32_t *arena,
+                            uint32_t *failed_bits, uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap,
+                            uint32_t *overflow, hipStream_t s);
+// inv[t m + pi[t m + x]] = x for the three permutations of pi[3m].
+hipError_t launch_invert_perms(const uint32_t *pi, uint32_t m, uint32_t *inv, hipStream_t s);
 
 // Corrections (Sec. III-C).
 hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off, const uint32_t *tids,

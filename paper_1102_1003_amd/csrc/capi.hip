@@ -298,6 +298,7 @@ struct bm_index {
     DevBuf<uint64_t> off;
     DevBuf<uint32_t> tids;
     DevBuf<uint32_t> pi;            // 3 m, only for caller-given permutations
+    DevBuf<uint32_t> pinv;          // their inverses, 3 m
     PermSpec perm;                  // pi_t: table (caller's) or keyed bijection
     DevBuf<uint32_t> sorted_items;  // n
     DevBuf<uint32_t> r_sorted;      // n
@@ -561,8 +562,11 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             return st;
         if (h)
             return fail(ctx, BM_EINVAL, "bm_build_opts.perm: not three permutations of 0..m-1");
+        HIPC(ctx, idx->pinv.alloc(3ull * m));
+        HIPC(ctx, launch_invert_perms(idx->pi.p, m, idx->pinv.p, s));
         idx->perm = make_perm_spec(m, o->seed);
         idx->perm.table = idx->pi.p;
+        idx->perm.inv_table = idx->pinv.p;
     } else {
         idx->perm = make_perm_spec(m, o->seed);
     }
@@ -659,22 +663,34 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         uint32_t p, q;
         uint64_t groups, n_elems, eoff;  // eoff: offset of this batch's element bases
     };
+    // Maps narrow enough for LDS (a prefix of the size order) are built whole
+    // in LDS, one launch per width; the rest go through staging in batches.
+    // BM_LDS_BUILD=0 turns the LDS path off.
+    const char *lds_env = getenv("BM_LDS_BUILD");
+    const uint32_t lds_r = (lds_env && atoi(lds_env) == 0) ? 0 : lds_build_max_r();
+    auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / 3); };
+    uint32_t p_lds = first_built;
+    while (p_lds < n && width_of(p_lds) <= lds_r)
+        p_lds++;
     std::vector<Batch> batches;
     std::vector<uint64_t> eb_all;
     uint64_t max_groups = 0;
-    for (uint32_t p = first_built; p < n;) {
-        uint32_t q = p + 1;
-        while (q < n && h_goff[q + 1] - h_goff[p] <= budget_groups)
-            q++;
-        Batch b{p, q, h_goff[q] - h_goff[p], 0, eb_all.size()};
-        eb_all.push_back(0);
-        for (uint32_t k = p; k < q; k++)
-            eb_all.push_back(eb_all.back() + idx->h_sizes_sorted[k]);
-        b.n_elems = eb_all.back();
-        max_groups = std::max(max_groups, b.groups);
-        batches.push_back(b);
-        p = q;
-    }
+    auto make_batches = [&](uint32_t from) {
+        for (uint32_t p = from; p < n;) {
+            uint32_t q = p + 1;
+            while (q < n && h_goff[q + 1] - h_goff[p] <= budget_groups)
+                q++;
+            Batch b{p, q, h_goff[q] - h_goff[p], 0, eb_all.size()};
+            eb_all.push_back(0);
+            for (uint32_t k = p; k < q; k++)
+                eb_all.push_back(eb_all.back() + idx->h_sizes_sorted[k]);
+            b.n_elems = eb_all.back();
+            max_groups = std::max(max_groups, b.groups);
+            batches.push_back(b);
+            p = q;
+        }
+    };
+    make_batches(p_lds);
     DevBuf<uint32_t> stage, cand, counters;
     DevBuf<uint8_t> codes;
     DevBuf<uint64_t> ebase;
@@ -685,8 +701,10 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
     HIPC(ctx, counters.alloc(4));
     // counters: [0] candidates of the running batch, [1] failures so far,
-    // [2] largest candidate count of any batch.  Capacities are checked once
-    // at the end; on overflow the whole construction runs again, larger.
+    // [2] largest candidate count of any batch, [3] an LDS-built map left too
+    // many nestless elements.  Capacities are checked once at the end; on
+    // overflow the whole construction runs again, larger (or, for [3],
+    // through staging only).
     uint64_t cand_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
     uint64_t fail_cap = cand_cap;
     uint64_t n_failed_total = 0;
@@ -696,6 +714,19 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         HIPC(ctx, fill_u32(counters.p, 4, 0, s));
         if (attempt)
             HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+        if (p_lds > first_built) {
+            Span span_construct(ctx, PH_CONSTRUCT);
+            for (uint32_t p = first_built; p < p_lds;) {
+                uint32_t q = p + 1;
+                while (q < p_lds && width_of(q) == width_of(p))
+                    q++;
+                HIPC(ctx, launch_lds_build(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
+                                           p, q - p, width_of(p), idx->perm, shift, idx->r0, o->max_loop,
+                                           idx->arena.p, failed_bits.p, idx->failed.p, counters.p + 1,
+                                           (uint32_t)fail_cap, counters.p + 3, s));
+                p = q;
+            }
+        }
         for (const Batch &b : batches) {
             BuildBatch bb{b.p, b.q, h_goff[b.p]};
             {
@@ -727,6 +758,20 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         st = read_back(ctx, h, counters.p, 16);
         if (st != BM_OK)
             return st;
+        if (h[3]) {
+            // an LDS-built map could not resolve its failures: stage everything
+            p_lds = first_built;
+            batches.clear();
+            eb_all.clear();
+            max_groups = 0;
+            make_batches(first_built);
+            HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
+            HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
+            HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
+            if (!eb_all.empty())
+                HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
+            continue;
+        }
         if (h[2] <= cand_cap && h[1] <= fail_cap) {
             n_failed_total = h[1];
             break;

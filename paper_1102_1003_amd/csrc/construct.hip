@@ -32,6 +32,7 @@ namespace bm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kLdsBlock = 1024;  // most threads a workgroup of the LDS build may have
 
 uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 22)
 {
@@ -541,6 +542,216 @@ __global__ void __launch_bounds__(kBlock) bits_kernel(const uint32_t *__restrict
     }
 }
 
+// ------------------------------------------------------- maps built in LDS
+// A map whose three tables fit in LDS as their final code bytes (3 r bytes,
+// plus 3 r indicator bits) is built whole by one workgroup: insertion
+// (Sec. II-A) by LDS exchanges, the failure policy of the staged path, the
+// indicators, then the encoding written straight to the arena.  A slot's
+// byte and its hash value fix the element it holds: code c at hash value q
+// of table t holds pi_t^-1((c << s) | (q mod 2^s)), because r >= r_0 >= 2^s.
+// So an evicted element is recovered with the inverse permutation and no
+// staging words are needed.
+constexpr uint32_t kLdsFailCap = 1024;  // nestless elements one map may leave
+
+struct LdsHead {
+    uint32_t count;  // nestless elements
+    uint32_t pad;
+    uint32_t elem[kLdsFailCap];
+};
+
+size_t lds_build_bytes(uint32_t r)
+{
+    return sizeof(LdsHead) + 3ull * r + 3ull * r / 8;
+}
+
+// Sets byte i of the LDS tables to v; returns the byte it held.
+__device__ inline uint32_t lds_swap_byte(uint32_t *W, uint32_t i, uint32_t v)
+{
+    uint32_t *w = W + (i >> 2);
+    const uint32_t sh = (i & 3u) * 8u;
+    uint32_t old = *w;
+    for (;;) {
+        const uint32_t prev = atomicCAS(w, old, (old & ~(0xFFu << sh)) | (v << sh));
+        if (prev == old)
+            return (old >> sh) & 0xFFu;
+        old = prev;
+    }
+}
+
+// Empties byte i of the LDS tables if it holds `code`.
+__device__ inline void lds_clear_byte(uint32_t *W, uint32_t i, uint32_t code)
+{
+    uint32_t *w = W + (i >> 2);
+    const uint32_t sh = (i & 3u) * 8u;
+    uint32_t old = *w;
+    while (((old >> sh) & 0xFFu) == code) {
+        const uint32_t prev = atomicCAS(w, old, (old & ~(0xFFu << sh)) | (0x7Fu << sh));
+        if (prev == old)
+            break;
+        old = prev;
+    }
+}
+
+__global__ void __launch_bounds__(kLdsBlock)
+    lds_build_kernel(const uint32_t *__restrict__ tids, const uint64_t *__restrict__ off,
+                     const uint32_t *__restrict__ sorted_items, const uint32_t *__restrict__ r_sorted,
+                     const uint64_t *__restrict__ goff, uint32_t p_first, PermSpec P, uint32_t shift, uint32_t lr0,
+                     uint32_t max_loop, uint32_t *__restrict__ arena, uint32_t *failed_bits, uint32_t *failed,
+                     uint32_t *n_failed, uint32_t fail_cap, uint32_t *overflow)
+{
+    extern __shared__ uint32_t lds_dyn[];
+    LdsHead &H = *reinterpret_cast<LdsHead *>(lds_dyn);
+    const uint32_t p = p_first + blockIdx.x;
+    const uint32_t item = sorted_items[p];
+    const uint32_t r = r_sorted[p];
+    const uint32_t lr = 31u - (uint32_t)__builtin_clz(r);
+    uint32_t *W = lds_dyn + sizeof(LdsHead) / 4;  // tables 0, 1, 2: r code bytes each
+    uint32_t *IND = W + 3u * r / 4u;              // their indicator bits, 3 r / 32 words
+    const uint8_t *B = reinterpret_cast<const uint8_t *>(W);
+    const uint64_t e_first = off[item];
+    const uint32_t n_el = (uint32_t)(off[item + 1] - e_first);
+    const uint32_t *T = tids + e_first;
+    const uint32_t low = (1u << shift) - 1u;
+
+    for (uint32_t i = threadIdx.x; i < 3u * r / 4u; i += blockDim.x)
+        W[i] = 0x7F7F7F7Fu;
+    for (uint32_t i = threadIdx.x; i < 3u * r / 32u; i += blockDim.x)
+        IND[i] = 0;
+    if (threadIdx.x == 0)
+        H.count = 0;
+    __syncthreads();
+
+    // Insertion.  Copy j of the map is chain j mod 2 of element j / 2,
+    // entering at A_1 or A_2 as in the staged path; a lane takes its next
+    // copy as soon as its chain ends, so no lane idles while another runs a
+    // long chain.
+    {
+        const uint32_t steps = 3u * max_loop;
+        uint32_t j = threadIdx.x, tau = 0, tb = 0, left = 0;
+        bool busy = false;
+        for (;;) {
+            if (!busy) {
+                if (j >= 2u * n_el)
+                    break;
+                tau = T[j >> 1];
+                tb = j & 1u;
+                left = steps;
+                busy = true;
+                j += blockDim.x;
+            }
+            if (left == 0) {
+                const uint32_t slot = atomicAdd(&H.count, 1u);
+                if (slot < kLdsFailCap)
+                    H.elem[slot] = tau;
+                busy = false;
+                continue;
+            }
+            const uint32_t y = perm_eval_lane(P, (int)tb, tau);
+            const uint32_t q = y & (r - 1u);
+            const uint32_t old = lds_swap_byte(W, (tb << lr) + q, y >> shift);
+            if (old == 0x7Fu) {
+                busy = false;
+            } else {
+                tau = perm_inverse_lane(P, (int)tb, (old << shift) | (q & low));
+                tb = tb == 2u ? 0u : tb + 1u;
+                left--;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nf = H.count;
+    if (nf > kLdsFailCap) {
+        // too many nestless elements to resolve here: the host builds again
+        // without this path
+        if (threadIdx.x == 0)
+            atomicOr(overflow, 1u);
+        return;
+    }
+
+    // failures: delete the remaining copy, record the element once
+    for (uint32_t f = threadIdx.x; f < nf; f += blockDim.x) {
+        const uint32_t tau = H.elem[f];
+        for (int t = 0; t < 3; t++) {
+            const uint32_t y = perm_eval_lane(P, t, tau);
+            lds_clear_byte(W, ((uint32_t)t << lr) + (y & (r - 1u)), y >> shift);
+        }
+        const int64_t k = find_tid(T, n_el, tau);
+        if (k < 0)
+            continue;  // cannot happen: tau came from this set
+        const uint64_t kk = e_first + (uint64_t)k;
+        const uint32_t bit = 1u << (kk % 32);
+        const uint32_t old = atomicOr(&failed_bits[kk / 32], bit);
+        if (!(old & bit)) {
+            const uint32_t slot = atomicAdd(n_failed, 1u);
+            if (slot < fail_cap) {
+                failed[2 * (uint64_t)slot] = item;
+                failed[2 * (uint64_t)slot + 1] = tau;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Indicators (Fig. 3), by element: the copy in table t is flagged when the
+    // other copy sits in table t - 1 (mod 3).  A placed element has exactly
+    // two copies, so exactly one of them is flagged; a failed one has none.
+    for (uint32_t e = threadIdx.x; e < n_el; e += blockDim.x) {
+        const uint32_t x = T[e];
+        uint32_t pos[3];
+        bool in[3];
+#pragma unroll
+        for (int t = 0; t < 3; t++) {
+            const uint32_t y = perm_eval(P, t, x);
+            pos[t] = ((uint32_t)t << lr) + (y & (r - 1u));
+            in[t] = B[pos[t]] == (y >> shift);
+        }
+#pragma unroll
+        for (int t = 0; t < 3; t++)
+            if (in[t] && in[t == 0 ? 2 : t - 1])
+                atomicOr(&IND[pos[t] >> 5], 1u << (pos[t] & 31u));
+    }
+    __syncthreads();
+
+    // Encoding: a wavefront per 8 groups (256 slots of the Fig. 4 layout),
+    // lane = (group, plane).  A group's 32 slots are 32 consecutive hash
+    // values of one table (r_0 >= 128), so its code bytes are 32 consecutive
+    // LDS bytes and its indicators one LDS word.  Plane b < 7 gathers bit b
+    // of the 32 bytes, four at a time by a dot product with 1, 2, 4, 8.
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
+    const uint32_t n_waves = blockDim.x / 64u;
+    const uint32_t plane = lane & 7u;
+    uint32_t *out = arena + goff[p] * kWordsPerGroup;
+    for (uint32_t v0 = wave * 256u; v0 < 3u * r; v0 += n_waves * 256u) {
+        const uint32_t v = v0 + (lane >> 3) * kSlotsPerGroup;
+        if (v >= 3u * r)
+            continue;
+        const uint32_t a = v >> lr0;
+        const uint32_t t = a % 3u;
+        const uint32_t q = ((a / 3u) << lr0) | (v & ((1u << lr0) - 1u));
+        const uint32_t i0 = (t << lr) + q;  // a multiple of 32
+        const uint4 lo = *reinterpret_cast<const uint4 *>(B + i0);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(B + i0 + 16);
+        const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        uint32_t word = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            word |= __builtin_amdgcn_udot4((d[k] >> plane) & 0x01010101u, 0x08040201u, 0u, false) << (4 * k);
+        if (plane == 7u)
+            word = IND[i0 >> 5];
+        out[(uint64_t)v / kSlotsPerGroup * kWordsPerGroup + plane] = word;
+    }
+}
+
+// inv[t m + pi_t(x)] = x
+__global__ void invert_perms_kernel(const uint32_t *pi, uint32_t m, uint32_t *inv)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3ull * m; i += stride) {
+        const uint64_t t = i / m;
+        inv[t * m + pi[i]] = (uint32_t)(i - t * m);
+    }
+}
+
 __global__ void decode_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes)
 {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -563,6 +774,7 @@ PermSpec make_perm_spec(uint32_t m, uint64_t seed)
     PermSpec P;
     memset(&P, 0, sizeof(P));
     P.table = nullptr;
+    P.inv_table = nullptr;
     P.m = m;
     uint32_t bits = 1;
     while (bits < 32 && (1ull << bits) < m)
@@ -577,12 +789,23 @@ PermSpec make_perm_spec(uint32_t m, uint64_t seed)
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         return z ^ (z >> 31);
     };
+    // a * inv = 1 mod 2^32 for odd a (Newton's iteration doubles the correct
+    // low bits: 3, 6, 12, 24, 48)
+    auto inverse = [](uint32_t a) {
+        uint32_t x = a;
+        for (int i = 0; i < 4; i++)
+            x *= 2u - a * x;
+        return x;
+    };
     for (int t = 0; t < 3; t++) {
         P.mul1[t] = ((uint32_t)next() & P.mask) | 1u;
         P.add1[t] = (uint32_t)next() & P.mask;
         P.mul2[t] = ((uint32_t)next() & P.mask) | 1u;
         P.mul3[t] = ((uint32_t)next() & P.mask) | 1u;
         P.add3[t] = (uint32_t)next() & P.mask;
+        P.inv1[t] = inverse(P.mul1[t]);
+        P.inv2[t] = inverse(P.mul2[t]);
+        P.inv3[t] = inverse(P.mul3[t]);
     }
     return P;
 }
@@ -683,6 +906,52 @@ hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const 
         return e;
     bits_kernel<<<grid[1], kBlock, 0, s>>>(stage, codes, r_sorted, goff, span_map, b.p0, b.g0, n_slots, P, shift,
                                            31u - (uint32_t)__builtin_clz(r0), arena);
+    return hipGetLastError();
+}
+
+uint32_t lds_build_max_r()
+{
+    static int limit = -1;
+    if (limit < 0) {
+        int dev = 0, bytes = 0;
+        limit = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(lds_build_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess)
+            limit = bytes;
+        (void)hipGetLastError();
+    }
+    uint32_t r = 0;
+    for (uint32_t c = kMinR0; c <= (1u << 20); c <<= 1)
+        if (lds_build_bytes(c) <= (uint64_t)limit)
+            r = c;
+    return r;
+}
+
+hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                            const uint32_t *r_sorted, const uint64_t *goff, uint32_t p_first, uint32_t count, uint32_t r,
+                            const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t max_loop, uint32_t *arena,
+                            uint32_t *failed_bits, uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap,
+                            uint32_t *overflow, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    if (r > lds_build_max_r() || (r & (r - 1)) || r < r0)
+        return hipErrorInvalidValue;
+    const size_t lds = lds_build_bytes(r);
+    // A CU holds 160 KB of LDS and 32 wavefronts: a workgroup of 16 wavefronts
+    // where only one fits by LDS, else of 8.
+    const int threads = lds > 160u * 1024u / 2u ? kLdsBlock : kLdsBlock / 2;
+    lds_build_kernel<<<count, threads, lds, s>>>(tids, off, sorted_items, r_sorted, goff, p_first, P, shift,
+                                                  31u - (uint32_t)__builtin_clz(r0), max_loop, arena, failed_bits,
+                                                  failed, n_failed, fail_cap, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_perms(const uint32_t *pi, uint32_t m, uint32_t *inv, hipStream_t s)
+{
+    invert_perms_kernel<<<blocks_for(3ull * m, 65536), kBlock, 0, s>>>(pi, m, inv);
     return hipGetLastError();
 }
 
