@@ -324,7 +324,7 @@ __device__ inline EncWalk enc_walk(uint64_t n_spans)
 
 // Wavefront-private LDS of the compaction below: the element (then the
 // result) and the table of each occupied slot of a span, in slot order.
-struct EncLds {
+struct alignas(16) EncLds {
     uint32_t v[kEncSpan];
     uint8_t t[kEncSpan];
 };
@@ -501,13 +501,28 @@ __global__ void __launch_bounds__(kBlock) bits_kernel(const uint32_t *__restrict
                     L.v[idx] = occ[k] != 0x7Fu && (occ[k] >> dsh) == want[k] ? 0x80u : 0u;
             }
             wave_lds_sync();
+            // slot bytes into LDS in staging order (the table bytes are free now)
 #pragma unroll
-            for (int u = 0; u < kEncChunks; u++) {
+            for (int u = 0; u < kEncChunks; u++)
+                L.t[64u * u + lane] = (uint8_t)((x[u] == kEmpty ? 0u : L.v[pos[u]]) | code[u]);
+            wave_lds_sync();
+            // bit planes: lane = (chunk, group of the chunk, plane) for two
+            // chunks at a time; plane b gathers bit b of the group's 32 bytes,
+            // four at a time by a dot product with 1, 2, 4, 8
+#pragma unroll
+            for (int h = 0; h < kEncChunks / 4; h++) {
+                const uint32_t u = 4u * h + (lane >> 4), half = (lane >> 3) & 1u, plane = lane & 7u;
+                const uint4 *src = reinterpret_cast<const uint4 *>(L.t + 64u * u + 32u * half);
+                const uint4 lo = src[0], hi = src[1];
+                const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                uint32_t word = 0;
+#pragma unroll
+                for (int k = 0; k < 8; k++)
+                    word |= __builtin_amdgcn_udot4((d[k] >> plane) & 0x01010101u, 0x08040201u, 0u, false) << (4 * k);
                 const uint64_t local = first + 64u * u - m.base;
                 const uint32_t t = (uint32_t)(local >> m.lr);
                 const uint64_t q0 = local - ((uint64_t)t << m.lr);
-                const uint32_t ind = x[u] == kEmpty ? 0u : L.v[pos[u]];
-                store_chunk(ind | code[u], chunk_group(g0, m.base, q0, t, lr0), arena);
+                arena[(chunk_group(g0, m.base, q0, t, lr0) + half) * kWordsPerGroup + plane] = word;
             }
             wave_lds_sync();  // the next span's packing overwrites L
         } else {

@@ -18,14 +18,42 @@ uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 20)
     return (uint32_t)(g > cap ? cap : g);
 }
 
-// row_of[k] = b for every k in transaction b.
+// row_of[k] = b for every k in transaction b.  A wavefront takes 64
+// consecutive transactions, keeps their offsets in LDS and writes their
+// incidences in order, 64 at a time; lane k finds its transaction by binary
+// search (the last offset <= k, which skips empty transactions).
 __global__ void expand_rows_kernel(const uint64_t *row_off, uint32_t m, uint32_t *row_of)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += stride) {
-        uint64_t e = row_off[b + 1];
-        for (uint64_t k = row_off[b]; k < e; k++)
-            row_of[k] = (uint32_t)b;
+    __shared__ uint64_t offs_all[kBlock / 64][65];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
+    uint64_t *offs = offs_all[wave];
+    const uint64_t n_blocks = ((uint64_t)m + 63) / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * (blockDim.x / 64u);
+    for (uint64_t rb = (uint64_t)blockIdx.x * (blockDim.x / 64u) + wave; rb < n_blocks; rb += stride) {
+        const uint64_t b0 = rb * 64;
+        const uint32_t rows = (uint32_t)(m - b0 < 64 ? m - b0 : 64);
+        offs[lane] = row_off[b0 + (lane < rows ? lane : rows)];
+        if (lane == 0)
+            offs[64] = row_off[b0 + rows];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t first = offs[0], end = offs[64];
+        for (uint64_t k = first + lane; k < end; k += 64) {
+            uint32_t lo = 0, hi = rows;  // offs[lo] <= k < offs[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (offs[mid] <= k)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            row_of[k] = (uint32_t)(b0 + lo);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -115,7 +143,7 @@ __global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, 
 
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s)
 {
-    expand_rows_kernel<<<blocks_for(m), kBlock, 0, s>>>(row_off, m, row_of);
+    expand_rows_kernel<<<blocks_for(((uint64_t)m + 63) / 64 * 64, 8192), kBlock, 0, s>>>(row_off, m, row_of);
     return hipGetLastError();
 }
 
