@@ -59,7 +59,11 @@ __device__ inline uint32_t group_hits(const uint32_t (&x)[8], const uint32_t (&y
     for (int b = 1; b < 7; b++)
         mm = __builtin_amdgcn_bitop3_b32(x[b], y[b], mm, kXorOr);
     uint32_t hit = __builtin_amdgcn_bitop3_b32(mm, x[7], y[7], kNotAndOr);
-    return __builtin_popcount(hit) + acc;
+    acc += __builtin_popcount(hit);
+    // one v_bcnt_u32_b32 with the running count as its addend: keeps the
+    // compiler from pairing counts into an extra v_add3 per two groups
+    asm("" : "+v"(acc));
+    return acc;
 }
 
 __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)

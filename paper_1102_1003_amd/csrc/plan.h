@@ -53,11 +53,15 @@ constexpr int kWrapBuckets = 3;
 inline int wrap_bucket(uint32_t ratio) { return ratio <= 1 ? 0 : (ratio <= 8 ? 1 : 2); }
 
 // Compare work is split into group ranges whose working set (that range of
-// every map of a class pair) fits in the last-level caches (256 MB Infinity
-// Cache, 8 x 4 MB L2).
-constexpr double kLocalityBytes = 64.0 * (1 << 20);
-// Shortest range, in steps of the shape (at least kMinPieceGroups groups).
-constexpr uint32_t kMinPieceGroups = 64;
+// every map of a class pair) fits in one XCD's 4 MB L2: the column groups
+// arrive as scalar loads, which almost never hit the scalar cache, so their
+// latency is that of the L2 or beyond.
+constexpr double kLocalityBytes = 4.0 * (1 << 20);
+// Shortest range, in groups visited per pair.  Every range of a pair ends
+// in one atomic add of its count, and device atomics run at roughly one per
+// 1500 lane-operations of compare work: 256 groups (2304 lane-operations)
+// per pair keep those adds from limiting the launch.
+constexpr uint32_t kMinPieceGroups = 256;
 
 struct Cls {
     uint32_t r, start, count;  // width r; sorted-index range [start, start + count)
