@@ -215,6 +215,11 @@ struct bm_context {
     // autotuned tile speeds, [variant * kWrapBuckets + bucket], group pairs per us
     std::vector<float> speeds;
     uint32_t tune_gen = 0;
+    // side streams (default priority) that run a compare's per-shape launches
+    // beside the first one, so each launch's tail overlaps the others
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
 };
 
 namespace {
@@ -484,10 +489,32 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
         HIPC(ctx, launch_compare_multi_persistent(items, q, nullptr, d0, ctx->counter.p, ctx->grid, ctx->stream));
         return BM_OK;
     }
+    // the first shape on the context's stream, up to kSide more on side
+    // streams that start after everything queued so far and that the
+    // context's stream waits for (event waits, so graph capture follows)
+    const int n_side = std::min<int>((int)ranges.size() - 1, bm_context::kSide);
+    if (n_side > 0 && !ctx->fork) {
+        for (int k = 0; k < bm_context::kSide; k++) {
+            HIPC(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+            HIPC(ctx, hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming));
+        }
+        HIPC(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    }
+    if (n_side > 0) {
+        HIPC(ctx, hipEventRecord(ctx->fork, ctx->stream));
+        for (int k = 0; k < n_side; k++)
+            HIPC(ctx, hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
+    }
     uint64_t at = 0;
-    for (auto &r : ranges) {
-        HIPC(ctx, launch_compare(items + at, r.second, nullptr, d0, r.first, ctx->stream));
-        at += r.second;
+    for (size_t i = 0; i < ranges.size(); i++) {
+        const int k = (int)i - 1;
+        hipStream_t s = (k >= 0 && k < n_side) ? ctx->side[k] : ctx->stream;
+        HIPC(ctx, launch_compare(items + at, ranges[i].second, nullptr, d0, ranges[i].first, s));
+        at += ranges[i].second;
+    }
+    for (int k = 0; k < n_side; k++) {
+        HIPC(ctx, hipEventRecord(ctx->join[k], ctx->side[k]));
+        HIPC(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[k], 0));
     }
     return BM_OK;
 }
@@ -1055,6 +1082,16 @@ void bm_context_destroy(bm_context *ctx)
     clear_phases(ctx, 0, PH_COUNT - 1);
     for (hipEvent_t e : ctx->event_pool)
         (void)hipEventDestroy(e);
+    for (int k = 0; k < bm_context::kSide; k++) {
+        if (ctx->side[k]) {
+            (void)hipStreamSynchronize(ctx->side[k]);
+            (void)hipStreamDestroy(ctx->side[k]);
+        }
+        if (ctx->join[k])
+            (void)hipEventDestroy(ctx->join[k]);
+    }
+    if (ctx->fork)
+        (void)hipEventDestroy(ctx->fork);
     if (ctx->own_stream)
         (void)hipStreamDestroy(ctx->stream);
     delete ctx;

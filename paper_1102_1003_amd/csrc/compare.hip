@@ -234,14 +234,26 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
             na[e][r] = arena[rbase[r] + 2 * (uint64_t)(h0 + e)];
             nb[e][r] = arena[rbase[r] + 2 * (uint64_t)(h0 + e) + 1];
         }
+    // with three or more rows per lane the next step's rows are not
+    // prefetched: the registers keep four wavefronts per SIMD instead
+    constexpr bool kPrefetch = R <= 2;
     for (uint32_t h = h0; h < h1; h += H) {
         uint32_t x[H][R][8];
+        if (!kPrefetch && h != h0) {
+#pragma unroll
+            for (int e = 0; e < H; e++)
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    na[e][r] = arena[rbase[r] + 2 * (uint64_t)(h + e)];
+                    nb[e][r] = arena[rbase[r] + 2 * (uint64_t)(h + e) + 1];
+                }
+        }
 #pragma unroll
         for (int e = 0; e < H; e++)
 #pragma unroll
             for (int r = 0; r < R; r++)
                 unpack4(na[e][r], nb[e][r], x[e][r]);
-        if (h + H < h1) {
+        if (kPrefetch && h + H < h1) {
 #pragma unroll
             for (int e = 0; e < H; e++)
 #pragma unroll
@@ -567,7 +579,7 @@ const Kernels kKernels[] = {
     BM_ROWS(2, 12, 2),   BM_ROWS(2, 8, 2),    BM_ROWS(1, 16, 2),
     BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),
     BM_GP(4, 4),         BM_GP(2, 8),
-    BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),
+    BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),    BM_ROWS(3, 12, 2),
 };
 static_assert(sizeof(kKernels) / sizeof(kKernels[0]) == kVariantCount, "one kernel entry per tile shape");
 

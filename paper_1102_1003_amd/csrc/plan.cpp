@@ -42,6 +42,12 @@ const VariantInfo kInfo[kVariantCount] = {
     // row-resident, two row groups per step, 16 and 4 columns
     {128, 16, true, 2, -1, false, 1.20f},
     {128, 4, true, 2, -1, false, 0.70f},
+    // row-resident, three rows per lane (192 x 12), two row groups per step.
+    // Its rows are not prefetched (registers), so a step needs the wrapped
+    // column groups of a wider class to hide their load: 5.54 ms against
+    // 5.98 ms for 128 x 12 on the large Zipf instance, but 2.40 against 2.28
+    // between maps of one width (the paper-replica instance).
+    {192, 12, true, 2, -1, true, 1.40f, 1.20f},
 };
 
 }  // namespace
@@ -151,7 +157,8 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                 if (single ? V.multi < 0
                            : (pinned >= 0 ? v != pinned : !V.default_choice))
                     continue;
-                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : V.speed;
+                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket]
+                                          : (bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed);
                 if (!(speed > 0))
                     continue;
                 const uint32_t bi = V.bi, bj = V.bj;

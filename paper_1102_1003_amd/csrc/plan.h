@@ -44,8 +44,9 @@ struct VariantInfo {
     int multi;            // body code in the single-launch kernel (0..3), -1 if it has none
     bool default_choice;  // offered to the planner unless a shape is pinned
     float speed;          // relative group-pair rate of an unpadded tile (planner weight)
+    float speed_nowrap = 0;  // the same between maps of one width, when it differs (0: as speed)
 };
-constexpr int kVariantCount = 21;
+constexpr int kVariantCount = 22;
 const VariantInfo &variant_info(int v);
 
 // Measured speeds are kept per wrap ratio G_col / G_row: 1 | 2..8 | >= 16.

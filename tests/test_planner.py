@@ -12,7 +12,7 @@ import datagen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1102_1003_amd", "csrc")
-N_SHAPES = 21
+N_SHAPES = 22
 CU64 = 256 * 64     # items a full MI355X plan aims at
 
 
