@@ -1684,13 +1684,19 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
         b->idx.push_back(idx);
         b->outs.push_back(outs[q]);
     }
-    // one work list over all instances, longest items first
+    // one work list over all instances, longest items first; each instance
+    // gets a share of the items in proportion to its work, so that items of
+    // every instance take about the same time
+    std::vector<double> inst_work(count);
+    for (uint32_t q = 0; q < count; q++)
+        inst_work[q] = class_work(idxs[q]->classes);
+    const std::vector<uint64_t> inst_target = shared_targets(inst_work, target_items(ctx), 8);
     auto make_list = [&](const std::vector<float> *speeds, std::vector<WorkItem> &flat, double &slot_pairs) {
         flat.clear();
         slot_pairs = 0;
         for (uint32_t q = 0; q < count; q++) {
             Plan one;
-            plan_classes(idxs[q]->classes, q, target_items(ctx) / count + 64, one, speeds, 1, -1);
+            plan_classes(idxs[q]->classes, q, inst_target[q], one, speeds, 1, -1);
             slot_pairs += one.slot_pairs;
             for (auto &v : one.by_variant)
                 flat.insert(flat.end(), v.begin(), v.end());
@@ -2077,6 +2083,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
             return e;
         L.cap_descs = nq;
     }
+    std::vector<std::vector<Cls>> q_cls(nq);
     for (uint32_t j = 0; j < nq; j++) {
         SrvRequest &r = reqs[ids[j]];
         const uint32_t k = r.k;
@@ -2089,7 +2096,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         uint64_t *hg = reinterpret_cast<uint64_t *>(hpool + r.off + r.o_goff);
         uint32_t *ho = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_pos);
         uint32_t *hi = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_item);
-        std::vector<Cls> cls;
+        std::vector<Cls> &cls = q_cls[j];
         for (uint32_t t = 0; t < k; t++) {
             uint32_t p = ord[t];
             int32_t sp = sorted_pos[r.items[p]];
@@ -2102,10 +2109,6 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         }
         for (uint32_t p = 0; p < k; p++)
             hi[p] = r.items[p];
-        Plan plan;
-        plan_classes(cls, j, target_items(ix->ctx) / nq + 64, plan, nullptr, 1, -1);
-        for (auto &v : plan.by_variant)
-            flat.insert(flat.end(), v.begin(), v.end());
         InstDesc &d = L.h_descs[j];
         d.arena = reinterpret_cast<const uint4 *>(ix->arena.p);
         d.goff = reinterpret_cast<const uint64_t *>(dpool + r.off + r.o_goff);
@@ -2114,6 +2117,17 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         d.n_out = k;
         d.gb = ix->gb;
         d.pad = 0;
+    }
+    // the launch's items shared among its queries in proportion to their work
+    std::vector<double> q_work(nq);
+    for (uint32_t j = 0; j < nq; j++)
+        q_work[j] = class_work(q_cls[j]);
+    const std::vector<uint64_t> q_target = shared_targets(q_work, target_items(ix->ctx), 64);
+    for (uint32_t j = 0; j < nq; j++) {
+        Plan plan;
+        plan_classes(q_cls[j], j, q_target[j], plan, nullptr, 1, -1);
+        for (auto &v : plan.by_variant)
+            flat.insert(flat.end(), v.begin(), v.end());
     }
     XcdQueues queues;
     xcd_queues(flat, queues.off);

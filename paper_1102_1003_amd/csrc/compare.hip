@@ -527,7 +527,7 @@ __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__rest
 
 
 // One persistent launch for items of every shape the single-launch forms use
-// (row-resident 128 x 16, 128 x 12 and 128 x 8 two row groups per step,
+// (row-resident, two row groups per step: 192 x 12, 128 x 12, 128 x 8 and
 // 128 x 4; body codes 0..3): the shape travels in the item's flags (bits
 // 2..4) and selects the specialised body.
 __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
@@ -551,10 +551,10 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
             const WorkItem w = items[base + it];
             const InstDesc d = descs ? descs[w.inst] : d0;
             switch ((w.flags >> 2) & 7u) {
-            case 0: process_rows<2, 16>(w, d); break;
+            case 0: process_rows<3, 12, 2>(w, d); break;
             case 1: process_rows<2, 12, 2>(w, d); break;
             case 2: process_rows<2, 8, 2>(w, d); break;
-            default: process_rows<2, 4>(w, d); break;
+            default: process_rows<2, 4, 2>(w, d); break;
             }
         }
     }

@@ -19,10 +19,10 @@ const VariantInfo kInfo[kVariantCount] = {
     {256, 16, false, kStageGroups, -1, false, 0.60f},
     {256, 8, false, kStageGroups, -1, false, 0.60f},
     // row-resident, 64 R rows x MJ columns, one row group per step
-    {128, 16, true, 1, 0, true, 1.00f},
+    {128, 16, true, 1, -1, true, 1.00f},
     {128, 12, true, 1, -1, false, 1.00f},
     {128, 8, true, 1, -1, false, 0.92f},
-    {128, 4, true, 1, 3, true, 0.60f},
+    {128, 4, true, 1, -1, true, 0.60f},
     {256, 8, true, 1, -1, false, 0.85f},
     {64, 16, true, 1, -1, false, 0.65f},
     // row-resident, two row groups per step (one 64-byte scalar load per
@@ -41,13 +41,13 @@ const VariantInfo kInfo[kVariantCount] = {
     {2, 8, true, 64, -1, true, 0.30f},
     // row-resident, two row groups per step, 16 and 4 columns
     {128, 16, true, 2, -1, false, 1.20f},
-    {128, 4, true, 2, -1, false, 0.70f},
+    {128, 4, true, 2, 3, false, 0.70f},
     // row-resident, three rows per lane (192 x 12), two row groups per step.
     // Its rows are not prefetched (registers), so a step needs the wrapped
     // column groups of a wider class to hide their load: 5.54 ms against
     // 5.98 ms for 128 x 12 on the large Zipf instance, but 2.40 against 2.28
     // between maps of one width (the paper-replica instance).
-    {192, 12, true, 2, -1, true, 1.40f, 1.20f},
+    {192, 12, true, 2, 0, true, 1.40f, 1.20f},
 };
 
 }  // namespace
@@ -318,6 +318,30 @@ void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1])
         flat.insert(flat.end(), q[x].begin(), q[x].end());
         off[x + 1] = (uint32_t)flat.size();
     }
+}
+
+double class_work(const std::vector<Cls> &cls)
+{
+    double sp = 0;
+    for (size_t a = 0; a < cls.size(); a++)
+        for (size_t b = a; b < cls.size(); b++) {
+            const double pairs = a == b ? 0.5 * cls[a].count * (cls[a].count - 1.0)
+                                        : (double)cls[a].count * cls[b].count;
+            sp += pairs * 3.0 * std::max(cls[a].r, cls[b].r);
+        }
+    return sp;
+}
+
+std::vector<uint64_t> shared_targets(const std::vector<double> &work, uint64_t total, uint64_t floor)
+{
+    double sum = 0;
+    for (double w : work)
+        sum += w;
+    std::vector<uint64_t> t(work.size(), floor);
+    if (sum > 0)
+        for (size_t q = 0; q < work.size(); q++)
+            t[q] = std::max<uint64_t>(floor, (uint64_t)std::llround((double)total * work[q] / sum));
+    return t;
 }
 
 std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first)

@@ -92,6 +92,15 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
                   const std::vector<float> *speeds, int single, int pinned, bool cross_only = false);
 
+// Slot pairs compared by an all-pairs plan of the classes: the sum over
+// pairs of 3 max(r_i, r_j) (what plan_classes reports as slot_pairs).
+double class_work(const std::vector<Cls> &cls);
+
+// Items to ask of each of several plans run in one launch: `total` shared in
+// proportion to their work, so that items of all of them take about the same
+// time (at least `floor` each).
+std::vector<uint64_t> shared_targets(const std::vector<double> &work, uint64_t total, uint64_t floor);
+
 // Classes restricted to sorted indices >= first.
 std::vector<Cls> classes_from(const std::vector<Cls> &cls, uint32_t first);
 

@@ -211,7 +211,7 @@ def test_single_launch_and_every_default_shape(monkeypatch):
     rng = np.random.default_rng(44)
     q = rng.choice(n, size=150, replace=False).astype(np.uint32)
     ref_q = oracle.subset_pairs(off, tids, q)
-    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in (4, 7, 10, 11, 17, 18)]
+    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in (4, 7, 10, 11, 17, 18, 20, 21)]
     for key, val in settings:
         monkeypatch.setenv(key, val)
         c = bm.Context(0)
