@@ -156,6 +156,11 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, voi
 size_t radix_tmp_bytes(uint64_t n);
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2, uint64_t n, int key_bits,
                             void *tmp, hipStream_t s);
+// The same, with the first pass reading keys from keys_in (left untouched;
+// may be the caller's buffer) and, when bad is not null, setting bit 0 of
+// *bad if some key is >= limit.  The sorted keys end in `keys`.
+hipError_t radix_sort_pairs_from(const uint32_t *keys_in, uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2,
+                                 uint64_t n, int key_bits, void *tmp, uint32_t limit, uint32_t *bad, hipStream_t s);
 
 // Ingest.
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s);
@@ -168,6 +173,9 @@ hipError_t launch_mark_dups(const uint32_t *keys, const uint32_t *vals, uint64_t
 hipError_t launch_compact_pairs(const uint32_t *keys, const uint32_t *vals, const uint32_t *keep,
                                 const uint64_t *pos, uint64_t nnz, uint32_t *ko, uint32_t *vo, hipStream_t s);
 hipError_t launch_offsets_from_sorted(const uint32_t *keys, uint64_t nnz, uint32_t n, uint64_t *off, hipStream_t s);
+// The same, also adding to *n_dup the adjacent equal (key, value) pairs.
+hipError_t launch_offsets_and_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t n, uint64_t *off,
+                                  uint32_t *n_dup, hipStream_t s);
 hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t nnz, uint32_t m,
                                 uint32_t *flags, hipStream_t s);
 

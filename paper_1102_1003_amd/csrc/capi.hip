@@ -1331,53 +1331,63 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     HIPC(ctx, vals.alloc(N));
     HIPC(ctx, k2.alloc(N));
     HIPC(ctx, v2.alloc(N));
-    HIPC(ctx, flag.alloc(1));
-    st = copy_in(ctx, keys.p, items, nnz_in * 4);
-    if (st != BM_OK)
-        return st;
-    HIPC(ctx, fill_u32(flag.p, 1, 0, s));
-    if (dev_off)
-        HIPC(ctx, launch_check_offsets(row_off, m_txn, flag.p, s));
-    HIPC(ctx, launch_check_items(keys.p, nnz_in, n_items, flag.p, s));
-    uint32_t hflag = 0;
-    st = read_back(ctx, &hflag, flag.p, 4);
-    if (st != BM_OK)
-        return st;
-    if (hflag & 2u)
-        return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
-    if (hflag & 4u)
-        return fail(ctx, BM_EINVAL, "offsets decrease");
-    if (hflag)
-        return fail(ctx, BM_ERANGE, "an item id is >= n_items");
-    HIPC(ctx, launch_expand_rows(row_off, m_txn, vals.p, s));
-    HIPC(ctx, tmp.alloc(std::max(radix_tmp_bytes(N), scan_tmp_bytes(N))));
-    HIPC(ctx, radix_sort_pairs(keys.p, vals.p, k2.p, v2.p, nnz_in, bits_for(n_items - 1), tmp.p, s));
-    // drop an item repeated within one transaction (now adjacent equal pairs)
-    uint64_t nnz = nnz_in;
-    {
-        DevBuf<uint32_t> keep, ndup;
-        HIPC(ctx, keep.alloc(N));
-        HIPC(ctx, ndup.alloc(1));
-        HIPC(ctx, fill_u32(ndup.p, 1, 0, s));
-        HIPC(ctx, launch_mark_dups(keys.p, vals.p, nnz_in, keep.p, ndup.p, s));
-        uint32_t nd = 0;
-        st = read_back(ctx, &nd, ndup.p, 4);
+    HIPC(ctx, flag.alloc(2));
+    // device items are read in place by the sort's first pass, which also
+    // checks their range; host items are copied in first
+    const bool dev_items = ptr_kind(items) == PTR_DEVICE;
+    if (!dev_items) {
+        st = copy_in(ctx, keys.p, items, nnz_in * 4);
         if (st != BM_OK)
             return st;
-        if (nd) {
-            DevBuf<uint64_t> pos;
-            HIPC(ctx, pos.alloc(N));
-            HIPC(ctx, exclusive_scan_u32_to_u64(keep.p, pos.p, nnz_in, tmp.p, s));
-            HIPC(ctx, launch_compact_pairs(keys.p, vals.p, keep.p, pos.p, nnz_in, k2.p, v2.p, s));
-            HIPC(ctx, hipStreamSynchronize(s));
-            std::swap(keys.p, k2.p);
-            std::swap(vals.p, v2.p);
-            nnz = nnz_in - nd;
-        }
+    }
+    HIPC(ctx, fill_u32(flag.p, 2, 0, s));
+    if (dev_off) {
+        // the row offsets must hold before the expansion reads them
+        HIPC(ctx, launch_check_offsets(row_off, m_txn, flag.p, s));
+        uint32_t hflag = 0;
+        st = read_back(ctx, &hflag, flag.p, 4);
+        if (st != BM_OK)
+            return st;
+        if (hflag & 2u)
+            return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+        if (hflag & 4u)
+            return fail(ctx, BM_EINVAL, "offsets decrease");
+    }
+    HIPC(ctx, launch_expand_rows(row_off, m_txn, vals.p, s));
+    HIPC(ctx, tmp.alloc(std::max(radix_tmp_bytes(N), scan_tmp_bytes(N))));
+    HIPC(ctx, radix_sort_pairs_from(dev_items ? static_cast<const uint32_t *>(items) : keys.p, keys.p, vals.p, k2.p,
+                                    v2.p, nnz_in, bits_for(n_items - 1), tmp.p, n_items, flag.p, s));
+    if (nnz_in == 1)  // a single pair is not sorted: check its item here
+        HIPC(ctx, launch_check_items(keys.p, nnz_in, n_items, flag.p, s));
+    // item offsets, and a count of items repeated within one transaction
+    // (now adjacent equal pairs)
+    HIPC(ctx, idx->off.alloc((uint64_t)n_items + 1));
+    HIPC(ctx, launch_offsets_and_dups(keys.p, vals.p, nnz_in, n_items, idx->off.p, flag.p + 1, s));
+    uint32_t hf[2] = {0, 0};
+    st = read_back(ctx, hf, flag.p, 8);
+    if (st != BM_OK)
+        return st;
+    if (hf[0] & 1u)
+        return fail(ctx, BM_ERANGE, "an item id is >= n_items");
+    uint64_t nnz = nnz_in;
+    if (hf[1]) {
+        // drop the repeats, then the offsets again
+        DevBuf<uint32_t> keep, ndup;
+        DevBuf<uint64_t> pos;
+        HIPC(ctx, keep.alloc(N));
+        HIPC(ctx, ndup.alloc(1));
+        HIPC(ctx, pos.alloc(N));
+        HIPC(ctx, fill_u32(ndup.p, 1, 0, s));
+        HIPC(ctx, launch_mark_dups(keys.p, vals.p, nnz_in, keep.p, ndup.p, s));
+        HIPC(ctx, exclusive_scan_u32_to_u64(keep.p, pos.p, nnz_in, tmp.p, s));
+        HIPC(ctx, launch_compact_pairs(keys.p, vals.p, keep.p, pos.p, nnz_in, k2.p, v2.p, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+        std::swap(keys.p, k2.p);
+        std::swap(vals.p, v2.p);
+        nnz = nnz_in - hf[1];
+        HIPC(ctx, launch_offsets_from_sorted(keys.p, nnz, n_items, idx->off.p, s));
     }
     idx->nnz = nnz;
-    HIPC(ctx, idx->off.alloc((uint64_t)n_items + 1));
-    HIPC(ctx, launch_offsets_from_sorted(keys.p, nnz, n_items, idx->off.p, s));
     idx->h_off.resize((size_t)n_items + 1);
     st = read_back(ctx, idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8);
     if (st != BM_OK)

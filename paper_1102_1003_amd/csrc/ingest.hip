@@ -119,6 +119,25 @@ __global__ void offsets_from_sorted_kernel(const uint32_t *keys, uint64_t nnz, u
     }
 }
 
+// offsets_from_sorted and, in the same pass, the number of adjacent equal
+// (key, value) pairs (an item repeated within one transaction).
+__global__ void offsets_and_dups_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t n,
+                                        uint64_t *off, uint32_t *n_dup)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t dups = 0;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nnz; k += stride) {
+        const uint32_t cur = k == nnz ? n : keys[k];
+        const uint32_t prev = k == 0 ? 0u : keys[k - 1];
+        uint32_t lo = k == 0 ? 0u : prev + 1u;  // first key not yet started
+        for (uint32_t a = lo; a <= cur && a <= n; a++)
+            off[a] = k;
+        dups += (k > 0 && k < nnz && cur == prev && vals[k] == vals[k - 1]) ? 1u : 0u;
+    }
+    if (dups)
+        atomicAdd(n_dup, dups);
+}
+
 // One block per set: every tid < m and strictly increasing.
 // flags[0] |= 1 on a range error, flags[1] |= 1 on an order error.
 __global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, uint32_t n, uint32_t m,
@@ -144,6 +163,13 @@ __global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, 
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s)
 {
     expand_rows_kernel<<<blocks_for(((uint64_t)m + 63) / 64 * 64, 8192), kBlock, 0, s>>>(row_off, m, row_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets_and_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t n, uint64_t *off,
+                                  uint32_t *n_dup, hipStream_t s)
+{
+    offsets_and_dups_kernel<<<blocks_for(nnz + 1, 4096), kBlock, 0, s>>>(keys, vals, nnz, n, off, n_dup);
     return hipGetLastError();
 }
 

@@ -152,8 +152,11 @@ hipError_t scan_rec(const In *in, Out *out, uint64_t n, char *tmp, hipStream_t s
 // wavefronts owns a quarter of the tile.  The digit of a pass has `bits` bits
 // (at most 8), so a pass has 2^bits buckets.
 
+// With `bad` set, keys >= limit also set bit 0 of *bad (a validation pass
+// folded into the first histogram).
 __global__ __launch_bounds__(256) void radix_hist_kernel(const uint32_t *keys, uint64_t n, int shift, int bits,
-                                                         uint32_t *hist, uint32_t tiles)
+                                                         uint32_t *hist, uint32_t tiles, uint32_t limit,
+                                                         uint32_t *bad)
 {
     __shared__ uint32_t h[256];
     const uint32_t nb = 1u << bits, mask = nb - 1u;
@@ -162,11 +165,17 @@ __global__ __launch_bounds__(256) void radix_hist_kernel(const uint32_t *keys, u
     __syncthreads();
     const uint32_t t = blockIdx.x;
     const uint64_t base = (uint64_t)t * kRadixTile;
+    bool out = false;
     for (int r = 0; r < kRadixTile / 256; r++) {
         uint64_t idx = base + (uint64_t)r * 256 + threadIdx.x;
-        if (idx < n)
-            atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+        if (idx < n) {
+            const uint32_t k = keys[idx];
+            out |= k >= limit;
+            atomicAdd(&h[(k >> shift) & mask], 1u);
+        }
     }
+    if (bad && out)
+        atomicOr(bad, 1u);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
         hist[(uint64_t)i * tiles + t] = h[i];
@@ -318,14 +327,26 @@ size_t radix_tmp_bytes(uint64_t n)
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2, uint64_t n, int key_bits,
                             void *tmp, hipStream_t s)
 {
-    if (n <= 1 || key_bits <= 0)
+    return radix_sort_pairs_from(keys, keys, vals, k2, v2, n, key_bits, tmp, 0, nullptr, s);
+}
+
+hipError_t radix_sort_pairs_from(const uint32_t *keys_in, uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32_t *v2,
+                                 uint64_t n, int key_bits, void *tmp, uint32_t limit, uint32_t *bad, hipStream_t s)
+{
+    if (n <= 1 || key_bits <= 0) {
+        if (n == 1 && keys_in != keys)
+            return hipMemcpyAsync(keys, keys_in, sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
         return hipSuccess;
+    }
     uint32_t tiles = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
     char *base = reinterpret_cast<char *>(tmp);
     uint32_t *hist = reinterpret_cast<uint32_t *>(base);
     uint32_t *hoff = reinterpret_cast<uint32_t *>(base + align256((uint64_t)tiles * 256 * sizeof(uint32_t)));
     char *stmp = base + 2 * align256((uint64_t)tiles * 256 * sizeof(uint32_t));
-    uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+    // pass p reads the previous pass's output (the first reads keys_in) and
+    // writes k2 when p is even, keys when odd; values alternate vals -> v2
+    const uint32_t *ka = keys_in;
+    uint32_t *va = vals, *vb = v2;
     // as few passes as 8-bit digits need, with the bits spread evenly over
     // them: fewer buckets per pass give longer contiguous runs per tile
     const int passes = (key_bits + 7) / 8;
@@ -333,20 +354,22 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *k2, uint32
     for (int p = 0; p < passes; p++) {
         const int bits = (key_bits - shift + (passes - p) - 1) / (passes - p);
         const uint64_t h = (uint64_t)tiles << bits;
-        radix_hist_kernel<<<tiles, kBlock, 0, s>>>(ka, n, shift, bits, hist, tiles);
+        radix_hist_kernel<<<tiles, kBlock, 0, s>>>(ka, n, shift, bits, hist, tiles, limit, p == 0 ? bad : nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
         e = exclusive_scan_u32(hist, hoff, h, stmp, s);
         if (e != hipSuccess)
             return e;
+        uint32_t *kb = (p & 1) ? keys : k2;
         radix_scatter_kernel<<<tiles, kBlock, 0, s>>>(ka, va, n, shift, bits, hoff, tiles, kb, vb);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        uint32_t *t;
-        t = ka; ka = kb; kb = t;
-        t = va; va = vb; vb = t;
+        ka = kb;
+        uint32_t *t = va;
+        va = vb;
+        vb = t;
         shift += bits;
     }
     if (passes & 1) {
