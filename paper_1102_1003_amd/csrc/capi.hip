@@ -478,6 +478,36 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
     return BM_OK;
 }
 
+// Side streams: work queued on side[0 .. n) after fork_side starts after
+// everything queued on the context's stream so far, and work queued on the
+// context's stream after join_side waits for it (event waits, so graph
+// capture follows).
+bm_status fork_side(bm_context *ctx, int n)
+{
+    if (n <= 0)
+        return BM_OK;
+    if (!ctx->fork) {
+        for (int k = 0; k < bm_context::kSide; k++) {
+            HIPC(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+            HIPC(ctx, hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming));
+        }
+        HIPC(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    }
+    HIPC(ctx, hipEventRecord(ctx->fork, ctx->stream));
+    for (int k = 0; k < n; k++)
+        HIPC(ctx, hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
+    return BM_OK;
+}
+
+bm_status join_side(bm_context *ctx, int n)
+{
+    for (int k = 0; k < n; k++) {
+        HIPC(ctx, hipEventRecord(ctx->join[k], ctx->side[k]));
+        HIPC(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[k], 0));
+    }
+    return BM_OK;
+}
+
 bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<std::pair<int, uint32_t>> &ranges,
                       const InstDesc &d0)
 {
@@ -490,21 +520,11 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
         return BM_OK;
     }
     // the first shape on the context's stream, up to kSide more on side
-    // streams that start after everything queued so far and that the
-    // context's stream waits for (event waits, so graph capture follows)
+    // streams (see fork_side)
     const int n_side = std::min<int>((int)ranges.size() - 1, bm_context::kSide);
-    if (n_side > 0 && !ctx->fork) {
-        for (int k = 0; k < bm_context::kSide; k++) {
-            HIPC(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
-            HIPC(ctx, hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming));
-        }
-        HIPC(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-    }
-    if (n_side > 0) {
-        HIPC(ctx, hipEventRecord(ctx->fork, ctx->stream));
-        for (int k = 0; k < n_side; k++)
-            HIPC(ctx, hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
-    }
+    bm_status st = fork_side(ctx, n_side);
+    if (st != BM_OK)
+        return st;
     uint64_t at = 0;
     for (size_t i = 0; i < ranges.size(); i++) {
         const int k = (int)i - 1;
@@ -512,11 +532,7 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
         HIPC(ctx, launch_compare(items + at, ranges[i].second, nullptr, d0, ranges[i].first, s));
         at += ranges[i].second;
     }
-    for (int k = 0; k < n_side; k++) {
-        HIPC(ctx, hipEventRecord(ctx->join[k], ctx->side[k]));
-        HIPC(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[k], 0));
-    }
-    return BM_OK;
+    return join_side(ctx, n_side);
 }
 
 
@@ -741,17 +757,32 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         HIPC(ctx, fill_u32(counters.p, 4, 0, s));
         if (attempt)
             HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+        // LDS-built maps, one launch per width, on the side streams: they are
+        // bound by LDS and VALU work, the staged insertion below by device
+        // atomics, so the two overlap (disjoint maps and arena groups; the
+        // failure list and counters are shared through atomics)
+        int n_side = 0;
         if (p_lds > first_built) {
-            Span span_construct(ctx, PH_CONSTRUCT);
+            std::vector<std::pair<uint32_t, uint32_t>> runs;
             for (uint32_t p = first_built; p < p_lds;) {
                 uint32_t q = p + 1;
                 while (q < p_lds && width_of(q) == width_of(p))
                     q++;
-                HIPC(ctx, launch_lds_build(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
-                                           p, q - p, width_of(p), idx->perm, shift, idx->r0, o->max_loop,
-                                           idx->arena.p, failed_bits.p, idx->failed.p, counters.p + 1,
-                                           (uint32_t)fail_cap, counters.p + 3, s));
+                runs.push_back({p, q});
                 p = q;
+            }
+            n_side = std::min<int>((int)runs.size(), bm_context::kSide);
+            st = fork_side(ctx, n_side);
+            if (st != BM_OK)
+                return st;
+            // widest first: the longest launches start first
+            for (size_t i = 0; i < runs.size(); i++) {
+                const auto &run = runs[runs.size() - 1 - i];
+                HIPC(ctx, launch_lds_build(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
+                                           run.first, run.second - run.first, width_of(run.first), idx->perm, shift,
+                                           idx->r0, o->max_loop, idx->arena.p, failed_bits.p, idx->failed.p,
+                                           counters.p + 1, (uint32_t)fail_cap, counters.p + 3,
+                                           ctx->side[i % n_side]));
             }
         }
         for (const Batch &b : batches) {
@@ -772,6 +803,9 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift, idx->r0,
                                     codes.p, idx->arena.p, s));
         }
+        st = join_side(ctx, n_side);
+        if (st != BM_OK)
+            return st;
         // the all-pairs plan depends only on the width classes: make and
         // upload it on the host while the construction kernels run (indexes of
         // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
