@@ -206,12 +206,13 @@ hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const 
                          uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint8_t *scratch,
                          uint32_t *arena, hipStream_t s);
 hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
-// Maps of width r <= lds_build_max_r() (0 when LDS cannot hold any) can be
-// built whole in LDS: insertion, failures (recorded as the staged path
-// does) and encoding.  One launch builds the `count` maps of width r from
-// sorted index p_first on; *overflow is set when a map leaves more nestless
-// elements than the kernel can resolve (that map is then left unbuilt).
-uint32_t lds_build_max_r();
+// Maps of width r can be built whole in LDS (insertion, failures recorded as
+// the staged path does, encoding) when lds_build_field_bits(r, m) is not 0
+// (8: code bytes; 5: packed fields, for r up to 65536 when m <= 31 r).  One
+// launch builds the `count` maps of width r from sorted index p_first on;
+// *overflow is set when a map leaves more nestless elements than the kernel
+// can resolve (that map is then left unbuilt).
+int lds_build_field_bits(uint32_t r, uint32_t m);
 hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
                             const uint32_t *r_sorted, const uint64_t *goff, uint32_t p_first, uint32_t count, uint32_t r,
                             const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t max_loop, uint32_t *arena,

@@ -710,10 +710,10 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // in LDS, one launch per width; the rest go through staging in batches.
     // BM_LDS_BUILD=0 turns the LDS path off.
     const char *lds_env = getenv("BM_LDS_BUILD");
-    const uint32_t lds_r = (lds_env && atoi(lds_env) == 0) ? 0 : lds_build_max_r();
+    const bool lds_on = !(lds_env && atoi(lds_env) == 0);
     auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / 3); };
     uint32_t p_lds = first_built;
-    while (p_lds < n && width_of(p_lds) <= lds_r)
+    while (lds_on && p_lds < n && lds_build_field_bits(width_of(p_lds), m) != 0)
         p_lds++;
     std::vector<Batch> batches;
     std::vector<uint64_t> eb_all;

@@ -558,14 +558,16 @@ __global__ void __launch_bounds__(kBlock) bits_kernel(const uint32_t *__restrict
 }
 
 // ------------------------------------------------------- maps built in LDS
-// A map whose three tables fit in LDS as their final code bytes (3 r bytes,
-// plus 3 r indicator bits) is built whole by one workgroup: insertion
-// (Sec. II-A) by LDS exchanges, the failure policy of the staged path, the
-// indicators, then the encoding written straight to the arena.  A slot's
-// byte and its hash value fix the element it holds: code c at hash value q
-// of table t holds pi_t^-1((c << s) | (q mod 2^s)), because r >= r_0 >= 2^s.
-// So an evicted element is recovered with the inverse permutation and no
-// staging words are needed.
+// A map whose three tables fit in LDS is built whole by one workgroup:
+// insertion (Sec. II-A) by LDS exchanges, the failure policy of the staged
+// path, the indicators, then the encoding written straight to the arena.
+// Each slot holds a K-bit field h = pi_t(x) >> HS (all ones when empty)
+// beside its hash value q = pi_t(x) mod r, and the two fix the element:
+// x = pi_t^-1((h << HS) | (q mod 2^HS)).  So an evicted element is recovered
+// with the inverse permutation and no staging words are needed.  K = 8 with
+// HS = s stores the final code bytes (maps up to r = 32768 in 160 KB);
+// K = 5 with HS = log2 r packs six fields per word, which takes r = 65536
+// when m <= 31 r.
 constexpr uint32_t kLdsFailCap = 1024;  // nestless elements one map may leave
 
 struct LdsHead {
@@ -574,39 +576,61 @@ struct LdsHead {
     uint32_t elem[kLdsFailCap];
 };
 
+template <int K>
+struct LdsFields {
+    static constexpr uint32_t kPer = 32 / K;                      // fields per word
+    static constexpr uint32_t kEmpty = K == 8 ? 0x7Fu : (1u << K) - 1u;
+    static constexpr uint32_t kMask = (1u << K) - 1u;
+    static constexpr uint32_t kFill = K == 8 ? 0x7F7F7F7Fu : (uint32_t)((1ull << (kPer * K)) - 1);
+    __host__ __device__ static uint32_t words(uint32_t n) { return (n + kPer - 1) / kPer; }
+};
+
+template <int K>
 size_t lds_build_bytes(uint32_t r)
 {
-    return sizeof(LdsHead) + 3ull * r + 3ull * r / 8;
+    return sizeof(LdsHead) + 4ull * LdsFields<K>::words(3u * r) + 3ull * r / 8;
 }
 
-// Sets byte i of the LDS tables to v; returns the byte it held.
-__device__ inline uint32_t lds_swap_byte(uint32_t *W, uint32_t i, uint32_t v)
+// Sets field i of the LDS tables to v; returns the field it held.
+template <int K>
+__device__ inline uint32_t lds_swap(uint32_t *W, uint32_t i, uint32_t v)
 {
-    uint32_t *w = W + (i >> 2);
-    const uint32_t sh = (i & 3u) * 8u;
+    using Fd = LdsFields<K>;
+    uint32_t *w = W + i / Fd::kPer;
+    const uint32_t sh = (i % Fd::kPer) * K;
     uint32_t old = *w;
     for (;;) {
-        const uint32_t prev = atomicCAS(w, old, (old & ~(0xFFu << sh)) | (v << sh));
+        const uint32_t prev = atomicCAS(w, old, (old & ~(Fd::kMask << sh)) | (v << sh));
         if (prev == old)
-            return (old >> sh) & 0xFFu;
+            return (old >> sh) & Fd::kMask;
         old = prev;
     }
 }
 
-// Empties byte i of the LDS tables if it holds `code`.
-__device__ inline void lds_clear_byte(uint32_t *W, uint32_t i, uint32_t code)
+// Empties field i of the LDS tables if it holds h.
+template <int K>
+__device__ inline void lds_clear(uint32_t *W, uint32_t i, uint32_t h)
 {
-    uint32_t *w = W + (i >> 2);
-    const uint32_t sh = (i & 3u) * 8u;
+    using Fd = LdsFields<K>;
+    uint32_t *w = W + i / Fd::kPer;
+    const uint32_t sh = (i % Fd::kPer) * K;
     uint32_t old = *w;
-    while (((old >> sh) & 0xFFu) == code) {
-        const uint32_t prev = atomicCAS(w, old, (old & ~(0xFFu << sh)) | (0x7Fu << sh));
+    while (((old >> sh) & Fd::kMask) == h) {
+        const uint32_t prev = atomicCAS(w, old, (old & ~(Fd::kMask << sh)) | (Fd::kEmpty << sh));
         if (prev == old)
             break;
         old = prev;
     }
 }
 
+template <int K>
+__device__ inline uint32_t lds_get(const uint32_t *W, uint32_t i)
+{
+    using Fd = LdsFields<K>;
+    return (W[i / Fd::kPer] >> ((i % Fd::kPer) * K)) & Fd::kMask;
+}
+
+template <int K>
 __global__ void __launch_bounds__(kLdsBlock)
     lds_build_kernel(const uint32_t *__restrict__ tids, const uint64_t *__restrict__ off,
                      const uint32_t *__restrict__ sorted_items, const uint32_t *__restrict__ r_sorted,
@@ -614,22 +638,24 @@ __global__ void __launch_bounds__(kLdsBlock)
                      uint32_t max_loop, uint32_t *__restrict__ arena, uint32_t *failed_bits, uint32_t *failed,
                      uint32_t *n_failed, uint32_t fail_cap, uint32_t *overflow)
 {
+    using Fd = LdsFields<K>;
     extern __shared__ uint32_t lds_dyn[];
     LdsHead &H = *reinterpret_cast<LdsHead *>(lds_dyn);
     const uint32_t p = p_first + blockIdx.x;
     const uint32_t item = sorted_items[p];
     const uint32_t r = r_sorted[p];
     const uint32_t lr = 31u - (uint32_t)__builtin_clz(r);
-    uint32_t *W = lds_dyn + sizeof(LdsHead) / 4;  // tables 0, 1, 2: r code bytes each
-    uint32_t *IND = W + 3u * r / 4u;              // their indicator bits, 3 r / 32 words
-    const uint8_t *B = reinterpret_cast<const uint8_t *>(W);
+    const uint32_t hs = K == 8 ? shift : lr;       // a field is pi >> hs
+    uint32_t *W = lds_dyn + sizeof(LdsHead) / 4;   // tables 0, 1, 2: r fields each
+    const uint32_t n_words = Fd::words(3u * r);
+    uint32_t *IND = W + n_words;                   // their indicator bits, 3 r / 32 words
     const uint64_t e_first = off[item];
     const uint32_t n_el = (uint32_t)(off[item + 1] - e_first);
     const uint32_t *T = tids + e_first;
-    const uint32_t low = (1u << shift) - 1u;
+    const uint32_t low = (1u << hs) - 1u;
 
-    for (uint32_t i = threadIdx.x; i < 3u * r / 4u; i += blockDim.x)
-        W[i] = 0x7F7F7F7Fu;
+    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x)
+        W[i] = Fd::kFill;
     for (uint32_t i = threadIdx.x; i < 3u * r / 32u; i += blockDim.x)
         IND[i] = 0;
     if (threadIdx.x == 0)
@@ -663,11 +689,11 @@ __global__ void __launch_bounds__(kLdsBlock)
             }
             const uint32_t y = perm_eval_lane(P, (int)tb, tau);
             const uint32_t q = y & (r - 1u);
-            const uint32_t old = lds_swap_byte(W, (tb << lr) + q, y >> shift);
-            if (old == 0x7Fu) {
+            const uint32_t old = lds_swap<K>(W, (tb << lr) + q, y >> hs);
+            if (old == Fd::kEmpty) {
                 busy = false;
             } else {
-                tau = perm_inverse_lane(P, (int)tb, (old << shift) | (q & low));
+                tau = perm_inverse_lane(P, (int)tb, (old << hs) | (q & low));
                 tb = tb == 2u ? 0u : tb + 1u;
                 left--;
             }
@@ -688,7 +714,7 @@ __global__ void __launch_bounds__(kLdsBlock)
         const uint32_t tau = H.elem[f];
         for (int t = 0; t < 3; t++) {
             const uint32_t y = perm_eval_lane(P, t, tau);
-            lds_clear_byte(W, ((uint32_t)t << lr) + (y & (r - 1u)), y >> shift);
+            lds_clear<K>(W, ((uint32_t)t << lr) + (y & (r - 1u)), y >> hs);
         }
         const int64_t k = find_tid(T, n_el, tau);
         if (k < 0)
@@ -717,7 +743,7 @@ __global__ void __launch_bounds__(kLdsBlock)
         for (int t = 0; t < 3; t++) {
             const uint32_t y = perm_eval(P, t, x);
             pos[t] = ((uint32_t)t << lr) + (y & (r - 1u));
-            in[t] = B[pos[t]] == (y >> shift);
+            in[t] = lds_get<K>(W, pos[t]) == (y >> hs);
         }
 #pragma unroll
         for (int t = 0; t < 3; t++)
@@ -728,32 +754,59 @@ __global__ void __launch_bounds__(kLdsBlock)
 
     // Encoding: a wavefront per 8 groups (256 slots of the Fig. 4 layout),
     // lane = (group, plane).  A group's 32 slots are 32 consecutive hash
-    // values of one table (r_0 >= 128), so its code bytes are 32 consecutive
-    // LDS bytes and its indicators one LDS word.  Plane b < 7 gathers bit b
-    // of the 32 bytes, four at a time by a dot product with 1, 2, 4, 8.
+    // values of one table (r_0 >= 128) and its indicators one LDS word.
+    // Plane b < 7 gathers bit b of the group's 32 code bytes, four at a time
+    // by a dot product with 1, 2, 4, 8.  With K = 8 the code bytes are the
+    // fields themselves; otherwise each lane first writes the codes of four
+    // slots, (pi >> s), into a per-wavefront byte area (the failure list's,
+    // free by now).
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
     const uint32_t n_waves = blockDim.x / 64u;
     const uint32_t plane = lane & 7u;
     uint32_t *out = arena + goff[p] * kWordsPerGroup;
+    uint32_t *cbuf = lds_dyn + wave * 64u;  // K < 8: 256 code bytes of this wavefront
     for (uint32_t v0 = wave * 256u; v0 < 3u * r; v0 += n_waves * 256u) {
-        const uint32_t v = v0 + (lane >> 3) * kSlotsPerGroup;
-        if (v >= 3u * r)
-            continue;
-        const uint32_t a = v >> lr0;
-        const uint32_t t = a % 3u;
-        const uint32_t q = ((a / 3u) << lr0) | (v & ((1u << lr0) - 1u));
-        const uint32_t i0 = (t << lr) + q;  // a multiple of 32
-        const uint4 lo = *reinterpret_cast<const uint4 *>(B + i0);
-        const uint4 hi = *reinterpret_cast<const uint4 *>(B + i0 + 16);
-        const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-        uint32_t word = 0;
+        if (K != 8) {
+            uint32_t packed = 0;
 #pragma unroll
-        for (int k = 0; k < 8; k++)
-            word |= __builtin_amdgcn_udot4((d[k] >> plane) & 0x01010101u, 0x08040201u, 0u, false) << (4 * k);
-        if (plane == 7u)
-            word = IND[i0 >> 5];
-        out[(uint64_t)v / kSlotsPerGroup * kWordsPerGroup + plane] = word;
+            for (int c = 0; c < 4; c++) {
+                const uint32_t v = v0 + 4u * lane + c;
+                uint32_t code = 0x7Fu;
+                if (v < 3u * r) {
+                    const uint32_t a = v >> lr0;
+                    const uint32_t t = a % 3u;
+                    const uint32_t q = ((a / 3u) << lr0) | (v & ((1u << lr0) - 1u));
+                    const uint32_t h = lds_get<K>(W, (t << lr) + q);
+                    if (h != Fd::kEmpty)
+                        code = ((h << hs) | q) >> shift;
+                }
+                packed |= code << (8 * c);
+            }
+            cbuf[lane] = packed;
+            wave_lds_sync();
+        }
+        const uint32_t v = v0 + (lane >> 3) * kSlotsPerGroup;
+        if (v < 3u * r) {
+            const uint32_t a = v >> lr0;
+            const uint32_t t = a % 3u;
+            const uint32_t q = ((a / 3u) << lr0) | (v & ((1u << lr0) - 1u));
+            const uint32_t i0 = (t << lr) + q;  // a multiple of 32
+            const uint8_t *src = K == 8 ? reinterpret_cast<const uint8_t *>(W) + i0
+                                        : reinterpret_cast<const uint8_t *>(cbuf) + (lane >> 3) * kSlotsPerGroup;
+            const uint4 lo = *reinterpret_cast<const uint4 *>(src);
+            const uint4 hi = *reinterpret_cast<const uint4 *>(src + 16);
+            const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            uint32_t word = 0;
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                word |= __builtin_amdgcn_udot4((d[k] >> plane) & 0x01010101u, 0x08040201u, 0u, false) << (4 * k);
+            if (plane == 7u)
+                word = IND[i0 >> 5];
+            out[(uint64_t)v / kSlotsPerGroup * kWordsPerGroup + plane] = word;
+        }
+        if (K != 8)
+            wave_lds_sync();  // the next iteration rewrites cbuf
     }
 }
 
@@ -924,7 +977,9 @@ hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const 
     return hipGetLastError();
 }
 
-uint32_t lds_build_max_r()
+namespace {
+
+int lds_limit()
 {
     static int limit = -1;
     if (limit < 0) {
@@ -932,16 +987,37 @@ uint32_t lds_build_max_r()
         limit = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(lds_build_kernel),
+            hipFuncSetAttribute(reinterpret_cast<const void *>(lds_build_kernel<8>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(lds_build_kernel<5>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess)
             limit = bytes;
         (void)hipGetLastError();
     }
+    return limit;
+}
+
+template <int K>
+uint32_t max_r_for()
+{
     uint32_t r = 0;
     for (uint32_t c = kMinR0; c <= (1u << 20); c <<= 1)
-        if (lds_build_bytes(c) <= (uint64_t)limit)
+        if (lds_build_bytes<K>(c) <= (uint64_t)lds_limit())
             r = c;
     return r;
+}
+
+}  // namespace
+
+int lds_build_field_bits(uint32_t r, uint32_t m)
+{
+    if (r <= max_r_for<8>())
+        return 8;
+    // five-bit fields: pi >> log2 r must stay below the all-ones empty mark
+    const uint32_t lr = 31u - (uint32_t)__builtin_clz(r);
+    if (r <= max_r_for<5>() && m > 0 && ((m - 1u) >> lr) < LdsFields<5>::kEmpty)
+        return 5;
+    return 0;
 }
 
 hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
@@ -952,15 +1028,22 @@ hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uin
 {
     if (count == 0)
         return hipSuccess;
-    if (r > lds_build_max_r() || (r & (r - 1)) || r < r0)
+    const int K = lds_build_field_bits(r, P.m);
+    if (K == 0 || (r & (r - 1)) || r < r0)
         return hipErrorInvalidValue;
-    const size_t lds = lds_build_bytes(r);
+    const size_t lds = K == 8 ? lds_build_bytes<8>(r) : lds_build_bytes<5>(r);
     // A CU holds 160 KB of LDS and 32 wavefronts: a workgroup of 16 wavefronts
     // where only one fits by LDS, else of 8.
     const int threads = lds > 160u * 1024u / 2u ? kLdsBlock : kLdsBlock / 2;
-    lds_build_kernel<<<count, threads, lds, s>>>(tids, off, sorted_items, r_sorted, goff, p_first, P, shift,
-                                                  31u - (uint32_t)__builtin_clz(r0), max_loop, arena, failed_bits,
-                                                  failed, n_failed, fail_cap, overflow);
+    const uint32_t lr0 = 31u - (uint32_t)__builtin_clz(r0);
+    if (K == 8)
+        lds_build_kernel<8><<<count, threads, lds, s>>>(tids, off, sorted_items, r_sorted, goff, p_first, P, shift, lr0,
+                                                        max_loop, arena, failed_bits, failed, n_failed, fail_cap,
+                                                        overflow);
+    else
+        lds_build_kernel<5><<<count, threads, lds, s>>>(tids, off, sorted_items, r_sorted, goff, p_first, P, shift, lr0,
+                                                        max_loop, arena, failed_bits, failed, n_failed, fail_cap,
+                                                        overflow);
     return hipGetLastError();
 }
 

@@ -99,6 +99,22 @@ def test_power_of_two_set_sizes(ctx):
         np.testing.assert_array_equal(supports_dev(idx, len(lists)), oracle.all_pairs(off, tids))
 
 
+def test_packed_field_lds_build(ctx):
+    """Maps of width 65536 (|S| in 16385..32768) are built in LDS with 5-bit fields when m <= 31 r;
+    with m above that bound they go through staging.  Both, with and without failures."""
+    rng = np.random.default_rng(12)
+    for m in (200_000, 2_500_000):
+        sizes = [20_000, 25_000, 32_768, 16_385, 9_000, 300]
+        lists = [np.sort(rng.choice(m, size=s, replace=False)).astype(np.uint32) for s in sizes]
+        off = np.zeros(len(lists) + 1, dtype=np.uint64)
+        np.cumsum([len(x) for x in lists], out=off[1:])
+        tids = np.concatenate(lists)
+        ref = oracle.all_pairs(off, tids)
+        for ml in (64, 1):
+            idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=ml)
+            np.testing.assert_array_equal(supports_dev(idx, len(lists)), ref, err_msg=f"m={m} max_loop={ml}")
+
+
 def test_edge_shapes(ctx):
     # n = 1: no pairs; n = 2; m = 1; all-empty; identical sets; full sets
     for m, lists in [
