@@ -5,6 +5,8 @@
 // int32 accumulation, exact while m < 2^31).  Only tiles on or above the
 // diagonal are computed; the contraction dimension may be split across
 // workgroups, partial sums being added atomically.
+#include <algorithm>
+
 #include "bm_internal.h"
 
 namespace bm {
@@ -45,14 +47,27 @@ __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
 // traffic of a 128 x 128 tile.
 constexpr int DTHREADS = 512;
 
+// Workgroup b runs on XCD b mod kXcds.  The contraction chunks are dealt to
+// the XCDs (chunk c to XCD c mod kXcds) and, within an XCD, the workgroups of
+// one chunk take every tile on or above the diagonal: they run at the same
+// time and read the same T row panels over the same bytes, so each panel's
+// lines come from HBM once per XCD and serve T tiles from its L2.
 __global__ __launch_bounds__(DTHREADS, 1) void dense_gram_kernel(const int8_t *__restrict__ A, uint32_t n,
                                                                  uint64_t ld, uint64_t k_len, uint32_t T,
-                                                                 uint64_t k_chunk, uint32_t *out)
+                                                                 uint64_t k_chunk, uint32_t n_chunks, uint32_t *out)
 {
-    const uint32_t ti = blockIdx.x / T, tj = blockIdx.x % T;
-    if (ti > tj)
+    const uint32_t n_tiles = T * (T + 1) / 2;
+    const uint32_t x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    const uint32_t kc = x + kXcds * (slot / n_tiles);
+    if (kc >= n_chunks)
         return;
-    const uint64_t k0 = (uint64_t)blockIdx.y * k_chunk;
+    uint32_t tile = slot % n_tiles, ti = 0;
+    while (tile >= T - ti) {  // row ti holds tiles (ti, ti) .. (ti, T - 1)
+        tile -= T - ti;
+        ti++;
+    }
+    const uint32_t tj = ti + tile;
+    const uint64_t k0 = (uint64_t)kc * k_chunk;
     const uint64_t k1 = k0 + k_chunk < k_len ? k0 + k_chunk : k_len;
     __shared__ __attribute__((aligned(16))) int8_t sA[DT][DK + DPAD];
     __shared__ __attribute__((aligned(16))) int8_t sB[DT][DK + DPAD];
@@ -150,12 +165,18 @@ hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t 
                              uint32_t k_split, hipStream_t s)
 {
     uint32_t T = (n + DT - 1) / DT;
-    if (T == 0)
+    if (T == 0 || k_len == 0)
         return hipSuccess;
-    uint64_t chunk = (k_len + k_split - 1) / k_split;
+    // a multiple of kXcds contraction chunks, so every XCD gets as many
+    const uint64_t want = ((uint64_t)std::max<uint32_t>(k_split, 1) + kXcds - 1) / kXcds * kXcds;
+    uint64_t chunk = (k_len + want - 1) / want;
     chunk = (chunk + DK - 1) / DK * DK;
-    uint32_t ks = (uint32_t)((k_len + chunk - 1) / chunk);
-    dense_gram_kernel<<<dim3(T * T, ks), DTHREADS, 0, s>>>(A, n, ld, k_len, T, chunk, out);
+    const uint32_t ks = (uint32_t)((k_len + chunk - 1) / chunk);
+    const uint64_t n_tiles = (uint64_t)T * (T + 1) / 2;
+    const uint64_t grid = n_tiles * ((ks + kXcds - 1) / kXcds * kXcds);
+    if (grid > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
+    dense_gram_kernel<<<(uint32_t)grid, DTHREADS, 0, s>>>(A, n, ld, k_len, T, chunk, ks, out);
     return hipGetLastError();
 }
 
