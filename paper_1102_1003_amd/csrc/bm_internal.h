@@ -239,12 +239,18 @@ uint32_t multi_persistent_grid(uint32_t n_cu);
 struct XcdQueues {
     uint32_t off[kXcds + 1];
 };
+// Queue counters sit kQueueStride words apart, each in a line of its own:
+// atomics of eight XCDs on one shared line serialise where it is kept.
+constexpr uint32_t kQueueStride = 64;
+constexpr uint32_t kQueueCounterWords = kXcds * kQueueStride;
 // Items of the row-resident single-launch shapes (body codes 0..3) as one
 // persistent launch on s.  Workgroups drain the queue of their own XCD, then
-// take what is left in the others.  counters[0..kXcds) must be zero.
-// descs == nullptr: every item uses d0.
+// take what is left in the others.  counters[0 .. kQueueCounterWords) must be
+// zero.  Item w uses descs[w.inst] (device memory).
 hipError_t launch_compare_multi_persistent(const WorkItem *items, const XcdQueues &q, const InstDesc *descs,
-                                           const InstDesc &d0, uint32_t *counters, uint32_t grid, hipStream_t s);
+                                           uint32_t *counters, uint32_t grid, hipStream_t s);
+// *dst = d, stream-ordered (a kernel, so graph capture records it).
+hipError_t launch_store_desc(InstDesc *dst, const InstDesc &d, hipStream_t s);
 
 
 // Threshold + compaction.

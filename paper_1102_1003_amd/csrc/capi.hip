@@ -196,7 +196,8 @@ struct bm_context {
     bool own_stream = false;
     int n_cu = 256;
     std::string err;
-    DevBuf<uint32_t> counter;  // persistent-kernel work counter
+    DevBuf<uint32_t> counter;  // persistent-kernel work counters
+    DevBuf<InstDesc> desc1;    // the instance of a single-call persistent compare
     std::shared_ptr<AllocStream> as;  // stream-ordered allocation on `stream` (null: plain hipMalloc)
     // pinned staging of work lists: uploads are asynchronous; `staged` marks
     // the end of the last upload, before which the buffer is not rewritten
@@ -515,8 +516,9 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
         XcdQueues q;
         for (uint32_t x = 0; x <= kXcds; x++)
             q.off[x] = ranges[x].second;
-        HIPC(ctx, fill_u32(ctx->counter.p, kXcds, 0, ctx->stream));
-        HIPC(ctx, launch_compare_multi_persistent(items, q, nullptr, d0, ctx->counter.p, ctx->grid, ctx->stream));
+        HIPC(ctx, fill_u32(ctx->counter.p, kQueueCounterWords, 0, ctx->stream));
+        HIPC(ctx, launch_store_desc(ctx->desc1.p, d0, ctx->stream));
+        HIPC(ctx, launch_compare_multi_persistent(items, q, ctx->desc1.p, ctx->counter.p, ctx->grid, ctx->stream));
         return BM_OK;
     }
     // the first shape on the context's stream, up to kSide more on side
@@ -918,12 +920,12 @@ bm_status count_pairs(bm_index *idx, uint32_t first, uint32_t *out)
 
 hipError_t bm_batch::enqueue(hipStream_t s)
 {
-    hipError_t e = fill_u32(counter.p, kXcds, 0, s);
+    hipError_t e = fill_u32(counter.p, kQueueCounterWords, 0, s);
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         if (n_pairs(idx[q]->n))
             e = fill_u32(outs[q], n_pairs(idx[q]->n), 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(items.p, queues, descs.p, InstDesc{}, counter.p, grid, s);
+        e = launch_compare_multi_persistent(items.p, queues, descs.p, counter.p, grid, s);
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         e = launch_apply_corrections(idx[q]->corr.p, idx[q]->n_corr, outs[q], idx[q]->n, s);
     return e;
@@ -1064,7 +1066,10 @@ bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
         ctx->n_cu = prop.multiProcessorCount;
     // BM_COMPARE_PERSISTENT=1 runs single-call compares as one multi-shape
     // persistent launch (tuning aid).  The default, one launch per tile shape,
-    // is faster there: each shape's kernel keeps its own, higher occupancy.
+    // is faster there on the same items: its waves retire after one item, so
+    // the hardware's oldest-first issue order keeps changing hands, while
+    // persistent waves keep their ages and the oldest wave of each SIMD takes
+    // most of the issue slots.
     const char *pe = getenv("BM_COMPARE_PERSISTENT");
     ctx->persistent = pe && pe[0] == '1';
     ctx->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
@@ -1085,7 +1090,7 @@ bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
             (void)hipGetLastError();
         }
     }
-    if (ctx->counter.alloc(kXcds) != hipSuccess) {
+    if (ctx->counter.alloc(kQueueCounterWords) != hipSuccess || ctx->desc1.alloc(1) != hipSuccess) {
         (void)hipGetLastError();
         if (ctx->own_stream)
             (void)hipStreamDestroy(ctx->stream);
@@ -1104,6 +1109,7 @@ void bm_context_destroy(bm_context *ctx)
     if (ctx->stream)
         (void)hipStreamSynchronize(ctx->stream);
     ctx->counter.reset();
+    ctx->desc1.reset();
     if (ctx->as) {
         ctx->as->release();
         std::lock_guard<std::mutex> lk(ctx->as->mu);
@@ -1762,7 +1768,7 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
     b->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     HIPC(ctx, b->descs.alloc(count));
     HIPC(ctx, b->items.alloc(std::max<uint64_t>(std::max(flat.size(), cand.size()), 1)));
-    HIPC(ctx, b->counter.alloc(kXcds));
+    HIPC(ctx, b->counter.alloc(kQueueCounterWords));
     HIPC(ctx, hipMemcpyAsync(b->descs.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
     if (tuned) {
         hipEvent_t e0, e1;
@@ -2202,9 +2208,9 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
             e = fill_u32(reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), (uint64_t)r.k * (r.k - 1) / 2, 0, s);
     }
     if (e == hipSuccess)
-        e = fill_u32(L.counter.p, kXcds, 0, s);
+        e = fill_u32(L.counter.p, kQueueCounterWords, 0, s);
     if (e == hipSuccess)
-        e = launch_compare_multi_persistent(L.items.p, queues, L.descs.p, InstDesc{}, L.counter.p,
+        e = launch_compare_multi_persistent(L.items.p, queues, L.descs.p, L.counter.p,
                                             grid, s);
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];
@@ -2377,7 +2383,7 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         SrvLaunch &L = *srv->launches.back();
         HIPC(ctx, hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
         HIPC(ctx, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
-        HIPC(ctx, L.counter.alloc(kXcds));
+        HIPC(ctx, L.counter.alloc(kQueueCounterWords));
         HIPC(ctx, L.flag.alloc(1));
     }
     bm_server *raw = srv.get();

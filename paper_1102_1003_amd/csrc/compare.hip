@@ -533,7 +533,7 @@ __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__rest
 __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const WorkItem *__restrict__ items,
                                                                            XcdQueues q,
                                                                            const InstDesc *__restrict__ descs,
-                                                                           InstDesc d0, uint32_t *counters)
+                                                                           uint32_t *counters)
 {
     // workgroup b runs on XCD b mod kXcds: its own queue first (the items
     // whose row tiles that XCD's L2 holds), then the rest of the others
@@ -544,12 +544,12 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
         for (;;) {
             uint32_t it = 0;
             if ((threadIdx.x & 63) == 0)
-                it = atomicAdd(&counters[x], 1u);
+                it = atomicAdd(&counters[x * kQueueStride], 1u);
             it = __builtin_amdgcn_readfirstlane(it);
             if (it >= size)
                 break;
             const WorkItem w = items[base + it];
-            const InstDesc d = descs ? descs[w.inst] : d0;
+            const InstDesc d = descs[w.inst];
             switch ((w.flags >> 2) & 7u) {
             case 0: process_rows<3, 12, 2>(w, d); break;
             case 1: process_rows<2, 12, 2>(w, d); break;
@@ -558,6 +558,12 @@ __global__ __launch_bounds__(64) void compare_rows_multi_persistent_kernel(const
             }
         }
     }
+}
+
+__global__ void store_desc_kernel(InstDesc *dst, InstDesc d)
+{
+    if (threadIdx.x == 0)
+        *dst = d;
 }
 
 
@@ -618,10 +624,16 @@ uint32_t multi_persistent_grid(uint32_t n_cu)
 }
 
 hipError_t launch_compare_multi_persistent(const WorkItem *items, const XcdQueues &q, const InstDesc *descs,
-                                           const InstDesc &d0, uint32_t *counters, uint32_t grid, hipStream_t s)
+                                           uint32_t *counters, uint32_t grid, hipStream_t s)
 {
     if (q.off[kXcds] > q.off[0])
-        compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, q, descs, d0, counters);
+        compare_rows_multi_persistent_kernel<<<grid, 64, 0, s>>>(items, q, descs, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_desc(InstDesc *dst, const InstDesc &d, hipStream_t s)
+{
+    store_desc_kernel<<<1, 64, 0, s>>>(dst, d);
     return hipGetLastError();
 }
 

@@ -307,17 +307,25 @@ void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1])
         queue_of[g] = best;
         load[best] += group_cost[g];
     }
-    std::vector<std::vector<WorkItem>> q(kXcds);
-    for (size_t t = 0; t < flat.size(); t++)
-        q[queue_of[item_group[t]]].push_back(flat[t]);
-    flat.clear();
+    // each queue: longest first; items of equal cost group by group, groups
+    // in the order they first appear (range-major), so the waves of one XCD
+    // work on one or two row tiles and one range at a time
+    std::vector<std::vector<uint32_t>> q(kXcds);
+    for (uint32_t t = 0; t < (uint32_t)flat.size(); t++)
+        q[queue_of[item_group[t]]].push_back(t);
+    std::vector<WorkItem> out;
+    out.reserve(flat.size());
     off[0] = 0;
     for (uint32_t x = 0; x < kXcds; x++) {
-        std::stable_sort(q[x].begin(), q[x].end(),
-                         [](const WorkItem &a, const WorkItem &b) { return item_cost(a) > item_cost(b); });
-        flat.insert(flat.end(), q[x].begin(), q[x].end());
-        off[x + 1] = (uint32_t)flat.size();
+        std::stable_sort(q[x].begin(), q[x].end(), [&](uint32_t a, uint32_t b) {
+            const uint64_t ca = item_cost(flat[a]), cb = item_cost(flat[b]);
+            return ca != cb ? ca > cb : item_group[a] < item_group[b];
+        });
+        for (uint32_t t : q[x])
+            out.push_back(flat[t]);
+        off[x + 1] = (uint32_t)out.size();
     }
+    flat.swap(out);
 }
 
 double class_work(const std::vector<Cls> &cls)

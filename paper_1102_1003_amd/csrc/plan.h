@@ -111,7 +111,9 @@ constexpr uint32_t kXcds = 8;
 // Work list of a single persistent launch, split into one queue per XCD:
 // items of one (instance, range, row tile) group share a queue (groups dealt
 // greedily to the least-loaded queue, largest first), each queue longest
-// first.  Queue x is items [off[x], off[x+1]) of the reordered list.
+// first and, among items of equal cost, group by group in the order the
+// groups first appear in `flat`.  Queue x is items [off[x], off[x+1]) of the
+// reordered list.
 void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1]);
 
 
