@@ -184,6 +184,14 @@ hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint3
 hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s);
 hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, uint32_t *flag, hipStream_t s);
 hipError_t launch_size_keys(const uint64_t *off, uint32_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
+// Size order (ascending size, ties by id) of n <= kSmallSortMax maps in one
+// launch: the order the radix sort of launch_size_keys' pairs gives.
+constexpr uint32_t kSmallSortMax = 4096;
+hipError_t launch_size_order_small(const uint64_t *off, uint32_t n, uint32_t *sorted_items, hipStream_t s);
+// sorted_pos[item] = sorted index (or -1 below first_built), has_map[item] =
+// whether its map is built.
+hipError_t launch_sorted_pos(const uint32_t *sorted_items, uint32_t n, uint32_t first_built, int32_t *sorted_pos,
+                             uint8_t *has_map, hipStream_t s);
 hipError_t launch_map_layout(const uint32_t *sorted_items, const uint64_t *off, uint32_t n, uint32_t first_built,
                              uint32_t r0, uint32_t *r_sorted, uint32_t *gcount, hipStream_t s);
 struct BuildBatch {

@@ -203,6 +203,9 @@ struct bm_context {
     // the end of the last upload, before which the buffer is not rewritten
     void *h_stage = nullptr;
     uint64_t h_stage_bytes = 0;
+    // pinned landing area of read-backs (several copies, one wait)
+    void *h_rb = nullptr;
+    uint64_t h_rb_bytes = 0;
     hipEvent_t staged = nullptr;
     // one persistent multi-shape launch per compare (else one launch per tile shape)
     bool persistent = false;
@@ -549,13 +552,51 @@ bm_status copy_in(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
     return BM_OK;
 }
 
+// Device-to-host copies queued on the context's stream, then one wait: each
+// lands in pinned memory (so the copies are asynchronous) and is moved to
+// its destination after the wait.
+struct ReadBack {
+    void *dst;
+    const void *src;
+    uint64_t bytes;
+};
+
+bm_status read_back_many(bm_context *ctx, std::initializer_list<ReadBack> reads)
+{
+    uint64_t total = 0;
+    for (const ReadBack &r : reads)
+        total += (r.bytes + 15) / 16 * 16;
+    if (total == 0)
+        return BM_OK;
+    if (ctx->h_rb_bytes < total) {
+        if (ctx->h_rb)
+            HIPC(ctx, hipHostFree(ctx->h_rb));
+        ctx->h_rb = nullptr;
+        ctx->h_rb_bytes = 0;
+        const uint64_t want = std::max<uint64_t>(total + total / 2, 1 << 16);
+        HIPC(ctx, hipHostMalloc(&ctx->h_rb, want));
+        ctx->h_rb_bytes = want;
+    }
+    char *h = static_cast<char *>(ctx->h_rb);
+    uint64_t at = 0;
+    for (const ReadBack &r : reads) {
+        if (r.bytes)
+            HIPC(ctx, hipMemcpyAsync(h + at, r.src, r.bytes, hipMemcpyDeviceToHost, ctx->stream));
+        at += (r.bytes + 15) / 16 * 16;
+    }
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    at = 0;
+    for (const ReadBack &r : reads) {
+        if (r.bytes)
+            memcpy(r.dst, h + at, r.bytes);
+        at += (r.bytes + 15) / 16 * 16;
+    }
+    return BM_OK;
+}
+
 bm_status read_back(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
 {
-    if (bytes == 0)
-        return BM_OK;
-    HIPC(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(ctx, hipStreamSynchronize(ctx->stream));
-    return BM_OK;
+    return read_back_many(ctx, {{dst, src, bytes}});
 }
 
 bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
@@ -616,57 +657,64 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         idx->perm = make_perm_spec(m, o->seed);
     }
 
-    // size order (Sec. III-C: sort by increasing width; ties by size then id)
-    uint32_t max_size = 0;
-    for (uint32_t i = 0; i < n; i++)
-        max_size = std::max<uint32_t>(max_size, (uint32_t)(idx->h_off[i + 1] - idx->h_off[i]));
-    {
+    // size order (Sec. III-C: sort by increasing width; ties by size then id).
+    // Maps below the support threshold are a prefix of that order, so their
+    // count comes from the sizes alone.
+    uint32_t max_size = 0, first_built = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const uint64_t sz = idx->h_off[i + 1] - idx->h_off[i];
+        max_size = std::max<uint32_t>(max_size, (uint32_t)std::min<uint64_t>(sz, 0xFFFFFFFFu));
+        if (sz < o->min_support)
+            first_built++;
+    }
+    idx->first_built = first_built;
+    HIPC(ctx, idx->sorted_items.alloc(n));
+    if (n <= kSmallSortMax) {
+        HIPC(ctx, launch_size_order_small(idx->off.p, n, idx->sorted_items.p, s));
+    } else {
         DevBuf<uint32_t> keys, k2, v2;
         DevBuf<char> tmp;
         HIPC(ctx, keys.alloc(n));
         HIPC(ctx, k2.alloc(n));
         HIPC(ctx, v2.alloc(n));
-        HIPC(ctx, idx->sorted_items.alloc(n));
         HIPC(ctx, tmp.alloc(radix_tmp_bytes(n)));
         HIPC(ctx, launch_size_keys(idx->off.p, n, keys.p, idx->sorted_items.p, s));
         HIPC(ctx, radix_sort_pairs(keys.p, idx->sorted_items.p, k2.p, v2.p, n, bits_for(max_size), tmp.p, s));
     }
-    idx->h_sorted_items.resize(n);
-    bm_status st = read_back(ctx, idx->h_sorted_items.data(), idx->sorted_items.p, (uint64_t)n * 4);
-    if (st != BM_OK)
-        return st;
-    idx->h_sizes_sorted.resize(n);
-    uint32_t first_built = 0;
-    for (uint32_t p = 0; p < n; p++) {
-        uint32_t it = idx->h_sorted_items[p];
-        idx->h_sizes_sorted[p] = (uint32_t)(idx->h_off[it + 1] - idx->h_off[it]);
-        if (idx->h_sizes_sorted[p] < o->min_support)
-            first_built = p + 1;
-    }
-    idx->first_built = first_built;
 
     // layout: r_i and group offsets
     HIPC(ctx, idx->r_sorted.alloc(n));
     HIPC(ctx, idx->goff.alloc((uint64_t)n + 1));
-    {
-        DevBuf<uint32_t> gcount;
-        DevBuf<char> tmp;
-        HIPC(ctx, gcount.alloc((uint64_t)n + 1));
-        HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
-        HIPC(ctx, tmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
-        HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
-                                    gcount.p, s));
-        HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, tmp.p, s));
-    }
+    DevBuf<uint32_t> gcount;
+    DevBuf<char> gtmp;
+    HIPC(ctx, gcount.alloc((uint64_t)n + 1));
+    HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
+    HIPC(ctx, gtmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
+    HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                gcount.p, s));
+    HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, gtmp.p, s));
+    // sorted_pos: item -> sorted index (or -1 when unbuilt); has_map for the
+    // corrections
+    DevBuf<uint8_t> has_map;
+    HIPC(ctx, idx->sorted_pos.alloc(n));
+    HIPC(ctx, has_map.alloc(std::max<uint32_t>(n, 1)));
+    HIPC(ctx, launch_sorted_pos(idx->sorted_items.p, n, first_built, idx->sorted_pos.p, has_map.p, s));
+    idx->h_sorted_items.resize(n);
     idx->h_r_sorted.resize(n);
     std::vector<uint64_t> &h_goff = idx->h_goff;
     h_goff.assign((size_t)n + 1, 0);
-    st = read_back(ctx, idx->h_r_sorted.data(), idx->r_sorted.p, (uint64_t)n * 4);
+    bm_status st = read_back_many(ctx, {{idx->h_sorted_items.data(), idx->sorted_items.p, (uint64_t)n * 4},
+                                        {idx->h_r_sorted.data(), idx->r_sorted.p, (uint64_t)n * 4},
+                                        {h_goff.data(), idx->goff.p, ((uint64_t)n + 1) * 8}});
     if (st != BM_OK)
         return st;
-    st = read_back(ctx, h_goff.data(), idx->goff.p, ((uint64_t)n + 1) * 8);
-    if (st != BM_OK)
-        return st;
+    gcount.reset();
+    gtmp.reset();
+    idx->h_sizes_sorted.resize(n);
+    for (uint32_t p = 0; p < n; p++) {
+        const uint32_t it = idx->h_sorted_items[p];
+        idx->h_sizes_sorted[p] = (uint32_t)(idx->h_off[it + 1] - idx->h_off[it]);
+    }
     idx->total_groups = h_goff[n];
     idx->classes.clear();
     for (uint32_t p = first_built; p < n; p++) {
@@ -674,16 +722,6 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         if (idx->classes.empty() || idx->classes.back().r != r)
             idx->classes.push_back({r, p, 0});
         idx->classes.back().count++;
-    }
-
-    // sorted_pos: item -> sorted index (or -1 when unbuilt)
-    {
-        std::vector<int32_t> sp(n, -1);
-        for (uint32_t p = first_built; p < n; p++)
-            sp[idx->h_sorted_items[p]] = (int32_t)p;
-        HIPC(ctx, idx->sorted_pos.alloc(n));
-        HIPC(ctx, hipMemcpyAsync(idx->sorted_pos.p, sp.data(), (uint64_t)n * 4, hipMemcpyHostToDevice, s));
-        HIPC(ctx, hipStreamSynchronize(s));
     }
 
     // construction, in batches of maps whose staging fits the budget
@@ -850,14 +888,8 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // corrections (Sec. III-C)
     {
         Span span_correct(ctx, PH_CORRECT);
-        std::vector<uint8_t> hm(n, 0);
-        for (uint32_t k = first_built; k < n; k++)
-            hm[idx->h_sorted_items[k]] = 1;
-        DevBuf<uint8_t> has_map;
         DevBuf<unsigned long long> cnt;
-        HIPC(ctx, has_map.alloc(n));
         HIPC(ctx, cnt.alloc(1));
-        HIPC(ctx, hipMemcpyAsync(has_map.p, hm.data(), n, hipMemcpyHostToDevice, s));
         HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
         HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p, failed_bits.p,
                                      has_map.p, n, nullptr, 0, cnt.p, s));
@@ -1117,6 +1149,8 @@ void bm_context_destroy(bm_context *ctx)
     }
     if (ctx->h_stage)
         (void)hipHostFree(ctx->h_stage);
+    if (ctx->h_rb)
+        (void)hipHostFree(ctx->h_rb);
     if (ctx->staged)
         (void)hipEventDestroy(ctx->staged);
     clear_phases(ctx, 0, PH_COUNT - 1);
@@ -1403,8 +1437,11 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     // (now adjacent equal pairs)
     HIPC(ctx, idx->off.alloc((uint64_t)n_items + 1));
     HIPC(ctx, launch_offsets_and_dups(keys.p, vals.p, nnz_in, n_items, idx->off.p, flag.p + 1, s));
+    // the flags and the item offsets come back together (the offsets are
+    // read again below in the rare case of repeats)
     uint32_t hf[2] = {0, 0};
-    st = read_back(ctx, hf, flag.p, 8);
+    idx->h_off.resize((size_t)n_items + 1);
+    st = read_back_many(ctx, {{hf, flag.p, 8}, {idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8}});
     if (st != BM_OK)
         return st;
     if (hf[0] & 1u)
@@ -1426,12 +1463,11 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
         std::swap(vals.p, v2.p);
         nnz = nnz_in - hf[1];
         HIPC(ctx, launch_offsets_from_sorted(keys.p, nnz, n_items, idx->off.p, s));
+        st = read_back(ctx, idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8);
+        if (st != BM_OK)
+            return st;
     }
     idx->nnz = nnz;
-    idx->h_off.resize((size_t)n_items + 1);
-    st = read_back(ctx, idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8);
-    if (st != BM_OK)
-        return st;
     // the sorted values are the tidlists
     idx->tids.p = vals.p;
     idx->tids.n = vals.n;

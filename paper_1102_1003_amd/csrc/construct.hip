@@ -102,6 +102,59 @@ __global__ void map_layout_kernel(const uint32_t *sorted_items, const uint64_t *
     }
 }
 
+// Size order of at most kSmallSortMax maps in one workgroup: keys (size, id)
+// are distinct, so any sort gives the order of a stable sort by size (the
+// radix path's); a bitonic network over the padded power of two in LDS.
+__global__ __launch_bounds__(1024) void size_order_small_kernel(const uint64_t *off, uint32_t n,
+                                                                 uint32_t *sorted_items)
+{
+    __shared__ uint64_t key[kSmallSortMax];
+    uint32_t len = 1;
+    while (len < n)
+        len <<= 1;
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        uint64_t k = ~0ull;
+        if (i < n) {
+            const uint64_t sz = off[i + 1] - off[i];
+            k = ((sz > 0xFFFFFFFFull ? 0xFFFFFFFFull : sz) << 32) | i;
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= len; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = key[i], b = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        sorted_items[i] = (uint32_t)key[i];
+}
+
+// sorted_pos[item] = its sorted index, or -1 for maps not built (sorted index
+// below first_built); has_map[item] = 1 for built maps.  sorted_items is a
+// permutation of 0..n-1, so every entry is written.
+__global__ void sorted_pos_kernel(const uint32_t *sorted_items, uint32_t n, uint32_t first_built,
+                                  int32_t *sorted_pos, uint8_t *has_map)
+{
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const uint32_t item = sorted_items[p];
+        const bool built = p >= first_built;
+        sorted_pos[item] = built ? (int32_t)p : -1;
+        has_map[item] = built ? 1 : 0;
+    }
+}
+
 // --------------------------------------------------------------- insertion
 
 __device__ inline uint32_t find_segment(const uint64_t *base, uint32_t count, uint64_t e)
@@ -896,6 +949,25 @@ hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, ui
 hipError_t launch_size_keys(const uint64_t *off, uint32_t n, uint32_t *keys, uint32_t *vals, hipStream_t s)
 {
     size_keys_kernel<<<blocks_for(n), kBlock, 0, s>>>(off, n, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_size_order_small(const uint64_t *off, uint32_t n, uint32_t *sorted_items, hipStream_t s)
+{
+    if (n > kSmallSortMax)
+        return hipErrorInvalidValue;
+    if (n == 0)
+        return hipSuccess;
+    size_order_small_kernel<<<1, 1024, 0, s>>>(off, n, sorted_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_sorted_pos(const uint32_t *sorted_items, uint32_t n, uint32_t first_built, int32_t *sorted_pos,
+                             uint8_t *has_map, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    sorted_pos_kernel<<<blocks_for(n), kBlock, 0, s>>>(sorted_items, n, first_built, sorted_pos, has_map);
     return hipGetLastError();
 }
 

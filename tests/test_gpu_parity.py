@@ -188,6 +188,25 @@ def test_exported_batmaps_pass_the_structural_check(ctx):
         assert np.all(np.diff(sizes.astype(np.int64)) >= 0)
 
 
+@pytest.mark.parametrize("n,min_support", [(1, 0), (37, 0), (4096, 3), (4097, 0), (9000, 5)])
+def test_size_order_is_by_size_then_id(ctx, n, min_support):
+    # one-workgroup sort up to 4096 maps, radix sort above: the same order
+    rng = np.random.default_rng(n)
+    m = 3000
+    sizes = rng.integers(0, 24, size=n)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=off[1:])
+    tids = np.concatenate([np.sort(rng.choice(m, size=int(k), replace=False)) for k in sizes]
+                          + [np.zeros(0, np.int64)]).astype(np.uint32)
+    idx = bm.Index.from_sets(ctx, m, off, tids, min_support=min_support)
+    ex = idx.export()
+    order = np.lexsort((np.arange(n), sizes))
+    np.testing.assert_array_equal(ex["sorted_items"], order[sizes[order] >= min_support])
+    for item, r in zip(ex["sorted_items"], ex["r"]):
+        assert r == oracle.r_for(int(sizes[item]), ex["stats"]["r0"])
+    idx.close()
+
+
 def test_generated_permutations_are_bijections(ctx):
     m = 1_234_567
     off = np.array([0, 3], dtype=np.uint64)
