@@ -885,26 +885,39 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     cand.reset();
     idx->n_failed = n_failed_total;
 
-    // corrections (Sec. III-C)
+    // corrections (Sec. III-C).  One pass into a list sized for the usual
+    // count (a failure pairs with the few maps whose sets hold its
+    // transaction; at most n - 1 of them); a second pass, into a list of the
+    // exact size, only when that was too small.
     {
         Span span_correct(ctx, PH_CORRECT);
-        DevBuf<unsigned long long> cnt;
-        HIPC(ctx, cnt.alloc(1));
-        HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
-        HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p, failed_bits.p,
-                                     has_map.p, n, nullptr, 0, cnt.p, s));
-        unsigned long long total = 0;
-        st = read_back(ctx, &total, cnt.p, 8);
-        if (st != BM_OK)
-            return st;
-        idx->n_corr = total;
-        HIPC(ctx, idx->corr.alloc(2 * std::max<uint64_t>(total, 1)));
-        if (total) {
+        idx->n_corr = 0;
+        HIPC(ctx, idx->corr.alloc(2));
+        if (idx->n_failed && n > 1) {
+            DevBuf<unsigned long long> cnt;
+            HIPC(ctx, cnt.alloc(1));
+            const uint64_t bound = idx->n_failed * (uint64_t)(n - 1);
+            uint64_t cap = std::min<uint64_t>(bound, std::max<uint64_t>(1u << 16, 64 * idx->n_failed));
+            // BM_CORR_CAP sets a lower first capacity (exercises the second pass)
+            if (const char *e = getenv("BM_CORR_CAP"))
+                if (atoll(e) > 0)
+                    cap = std::min<uint64_t>(cap, (uint64_t)atoll(e));
+            HIPC(ctx, idx->corr.alloc(2 * cap));
             HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
             HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p,
-                                         failed_bits.p, has_map.p, n, idx->corr.p, total, cnt.p, s));
+                                         failed_bits.p, has_map.p, n, idx->corr.p, cap, cnt.p, s));
+            unsigned long long total = 0;
+            st = read_back(ctx, &total, cnt.p, 8);
+            if (st != BM_OK)
+                return st;
+            if (total > cap) {
+                HIPC(ctx, idx->corr.alloc(2 * total));
+                HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
+                HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p,
+                                             failed_bits.p, has_map.p, n, idx->corr.p, total, cnt.p, s));
+            }
+            idx->n_corr = total;
         }
-        HIPC(ctx, hipStreamSynchronize(s));
     }
 
     return BM_OK;

@@ -85,6 +85,17 @@ def test_forced_failures_are_corrected(ctx, max_loop):
     np.testing.assert_array_equal(supports_dev(idx, 60), oracle.all_pairs(off, tids))
 
 
+@pytest.mark.parametrize("max_loop", [0, 1])
+def test_corrections_list_regrows(ctx, monkeypatch, max_loop):
+    # a first correction list of one entry: the exact-size second pass
+    monkeypatch.setenv("BM_CORR_CAP", "1")
+    off, tids = instance(12, 4000, 60, 0.0, 0.4)
+    idx = bm.Index.from_sets(ctx, 4000, off, tids, max_loop=max_loop)
+    assert idx.stats()["n_failed"] > 0
+    np.testing.assert_array_equal(supports_dev(idx, 60), oracle.all_pairs(off, tids))
+    idx.close()
+
+
 def test_power_of_two_set_sizes(ctx):
     """|S| a power of two gives load 1/3 (r = 2|S|): failures appear at MaxLoop 64 too."""
     m = 200_000
