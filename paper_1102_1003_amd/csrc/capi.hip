@@ -1379,16 +1379,25 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     idx->n = n_items;
     hipStream_t s = ctx->stream;
 
-    // Offsets in device memory are used in place and checked by a kernel (only
-    // their last entry, the incidence count, comes back first); host offsets
-    // are checked here and copied in.
+    // Offsets in device memory are used in place and checked by a kernel,
+    // whose verdict comes back with their last entry (the incidence count)
+    // before anything reads them; host offsets are checked here and copied in.
     const bool dev_off = ptr_kind(offsets) == PTR_DEVICE;
     uint64_t nnz_in = 0;
     std::vector<uint64_t> roff;
     if (dev_off) {
-        st = read_back(ctx, &nnz_in, offsets + m_txn, 8);
+        DevBuf<uint32_t> oflag;
+        HIPC(ctx, oflag.alloc(1));
+        HIPC(ctx, fill_u32(oflag.p, 1, 0, s));
+        HIPC(ctx, launch_check_offsets(offsets, m_txn, oflag.p, s));
+        uint32_t hflag = 0;
+        st = read_back_many(ctx, {{&nnz_in, offsets + m_txn, 8}, {&hflag, oflag.p, 4}});
         if (st != BM_OK)
             return st;
+        if (hflag & 2u)
+            return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
+        if (hflag & 4u)
+            return fail(ctx, BM_EINVAL, "offsets decrease");
     } else {
         roff.assign(offsets, offsets + (size_t)m_txn + 1);
         if (roff[0] != 0)
@@ -1428,18 +1437,6 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
             return st;
     }
     HIPC(ctx, fill_u32(flag.p, 2, 0, s));
-    if (dev_off) {
-        // the row offsets must hold before the expansion reads them
-        HIPC(ctx, launch_check_offsets(row_off, m_txn, flag.p, s));
-        uint32_t hflag = 0;
-        st = read_back(ctx, &hflag, flag.p, 4);
-        if (st != BM_OK)
-            return st;
-        if (hflag & 2u)
-            return fail(ctx, BM_EINVAL, "offsets[0] must be 0");
-        if (hflag & 4u)
-            return fail(ctx, BM_EINVAL, "offsets decrease");
-    }
     HIPC(ctx, launch_expand_rows(row_off, m_txn, vals.p, s));
     HIPC(ctx, tmp.alloc(std::max(radix_tmp_bytes(N), scan_tmp_bytes(N))));
     HIPC(ctx, radix_sort_pairs_from(dev_items ? static_cast<const uint32_t *>(items) : keys.p, keys.p, vals.p, k2.p,

@@ -329,6 +329,17 @@ def test_error_codes(ctx):
     assert e.value.status == bm.BM_EINVAL
 
 
+def test_device_transaction_offsets_are_checked(ctx):
+    items = dev(np.array([0, 1, 2], dtype=np.uint32))
+    for off in ([0, 3, 2], [1, 2, 3]):
+        with pytest.raises(bm.BatmapError) as e:
+            bm.Index.from_transactions(ctx, 4, dev(np.array(off, dtype=np.uint64)), items)
+        assert e.value.status == bm.BM_EINVAL
+    idx = bm.Index.from_transactions(ctx, 4, dev(np.array([0, 2, 3], dtype=np.uint64)), items)
+    np.testing.assert_array_equal(supports_dev(idx, 4), np.array([1, 0, 0, 0, 0, 0]))
+    idx.close()
+
+
 def test_pruned_build_frequent_pairs(ctx):
     m, n = 6000, 200
     off, tids = instance(61, m, n, 0.0, 0.1)
