@@ -19,6 +19,15 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
         p[i] = v;
 }
 
+__global__ void fill_u32x4_kernel(uint4 *p, uint64_t n4, uint32_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint4 w = make_uint4(v, v, v, v);
+    for (; i < n4; i += stride)
+        p[i] = w;
+}
+
 __global__ void fill_u8_kernel(uint8_t *p, uint64_t n, uint8_t v)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -285,6 +294,14 @@ hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
+    // large 16-byte aligned fills store 16 bytes per lane
+    if (n >= 4096 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        const uint64_t n4 = n / 4;
+        fill_u32x4_kernel<<<grid_for(n4), kBlock, 0, s>>>(reinterpret_cast<uint4 *>(p), n4, v);
+        if (n % 4)
+            fill_u32_kernel<<<1, kBlock, 0, s>>>(p + n4 * 4, n % 4, v);
+        return hipGetLastError();
+    }
     fill_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
