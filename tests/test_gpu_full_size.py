@@ -1,0 +1,105 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times: the
+transactions path on a borrowed stream, the batch's single graph launch, the dense comparator.
+The oracle cannot produce every support at these sizes, so each test checks sampled rows
+against it, plus properties that hold at any size (the closed-form sum of all supports, the
+frequent pairs as the σ filter of the full result)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+bm = pytest.importorskip("paper_1102_1003_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stream_ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    stream = torch.cuda.Stream(torch.device("cuda:0"))
+    torch.cuda.set_stream(stream)
+    c = bm.Context(0, stream)
+    yield c
+    c.close()
+    torch.cuda.set_stream(torch.cuda.default_stream(torch.device("cuda:0")))
+
+
+def closed_form_sum(m, tids):
+    # sum over all pairs of |S_i ∩ S_j| = sum over transactions of C(len, 2)
+    row_len = np.bincount(tids, minlength=m).astype(np.int64)
+    return int((row_len * (row_len - 1) // 2).sum())
+
+
+def check_rows(got, off, tids, n, rows):
+    ref = oracle.pair_rows(off, tids, np.asarray(rows, dtype=np.uint32))
+    for r_i, i in enumerate(rows):
+        for j in range(n):
+            if j == i:
+                continue
+            lo, hi = min(i, j), max(i, j)
+            assert got[int(oracle.packed_index(n, lo, hi))] == ref[r_i, j], (i, j)
+
+
+@pytest.mark.parametrize("w", [datagen.LARGE, datagen.PAPER_REPLICA], ids=lambda w: w.name)
+def test_transactions_step_full_size(stream_ctx, w):
+    ctx = stream_ctx
+    dev = torch.device("cuda:0")
+    off, tids = w.sets()
+    rows, items = datagen.sets_to_transactions(w.m, off, tids)
+    d_rows = torch.from_numpy(rows.view(np.int64)).to(dev)
+    d_items = torch.from_numpy(items.view(np.int32)).to(dev)
+    n_pairs = bm.n_pairs(w.n)
+    idx = bm.Index.from_transactions(ctx, w.n, d_rows, d_items)
+    out = torch.empty(n_pairs, dtype=torch.int32, device=dev)
+    idx.all_pair_supports(out)
+    d_fp = torch.empty(3 * n_pairs, dtype=torch.int32, device=dev)
+    k = idx.frequent_pairs_into(w.sigma, d_fp)
+    ctx.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    assert int(got.astype(np.int64).sum()) == closed_form_sum(w.m, tids)
+    # the frequent pairs are the σ filter of the full result, in (i, j) order
+    fp = d_fp[:3 * k].cpu().numpy().view(np.uint32).reshape(-1, 3)
+    keep = np.nonzero(got >= w.sigma)[0]
+    assert k == keep.size
+    iu, ju = np.triu_indices(w.n, 1)
+    np.testing.assert_array_equal(fp[:, 0], iu[keep])
+    np.testing.assert_array_equal(fp[:, 1], ju[keep])
+    np.testing.assert_array_equal(fp[:, 2], got[keep])
+    rng = np.random.default_rng(7)
+    sample = sorted(set([0, w.n - 1] + rng.choice(w.n, size=6, replace=False).tolist()))
+    check_rows(got, off, tids, w.n, sample)
+    idx.close()
+
+
+def test_batch_full_size(stream_ctx):
+    """The 64 uneven instances of the batched form at full size, one graph launch: equal to the
+    per-instance calls, the closed form per instance, and oracle rows on two instances."""
+    ctx = stream_ctx
+    dev = torch.device("cuda:0")
+    specs = datagen.batch_instances(64)
+    sets = [datagen.bernoulli_sets_device(w.m, w.n, w.density, seed=w.seed) for w in specs]
+    idxs = [bm.Index.from_sets(ctx, w.m, o, t) for w, (o, t) in zip(specs, sets)]
+    pairs = [bm.n_pairs(w.n) for w in specs]
+    outs_a = [torch.empty(max(p, 1), dtype=torch.int32, device=dev) for p in pairs]
+    outs_b = [torch.full((max(p, 1),), -1, dtype=torch.int32, device=dev) for p in pairs]
+    for ix, o in zip(idxs, outs_a):
+        ix.all_pair_supports(o)
+    batch = bm.Batch(ctx, idxs, outs_b)
+    batch.run()
+    ctx.synchronize()
+    for q, (w, (o, t)) in enumerate(zip(specs, sets)):
+        assert torch.equal(outs_a[q][:pairs[q]], outs_b[q][:pairs[q]]), q
+        tl = torch.bincount(t.long(), minlength=w.m).double()
+        assert abs(outs_b[q][:pairs[q]].double().sum().item() - (tl * (tl - 1) / 2).sum().item()) < 0.5, q
+    for q in (0, 63):
+        w = specs[q]
+        off = sets[q][0].cpu().numpy().astype(np.uint64)
+        tids = sets[q][1].cpu().numpy().view(np.uint32)
+        got = outs_b[q][:pairs[q]].cpu().numpy().view(np.uint32)
+        check_rows(got, off, tids, w.n, [0, w.n // 2, w.n - 1])
+    batch.close()
+    for ix in idxs:
+        ix.close()
