@@ -103,3 +103,27 @@ def test_batch_full_size(stream_ctx):
     batch.close()
     for ix in idxs:
         ix.close()
+
+
+def test_dense_comparator_full_size(stream_ctx):
+    """The dense comparator's configuration (m = 2^20 transactions, n = 8192 items) at 5 %
+    density: the int8 MFMA bitmap product equals BatMap element by element, both equal the
+    closed form, and two rows equal the oracle."""
+    ctx = stream_ctx
+    dev = torch.device("cuda:0")
+    m, n = 1 << 20, 8192
+    d_off, d_tids = datagen.bernoulli_sets_device(m, n, 0.05, seed=4006)
+    idx = bm.Index.from_sets(ctx, m, d_off, d_tids)
+    n_pairs = bm.n_pairs(n)
+    out = torch.empty(n_pairs, dtype=torch.int32, device=dev)
+    out_d = torch.full((n_pairs,), -1, dtype=torch.int32, device=dev)
+    idx.all_pair_supports(out)
+    idx.all_pair_supports_dense(out_d)
+    ctx.synchronize()
+    assert torch.equal(out, out_d)
+    tl = torch.bincount(d_tids.long(), minlength=m).double()
+    assert abs(out.double().sum().item() - (tl * (tl - 1) / 2).sum().item()) < 0.5
+    off = d_off.cpu().numpy().astype(np.uint64)
+    tids = d_tids.cpu().numpy().view(np.uint32)
+    check_rows(out.cpu().numpy().view(np.uint32), off, tids, n, [5, n - 2])
+    idx.close()
