@@ -264,8 +264,11 @@ hipError_t launch_store_desc(InstDesc *dst, const InstDesc &d, hipStream_t s);
 // Threshold + compaction.
 hipError_t launch_threshold_count(const uint32_t *sup, uint64_t n_pairs, uint32_t sigma, uint32_t *block_counts,
                                   uint32_t n_blocks, hipStream_t s);
+// Writes the pairs only when the total, block_off[n_blocks], is at most
+// capacity (so it may be queued before the host reads the total).
 hipError_t launch_threshold_write(const uint32_t *sup, uint64_t n_pairs, uint64_t n, uint32_t sigma,
-                                  const uint64_t *block_off, uint32_t n_blocks, bm_pair *out, hipStream_t s);
+                                  const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity, bm_pair *out,
+                                  hipStream_t s);
 uint32_t threshold_blocks(uint64_t n_pairs);
 
 // Subset queries.

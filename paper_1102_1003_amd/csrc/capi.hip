@@ -156,6 +156,16 @@ struct DevBuf {
             return hipSuccess;
         return alloc(count);
     }
+    // Exchanges the blocks of two buffers.  Every field moves with its block:
+    // a spare block is filed under its recorded size, so a size left behind
+    // would later hand the block out for requests larger than it.
+    void swap(DevBuf &o)
+    {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+        std::swap(bytes, o.bytes);
+        std::swap(as, o.as);
+    }
 };
 
 
@@ -384,6 +394,14 @@ bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
         }                                                                                              \
     } while (0)
 
+// Returns the status of a library call that failed.
+#define BMC(expr)                      \
+    do {                               \
+        const bm_status st_ = (expr);  \
+        if (st_ != BM_OK)              \
+            return st_;                \
+    } while (0)
+
 // ------------------------------------------------------------------ planner
 // Tiles of a width-class pair (a <= b): rows from class a, columns from class
 // b; within one class only tiles holding some row < column.  A variant (tile
@@ -416,6 +434,13 @@ constexpr uint32_t kPlanAtBuild = 4096;
 // Items a plan aims at: about 64 per CU.
 uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
 
+// Host data to and from the device, through pinned buffers of the context
+// (defined with the read-back below): the copies are asynchronous, and the
+// runtime is never handed a pageable host address (a caller's array or a
+// vector's storage) to look up.
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
+bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
+
 bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
                       std::vector<std::pair<int, uint32_t>> &ranges)
 {
@@ -441,25 +466,8 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
             ranges.push_back({-1, off[x]});
     }
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
-    if (total) {
-        const uint64_t bytes = total * sizeof(WorkItem);
-        if (ctx->staged)
-            HIPC(ctx, hipEventSynchronize(ctx->staged));  // the previous upload has left the buffer
-        else
-            HIPC(ctx, hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
-        if (ctx->h_stage_bytes < bytes) {
-            if (ctx->h_stage)
-                HIPC(ctx, hipHostFree(ctx->h_stage));
-            ctx->h_stage = nullptr;
-            ctx->h_stage_bytes = 0;
-            const uint64_t want = std::max<uint64_t>(bytes + bytes / 2, 1 << 20);
-            HIPC(ctx, hipHostMalloc(&ctx->h_stage, want));
-            ctx->h_stage_bytes = want;
-        }
-        memcpy(ctx->h_stage, flat.data(), bytes);
-        HIPC(ctx, hipMemcpyAsync(dst.p, ctx->h_stage, bytes, hipMemcpyHostToDevice, ctx->stream));
-        HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
-    }
+    if (total)
+        return upload(ctx, dst.p, flat.data(), total * sizeof(WorkItem));
     return BM_OK;
 }
 
@@ -547,8 +555,9 @@ bm_status copy_in(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
 {
     if (bytes == 0)
         return BM_OK;
-    hipMemcpyKind kind = ptr_kind(src) == PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIPC(ctx, hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
+    if (ptr_kind(src) != PTR_DEVICE)
+        return upload(ctx, dst, src, bytes);
+    HIPC(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     return BM_OK;
 }
 
@@ -597,6 +606,59 @@ bm_status read_back_many(bm_context *ctx, std::initializer_list<ReadBack> reads)
 bm_status read_back(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
 {
     return read_back_many(ctx, {{dst, src, bytes}});
+}
+
+// Chunks of host data through the context's pinned staging buffer; a chunk
+// waits until the previous upload has left the buffer.
+constexpr uint64_t kStageChunk = 16ull << 20;
+
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
+{
+    for (uint64_t at = 0; at < bytes; at += kStageChunk) {
+        const uint64_t c = std::min<uint64_t>(kStageChunk, bytes - at);
+        if (ctx->staged)
+            HIPC(ctx, hipEventSynchronize(ctx->staged));
+        else
+            HIPC(ctx, hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+        if (ctx->h_stage_bytes < c) {
+            if (ctx->h_stage)
+                HIPC(ctx, hipHostFree(ctx->h_stage));
+            ctx->h_stage = nullptr;
+            ctx->h_stage_bytes = 0;
+            const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(c + c / 2, 1 << 20), kStageChunk);
+            HIPC(ctx, hipHostMalloc(&ctx->h_stage, want));
+            ctx->h_stage_bytes = want;
+        }
+        memcpy(ctx->h_stage, static_cast<const char *>(src) + at, c);
+        const hipError_t e = hipMemcpyAsync(static_cast<char *>(dst) + at, ctx->h_stage, c, hipMemcpyHostToDevice,
+                                            ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            hipPointerAttribute_t a{};
+            const hipError_t ea = hipPointerGetAttributes(&a, dst);
+            (void)hipGetLastError();
+            return fail(ctx, e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EDEVICE,
+                        "uploading %llu bytes to %p (attributes %s: type %d, device %d, base %p, size %zu): %s",
+                        (unsigned long long)c, static_cast<char *>(dst) + at, hipGetErrorString(ea), (int)a.type,
+                        a.device, a.devicePointer, (size_t)0, hipGetErrorString(e));
+        }
+        HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
+    }
+    return BM_OK;
+}
+
+// Device data into host memory, in chunks through the read-back buffer
+// (returns when the data is in place).
+bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
+{
+    constexpr uint64_t kChunk = 64ull << 20;
+    for (uint64_t at = 0; at < bytes; at += kChunk) {
+        const uint64_t c = std::min<uint64_t>(kChunk, bytes - at);
+        bm_status st = read_back_many(ctx, {{static_cast<char *>(dst) + at, static_cast<const char *>(src) + at, c}});
+        if (st != BM_OK)
+            return st;
+    }
+    return BM_OK;
 }
 
 bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
@@ -781,7 +843,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
     HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
     if (!eb_all.empty())
-        HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
+        BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
     HIPC(ctx, counters.alloc(4));
     // counters: [0] candidates of the running batch, [1] failures so far,
     // [2] largest candidate count of any batch, [3] an LDS-built map left too
@@ -870,7 +932,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
             HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
             if (!eb_all.empty())
-                HIPC(ctx, hipMemcpyAsync(ebase.p, eb_all.data(), eb_all.size() * 8, hipMemcpyHostToDevice, s));
+                BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
             continue;
         }
         if (h[2] <= cand_cap && h[1] <= fail_cap) {
@@ -1010,13 +1072,13 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
     HIPC(ctx, arena.alloc(total_groups * kWordsPerGroup));
     HIPC(ctx, fill_u32(arena.p, total_groups * kWordsPerGroup, 0x5A5A5A5Au, s));
     HIPC(ctx, goff.alloc(h_goff.size()));
-    HIPC(ctx, hipMemcpyAsync(goff.p, h_goff.data(), h_goff.size() * 8, hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, goff.p, h_goff.data(), h_goff.size() * 8));
     const uint32_t n_pos = (uint32_t)h_goff.size() - 1;
     std::vector<uint32_t> h_pos(n_pos);
     for (uint32_t i = 0; i < n_pos; i++)
         h_pos[i] = i;
     HIPC(ctx, outpos.alloc(n_pos));
-    HIPC(ctx, hipMemcpyAsync(outpos.p, h_pos.data(), (uint64_t)n_pos * 4, hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, outpos.p, h_pos.data(), (uint64_t)n_pos * 4));
     HIPC(ctx, out.alloc(n_pairs(n_pos)));
     HIPC(ctx, hipStreamSynchronize(s));
     InstDesc d;
@@ -1045,7 +1107,7 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
             const std::vector<WorkItem> &list = plan.by_variant[v];
             const uint32_t Gb = grow * ratios[b];
             HIPC(ctx, items.ensure(list.size()));
-            HIPC(ctx, hipMemcpyAsync(items.p, list.data(), list.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+            BMC(upload(ctx, items.p, list.data(), list.size() * sizeof(WorkItem)));
             HIPC(ctx, launch_compare(items.p, (uint32_t)list.size(), nullptr, d, v, s));  // warm
             HIPC(ctx, hipEventRecord(e0, s));
             for (uint32_t rp = 0; rp < std::max(reps, 1u); rp++)
@@ -1325,7 +1387,7 @@ bm_status bm_index_build_sets(bm_context *ctx, uint32_t m, uint32_t n_sets, cons
     Span span_ingest(ctx, PH_INGEST);
     HIPC(ctx, idx->off.alloc((uint64_t)n_sets + 1));
     HIPC(ctx, idx->tids.alloc(std::max<uint64_t>(idx->nnz, 1)));
-    HIPC(ctx, hipMemcpyAsync(idx->off.p, idx->h_off.data(), ((uint64_t)n_sets + 1) * 8, hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, idx->off.p, idx->h_off.data(), ((uint64_t)n_sets + 1) * 8));
     st = copy_in(ctx, idx->tids.p, tids, idx->nnz * 4);
     if (st != BM_OK)
         return st;
@@ -1420,7 +1482,7 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     const uint64_t *row_off = offsets;
     if (!dev_off) {
         HIPC(ctx, d_roff.alloc((uint64_t)m_txn + 1));
-        HIPC(ctx, hipMemcpyAsync(d_roff.p, roff.data(), ((uint64_t)m_txn + 1) * 8, hipMemcpyHostToDevice, s));
+        BMC(upload(ctx, d_roff.p, roff.data(), ((uint64_t)m_txn + 1) * 8));
         row_off = d_roff.p;
     }
     HIPC(ctx, keys.alloc(N));
@@ -1469,8 +1531,8 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
         HIPC(ctx, exclusive_scan_u32_to_u64(keep.p, pos.p, nnz_in, tmp.p, s));
         HIPC(ctx, launch_compact_pairs(keys.p, vals.p, keep.p, pos.p, nnz_in, k2.p, v2.p, s));
         HIPC(ctx, hipStreamSynchronize(s));
-        std::swap(keys.p, k2.p);
-        std::swap(vals.p, v2.p);
+        keys.swap(k2);
+        vals.swap(v2);
         nnz = nnz_in - hf[1];
         HIPC(ctx, launch_offsets_from_sorted(keys.p, nnz, n_items, idx->off.p, s));
         st = read_back(ctx, idx->h_off.data(), idx->off.p, ((uint64_t)n_items + 1) * 8);
@@ -1479,10 +1541,7 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     }
     idx->nnz = nnz;
     // the sorted values are the tidlists
-    idx->tids.p = vals.p;
-    idx->tids.n = vals.n;
-    vals.p = nullptr;
-    vals.n = 0;
+    idx->tids.swap(vals);
     span_ingest.end();
     st = build_common(idx.get(), &o);
     if (st != BM_OK)
@@ -1552,7 +1611,7 @@ bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len)
     if (st != BM_OK)
         return st;
     if (host) {
-        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, ctx->stream));
+        BMC(download(ctx, out, dst, np * 4));
         HIPC(ctx, hipStreamSynchronize(ctx->stream));
     }
     return BM_OK;
@@ -1593,6 +1652,12 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
     HIPC(ctx, fill_u32(idx->thr_counts.p + nb, 1, 0, s));
     HIPC(ctx, launch_threshold_count(idx->pairbuf.p, np, min_support, idx->thr_counts.p, nb, s));
     HIPC(ctx, exclusive_scan_u32_to_u64(idx->thr_counts.p, idx->thr_off.p, (uint64_t)nb + 1, idx->scan_tmp.p, s));
+    // a device buffer is written before the total comes back (the kernel
+    // writes nothing when the total exceeds capacity)
+    const bool host = out && ptr_kind(out) == PTR_HOST;
+    if (out && !host)
+        HIPC(ctx, launch_threshold_write(idx->pairbuf.p, np, idx->n, min_support, idx->thr_off.p, nb, capacity, out,
+                                         s));
     uint64_t total = 0;
     span_thr.end();
     st = read_back(ctx, &total, idx->thr_off.p + nb, 8);
@@ -1606,18 +1671,15 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
     if (total > capacity)
         return fail(ctx, BM_ECAPACITY, "%llu frequent pairs, capacity %llu", (unsigned long long)total,
                     (unsigned long long)capacity);
-    bool host = ptr_kind(out) == PTR_HOST;
     bm_pair *dst = out;
     if (host) {
         HIPC(ctx, idx->pair_out.ensure(total));
         dst = idx->pair_out.p;
-    }
-    {
         Span sp(ctx, PH_THRESHOLD);
-        HIPC(ctx, launch_threshold_write(idx->pairbuf.p, np, idx->n, min_support, idx->thr_off.p, nb, dst, s));
+        HIPC(ctx, launch_threshold_write(idx->pairbuf.p, np, idx->n, min_support, idx->thr_off.p, nb, total, dst, s));
     }
     if (host) {
-        HIPC(ctx, hipMemcpyAsync(out, dst, total * sizeof(bm_pair), hipMemcpyDeviceToHost, s));
+        BMC(download(ctx, out, dst, total * sizeof(bm_pair)));
         HIPC(ctx, hipStreamSynchronize(s));
     }
     return BM_OK;
@@ -1654,7 +1716,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     HIPC(ctx, idx->pos_of_item.ensure(idx->n));
     HIPC(ctx, idx->sub_items.ensure(k));
     HIPC(ctx, idx->sub_flag.ensure(1));
-    HIPC(ctx, hipMemcpyAsync(idx->sub_items.p, q.data(), (uint64_t)k * 4, hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, idx->sub_items.p, q.data(), (uint64_t)k * 4));
     HIPC(ctx, fill_u32(idx->pos_of_item.p, idx->n, kEmpty, s));
     HIPC(ctx, fill_u32(idx->sub_flag.p, 1, 0, s));
     HIPC(ctx, launch_subset_prepare(idx->sub_items.p, k, idx->n, idx->sorted_pos.p, idx->pos_of_item.p,
@@ -1700,8 +1762,8 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     }
     HIPC(ctx, idx->sub_goff.ensure(k));
     HIPC(ctx, idx->sub_outpos.ensure(k));
-    HIPC(ctx, hipMemcpyAsync(idx->sub_goff.p, h_goff.data(), (uint64_t)k * 8, hipMemcpyHostToDevice, s));
-    HIPC(ctx, hipMemcpyAsync(idx->sub_outpos.p, h_outpos.data(), (uint64_t)k * 4, hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, idx->sub_goff.p, h_goff.data(), (uint64_t)k * 8));
+    BMC(upload(ctx, idx->sub_outpos.p, h_outpos.data(), (uint64_t)k * 4));
     bool host = ptr_kind(out) == PTR_HOST;
     uint32_t *dst = out;
     if (host) {
@@ -1738,7 +1800,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
         HIPC(ctx, launch_apply_corrections_subset(idx->corr.p, idx->n_corr, idx->pos_of_item.p, dst, k, s));
     }
     if (host) {
-        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, s));
+        BMC(download(ctx, out, dst, np * 4));
     }
     HIPC(ctx, hipStreamSynchronize(s));
     return BM_OK;
@@ -1815,7 +1877,7 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
     HIPC(ctx, b->descs.alloc(count));
     HIPC(ctx, b->items.alloc(std::max<uint64_t>(std::max(flat.size(), cand.size()), 1)));
     HIPC(ctx, b->counter.alloc(kQueueCounterWords));
-    HIPC(ctx, hipMemcpyAsync(b->descs.p, descs.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    BMC(upload(ctx, b->descs.p, descs.data(), count * sizeof(InstDesc)));
     if (tuned) {
         hipEvent_t e0, e1;
         HIPC(ctx, hipEventCreate(&e0));
@@ -1827,9 +1889,11 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
         for (int c = 0; c < 2 && e == hipSuccess; c++) {
             b->n_items = (uint32_t)lists[c]->size();
             b->queues = *qs[c];
-            if (b->n_items)
-                e = hipMemcpyAsync(b->items.p, lists[c]->data(), b->n_items * sizeof(WorkItem),
-                                   hipMemcpyHostToDevice, s);
+            if (b->n_items && upload(ctx, b->items.p, lists[c]->data(), b->n_items * sizeof(WorkItem)) != BM_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return BM_EDEVICE;  // upload() has set the message
+            }
             if (e == hipSuccess)
                 e = hipEventRecord(e0, s);
             if (e == hipSuccess)
@@ -1856,7 +1920,7 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
     b->n_items = (uint32_t)flat.size();
     b->queues = q_flat;
     if (!flat.empty())
-        HIPC(ctx, hipMemcpyAsync(b->items.p, flat.data(), flat.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+        BMC(upload(ctx, b->items.p, flat.data(), flat.size() * sizeof(WorkItem)));
     HIPC(ctx, hipStreamSynchronize(s));
     // the whole sequence as one graph: counter reset, output fills (kernels,
     // not memsets), one persistent compare launch, corrections
@@ -1997,7 +2061,7 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
         HIPC(ctx, launch_dense_gram(idx->dense_A.p, idx->n, idx->dense_ld, idx->dense_ld, dst, ksplit, s));
     }
     if (host) {
-        HIPC(ctx, hipMemcpyAsync(out, dst, np * 4, hipMemcpyDeviceToHost, s));
+        BMC(download(ctx, out, dst, np * 4));
         HIPC(ctx, hipStreamSynchronize(s));
     }
     return BM_OK;

@@ -146,9 +146,14 @@ __device__ inline uint64_t row_of_packed(uint64_t k, uint64_t n)
     return (uint64_t)i;
 }
 
+// Writes nothing when the total (block_off[n_blocks]) exceeds capacity, so the
+// write can be queued before the host has read the total.
 __global__ void threshold_write_kernel(const uint32_t *sup, uint64_t n_pairs, uint64_t n, uint32_t sigma,
-                                       const uint64_t *block_off, bm_pair *out)
+                                       const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity,
+                                       bm_pair *out)
 {
+    if (block_off[n_blocks] > capacity)
+        return;  // the same value for every thread of the grid
     uint64_t base = (uint64_t)blockIdx.x * kThrTile + (uint64_t)threadIdx.x * kThrItems;
     uint32_t v[kThrItems];
     uint32_t c = 0;
@@ -254,11 +259,12 @@ hipError_t launch_threshold_count(const uint32_t *sup, uint64_t n_pairs, uint32_
 }
 
 hipError_t launch_threshold_write(const uint32_t *sup, uint64_t n_pairs, uint64_t n, uint32_t sigma,
-                                  const uint64_t *block_off, uint32_t n_blocks, bm_pair *out, hipStream_t s)
+                                  const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity, bm_pair *out,
+                                  hipStream_t s)
 {
     if (n_blocks == 0)
         return hipSuccess;
-    threshold_write_kernel<<<n_blocks, kBlock, 0, s>>>(sup, n_pairs, n, sigma, block_off, out);
+    threshold_write_kernel<<<n_blocks, kBlock, 0, s>>>(sup, n_pairs, n, sigma, block_off, n_blocks, capacity, out);
     return hipGetLastError();
 }
 

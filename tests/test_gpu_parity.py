@@ -57,6 +57,17 @@ def test_tiny_config_all_pairs_and_filter(ctx):
         np.testing.assert_array_equal(idx.frequent_pairs(sigma), oracle.frequent_pairs(off, tids, sigma))
     # host output buffer gives the same result
     np.testing.assert_array_equal(idx.all_pair_supports()[:bm.n_pairs(w.n)], got)
+    # device output: too small a buffer gets BM_ECAPACITY and is left untouched
+    ref = oracle.frequent_pairs(off, tids, 8)
+    k = ref.shape[0]
+    small = torch.full((3 * (k - 1),), -7, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(bm.BatmapError) as e:
+        idx.frequent_pairs_into(8, small)
+    assert e.value.status == bm.BM_ECAPACITY
+    assert bool((small == -7).all())
+    fit = torch.full((3 * k,), -7, dtype=torch.int32, device="cuda:0")
+    assert idx.frequent_pairs_into(8, fit) == k
+    np.testing.assert_array_equal(fit.cpu().numpy().view(np.uint32).reshape(k, 3), ref)
 
 
 @pytest.mark.parametrize("seed,m,n,plo,phi", [
