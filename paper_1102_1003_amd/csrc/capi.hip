@@ -1442,7 +1442,7 @@ bm_status bm_index_build_transactions(bm_context *ctx, uint32_t n_items, uint32_
     hipStream_t s = ctx->stream;
 
     // Offsets in device memory are used in place and checked by a kernel,
-    // whose verdict comes back with their last entry (the incidence count)
+    // whose finding comes back with their last entry (the incidence count)
     // before anything reads them; host offsets are checked here and copied in.
     const bool dev_off = ptr_kind(offsets) == PTR_DEVICE;
     uint64_t nnz_in = 0;
