@@ -634,13 +634,8 @@ bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
                                             ctx->stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            hipPointerAttribute_t a{};
-            const hipError_t ea = hipPointerGetAttributes(&a, dst);
-            (void)hipGetLastError();
-            return fail(ctx, e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EDEVICE,
-                        "uploading %llu bytes to %p (attributes %s: type %d, device %d, base %p, size %zu): %s",
-                        (unsigned long long)c, static_cast<char *>(dst) + at, hipGetErrorString(ea), (int)a.type,
-                        a.device, a.devicePointer, (size_t)0, hipGetErrorString(e));
+            return fail(ctx, e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EDEVICE, "uploading %llu bytes to %p: %s",
+                        (unsigned long long)c, static_cast<char *>(dst) + at, hipGetErrorString(e));
         }
         HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
     }
