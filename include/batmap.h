@@ -123,7 +123,11 @@ bm_status bm_synchronize(bm_context *ctx);
  * and its plan from the built-in speeds on itself, once each, and keeps the
  * faster.  Single-index calls and the server plan with the built-in speeds
  * (relative rates measured on MI355X over real instances).  The table can be
- * read and restored (n = shapes x 3 floats) to skip the measurement later. */
+ * read and restored (n = shapes x 3 floats) to skip the measurement later;
+ * set_tile_speeds with n = 0 goes back to the built-in speeds, and returns
+ * BM_EINVAL for any other count or for an entry that is not a positive
+ * finite rate.  A measured rate that cannot be used (the autotuner stores 0
+ * for a shape it could not time) is replaced by the built-in speed. */
 bm_status bm_context_autotune(bm_context *ctx, uint32_t reps);
 bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capacity, uint32_t *n_out);
 bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint32_t n);
@@ -218,7 +222,7 @@ typedef struct bm_server bm_server;
 typedef struct {
     uint32_t streams;        /* concurrent launch slots (default 4) */
     uint32_t max_queue;      /* submits beyond this many waiting queries get BM_EBUSY (default 1 << 16) */
-    uint32_t max_batch;      /* queries admitted into one launch at most (default 64) */
+    uint32_t max_batch;      /* queries admitted into one launch at most (default 64, at most 65535) */
     uint32_t flags;          /* reserved, 0 */
     uint64_t memory_budget;  /* device bytes for in-flight queries (default 1 GiB) */
 } bm_server_opts;

@@ -54,7 +54,7 @@ def lib():
         L.orc_frequent_pairs.restype = ctypes.c_uint64
         L.orc_frequent_pairs.argtypes = [ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint32, _u32p, ctypes.c_uint64]
         L.orc_subset.restype = None
-        L.orc_subset.argtypes = [ctypes.c_uint32, _u64p, _u32p, _u32p, ctypes.c_uint32, _u32p]
+        L.orc_subset.argtypes = [ctypes.c_uint32, _u64p, _u32p, _u32p, ctypes.c_uint32, _u32p, ctypes.c_int]
         L.orc_transpose.restype = ctypes.c_int
         L.orc_transpose.argtypes = [ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint32, _u64p, _u32p]
         L.orc_shift.restype = ctypes.c_uint32
@@ -134,12 +134,14 @@ def frequent_pairs(offsets, tids, sigma: int) -> np.ndarray:
         cap = cnt
 
 
-def subset_pairs(offsets, tids, items) -> np.ndarray:
+def subset_pairs(offsets, tids, items, threads: int = 1) -> np.ndarray:
+    """Packed upper triangle of |S_items[p] cap S_items[q]|, p < q, in the query's order
+    (threads = 0: all cores)."""
     off, t = _csr(offsets, tids)
     items = np.ascontiguousarray(items, dtype=np.uint32)
     k = items.size
     out = np.zeros(max(n_pairs(k), 1), dtype=np.uint32)
-    lib().orc_subset(off.size - 1, off, t, items, k, out)
+    lib().orc_subset(off.size - 1, off, t, items, k, out, threads)
     return out[:n_pairs(k)]
 
 

@@ -134,9 +134,13 @@ uint64_t orc_frequent_pairs(uint32_t n, const uint64_t *off, const uint32_t *tid
 /* Packed upper triangle over the query order: entry (p,q), p<q, is
  * |S_items[p] cap S_items[q]|. */
 void orc_subset(uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *items, uint32_t k,
-                uint32_t *out)
+                uint32_t *out, int nthreads)
 {
     (void)n;
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+    /* rows are independent; nthreads = 1 keeps the plain sequential order */
+#pragma omp parallel for schedule(dynamic, 1) if (nthreads != 1)
     for (uint32_t p = 0; p < k; p++) {
         for (uint32_t q = p + 1; q < k; q++) {
             uint32_t a = items[p], b = items[q];

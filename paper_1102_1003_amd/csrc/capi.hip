@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -773,6 +774,10 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         idx->h_sizes_sorted[p] = (uint32_t)(idx->h_off[it + 1] - idx->h_off[it]);
     }
     idx->total_groups = h_goff[n];
+    // the compare kernels address map groups with 32-bit indices
+    if (idx->total_groups >= (1ull << 32))
+        return fail(ctx, BM_EINVAL, "BatMaps of %llu groups (%llu bytes); at most 2^32 groups per index",
+                    (unsigned long long)idx->total_groups, (unsigned long long)idx->total_groups * kSlotsPerGroup);
     idx->classes.clear();
     for (uint32_t p = first_built; p < n; p++) {
         uint32_t r = idx->h_r_sorted[p];
@@ -1315,6 +1320,9 @@ bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint3
     }
     if (!speeds || n != (uint32_t)kVariantCount * kWrapBuckets)
         return fail(ctx, BM_EINVAL, "expected %u speeds", (uint32_t)kVariantCount * kWrapBuckets);
+    for (uint32_t i = 0; i < n; i++)
+        if (!(speeds[i] > 0.f) || !std::isfinite(speeds[i]))
+            return fail(ctx, BM_EINVAL, "speed %u is not a positive finite rate", i);
     ctx->speeds.assign(speeds, speeds + n);
     ctx->tune_gen++;
     return BM_OK;
@@ -2463,7 +2471,9 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
     bm_server_opts_init(&o);
     if (opts)
         o = *opts;
-    if (o.streams == 0 || o.streams > 16 || o.max_batch == 0 || o.memory_budget < 4096 || o.flags != 0)
+    // a launch's work items name their query in 16 bits
+    if (o.streams == 0 || o.streams > 16 || o.max_batch == 0 || o.max_batch > 65535 || o.memory_budget < 4096 ||
+        o.flags != 0)
         return fail(ctx, BM_EINVAL, "bad server options");
     HIPC(ctx, hipSetDevice(idx->device));
     std::unique_ptr<bm_server> srv(new (std::nothrow) bm_server());

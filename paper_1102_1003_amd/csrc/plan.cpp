@@ -54,6 +54,14 @@ const VariantInfo kInfo[kVariantCount] = {
 
 const VariantInfo &variant_info(int v) { return kInfo[v]; }
 
+bool shape_allowed(int v, int single, int pinned)
+{
+    const VariantInfo &V = kInfo[v];
+    if (single)  // the single-launch kernel runs row-resident bodies only
+        return V.multi >= 0 && V.row_resident;
+    return pinned >= 0 ? v == pinned : V.default_choice;
+}
+
 uint64_t item_cost(const WorkItem &w)
 {
     return (w.flags & 2u) ? (uint64_t)(w.c1 - w.c0) * (w.col_groups / w.row_groups) : (uint64_t)(w.c1 - w.c0);
@@ -145,7 +153,7 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
             bool same = a == b;
             if (same && (cls[a].count < 2 || cross_only))
                 continue;
-            int best = 0;
+            int best = -1;
             double best_cost = 1e300, best_speed = 1;
             const int bucket = wrap_bucket(cls[b].r / cls[a].r);
             const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
@@ -154,13 +162,14 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                 // staged-tile shapes time well on uniform synthetic tiles but lose on
                 // skewed instances, so they are used only when pinned
                 const VariantInfo &V = variant_info(v);
-                if (single ? V.multi < 0
-                           : (pinned >= 0 ? v != pinned : !V.default_choice))
+                if (!shape_allowed(v, single, pinned))
                     continue;
-                const float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket]
-                                          : (bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed);
-                if (!(speed > 0))
-                    continue;
+                const float builtin = bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed;
+                float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : builtin;
+                // a measured speed that is not a positive finite rate says nothing
+                // about the shape: weigh it by the catalogue instead
+                if (!(speed > 0) || !std::isfinite(speed))
+                    speed = builtin;
                 const uint32_t bi = V.bi, bj = V.bj;
                 uint64_t cnt;
                 tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
@@ -172,6 +181,11 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                     best_speed = speed;
                 }
             }
+            // every mode allows at least one shape, and every catalogue speed is
+            // > 0, so some shape was chosen above
+            for (int v = 0; best < 0 && v < nv; v++)
+                if (shape_allowed(v, single, -1))
+                    best = v, best_speed = variant_info(v).speed;
             const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
             uint64_t cnt;
             tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);

@@ -48,6 +48,10 @@ struct VariantInfo {
 };
 constexpr int kVariantCount = 22;
 const VariantInfo &variant_info(int v);
+// Whether plan_classes may choose shape v: single-launch mode (single != 0)
+// takes only shapes with a body in the persistent kernel (multi >= 0, row
+// groups walked); otherwise the pinned shape alone, or the default shapes.
+bool shape_allowed(int v, int single, int pinned);
 
 // Measured speeds are kept per wrap ratio G_col / G_row: 1 | 2..8 | >= 16.
 constexpr int kWrapBuckets = 3;

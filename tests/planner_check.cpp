@@ -3,6 +3,14 @@
 // classes and verifies every work item against the shape catalogue, then that
 // the items together visit every pair i < j over all 3 max(r_i, r_j) / 32
 // groups of the wider map exactly once (the Fig. 1 wrap included).
+// Built with -DPLAN_CHECK_MAIN it is also a program (compiled with the
+// address and undefined-behaviour sanitizers by the same test) that reads
+// cases from stdin, one per line:
+//   single pinned inst target speed_kind n_cls r[0..n_cls) count[0..n_cls)
+// speed_kind: 0 built-in speeds, 1 all measured speeds 0, 2 all NaN,
+// 3 all negative, 4 seeded random positive, 5 only the single-launch shapes
+// unusable (0).
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -27,7 +35,8 @@ int fail(char *msg, uint32_t len, int code, const char *fmt, ...)
 }  // namespace
 
 extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *count, uint64_t target, int single,
-                          int pinned, uint32_t inst, char *msg, uint32_t msg_len, uint64_t *n_items)
+                          int pinned, uint32_t inst, const float *speeds, char *msg, uint32_t msg_len,
+                          uint64_t *n_items)
 {
     std::vector<Cls> cls;
     uint32_t n = 0;
@@ -40,7 +49,10 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
         for (uint32_t i = 0; i < count[c]; i++)
             cls_of[cls[c].start + i] = c;
     Plan plan;
-    plan_classes(cls, inst, target, plan, nullptr, single, pinned);
+    std::vector<float> sp_table;
+    if (speeds)
+        sp_table.assign(speeds, speeds + kVariantCount * kWrapBuckets);
+    plan_classes(cls, inst, target, plan, speeds ? &sp_table : nullptr, single, pinned);
     if ((int)plan.by_variant.size() != kVariantCount)
         return fail(msg, msg_len, 1, "plan has %zu shape lists", plan.by_variant.size());
     std::vector<uint64_t> cov((uint64_t)n * (n ? n - 1 : 0) / 2, 0);
@@ -50,8 +62,10 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
         const VariantInfo &V = variant_info(v);
         for (const WorkItem &w : plan.by_variant[v]) {
             items++;
-            if (single && V.multi < 0)
+            if (single && (V.multi < 0 || !V.row_resident))
                 return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
+            if (!single && pinned < 0 && !V.default_choice)
+                return fail(msg, msg_len, 2, "tuning-only shape %d chosen without a pin", v);
             if (!single && pinned >= 0 && v != pinned)
                 return fail(msg, msg_len, 3, "shape %d while %d is pinned", v, pinned);
             if (w.inst != inst)
@@ -157,3 +171,51 @@ extern "C" int queues_check(uint32_t n_cls, const uint32_t *r, const uint32_t *c
             return fail(msg, msg_len, 5, "a (range, row tile) group spans two queues");
     return 0;
 }
+
+#ifdef PLAN_CHECK_MAIN
+#include <random>
+
+int main()
+{
+    int single, pinned, kind;
+    unsigned inst, n_cls;
+    unsigned long long target;
+    int line = 0, bad = 0;
+    while (scanf("%d %d %u %llu %d %u", &single, &pinned, &inst, &target, &kind, &n_cls) == 6) {
+        line++;
+        std::vector<uint32_t> r(n_cls), count(n_cls);
+        for (auto &x : r)
+            if (scanf("%u", &x) != 1)
+                return 2;
+        for (auto &x : count)
+            if (scanf("%u", &x) != 1)
+                return 2;
+        std::vector<float> sp(kVariantCount * kWrapBuckets);
+        std::mt19937 gen(line);
+        for (int v = 0; v < kVariantCount; v++)
+            for (int b = 0; b < kWrapBuckets; b++) {
+                float &x = sp[v * kWrapBuckets + b];
+                switch (kind) {
+                case 1: x = 0.f; break;
+                case 2: x = NAN; break;
+                case 3: x = -1.f; break;
+                case 4: x = 0.05f + (float)(gen() % 1000) / 500.f; break;
+                case 5: x = variant_info(v).multi >= 0 ? 0.f : 1.f; break;
+                default: x = 1.f;
+                }
+            }
+        char msg[256];
+        uint64_t items = 0;
+        int st = plan_check(n_cls, r.data(), count.data(), target, single, pinned, inst, kind ? sp.data() : nullptr,
+                            msg, sizeof msg, &items);
+        if (st == 0 && single)
+            st = queues_check(n_cls, r.data(), count.data(), target, single, msg, sizeof msg);
+        if (st != 0) {
+            printf("case %d: %s\n", line, msg);
+            bad++;
+        }
+    }
+    printf("%d cases, %d failed\n", line, bad);
+    return bad ? 1 : 0;
+}
+#endif

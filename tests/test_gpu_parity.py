@@ -259,16 +259,20 @@ def test_subset_queries(ctx):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.subset_pairs(off, tids, q))
 
 
-def test_single_launch_and_every_default_shape(monkeypatch):
-    # the single persistent launch (per-XCD queues) for ordinary calls, and each
-    # default tile shape pinned for a whole plan, all equal to the definition
+N_SHAPES = 22   # tile shapes in the catalogue (plan.cpp / compare.hip)
+
+
+def test_single_launch_and_every_shape(monkeypatch):
+    # the single persistent launch (per-XCD queues) for ordinary calls, and every
+    # tile shape of the catalogue (defaults and tuning-only ones) pinned for a
+    # whole plan, all equal to the definition
     m, n = 9000, 280
     off, tids = instance(44, m, n, 0.0, 0.3)
     ref = oracle.all_pairs(off, tids)
     rng = np.random.default_rng(44)
     q = rng.choice(n, size=150, replace=False).astype(np.uint32)
     ref_q = oracle.subset_pairs(off, tids, q)
-    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in (4, 7, 10, 11, 17, 18, 20, 21)]
+    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in range(N_SHAPES)]
     for key, val in settings:
         monkeypatch.setenv(key, val)
         c = bm.Context(0)
@@ -303,6 +307,46 @@ def test_batched_equals_each_instance(ctx):
     bm.batch_all_pair_supports(ctx, idxs, outs)
     for o, r, w in zip(outs, refs, ws):
         np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)], r)
+
+
+def test_autotuned_batch(ctx):
+    """The autotuner's measured speeds feed a batch: creation runs the plan from built-in and
+    from measured speeds once each and keeps the faster; the kept plan's result equals the
+    per-instance calls and the definition.  Unusable speed tables are refused."""
+    c = bm.Context(0)
+    speeds = c.autotune(2)
+    assert speeds.size == N_SHAPES * 3 and np.all(np.isfinite(speeds)) and np.all(speeds > 0)
+    ws = datagen.batch_instances(count=10, seed=4242, m_lo=3e3, m_hi=6e4, n_lo=40, n_hi=400)
+    idxs, outs, refs, alone = [], [], [], []
+    for w in ws:
+        off, tids = w.sets()
+        ix = bm.Index.from_sets(c, w.m, off, tids, max_loop=4)
+        idxs.append(ix)
+        outs.append(torch.full((max(bm.n_pairs(w.n), 1),), -1, dtype=torch.int32, device="cuda:0"))
+        refs.append(oracle.all_pairs(off, tids))
+        alone.append(ix.all_pair_supports()[:bm.n_pairs(w.n)])
+    batch = bm.Batch(c, idxs, outs)
+    builtin_ms, measured_ms = batch.plan_trial
+    assert builtin_ms > 0 and measured_ms > 0          # both plans ran on the batch
+    for rep in range(2):
+        for o in outs:
+            o.fill_(-1)
+        batch.run()
+        c.synchronize()
+        for o, r, a, w in zip(outs, refs, alone, ws):
+            got = o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)]
+            np.testing.assert_array_equal(got, r)
+            np.testing.assert_array_equal(a, r)
+    batch.close()
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        table = speeds.copy().reshape(-1)
+        table[5] = bad
+        with pytest.raises(bm.BatmapError) as e:
+            c.set_tile_speeds(table)
+        assert e.value.status == bm.BM_EINVAL
+    for ix in idxs:
+        ix.close()
+    c.close()
 
 
 # -------------------------------------------------------------------- errors

@@ -28,16 +28,18 @@ def checker(tmp_path_factory):
                                  ctypes.c_char_p, ctypes.c_uint32]
     lib.plan_check.restype = ctypes.c_int
     lib.plan_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_uint32,
+                               ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint32,
                                ctypes.POINTER(ctypes.c_uint64)]
 
-    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0):
+    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0, speeds=None):
         r = np.ascontiguousarray(widths, dtype=np.uint32)
         c = np.ascontiguousarray(counts, dtype=np.uint32)
         msg = ctypes.create_string_buffer(256)
         n_items = ctypes.c_uint64(0)
-        st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst, msg, 256,
-                            ctypes.byref(n_items))
+        sp = None if speeds is None else np.ascontiguousarray(speeds, dtype=np.float32)
+        assert sp is None or sp.size == N_SHAPES * 3
+        st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst,
+                            None if sp is None else sp.ctypes.data, msg, 256, ctypes.byref(n_items))
         assert st == 0, f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned})"
         if single:
             st = lib.queues_check(r.size, r.ctypes.data, c.ctypes.data, target, single, msg, 256)
@@ -115,3 +117,46 @@ def test_edge_class_lists(checker):
     checker([1 << 16], [129], single=1)     # ragged 128-row tiles
     for single in (0, 1):
         checker([128, 512, 4096, 1 << 17], [1000, 37, 5, 2], single=single, target=17)
+
+
+@pytest.mark.parametrize("fill", [0.0, float("nan"), -1.0, float("inf")])
+def test_unusable_measured_speeds(checker, fill):
+    # a speed table with no usable entry (as bm_context_set_tile_speeds could once
+    # store) must still give full-coverage plans of shapes the mode can run
+    bad = np.full(N_SHAPES * 3, fill, dtype=np.float32)
+    for single in (0, 1):
+        checker([128, 512, 4096, 1 << 17], [1000, 37, 5, 2], single=single, speeds=bad)
+        checker([1 << 16], [129], single=single, speeds=bad)
+
+
+def _case_lines():
+    rng = np.random.default_rng(321)
+    lines = []
+    for kind in range(6):
+        for single in (0, 1):
+            for _ in range(6):
+                n_cls = int(rng.integers(1, 5))
+                vals = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536, 1 << 20], size=n_cls, replace=False))
+                counts = rng.integers(1, 260, size=n_cls)
+                target = int(rng.integers(1, 40000))
+                lines.append(f"{single} -1 {int(rng.integers(0, 64))} {target} {kind} {n_cls} "
+                             + " ".join(map(str, vals)) + " " + " ".join(map(str, counts)))
+    for pinned in range(N_SHAPES):
+        lines.append(f"0 {pinned} 0 {CU64} 0 3 128 1024 8192 300 40 9")
+    return "\n".join(lines) + "\n"
+
+
+def test_planner_under_sanitizers(tmp_path):
+    """The planner and its checker built as one program with AddressSanitizer and
+    UndefinedBehaviorSanitizer (any report aborts the run), over random class lists,
+    every pinned shape and every kind of measured-speed table."""
+    exe = str(tmp_path / "plancheck_asan")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-DPLAN_CHECK_MAIN", os.path.join(CSRC, "plan.cpp"),
+           os.path.join(ROOT, "tests", "planner_check.cpp"), "-o", exe]
+    subprocess.run(cmd, check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], input=_case_lines(), capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "failed" in r.stdout and ", 0 failed" in r.stdout, r.stdout
+    assert "Sanitizer" not in r.stderr, r.stderr[-4000:]
