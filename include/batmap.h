@@ -174,6 +174,25 @@ bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len);
  * writes nothing.  BM_EINVAL if min_support is below the build's. */
 bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity, uint64_t *n_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * result as bm_frequent_pairs, computed without any hipMalloc, hipFree or
+ * other allocating call.  Its intermediate counts, per-block counts, scan
+ * workspace and (when the index holds no plan covering these items) work
+ * list live in one scratch array of 48 MiB per GPU, part of the library and
+ * held until the process ends; the context and the index bring everything
+ * else.  Limits: n(n-1)/2 counts plus that bookkeeping must fit 48 MiB
+ * (about n <= 4000 items); a larger index gets BM_EINVAL and nothing runs.
+ * out: device memory (BM_EINVAL for a host pointer), or NULL to ask only for
+ * the count; capacity and *n_out as bm_frequent_pairs (BM_ECAPACITY, nothing
+ * written, when the pairs exceed capacity).  Every call on one GPU shares
+ * that GPU's scratch and leaves its contents there: calls that overlap on
+ * one GPU (several host threads, or contexts whose streams run concurrently)
+ * race and must be serialised by the caller.  BM_EDEVICE if the scratch
+ * address could not be found when the context was created. */
+bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity,
+                                    uint64_t *n_out);
+
 /* Pair supports among a subset of items (k distinct ids, host or device):
  * out (host or device) gets k(k-1)/2 entries, packed upper triangle in the
  * order given.  BM_EINVAL on a repeated id or an item without a BatMap,

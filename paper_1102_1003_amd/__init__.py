@@ -150,6 +150,8 @@ def load_library(path: str = LIB_PATH):
     L.bm_all_pair_supports.argtypes = [vp, vp, u64]
     L.bm_frequent_pairs.restype = i32
     L.bm_frequent_pairs.argtypes = [vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
+    L.bm_frequent_pairs_noalloc.restype = i32
+    L.bm_frequent_pairs_noalloc.argtypes = [vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
     L.bm_subset_pair_supports.restype = i32
     L.bm_subset_pair_supports.argtypes = [vp, vp, u32, vp]
     L.bm_batch_all_pair_supports.restype = i32
@@ -365,6 +367,15 @@ class Index:
         n_out = ctypes.c_uint64(0)
         cap = _numel(out) // 3
         self.ctx.check(load_library().bm_frequent_pairs(self._h, min_support, _ptr(out), cap, ctypes.byref(n_out)))
+        return int(n_out.value)
+
+    def frequent_pairs_noalloc(self, min_support: int, out=None) -> int:
+        """bm_frequent_pairs_noalloc: as frequent_pairs_into without any device allocation.
+        out: device tensor of 3*capacity int32 (or None to count only); returns the number of pairs."""
+        n_out = ctypes.c_uint64(0)
+        cap = _numel(out) // 3 if out is not None else 0
+        self.ctx.check(load_library().bm_frequent_pairs_noalloc(self._h, min_support, _ptr(out), cap,
+                                                                ctypes.byref(n_out)))
         return int(n_out.value)
 
     def frequent_pairs(self, min_support: int, capacity: int | None = None) -> np.ndarray:

@@ -195,6 +195,42 @@ int bits_for(uint64_t v)  // bits needed to hold values 0..v
 
 uint64_t n_pairs(uint64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// Scratch of bm_frequent_pairs_noalloc: one array per GPU in the library's
+// code object, held until the process ends.  Host code never passes the
+// array's name to the runtime or a kernel (on the host it is only a stand-in
+// for the symbol); it uses the device address that scratch_address() looks
+// up, once per device, with that device current.
+constexpr uint64_t kNoAllocScratchBytes = 48ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current); nullptr
+// if the lookup fails.
+uint8_t *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[device] = static_cast<uint8_t *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 
@@ -235,6 +271,8 @@ struct bm_context {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {};
     hipEvent_t fork = nullptr, join[kSide] = {};
+    // device address of this GPU's allocation-free scratch (see scratch below)
+    uint8_t *scratch = nullptr;
 };
 
 namespace {
@@ -439,17 +477,19 @@ uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
 // (defined with the read-back below): the copies are asynchronous, and the
 // runtime is never handed a pageable host address (a caller's array or a
 // vector's storage) to look up.
-bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow = true);
 bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
 
-bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
-                      std::vector<std::pair<int, uint32_t>> &ranges)
+// The plan as one work list in launch order: per-shape runs ((shape, count)
+// in `ranges`), or for a single persistent launch the per-XCD queues (ranges
+// hold the queue offsets, tagged -1).
+void flatten_plan(bm_context *ctx, const Plan &plan, std::vector<WorkItem> &flat,
+                  std::vector<std::pair<int, uint32_t>> &ranges)
 {
-    bm_context *ctx = idx->ctx;
     uint64_t total = 0;
     for (auto &v : plan.by_variant)
         total += v.size();
-    std::vector<WorkItem> flat;
+    flat.clear();
     flat.reserve(total);
     ranges.clear();
     for (size_t v = 0; v < plan.by_variant.size(); v++) {
@@ -466,6 +506,15 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
         for (uint32_t x = 0; x <= kXcds; x++)
             ranges.push_back({-1, off[x]});
     }
+}
+
+bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
+                      std::vector<std::pair<int, uint32_t>> &ranges)
+{
+    bm_context *ctx = idx->ctx;
+    std::vector<WorkItem> flat;
+    flatten_plan(ctx, plan, flat, ranges);
+    const uint64_t total = flat.size();
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total)
         return upload(ctx, dst.p, flat.data(), total * sizeof(WorkItem));
@@ -495,17 +544,23 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
 // everything queued on the context's stream so far, and work queued on the
 // context's stream after join_side waits for it (event waits, so graph
 // capture follows).
+bm_status create_side(bm_context *ctx)
+{
+    if (ctx->fork)
+        return BM_OK;
+    for (int k = 0; k < bm_context::kSide; k++) {
+        HIPC(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+        HIPC(ctx, hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming));
+    }
+    HIPC(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    return BM_OK;
+}
+
 bm_status fork_side(bm_context *ctx, int n)
 {
     if (n <= 0)
         return BM_OK;
-    if (!ctx->fork) {
-        for (int k = 0; k < bm_context::kSide; k++) {
-            HIPC(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
-            HIPC(ctx, hipEventCreateWithFlags(&ctx->join[k], hipEventDisableTiming));
-        }
-        HIPC(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-    }
+    BMC(create_side(ctx));
     HIPC(ctx, hipEventRecord(ctx->fork, ctx->stream));
     for (int k = 0; k < n; k++)
         HIPC(ctx, hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
@@ -613,10 +668,15 @@ bm_status read_back(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
 // waits until the previous upload has left the buffer.
 constexpr uint64_t kStageChunk = 16ull << 20;
 
-bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
+// grow = false: never reallocates the staging buffer (chunks of its current
+// size; the context allocates it, and the `staged` event, when created).
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow)
 {
-    for (uint64_t at = 0; at < bytes; at += kStageChunk) {
-        const uint64_t c = std::min<uint64_t>(kStageChunk, bytes - at);
+    const uint64_t chunk = grow ? kStageChunk : std::min<uint64_t>(kStageChunk, ctx->h_stage_bytes);
+    if (chunk == 0)
+        return fail(ctx, BM_ENOMEM, "no staging buffer");
+    for (uint64_t at = 0; at < bytes; at += chunk) {
+        const uint64_t c = std::min<uint64_t>(chunk, bytes - at);
         if (ctx->staged)
             HIPC(ctx, hipEventSynchronize(ctx->staged));
         else
@@ -1204,6 +1264,23 @@ bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
         delete ctx;
         return BM_ENOMEM;
     }
+    // Everything bm_frequent_pairs_noalloc uses besides its scratch exists
+    // from here on: pinned staging (1 MB) and read-back (64 KB) buffers, the
+    // staging event, the side streams, and this device's scratch address.
+    bool ready = hipHostMalloc(&ctx->h_stage, 1ull << 20) == hipSuccess;
+    if (ready)
+        ctx->h_stage_bytes = 1ull << 20;
+    ready = ready && hipHostMalloc(&ctx->h_rb, 1ull << 16) == hipSuccess;
+    if (ready)
+        ctx->h_rb_bytes = 1ull << 16;
+    ready = ready && hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) == hipSuccess;
+    ready = ready && create_side(ctx) == BM_OK;
+    if (!ready) {
+        (void)hipGetLastError();
+        bm_context_destroy(ctx);
+        return BM_ENOMEM;
+    }
+    ctx->scratch = scratch_address(device);  // nullptr: the allocation-free call reports BM_EDEVICE
     *out = ctx;
     return BM_OK;
 }
@@ -1685,6 +1762,84 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
         BMC(download(ctx, out, dst, total * sizeof(bm_pair)));
         HIPC(ctx, hipStreamSynchronize(s));
     }
+    return BM_OK;
+}
+
+bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity,
+                                    uint64_t *n_out)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    begin_query(ctx);
+    if (!n_out)
+        return fail(ctx, BM_EINVAL, "n_out is null");
+    *n_out = 0;
+    if (min_support < idx->min_support)
+        return fail(ctx, BM_EINVAL, "min_support %u is below the build's %u", min_support, idx->min_support);
+    const uint64_t np = n_pairs(idx->n);
+    if (np == 0)
+        return BM_OK;
+    if (out && ptr_kind(out) != PTR_DEVICE)
+        return fail(ctx, BM_EINVAL, "out must be device memory");
+    if (!ctx->scratch)
+        return fail(ctx, BM_EDEVICE, "no scratch address on device %d", ctx->device);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    uint32_t first = (uint32_t)(std::lower_bound(idx->h_sizes_sorted.begin(), idx->h_sizes_sorted.end(), min_support) -
+                                idx->h_sizes_sorted.begin());
+    first = std::max(first, idx->first_built);
+    // The index's resident plan serves when it covers every pair among sorted
+    // indices >= first (it was made for a prefix no longer than that; tile
+    // speeds only weigh shapes, every plan is complete).  Pairs it adds among
+    // items below the support bound cannot reach the bound.  Otherwise a plan
+    // is made here and placed in the scratch.
+    const bool own = idx->planned_first != UINT32_MAX && idx->planned_first <= first;
+    std::vector<WorkItem> flat;
+    std::vector<std::pair<int, uint32_t>> ranges;
+    double slot_pairs = idx->planned_slot_pairs;
+    if (!own) {
+        Plan plan;
+        plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
+                     use_persistent(ctx) ? 1 : 0, forced_variant());
+        flatten_plan(ctx, plan, flat, ranges);
+        slot_pairs = plan.slot_pairs;
+    }
+    // scratch: counts | per-block counts | their offsets | scan workspace | work list
+    const uint32_t nb = threshold_blocks(np);
+    const uint64_t o_cnt = align_up(np * 4, 256);
+    const uint64_t o_off = o_cnt + align_up(((uint64_t)nb + 1) * 4, 256);
+    const uint64_t o_tmp = o_off + align_up(((uint64_t)nb + 1) * 8, 256);
+    const uint64_t o_work = o_tmp + align_up(scan_tmp_bytes((uint64_t)nb + 1), 256);
+    const uint64_t end = o_work + flat.size() * sizeof(WorkItem);
+    if (end > kNoAllocScratchBytes)
+        return fail(ctx, BM_EINVAL, "%u items need %llu bytes of scratch; the allocation-free call has %llu", idx->n,
+                    (unsigned long long)end, (unsigned long long)kNoAllocScratchBytes);
+    uint8_t *sc = ctx->scratch;
+    uint32_t *counts = reinterpret_cast<uint32_t *>(sc);
+    uint32_t *thr_counts = reinterpret_cast<uint32_t *>(sc + o_cnt);
+    uint64_t *thr_off = reinterpret_cast<uint64_t *>(sc + o_off);
+    WorkItem *work = own ? idx->work.p : reinterpret_cast<WorkItem *>(sc + o_work);
+    if (!own && !flat.empty())
+        BMC(upload(ctx, work, flat.data(), flat.size() * sizeof(WorkItem), /*grow=*/false));
+    // the scratch keeps the last call's contents: counts and the block-count
+    // tail start from zero here (fill kernels, no memset nodes)
+    HIPC(ctx, fill_u32(counts, np, 0, s));
+    ctx->slot_pairs = slot_pairs;
+    BMC(run_compare(ctx, work, own ? idx->work_ranges : ranges, whole_desc(idx, counts)));
+    HIPC(ctx, launch_apply_corrections(idx->corr.p, idx->n_corr, counts, idx->n, s));
+    HIPC(ctx, fill_u32(thr_counts + nb, 1, 0, s));
+    HIPC(ctx, launch_threshold_count(counts, np, min_support, thr_counts, nb, s));
+    HIPC(ctx, exclusive_scan_u32_to_u64(thr_counts, thr_off, (uint64_t)nb + 1, sc + o_tmp, s));
+    if (out)
+        HIPC(ctx, launch_threshold_write(counts, np, idx->n, min_support, thr_off, nb, capacity, out, s));
+    uint64_t total = 0;
+    BMC(read_back(ctx, &total, thr_off + nb, 8));
+    *n_out = total;
+    if (out && total > capacity)
+        return fail(ctx, BM_ECAPACITY, "%llu frequent pairs, capacity %llu", (unsigned long long)total,
+                    (unsigned long long)capacity);
     return BM_OK;
 }
 
