@@ -9,7 +9,10 @@ use it.  The product library neither imports nor links it.
   :func:`frequent_pairs`, :func:`subset_pairs`, :func:`pair_rows`.
 * Method reference (Sec. II, II-A, III-A, III-C): BatMap build, the 4-slot
   word compare and the failed-insertion correction -> :func:`batmap_build`,
-  :func:`batmap_compare`, :func:`batmap_all_pairs`, :func:`batmap_check`.
+  :func:`batmap_compare`, :func:`batmap_all_pairs`, :func:`batmap_check`;
+  wider slots (Sec. III-A, uncompressed case: ``slot_bits`` 16 or 32,
+  :func:`slot_compare`); two set families (Sec. I, boolean matrix product)
+  -> :func:`cross` (definition), :func:`batmap_cross` (method).
 """
 from __future__ import annotations
 
@@ -71,6 +74,24 @@ def lib():
         L.orc_batmap_all_pairs.restype = ctypes.c_uint64
         L.orc_batmap_all_pairs.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _u32p] + [_u32p] * 3 + [
             ctypes.c_uint32, ctypes.c_uint32, _u32p]
+        L.orc_shift_w.restype = ctypes.c_uint32
+        L.orc_shift_w.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_batmap_build_w.restype = ctypes.c_uint32
+        L.orc_batmap_build_w.argtypes = [ctypes.c_uint32] * 4 + [_u32p] * 3 + [_u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                                                               ctypes.c_uint32, _u8p, _u32p]
+        L.orc_slot_compare_w.restype = ctypes.c_uint64
+        L.orc_slot_compare_w.argtypes = [_u8p, ctypes.c_uint32, _u8p, ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_batmap_all_pairs_w.restype = ctypes.c_uint64
+        L.orc_batmap_all_pairs_w.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _u32p] + [_u32p] * 3 + [
+            ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p]
+        L.orc_batmap_check_w.restype = ctypes.c_int
+        L.orc_batmap_check_w.argtypes = [ctypes.c_uint32] * 4 + [_u32p] * 6 + [_u32p, ctypes.c_uint32, _u32p,
+                                                                               ctypes.c_uint32, ctypes.c_uint32, _u8p]
+        L.orc_cross.restype = None
+        L.orc_cross.argtypes = [ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint32, _u64p, _u32p, _u32p, ctypes.c_int]
+        L.orc_batmap_cross.restype = ctypes.c_uint64
+        L.orc_batmap_cross.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint32, _u64p,
+                                       _u32p] + [_u32p] * 3 + [ctypes.c_uint32] * 3 + [_u32p]
         L.orc_batmap_check.restype = ctypes.c_int
         L.orc_batmap_check.argtypes = [ctypes.c_uint32] * 4 + [_u32p] * 6 + [_u32p, ctypes.c_uint32, _u32p,
                                                                              ctypes.c_uint32, _u8p]
@@ -158,8 +179,11 @@ def transpose(m: int, row_offsets, items, n: int):
 
 # ---- Part 2: the method ----------------------------------------------------
 
-def shift(m: int) -> int:
-    return int(lib().orc_shift(m))
+def shift(m: int, slot_bits: int = 8) -> int:
+    """s of Sec. III-A for w-bit slots (w - 1 code bits, the all-ones code reserved for empty)."""
+    if slot_bits == 8:
+        return int(lib().orc_shift(m))
+    return int(lib().orc_shift_w(m, slot_bits))
 
 
 def r_for(size: int, r0: int) -> int:
@@ -170,17 +194,27 @@ def swar_word(x: int, y: int) -> int:
     return int(lib().orc_swar_word(x, y))
 
 
-def batmap_build(m: int, r0: int, perms, set_tids, max_loop: int = 64, r: int | None = None):
-    """Canonical bytes (3r) and failed elements of one set."""
-    s = shift(m)
+def batmap_build(m: int, r0: int, perms, set_tids, max_loop: int = 64, r: int | None = None, slot_bits: int = 8):
+    """Canonical bytes (3r slots of slot_bits / 8 bytes, little-endian) and failed elements of one set."""
+    s = shift(m, slot_bits)
     set_tids = np.ascontiguousarray(set_tids, dtype=np.uint32)
     if r is None:
         r = r_for(set_tids.size, r0)
-    out = np.zeros(3 * r, dtype=np.uint8)
+    out = np.zeros(3 * r * (slot_bits // 8), dtype=np.uint8)
     failed = np.zeros(2 * set_tids.size + 1, dtype=np.uint32)
     p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms]
-    nf = lib().orc_batmap_build(m, s, r0, r, p[0], p[1], p[2], set_tids, set_tids.size, max_loop, out, failed)
+    if slot_bits == 8:
+        nf = lib().orc_batmap_build(m, s, r0, r, p[0], p[1], p[2], set_tids, set_tids.size, max_loop, out, failed)
+    else:
+        nf = lib().orc_batmap_build_w(m, s, r0, r, p[0], p[1], p[2], set_tids, set_tids.size, max_loop, slot_bits,
+                                      out, failed)
     return out, failed[:nf].copy(), r
+
+
+def slot_compare(bi, ri: int, bj, rj: int, slot_bits: int = 8) -> int:
+    """Sec. II counting rule slot by slot (any slot width; wrap-around of the narrower map)."""
+    return int(lib().orc_slot_compare_w(np.ascontiguousarray(bi, np.uint8), ri, np.ascontiguousarray(bj, np.uint8),
+                                        rj, slot_bits))
 
 
 def batmap_compare(bi, ri: int, bj, rj: int) -> int:
@@ -188,14 +222,40 @@ def batmap_compare(bi, ri: int, bj, rj: int) -> int:
                                         rj))
 
 
-def batmap_all_pairs(m: int, offsets, tids, perms, r0: int, max_loop: int = 64):
-    """Counts of the whole method (maps + word compare + correction); (packed, total_failed)."""
+def batmap_all_pairs(m: int, offsets, tids, perms, r0: int, max_loop: int = 64, slot_bits: int = 8):
+    """Counts of the whole method (maps + compare + correction); (packed, total_failed)."""
     off, t = _csr(offsets, tids)
     n = off.size - 1
     out = np.zeros(max(n_pairs(n), 1), dtype=np.uint32)
     p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms]
-    nf = lib().orc_batmap_all_pairs(m, n, off, t, p[0], p[1], p[2], r0, max_loop, out)
+    if slot_bits == 8:
+        nf = lib().orc_batmap_all_pairs(m, n, off, t, p[0], p[1], p[2], r0, max_loop, out)
+    else:
+        nf = lib().orc_batmap_all_pairs_w(m, n, off, t, p[0], p[1], p[2], r0, max_loop, slot_bits, out)
     return out[:n_pairs(n)], int(nf)
+
+
+def cross(offsets_a, tids_a, offsets_b, tids_b, threads: int = 1) -> np.ndarray:
+    """|A_i cap B_j| for all i, j (row-major na x nb, uint32) by merging (the definition)."""
+    oa, ta = _csr(offsets_a, tids_a)
+    ob, tb = _csr(offsets_b, tids_b)
+    na, nb = oa.size - 1, ob.size - 1
+    out = np.zeros(max(na * nb, 1), dtype=np.uint32)
+    if na and nb:
+        lib().orc_cross(na, oa, ta, nb, ob, tb, out, threads)
+    return out[:na * nb].reshape(na, nb)
+
+
+def batmap_cross(m: int, offsets_a, tids_a, offsets_b, tids_b, perms, r0: int, max_loop: int = 64,
+                 slot_bits: int = 8):
+    """The method on two families hashed alike: (na x nb counts, failed elements of both)."""
+    oa, ta = _csr(offsets_a, tids_a)
+    ob, tb = _csr(offsets_b, tids_b)
+    na, nb = oa.size - 1, ob.size - 1
+    out = np.zeros(max(na * nb, 1), dtype=np.uint32)
+    p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms]
+    nf = lib().orc_batmap_cross(m, na, oa, ta, nb, ob, tb, p[0], p[1], p[2], r0, max_loop, slot_bits, out)
+    return out[:na * nb].reshape(na, nb), int(nf)
 
 
 def inverse_perms(perms):
@@ -208,7 +268,7 @@ def inverse_perms(perms):
     return invs
 
 
-def batmap_check(m: int, s: int, r0: int, r: int, perms, invs, set_tids, failed, bytes_) -> int:
+def batmap_check(m: int, s: int, r0: int, r: int, perms, invs, set_tids, failed, bytes_, slot_bits: int = 8) -> int:
     p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms]
     iv = [np.ascontiguousarray(x, dtype=np.uint32) for x in invs]
     set_tids = np.ascontiguousarray(set_tids, dtype=np.uint32)
@@ -218,5 +278,8 @@ def batmap_check(m: int, s: int, r0: int, r: int, perms, invs, set_tids, failed,
         nf = 0
     else:
         nf = failed.size
-    return int(lib().orc_batmap_check(m, s, r0, r, p[0], p[1], p[2], iv[0], iv[1], iv[2], set_tids, set_tids.size,
-                                      failed, nf, np.ascontiguousarray(bytes_, dtype=np.uint8)))
+    if slot_bits == 8:
+        return int(lib().orc_batmap_check(m, s, r0, r, p[0], p[1], p[2], iv[0], iv[1], iv[2], set_tids, set_tids.size,
+                                          failed, nf, np.ascontiguousarray(bytes_, dtype=np.uint8)))
+    return int(lib().orc_batmap_check_w(m, s, r0, r, p[0], p[1], p[2], iv[0], iv[1], iv[2], set_tids, set_tids.size,
+                                        failed, nf, slot_bits, np.ascontiguousarray(bytes_, dtype=np.uint8)))

@@ -22,6 +22,14 @@
  *   - the failed-insertion correction (Sec. III-C, "Failed insertions").
  *   It also holds a structural checker for BatMaps in canonical byte form.
  *
+ * Part 3 widens the method along two lines the paper names:
+ *   - wider slots (Sec. III-A, the "uncompressed case"): w = 16 or 32 bits
+ *     per slot keep w - 1 bits of pi_t(x), so r_i is no longer floored at
+ *     2^s for the 7-bit code; the counting rule of Sec. II is unchanged;
+ *   - intersections of two set families A_i, B_j (Sec. I: sparse boolean
+ *     matrix multiplication and join-project), by definition and by the
+ *     method with both families hashed by the same pi_t, s and r_0.
+ *
  * Readings where the paper is silent or loose:
  *   C1 indicator bit = 1 on the copy whose other copy sits in the cyclically
  *      preceding table (Fig. 3);
@@ -202,13 +210,21 @@ int orc_transpose(uint32_t m, const uint64_t *toff, const uint32_t *items, uint3
 
 /* Sec. III-A: the 7 most significant bits of pi_t(x) are stored, so
  * m - 1 must fit in 7 bits after shifting right by s.  With code 127
- * reserved for the empty slot (reading C3): s = min{s : m <= 127 * 2^s}. */
-uint32_t orc_shift(uint32_t m)
+ * reserved for the empty slot (reading C3): s = min{s : m <= 127 * 2^s}.
+ * For w-bit slots (w - 1 code bits, Part 3) the same rule with the code
+ * 2^(w-1) - 1 reserved: s = min{s : m <= (2^(w-1) - 1) * 2^s}. */
+uint32_t orc_shift_w(uint32_t m, uint32_t w)
 {
+    const uint64_t top = ((uint64_t)1 << (w - 1)) - 1;
     uint32_t s = 0;
-    while ((uint64_t)m > (uint64_t)127 << s)
+    while ((uint64_t)m > top << s)
         s++;
     return s;
+}
+
+uint32_t orc_shift(uint32_t m)
+{
+    return orc_shift_w(m, 8);
 }
 
 /* Sec. II "Our adaptation" and Sec. III-A: r_i is a power of two, about
@@ -223,9 +239,32 @@ uint32_t orc_r_for(uint64_t size, uint32_t r0)
 
 typedef struct {
     uint32_t m, s, r0, r; /* universe, shift, smallest domain, this map's domain */
+    uint32_t w;           /* bits per slot: 8 (the paper's layout), 16 or 32 */
     const uint32_t *perm[3];
     uint32_t *T; /* 3 tables of r entries, T[t*r + q] */
 } orc_map;
+
+/* Slot v of a map in canonical form: w/8 bytes, little-endian. */
+static uint32_t slot_get(const uint8_t *bytes, uint32_t w, uint64_t v)
+{
+    uint32_t x = 0;
+    for (uint32_t k = 0; k < w / 8; k++)
+        x |= (uint32_t)bytes[v * (w / 8) + k] << (8 * k);
+    return x;
+}
+
+static void slot_put(uint8_t *bytes, uint32_t w, uint64_t v, uint32_t x)
+{
+    for (uint32_t k = 0; k < w / 8; k++)
+        bytes[v * (w / 8) + k] = (uint8_t)(x >> (8 * k));
+}
+
+/* The empty slot of a w-bit layout: every code bit set, indicator 0
+ * (0x7F for w = 8, reading C3). */
+static uint32_t empty_slot(uint32_t w)
+{
+    return (uint32_t)(((uint64_t)1 << (w - 1)) - 1);
+}
 
 static uint32_t h(const orc_map *B, int t, uint32_t x)
 {
@@ -292,13 +331,14 @@ static uint64_t slot_of(uint32_t r0, int t, uint32_t q)
     return (uint64_t)3 * r0 * (q / r0) + (uint64_t)t * r0 + (q % r0);
 }
 
-/* Encoded byte of each occupied slot: indicator (reading C1) in bit 7, the
- * 7 high bits of pi_t(x) (pi_t(x) >> s) below it; empty slots 0x7F (C3). */
+/* Encoded slot of each occupied position: indicator (reading C1) in the top
+ * bit (bit 7 for the paper's bytes), the high bits of pi_t(x) (pi_t(x) >> s)
+ * below it; empty slots all code bits set (0x7F for bytes, C3). */
 static void encode(const orc_map *B, uint8_t *bytes)
 {
     uint64_t total = (uint64_t)3 * B->r;
     for (uint64_t v = 0; v < total; v++)
-        bytes[v] = 0x7F;
+        slot_put(bytes, B->w, v, empty_slot(B->w));
     for (int t = 0; t < 3; t++) {
         for (uint32_t q = 0; q < B->r; q++) {
             uint32_t x = B->T[(uint64_t)t * B->r + q];
@@ -306,24 +346,26 @@ static void encode(const orc_map *B, uint8_t *bytes)
                 continue;
             int prev = (t + 2) % 3;
             uint32_t other = B->T[(uint64_t)prev * B->r + h(B, prev, x)];
-            uint8_t bit = (other == x) ? 1 : 0;
-            uint8_t code = (uint8_t)(B->perm[t][x] >> B->s);
-            bytes[slot_of(B->r0, t, q)] = (uint8_t)((bit << 7) | code);
+            uint32_t bit = (other == x) ? 1 : 0;
+            uint32_t code = B->perm[t][x] >> B->s;
+            slot_put(bytes, B->w, slot_of(B->r0, t, q), (bit << (B->w - 1)) | code);
         }
     }
 }
 
-/* Build the BatMap of one set in canonical byte form (3r bytes).
- * Returns the number of failed elements written to `failed` (capacity 2*size). */
-uint32_t orc_batmap_build(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
-                          const uint32_t *p2, const uint32_t *set, uint32_t size, uint32_t max_loop, uint8_t *bytes,
-                          uint32_t *failed)
+/* Build the BatMap of one set in canonical form with w-bit slots (3r w/8
+ * bytes).  Returns the number of failed elements written to `failed`
+ * (capacity 2*size). */
+uint32_t orc_batmap_build_w(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                            const uint32_t *p2, const uint32_t *set, uint32_t size, uint32_t max_loop, uint32_t w,
+                            uint8_t *bytes, uint32_t *failed)
 {
     orc_map B;
     B.m = m;
     B.s = s;
     B.r0 = r0;
     B.r = r;
+    B.w = w;
     B.perm[0] = p0;
     B.perm[1] = p1;
     B.perm[2] = p2;
@@ -335,6 +377,14 @@ uint32_t orc_batmap_build(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const
     encode(&B, bytes);
     free(B.T);
     return nf;
+}
+
+/* The paper's 8-bit layout (3r bytes). */
+uint32_t orc_batmap_build(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                          const uint32_t *p2, const uint32_t *set, uint32_t size, uint32_t max_loop, uint8_t *bytes,
+                          uint32_t *failed)
+{
+    return orc_batmap_build_w(m, s, r0, r, p0, p1, p2, set, size, max_loop, 8, bytes, failed);
 }
 
 /* Sec. III-A word compare of 4 slots packed little-endian in a 32-bit word:
@@ -371,14 +421,39 @@ uint64_t orc_batmap_compare(const uint8_t *bi, uint32_t ri, const uint8_t *bj, u
     return c;
 }
 
+/* Sec. II counting rule slot by slot, for any slot width: slot v of the
+ * wider map against slot v mod 3 r_small of the narrower; a pair counts
+ * when the w - 1 code bits agree and at least one indicator is set. */
+uint64_t orc_slot_compare_w(const uint8_t *bi, uint32_t ri, const uint8_t *bj, uint32_t rj, uint32_t w)
+{
+    if (ri > rj) {
+        const uint8_t *tb = bi;
+        bi = bj;
+        bj = tb;
+        uint32_t tr = ri;
+        ri = rj;
+        rj = tr;
+    }
+    const uint32_t code_mask = empty_slot(w), ind = (uint32_t)1 << (w - 1);
+    const uint64_t ni = (uint64_t)3 * ri, nj = (uint64_t)3 * rj;
+    uint64_t c = 0;
+    for (uint64_t v = 0; v < nj; v++) {
+        uint32_t x = slot_get(bj, w, v), y = slot_get(bi, w, v % ni);
+        if ((x & code_mask) == (y & code_mask) && ((x | y) & ind))
+            c++;
+    }
+    return c;
+}
+
 /* The whole method for all pairs i<j of one instance: BatMaps from the
  * sets (perms and max_loop given), word compares over max width, then the
  * Sec. III-C correction. out: packed upper triangle.  Returns the total
  * number of failed elements.  r0 is the common smallest domain (>= 2^s). */
-uint64_t orc_batmap_all_pairs(uint32_t m, uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *p0,
-                              const uint32_t *p1, const uint32_t *p2, uint32_t r0, uint32_t max_loop, uint32_t *out)
+uint64_t orc_batmap_all_pairs_w(uint32_t m, uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *p0,
+                                const uint32_t *p1, const uint32_t *p2, uint32_t r0, uint32_t max_loop, uint32_t w,
+                                uint32_t *out)
 {
-    uint32_t s = orc_shift(m);
+    uint32_t s = orc_shift_w(m, w);
     uint32_t *rs = (uint32_t *)malloc(((size_t)n + 1) * sizeof(uint32_t));
     uint8_t **maps = (uint8_t **)malloc(((size_t)n + 1) * sizeof(uint8_t *));
     uint32_t **fails = (uint32_t **)malloc(((size_t)n + 1) * sizeof(uint32_t *));
@@ -387,14 +462,17 @@ uint64_t orc_batmap_all_pairs(uint32_t m, uint32_t n, const uint64_t *off, const
     for (uint32_t i = 0; i < n; i++) {
         uint32_t size = (uint32_t)(off[i + 1] - off[i]);
         rs[i] = orc_r_for(size, r0);
-        maps[i] = (uint8_t *)malloc((size_t)3 * rs[i]);
+        maps[i] = (uint8_t *)malloc((size_t)3 * rs[i] * (w / 8));
         fails[i] = (uint32_t *)malloc(((size_t)2 * size + 1) * sizeof(uint32_t));
-        nfail[i] = orc_batmap_build(m, s, r0, rs[i], p0, p1, p2, tids + off[i], size, max_loop, maps[i], fails[i]);
+        nfail[i] = orc_batmap_build_w(m, s, r0, rs[i], p0, p1, p2, tids + off[i], size, max_loop, w, maps[i],
+                                      fails[i]);
         total_failed += nfail[i];
     }
+    /* the paper's word compare for its byte layout, the slot rule otherwise */
     for (uint32_t i = 0; i < n; i++)
         for (uint32_t j = i + 1; j < n; j++)
-            out[packed_index(n, i, j)] = (uint32_t)orc_batmap_compare(maps[i], rs[i], maps[j], rs[j]);
+            out[packed_index(n, i, j)] = (uint32_t)(w == 8 ? orc_batmap_compare(maps[i], rs[i], maps[j], rs[j])
+                                                           : orc_slot_compare_w(maps[i], rs[i], maps[j], rs[j], w));
 
     /* Sec. III-C: F_b = items whose insertion of b failed, A_b = all items
      * of transaction b; each pair {a,c}, a in F_b, c in A_b, gains one per
@@ -449,17 +527,24 @@ uint64_t orc_batmap_all_pairs(uint32_t m, uint32_t n, const uint64_t *off, const
     return total_failed;
 }
 
+uint64_t orc_batmap_all_pairs(uint32_t m, uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *p0,
+                              const uint32_t *p1, const uint32_t *p2, uint32_t r0, uint32_t max_loop, uint32_t *out)
+{
+    return orc_batmap_all_pairs_w(m, n, off, tids, p0, p1, p2, r0, max_loop, 8, out);
+}
+
 /* Structural check of one BatMap in canonical byte form against its set:
  * every byte is 0x7F or decodes (position + code) to pi_t(x) of an element
  * x of S minus F; each such x is held exactly twice, in two different
  * tables, with indicator bits as in Fig. 3 (reading C1); no element of F is
  * held; F is a subset of S.  inv0..2 are the inverse permutations.
  * Returns 0 when valid, else a positive code naming the first violation. */
-int orc_batmap_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
-                     const uint32_t *p2, const uint32_t *inv0, const uint32_t *inv1, const uint32_t *inv2,
-                     const uint32_t *set, uint32_t size, const uint32_t *failed, uint32_t nfailed,
-                     const uint8_t *bytes)
+int orc_batmap_check_w(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                       const uint32_t *p2, const uint32_t *inv0, const uint32_t *inv1, const uint32_t *inv2,
+                       const uint32_t *set, uint32_t size, const uint32_t *failed, uint32_t nfailed, uint32_t w,
+                       const uint8_t *bytes)
 {
+    const uint32_t empty = empty_slot(w), top = w - 1;
     const uint32_t *perm[3] = {p0, p1, p2};
     const uint32_t *inv[3] = {inv0, inv1, inv2};
     int rc = 0;
@@ -479,10 +564,10 @@ int orc_batmap_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint
         is_failed[failed[k]] = 1;
     }
     for (uint64_t v = 0; v < (uint64_t)3 * r; v++) {
-        uint8_t byte = bytes[v];
-        if (byte == 0x7F)
+        uint32_t slot = slot_get(bytes, w, v);
+        if (slot == empty)
             continue;
-        uint32_t code = byte & 0x7Fu;
+        uint32_t code = slot & empty;
         uint64_t blk = v / ((uint64_t)3 * r0);
         int t = (int)((v % ((uint64_t)3 * r0)) / r0);
         uint32_t q = (uint32_t)(blk * r0 + v % r0);
@@ -525,9 +610,9 @@ int orc_batmap_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint
             if (!(tb & (1u << t)))
                 continue;
             uint32_t q = perm[t][x] & (r - 1);
-            uint8_t bit = bytes[slot_of(r0, t, q)] >> 7;
+            uint32_t bit = slot_get(bytes, w, slot_of(r0, t, q)) >> top;
             int prev = (t + 2) % 3;
-            uint8_t want = (tb >> prev) & 1;
+            uint32_t want = (tb >> prev) & 1;
             if (bit != want) {
                 rc = 9; /* indicator bit disagrees with Fig. 3 */
                 goto done;
@@ -539,4 +624,122 @@ done:
     free(is_failed);
     free(seen_tables);
     return rc;
+}
+
+int orc_batmap_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                     const uint32_t *p2, const uint32_t *inv0, const uint32_t *inv1, const uint32_t *inv2,
+                     const uint32_t *set, uint32_t size, const uint32_t *failed, uint32_t nfailed,
+                     const uint8_t *bytes)
+{
+    return orc_batmap_check_w(m, s, r0, r, p0, p1, p2, inv0, inv1, inv2, set, size, failed, nfailed, 8, bytes);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Part 3b: two set families (Sec. I, sparse boolean matrix multiplication) */
+/* ---------------------------------------------------------------------- */
+
+/* Definition: out[i * nb + j] = |A_i cap B_j| for every i < na, j < nb, by
+ * merging the sorted lists; row i of the output is the boolean product's
+ * row i once counts are read as "> 0". */
+void orc_cross(uint32_t na, const uint64_t *offa, const uint32_t *tidsa, uint32_t nb, const uint64_t *offb,
+               const uint32_t *tidsb, uint32_t *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) if (nthreads != 1)
+#endif
+    for (int64_t i = 0; i < (int64_t)na; i++)
+        for (uint32_t j = 0; j < nb; j++)
+            out[(uint64_t)i * nb + j] = (uint32_t)orc_merge_count(tidsa + offa[i], offa[i + 1] - offa[i],
+                                                                  tidsb + offb[j], offb[j + 1] - offb[j]);
+    (void)nthreads;
+}
+
+static int in_sorted(const uint32_t *a, uint32_t n, uint32_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < n && a[lo] == x;
+}
+
+static int cmp_u32(const void *x, const void *y)
+{
+    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    return a < b ? -1 : (a > b);
+}
+
+/* The method on two families: both hashed with the same pi_t, s and r_0 (so
+ * every r divides every wider r and slot positions agree), each pair
+ * compared slot by slot over the wider map, then the Sec. III-C correction
+ * for the pair: one per shared element that failed in either map (reading
+ * C9 for one pair).  out as orc_cross.  Returns the failed elements of both
+ * families. */
+uint64_t orc_batmap_cross(uint32_t m, uint32_t na, const uint64_t *offa, const uint32_t *tidsa, uint32_t nb,
+                          const uint64_t *offb, const uint32_t *tidsb, const uint32_t *p0, const uint32_t *p1,
+                          const uint32_t *p2, uint32_t r0, uint32_t max_loop, uint32_t w, uint32_t *out)
+{
+    const uint32_t s = orc_shift_w(m, w);
+    const uint32_t nn[2] = {na, nb};
+    const uint64_t *offs[2] = {offa, offb};
+    const uint32_t *tl[2] = {tidsa, tidsb};
+    uint32_t *rs[2];
+    uint8_t **maps[2];
+    uint32_t **fails[2];
+    uint32_t *nfail[2];
+    uint64_t total = 0;
+    for (int f = 0; f < 2; f++) {
+        rs[f] = (uint32_t *)malloc(((size_t)nn[f] + 1) * sizeof(uint32_t));
+        maps[f] = (uint8_t **)malloc(((size_t)nn[f] + 1) * sizeof(uint8_t *));
+        fails[f] = (uint32_t **)malloc(((size_t)nn[f] + 1) * sizeof(uint32_t *));
+        nfail[f] = (uint32_t *)calloc((size_t)nn[f] + 1, sizeof(uint32_t));
+        for (uint32_t i = 0; i < nn[f]; i++) {
+            uint32_t size = (uint32_t)(offs[f][i + 1] - offs[f][i]);
+            rs[f][i] = orc_r_for(size, r0);
+            maps[f][i] = (uint8_t *)malloc((size_t)3 * rs[f][i] * (w / 8));
+            fails[f][i] = (uint32_t *)malloc(((size_t)2 * size + 1) * sizeof(uint32_t));
+            nfail[f][i] = orc_batmap_build_w(m, s, r0, rs[f][i], p0, p1, p2, tl[f] + offs[f][i], size, max_loop, w,
+                                             maps[f][i], fails[f][i]);
+            qsort(fails[f][i], nfail[f][i], sizeof(uint32_t), cmp_u32);
+            total += nfail[f][i];
+        }
+    }
+    for (uint32_t i = 0; i < na; i++) {
+        for (uint32_t j = 0; j < nb; j++) {
+            uint64_t c = orc_slot_compare_w(maps[0][i], rs[0][i], maps[1][j], rs[1][j], w);
+            /* shared elements lost by a failed insertion on either side */
+            const uint32_t *a = tidsa + offa[i], *b = tidsb + offb[j];
+            uint64_t x = 0, y = 0, xa = offa[i + 1] - offa[i], yb = offb[j + 1] - offb[j];
+            while (x < xa && y < yb) {
+                if (a[x] < b[y]) {
+                    x++;
+                } else if (a[x] > b[y]) {
+                    y++;
+                } else {
+                    if (in_sorted(fails[0][i], nfail[0][i], a[x]) || in_sorted(fails[1][j], nfail[1][j], a[x]))
+                        c++;
+                    x++;
+                    y++;
+                }
+            }
+            out[(uint64_t)i * nb + j] = (uint32_t)c;
+        }
+    }
+    for (int f = 0; f < 2; f++) {
+        for (uint32_t i = 0; i < nn[f]; i++) {
+            free(maps[f][i]);
+            free(fails[f][i]);
+        }
+        free(maps[f]);
+        free(fails[f]);
+        free(nfail[f]);
+        free(rs[f]);
+    }
+    return total;
 }

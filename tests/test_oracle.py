@@ -298,3 +298,201 @@ def test_wraparound_compare_against_definition():
             Bb, Fb, rb = maps[b]
             want = np.intersect1d(np.setdiff1d(sets[a], Fa), np.setdiff1d(sets[b], Fb)).size
             assert oracle.batmap_compare(Ba, ra, Bb, rb) == want
+
+
+# ---- Fig. 3 direction on bytes the oracle builds --------------------------------
+
+def _fig3_case(tables):
+    """Set and permutations of [0, 64) that make INSERT leave x = 1 in `tables` (1-based, Fig. 3):
+    {1, 2} from a lone element; {2, 3} when y = 5 meets x in A_1 (x moves on to A_3);
+    {1, 3} when y = 2 meets x in A_2.  Hash values are pi_t(x) mod 4 (r = r_0 = 4, s = 0)."""
+    m = 64
+    ident = np.arange(m, dtype=np.uint32)
+    p0, p1, p2 = ident.copy(), ident.copy(), ident.copy()
+    if tables == [1, 2]:
+        S = [1]
+    elif tables == [2, 3]:
+        S = [1, 5]                       # h_1(5) = h_1(1) = 1; h_2(5) = 2 != h_2(1) = 1
+        p1[5], p1[6] = 6, 5
+    else:
+        S = [1, 2]                       # h_2(2) = 5 mod 4 = h_2(1); h_1(2) = 2 != h_1(1)
+        p1[2], p1[5] = 5, 2
+    return m, np.array(S, dtype=np.uint32), [p0, p1, p2]
+
+
+@pytest.mark.parametrize("slot_bits", [8, 16, 32])
+def test_fig3_indicator_bits_of_built_maps(slot_bits):
+    """Reading C1 pinned on the oracle's own output: for each assignment printed in Fig. 3, a
+    map built with INSERT places x in exactly those two tables and sets the indicator bits
+    the figure prints next to them."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_fig3.json")))
+    w = slot_bits // 8
+    for a in g["assignments"]:
+        m, S, perms = _fig3_case(a["tables"])
+        B, F, r = oracle.batmap_build(m, 4, perms, S, 64, r=4, slot_bits=slot_bits)
+        assert len(F) == 0 and r == 4
+        slots = B.reshape(-1, w).astype(np.uint64) @ (np.uint64(256) ** np.arange(w, dtype=np.uint64))
+        x = 1
+        seen = {}
+        for t in range(3):
+            q = int(perms[t][x]) % 4
+            v = t * 4 + q                # Fig. 4 slot of (t, q) with r = r_0 = 4
+            code = int(slots[v]) & ((1 << (slot_bits - 1)) - 1)
+            if code == int(perms[t][x]):
+                seen[str(t + 1)] = int(slots[v]) >> (slot_bits - 1)
+        assert seen == a["bit"], (a, seen)
+
+
+def test_r_for_follows_the_papers_domain_size():
+    """Sec. III-A: hash domains of 2 * 2^ceil(log |S|) slots, floored at the common r_0."""
+    for k in range(0, 20):
+        assert oracle.r_for(1 << k, 1) == 2 << k              # |S| = 2^k: 2 * 2^k
+        assert oracle.r_for((1 << k) + 1, 1) == 4 << k        # one more element: 2 * 2^(k+1)
+    assert oracle.r_for(0, 128) == 128 and oracle.r_for(63, 128) == 128 and oracle.r_for(65, 128) == 256
+
+
+# ---- wider slots (Sec. III-A, the uncompressed case) ---------------------------
+
+@pytest.mark.parametrize("slot_bits", [8, 16, 32])
+def test_shift_keeps_codes_below_the_empty_code(slot_bits):
+    """The largest code (m - 1) >> s stays below the reserved all-ones code, and s is the
+    smallest shift that does so."""
+    empty = (1 << (slot_bits - 1)) - 1
+    for m in (1, 2, 127, 128, 32767, 32768, 10_000, 1_000_000, 1 << 20, 4_000_000, (1 << 31) - 1, 1 << 31,
+              (1 << 32) - 1):
+        s = oracle.shift(m, slot_bits)
+        assert ((m - 1) >> s) < empty
+        assert s == 0 or ((m - 1) >> (s - 1)) >= empty
+
+
+@pytest.mark.parametrize("slot_bits", [16, 32])
+@pytest.mark.parametrize("seed,max_loop", [(0, 64), (1, 8), (2, 2), (3, 1), (4, 0)])
+def test_wide_slot_method_equals_definition(slot_bits, seed, max_loop):
+    """Maps with 16- or 32-bit slots and domains floored only at 2^s of their own code width:
+    all counts (compare + correction) equal the definition, with failures forced."""
+    rng = np.random.default_rng(500 + seed)
+    m = int(rng.integers(300, 60_000))
+    n = int(rng.integers(2, 20))
+    off, tids = random_instance(rng, m, n, 0.0, 0.05)
+    perms = _perms(m, 40 + seed)
+    r0 = max(4, 1 << oracle.shift(m, slot_bits))
+    got, nfail = oracle.batmap_all_pairs(m, off, tids, perms, r0, max_loop, slot_bits=slot_bits)
+    np.testing.assert_array_equal(got, oracle.all_pairs(off, tids))
+    if max_loop == 0:
+        assert nfail == tids.size
+
+
+@pytest.mark.parametrize("slot_bits", [16, 32])
+def test_wide_slot_maps_pass_check_and_planted_mistakes_fail(slot_bits):
+    m = 70_000
+    rng = np.random.default_rng(61)
+    perms = _perms(m, 6)
+    invs = oracle.inverse_perms(perms)
+    s = oracle.shift(m, slot_bits)
+    r0 = max(4, 1 << s)
+    w = slot_bits // 8
+    empty = (1 << (slot_bits - 1)) - 1
+    for size in (0, 1, 9, 64, 700, 3000):
+        S = np.sort(rng.choice(m, size=size, replace=False)).astype(np.uint32)
+        for ml in (64, 1):
+            B, F, r = oracle.batmap_build(m, r0, perms, S, ml, slot_bits=slot_bits)
+            assert B.size == 3 * r * w
+            assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, B, slot_bits=slot_bits) == 0
+            assert oracle.slot_compare(B, r, B, r, slot_bits) == size - len(F)
+            slots = B.view(np.uint16 if w == 2 else np.uint32)
+            occupied = np.nonzero(slots != empty)[0]
+            if not occupied.size:
+                continue
+            v = int(occupied[0])
+            for planted in (slots[v] ^ (1 << (slot_bits - 1)),      # wrong indicator
+                            empty,                                   # one copy lost
+                            slots[v] ^ (1 << (slot_bits - 2))):      # top code bit, beyond the 8-bit layout
+                bad = slots.copy()
+                bad[v] = planted
+                assert oracle.batmap_check(m, s, r0, r, perms, invs, S, F, bad.view(np.uint8),
+                                           slot_bits=slot_bits) != 0
+            # every code bit takes part in the match: one bit flipped in all occupied slots
+            for b in range(slot_bits - 1):
+                other = slots.copy()
+                other[occupied] ^= other.dtype.type(1 << b)
+                assert oracle.slot_compare(B, r, other.view(np.uint8), r, slot_bits) == 0
+
+
+def test_slot_rule_equals_word_compare_on_bytes():
+    """The Sec. II rule slot by slot and the Sec. III-A word formula agree on 8-bit maps."""
+    m = 30_000
+    rng = np.random.default_rng(62)
+    perms = _perms(m, 7)
+    r0 = 1 << oracle.shift(m)
+    sets = [np.sort(rng.choice(m, size=k, replace=False)).astype(np.uint32) for k in (5, 400, 2000, 7000)]
+    sets[3] = np.union1d(sets[3], sets[1]).astype(np.uint32)
+    maps = [oracle.batmap_build(m, r0, perms, S, 3) for S in sets]
+    for Ba, _, ra in maps:
+        for Bb, _, rb in maps:
+            assert oracle.slot_compare(Ba, ra, Bb, rb, 8) == oracle.batmap_compare(Ba, ra, Bb, rb)
+
+
+@pytest.mark.parametrize("slot_bits", [16, 32])
+def test_wide_slot_wraparound_compare(slot_bits):
+    """Maps of different widths (the narrow ones below the 8-bit floor 2^s) compare exactly."""
+    m = 1 << 20
+    rng = np.random.default_rng(63)
+    perms = _perms(m, 9)
+    r0 = max(4, 1 << oracle.shift(m, slot_bits))
+    assert r0 < (1 << oracle.shift(m))                # below the 8-bit layout's floor
+    sets = [np.sort(rng.choice(m, size=k, replace=False)).astype(np.uint32) for k in (3, 40, 300, 2500)]
+    sets[2] = np.union1d(sets[2], sets[1][:20]).astype(np.uint32)
+    sets[3] = np.union1d(sets[3], sets[2]).astype(np.uint32)
+    maps = [oracle.batmap_build(m, r0, perms, S, 64, slot_bits=slot_bits) for S in sets]
+    assert maps[0][2] < maps[3][2]
+    for a, (Ba, Fa, ra) in enumerate(maps):
+        for b, (Bb, Fb, rb) in enumerate(maps):
+            want = np.intersect1d(np.setdiff1d(sets[a], Fa), np.setdiff1d(sets[b], Fb)).size
+            assert oracle.slot_compare(Ba, ra, Bb, rb, slot_bits) == want
+
+
+# ---- two set families (Sec. I: boolean matrix product, join-project) -----------
+
+@pytest.mark.parametrize("seed", range(8))
+def test_cross_equals_dense_product(seed):
+    rng = np.random.default_rng(700 + seed)
+    m = int(rng.integers(1, 300))
+    na, nb = int(rng.integers(1, 15)), int(rng.integers(1, 15))
+    oa, ta = random_instance(rng, m, na)
+    ob, tb = random_instance(rng, m, nb)
+    want = dense(m, oa, ta) @ dense(m, ob, tb).T
+    np.testing.assert_array_equal(oracle.cross(oa, ta, ob, tb), want.astype(np.uint32))
+    # the boolean product (join-project) is the nonzero pattern
+    np.testing.assert_array_equal(oracle.cross(oa, ta, ob, tb) > 0, want > 0)
+
+
+def test_cross_closed_forms_and_symmetry():
+    rng = np.random.default_rng(71)
+    m = 3000
+    oa, ta = random_instance(rng, m, 30, 0.0, 0.2)
+    ob, tb = random_instance(rng, m, 45, 0.0, 0.1)
+    C = oracle.cross(oa, ta, ob, tb, threads=0).astype(np.int64)
+    # row sums: sum_j |A_i cap B_j| = sum over t in A_i of the number of B sets holding t
+    deg_b = np.bincount(tb, minlength=m).astype(np.int64)
+    for i in range(30):
+        assert C[i].sum() == deg_b[ta[oa[i]:oa[i + 1]]].sum()
+    np.testing.assert_array_equal(oracle.cross(ob, tb, oa, ta), C.T)
+    # a family against itself: sizes on the diagonal, the all-pairs supports above it
+    CA = oracle.cross(oa, ta, oa, ta)
+    np.testing.assert_array_equal(np.diag(CA), np.diff(oa))
+    np.testing.assert_array_equal(CA[np.triu_indices(30, 1)], oracle.all_pairs(oa, ta))
+
+
+@pytest.mark.parametrize("slot_bits", [8, 16, 32])
+@pytest.mark.parametrize("max_loop", [64, 3, 1, 0])
+def test_batmap_cross_equals_definition(slot_bits, max_loop):
+    rng = np.random.default_rng(80 + max_loop + slot_bits)
+    m = 20_000
+    oa, ta = random_instance(rng, m, 12, 0.0, 0.08)
+    ob, tb = random_instance(rng, m, 9, 0.0, 0.3)
+    perms = _perms(m, 12)
+    r0 = max(4, 1 << oracle.shift(m, slot_bits))
+    got, nfail = oracle.batmap_cross(m, oa, ta, ob, tb, perms, r0, max_loop, slot_bits)
+    np.testing.assert_array_equal(got, oracle.cross(oa, ta, ob, tb))
+    if max_loop == 0:
+        assert nfail == ta.size + tb.size
