@@ -61,6 +61,10 @@ typedef struct {
     uint32_t min_support;   /* items with |S_i| < min_support get no BatMap (Sec. I-B pruning; default 0) */
     const uint32_t *perm[3];/* optional, host or device: three permutations of 0..m-1 (Sec. III-A pi_t);
                                all three or none; validated as permutations */
+    uint32_t slot_bits;     /* bits per BatMap slot (Sec. III-A): 8 (default) keeps the paper's 7-bit code, so
+                               every map has r_i >= 2^s with m <= 127 2^s; 16 or 32 keep 15 or 31 bits of
+                               pi_t(x) (the paper's "uncompressed case"), so sparse sets get maps near 2|S_i|
+                               slots; 0 picks the width with the least compare work for these set sizes */
     uint32_t flags;         /* reserved, must be 0 */
 } bm_build_opts;
 
@@ -78,9 +82,11 @@ typedef struct {
     uint32_t n_built;        /* items with a BatMap (|S_i| >= min_support) */
     uint32_t min_support;
     uint64_t nnz;            /* sum of |S_i| */
-    uint64_t batmap_bytes;   /* sum of 3 r_i over built BatMaps */
+    uint64_t batmap_bytes;   /* sum of 3 r_i slot_bits / 8 over built BatMaps */
     uint64_t n_failed;       /* failed insertions (Sec. III-C F_b entries) */
     uint64_t n_corrections;  /* +1 pair corrections derived from them */
+    uint32_t slot_bits;      /* bits per slot of this index's BatMaps (8, 16 or 32) */
+    uint32_t reserved;
 } bm_index_stats;
 
 /* Per-phase device times of the last build and the last query on a context,
@@ -193,6 +199,24 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
 bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair *out, uint64_t capacity,
                                     uint64_t *n_out);
 
+/* Two set families (Sec. I: sparse boolean matrix multiplication, where the
+ * product's (i, j) entry is set when A_i cap B_j is not empty, and the
+ * join-project of two tables).  a holds the sets A_0..A_{na-1}, b the sets
+ * B_0..B_{nb-1}; both indexes must come from the same context, be built
+ * with min_support 0 over the same universe [0, m), and hash alike: the
+ * same seed, or the same caller permutations (then every slot position and
+ * code means the same element in both, Sec. III-A).  BM_EINVAL otherwise.
+ * Failed insertions on either side are corrected exactly (Sec. III-C).
+ *
+ * bm_cross_pair_supports: out[i * nb + j] = |A_i cap B_j|, row-major
+ * na x nb uint32 (host or device, out_len >= na * nb, else BM_ECAPACITY). */
+bm_status bm_cross_pair_supports(bm_index *a, bm_index *b, uint32_t *out, uint64_t out_len);
+/* Pairs (i, j, |A_i cap B_j|) with support >= min_support, sorted by (i, j);
+ * min_support = 1 gives the nonzero pattern of the boolean product.  out
+ * (host or device), capacity and *n_out as bm_frequent_pairs. */
+bm_status bm_cross_pairs(bm_index *a, bm_index *b, uint32_t min_support, bm_pair *out, uint64_t capacity,
+                         uint64_t *n_out);
+
 /* Pair supports among a subset of items (k distinct ids, host or device):
  * out (host or device) gets k(k-1)/2 entries, packed upper triangle in the
  * order given.  BM_EINVAL on a repeated id or an item without a BatMap,
@@ -281,7 +305,9 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
  *   r[n_built]:            r_i in that order,
  *   bytes[batmap_bytes]:   every BatMap in the canonical byte form of
  *                          Sec. III-A (slot = indicator << 7 | pi_t(x) >> s,
- *                          empty slot 0x7F), concatenated in that order,
+ *                          empty slot 0x7F; with w-bit slots each slot is
+ *                          w/8 bytes, little-endian, indicator in bit w-1,
+ *                          empty slot 2^(w-1) - 1), concatenated in that order,
  *   failed[2*n_failed]:    (item, tid) of every failed insertion,
  *   perms[3*m]:            pi_0, pi_1, pi_2.
  * Any pointer may be NULL to skip that output. */

@@ -49,6 +49,7 @@ class bm_build_opts(ctypes.Structure):
         ("max_loop", ctypes.c_uint32),
         ("min_support", ctypes.c_uint32),
         ("perm", ctypes.c_void_p * 3),
+        ("slot_bits", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
     ]
 
@@ -63,6 +64,7 @@ class bm_index_stats(ctypes.Structure):
         ("max_loop", ctypes.c_uint32), ("n_classes", ctypes.c_uint32), ("n_built", ctypes.c_uint32),
         ("min_support", ctypes.c_uint32), ("nnz", ctypes.c_uint64), ("batmap_bytes", ctypes.c_uint64),
         ("n_failed", ctypes.c_uint64), ("n_corrections", ctypes.c_uint64),
+        ("slot_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -152,6 +154,10 @@ def load_library(path: str = LIB_PATH):
     L.bm_frequent_pairs.argtypes = [vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
     L.bm_frequent_pairs_noalloc.restype = i32
     L.bm_frequent_pairs_noalloc.argtypes = [vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
+    L.bm_cross_pair_supports.restype = i32
+    L.bm_cross_pair_supports.argtypes = [vp, vp, vp, u64]
+    L.bm_cross_pairs.restype = i32
+    L.bm_cross_pairs.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
     L.bm_subset_pair_supports.restype = i32
     L.bm_subset_pair_supports.argtypes = [vp, vp, u32, vp]
     L.bm_batch_all_pair_supports.restype = i32
@@ -294,12 +300,14 @@ class Context:
             pass
 
 
-def build_opts(seed: int = 0x5EED, max_loop: int = 64, min_support: int = 0, perms=None) -> bm_build_opts:
+def build_opts(seed: int = 0x5EED, max_loop: int = 64, min_support: int = 0, perms=None,
+               slot_bits: int = 8) -> bm_build_opts:
     o = bm_build_opts()
     load_library().bm_build_opts_init(ctypes.byref(o))
     o.seed = seed
     o.max_loop = max_loop
     o.min_support = min_support
+    o.slot_bits = slot_bits
     if perms is not None:
         for t in range(3):
             o.perm[t] = _ptr(perms[t])
@@ -434,6 +442,36 @@ class Index:
             self.close()
         except Exception:
             pass
+
+
+def cross_pair_supports(a: "Index", b: "Index", out=None):
+    """bm_cross_pair_supports: |A_i cap B_j| as an (na, nb) array (or into `out`, host or device,
+    na * nb uint32/int32 entries)."""
+    if out is None:
+        out = np.zeros((a.n, b.n), dtype=np.uint32)
+    a.ctx.check(load_library().bm_cross_pair_supports(a.handle, b.handle, _ptr(out), _numel(out)))
+    return out
+
+
+def cross_pairs(a: "Index", b: "Index", min_support: int, out=None) -> np.ndarray | int:
+    """bm_cross_pairs: (i, j, support) rows with support >= min_support, sorted by (i, j).  With a
+    device tensor `out` of 3 * capacity int32 it writes there and returns the count."""
+    L = load_library()
+    n_out = ctypes.c_uint64(0)
+    if out is not None:
+        a.ctx.check(L.bm_cross_pairs(a.handle, b.handle, min_support, _ptr(out), _numel(out) // 3,
+                                     ctypes.byref(n_out)))
+        return int(n_out.value)
+    cap = 1 << 16
+    while True:
+        buf = (bm_pair * max(cap, 1))()
+        st = L.bm_cross_pairs(a.handle, b.handle, min_support, ctypes.addressof(buf), cap, ctypes.byref(n_out))
+        if st == BM_ECAPACITY:
+            cap = int(n_out.value)
+            continue
+        a.ctx.check(st)
+        k = int(n_out.value)
+        return np.frombuffer(buf, dtype=np.uint32, count=3 * k).reshape(k, 3).copy()
 
 
 def batch_all_pair_supports(ctx: Context, indexes, outs):

@@ -24,16 +24,41 @@ struct Status {
 };
 
 
+// Output layouts of a compare (InstDesc::mode).  Row maps are a work item's
+// narrower maps, column maps its wider ones.
+enum OutMode : uint32_t {
+    OUT_PACKED = 0,     // packed upper triangle over output positions (one family)
+    OUT_RECT_ROWS = 1,  // out[pos(row) * n_out + pos(col)]: rows from the first family of a cross product
+    OUT_RECT_COLS = 2,  // out[pos(col) * n_out + pos(row)]: rows from the second family
+};
+
 // Per-instance view used by the compare kernel.
 struct InstDesc {
-    const uint4 *arena;     // BatMap groups, 2 x uint4 per group
-    const uint64_t *goff;   // group offset of each sorted index
+    const uint4 *arena;     // BatMap groups of the row maps, 2 x uint4 per group
+    const uint64_t *goff;   // group offset of each sorted index (in the arena its maps live in)
     const uint32_t *outpos; // sorted index -> output position (item id or query slot)
-    uint32_t *out;          // packed upper triangle over output positions
-    uint64_t n_out;         // number of output positions (packing width)
+    uint32_t *out;          // counts, laid out as `mode` says
+    uint64_t n_out;         // packing width (OUT_PACKED) or row length of the rectangle
     uint32_t gb;            // groups per block = 3 r_0 / 32
-    uint32_t pad;
+    uint32_t mode;          // OutMode
+    const uint4 *carena;    // BatMap groups of the column maps (== arena within one family)
 };
+
+// Descriptor of one family's compare into a packed triangle.
+inline InstDesc packed_desc(const uint32_t *arena, const uint64_t *goff, const uint32_t *outpos, uint32_t *out,
+                            uint64_t n_out, uint32_t gb)
+{
+    InstDesc d;
+    d.arena = reinterpret_cast<const uint4 *>(arena);
+    d.goff = goff;
+    d.outpos = outpos;
+    d.out = out;
+    d.n_out = n_out;
+    d.gb = gb;
+    d.mode = OUT_PACKED;
+    d.carena = d.arena;
+    return d;
+}
 
 // The three permutations pi_t of [0, m) (Sec. III-A).  Either a table of 3m
 // values given by the caller, or a keyed bijection evaluated on the fly: on
@@ -144,6 +169,8 @@ PermSpec make_perm_spec(uint32_t m, uint64_t seed);
 // ------------------------------------------------------------------ device
 // Host-side launchers.  All take a stream; none synchronises.
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// *flag |= 1 when a[i] != b[i] for some i < n.
+hipError_t launch_words_differ(const uint32_t *a, const uint32_t *b, uint64_t n, uint32_t *flag, hipStream_t s);
 hipError_t fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
 
 // Exclusive scans.  `tmp` must hold scan_tmp_bytes(n) bytes.
@@ -213,7 +240,12 @@ size_t encode_scratch_bytes(uint64_t n_groups);
 hipError_t launch_encode(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
                          uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint8_t *scratch,
                          uint32_t *arena, hipStream_t s);
-hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
+hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s, uint32_t planes = 8);
+// Codes and indicators of a batch's staged maps with 16- or 32-bit slots, as
+// `planes` bit planes per group (the 8-bit maps use launch_encode).
+hipError_t launch_encode_wide(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
+                              uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t planes,
+                              uint32_t *arena, hipStream_t s);
 // Maps of width r can be built whole in LDS (insertion, failures recorded as
 // the staged path does, encoding) when lds_build_field_bits(r, m) is not 0
 // (8: code bytes; 5: packed fields, for r up to 65536 when m <= 31 r).  One
@@ -233,6 +265,15 @@ hipError_t launch_invert_perms(const uint32_t *pi, uint32_t m, uint32_t *inv, hi
 hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off, const uint32_t *tids,
                               const uint32_t *failed_bits, const uint8_t *has_map, uint32_t n, uint32_t *pairs,
                               uint64_t cap, unsigned long long *count, hipStream_t s);
+// Corrections of a cross product (rows A, columns B, out[i * n_b + j]) for
+// the failures of family X against the items of family Y (x_is_a: X = A).
+hipError_t launch_cross_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off_y,
+                                    const uint32_t *tids_y, uint32_t n_y, const uint32_t *failed_bits_y, uint32_t *out,
+                                    uint64_t n_b, bool x_is_a, hipStream_t s);
+// Support >= sigma compaction of a row-major n_cells / n_cols rectangle.
+hipError_t launch_threshold_write_rect(const uint32_t *sup, uint64_t n_cells, uint64_t n_cols, uint32_t sigma,
+                                       const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity, bm_pair *out,
+                                       hipStream_t s);
 hipError_t launch_apply_corrections(const uint32_t *pairs, uint64_t n_corr, uint32_t *out, uint64_t n,
                                     hipStream_t s);
 hipError_t launch_apply_corrections_subset(const uint32_t *pairs, uint64_t n_corr, const uint32_t *pos_of_item,

@@ -351,6 +351,7 @@ struct bm_index {
     uint32_t m = 0, n = 0, shift = 0, r0 = 0, gb = 0, max_loop = 0, min_support = 0;
     uint64_t nnz = 0;
     uint32_t first_built = 0;  // sorted indices below this have no BatMap
+    uint32_t planes = 8;       // bits per slot = bit planes per group of 32 slots
     uint64_t total_groups = 0, n_failed = 0, n_corr = 0;
 
     DevBuf<uint64_t> off;
@@ -363,6 +364,7 @@ struct bm_index {
     DevBuf<uint64_t> goff;          // n + 1
     DevBuf<uint32_t> arena;         // total_groups * 8
     DevBuf<uint32_t> failed;        // 2 n_failed
+    DevBuf<uint32_t> failed_bits;   // bit per incidence of tids: its insertion failed
     DevBuf<uint32_t> corr;          // 2 n_corr
     DevBuf<int32_t> sorted_pos;     // item -> sorted index or -1
     std::vector<uint64_t> h_goff;   // n + 1
@@ -387,6 +389,11 @@ struct bm_index {
     DevBuf<uint32_t> sub_items, sub_flag, sub_outpos, sub_out;
     DevBuf<uint64_t> sub_goff;
     DevBuf<WorkItem> sub_work;
+    // two-family products with this index as the first family
+    DevBuf<uint64_t> x_goff;
+    DevBuf<uint32_t> x_outpos, x_out;
+    DevBuf<WorkItem> x_work;
+    DevBuf<InstDesc> x_descs;
     // dense comparator
     DevBuf<int8_t> dense_A;
     uint64_t dense_ld = 0;
@@ -466,6 +473,10 @@ int forced_variant()
 // longest first.
 bool use_persistent(const bm_context *ctx) { return ctx->persistent && forced_variant() < 0; }
 
+// Whether a compare over maps of `planes`-bit slots runs as the single
+// persistent launch (whose bodies are for 8-bit slots only).
+bool single_launch(const bm_context *ctx, uint32_t planes) { return use_persistent(ctx) && planes == 8; }
+
 
 // Largest index whose all-pairs plan is made during its build.
 constexpr uint32_t kPlanAtBuild = 4096;
@@ -483,7 +494,7 @@ bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
 // The plan as one work list in launch order: per-shape runs ((shape, count)
 // in `ranges`), or for a single persistent launch the per-XCD queues (ranges
 // hold the queue offsets, tagged -1).
-void flatten_plan(bm_context *ctx, const Plan &plan, std::vector<WorkItem> &flat,
+void flatten_plan(const Plan &plan, bool single, std::vector<WorkItem> &flat,
                   std::vector<std::pair<int, uint32_t>> &ranges)
 {
     uint64_t total = 0;
@@ -498,7 +509,7 @@ void flatten_plan(bm_context *ctx, const Plan &plan, std::vector<WorkItem> &flat
         ranges.push_back({(int)v, (uint32_t)plan.by_variant[v].size()});
         flat.insert(flat.end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
     }
-    if (use_persistent(ctx) && total) {
+    if (single && total) {
         // one single launch: ranges hold the per-XCD queue offsets, tagged -1
         uint32_t off[kXcds + 1];
         xcd_queues(flat, off);
@@ -512,8 +523,10 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
                       std::vector<std::pair<int, uint32_t>> &ranges)
 {
     bm_context *ctx = idx->ctx;
+    if (!plan.complete)
+        return fail(ctx, BM_EINVAL, "no compare tile shape for %u-bit slots in this launch mode", idx->planes);
     std::vector<WorkItem> flat;
-    flatten_plan(ctx, plan, flat, ranges);
+    flatten_plan(plan, single_launch(ctx, idx->planes), flat, ranges);
     const uint64_t total = flat.size();
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total)
@@ -530,7 +543,7 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
         return BM_OK;
     Plan plan;
     plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
-                 use_persistent(ctx) ? 1 : 0, forced_variant());
+                 single_launch(ctx, idx->planes) ? 1 : 0, forced_variant(), false, idx->planes);
     bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
     if (st != BM_OK)
         return st;
@@ -576,16 +589,21 @@ bm_status join_side(bm_context *ctx, int n)
     return BM_OK;
 }
 
+// descs (device, optional): per-instance descriptors the items name; else
+// every item uses d0.
 bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<std::pair<int, uint32_t>> &ranges,
-                      const InstDesc &d0)
+                      const InstDesc &d0, const InstDesc *descs = nullptr)
 {
     if (!ranges.empty() && ranges[0].first == -1) {
         XcdQueues q;
         for (uint32_t x = 0; x <= kXcds; x++)
             q.off[x] = ranges[x].second;
         HIPC(ctx, fill_u32(ctx->counter.p, kQueueCounterWords, 0, ctx->stream));
-        HIPC(ctx, launch_store_desc(ctx->desc1.p, d0, ctx->stream));
-        HIPC(ctx, launch_compare_multi_persistent(items, q, ctx->desc1.p, ctx->counter.p, ctx->grid, ctx->stream));
+        if (!descs) {
+            HIPC(ctx, launch_store_desc(ctx->desc1.p, d0, ctx->stream));
+            descs = ctx->desc1.p;
+        }
+        HIPC(ctx, launch_compare_multi_persistent(items, q, descs, ctx->counter.p, ctx->grid, ctx->stream));
         return BM_OK;
     }
     // the first shape on the context's stream, up to kSide more on side
@@ -598,7 +616,7 @@ bm_status run_compare(bm_context *ctx, const WorkItem *items, const std::vector<
     for (size_t i = 0; i < ranges.size(); i++) {
         const int k = (int)i - 1;
         hipStream_t s = (k >= 0 && k < n_side) ? ctx->side[k] : ctx->stream;
-        HIPC(ctx, launch_compare(items + at, ranges[i].second, nullptr, d0, ranges[i].first, s));
+        HIPC(ctx, launch_compare(items + at, ranges[i].second, descs, d0, ranges[i].first, s));
         at += ranges[i].second;
     }
     return join_side(ctx, n_side);
@@ -717,10 +735,58 @@ bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes)
     return BM_OK;
 }
 
+// s = min{s : m <= (2^(w-1) - 1) 2^s}: the code pi_t(x) >> s of every
+// element stays below the all-ones code of the empty slot (Sec. III-A).
+uint32_t slot_shift(uint32_t m, uint32_t w)
+{
+    const uint64_t top = (1ull << (w - 1)) - 1;
+    uint32_t s = 0;
+    while ((uint64_t)m > (top << s))
+        s++;
+    return s;
+}
+
+// Slot width with the least all-pairs compare work for these set sizes:
+// with widths sorted, the k-th map (from 0) is the wider one of k pairs, and
+// a pair costs 3 max(r) / 32 group pairs of w + 1 VALU ops.  Wider slots pay
+// more per slot but drop the floor r >= 2^s of the 7-bit code.
+uint32_t choose_slot_bits(const std::vector<uint64_t> &h_off, uint32_t m, uint32_t min_support)
+{
+    const size_t n = h_off.size() - 1;
+    std::vector<uint64_t> r;
+    uint32_t best = 8;
+    double best_cost = 0;
+    for (uint32_t w : {8u, 16u, 32u}) {
+        const uint64_t r0 = std::max<uint64_t>(kMinR0, 1ull << slot_shift(m, w));
+        r.clear();
+        for (size_t i = 0; i < n; i++) {
+            const uint64_t sz = h_off[i + 1] - h_off[i];
+            if (sz < min_support)
+                continue;
+            uint64_t ri = 1;
+            while (ri < 2 * sz)
+                ri <<= 1;
+            r.push_back(std::max(ri, r0));
+        }
+        std::sort(r.begin(), r.end());
+        double cost = 0;
+        for (size_t k = 0; k < r.size(); k++)
+            cost += (double)k * (double)r[k];
+        cost *= (double)(w + 1);
+        if (w == 8 || cost < best_cost) {
+            best = w;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
 {
     if (o->flags != 0)
         return fail(ctx, BM_EINVAL, "bm_build_opts.flags must be 0");
+    if (o->slot_bits != 0 && o->slot_bits != 8 && o->slot_bits != 16 && o->slot_bits != 32)
+        return fail(ctx, BM_EINVAL, "bm_build_opts.slot_bits must be 0, 8, 16 or 32");
     int given = (o->perm[0] != nullptr) + (o->perm[1] != nullptr) + (o->perm[2] != nullptr);
     if (given != 0 && given != 3)
         return fail(ctx, BM_EINVAL, "give all three permutations or none");
@@ -734,10 +800,12 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     hipStream_t s = ctx->stream;
     const uint32_t n = idx->n, m = idx->m;
 
-    // Sec. III-A parameters (reading: code 127 is the empty slot).
-    uint32_t shift = 0;
-    while ((uint64_t)m > ((uint64_t)127 << shift))
-        shift++;
+    // Sec. III-A parameters for w-bit slots (reading: the all-ones code is
+    // the empty slot, 127 for the paper's bytes); w chosen by the sizes when
+    // the caller leaves it to the library
+    const uint32_t w = o->slot_bits ? o->slot_bits : choose_slot_bits(idx->h_off, m, o->min_support);
+    idx->planes = w;
+    uint32_t shift = slot_shift(m, w);
     idx->shift = shift;
     idx->r0 = std::max<uint32_t>(kMinR0, 1u << shift);
     idx->gb = 3 * idx->r0 / kSlotsPerGroup;
@@ -848,8 +916,8 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
 
     // construction, in batches of maps whose staging fits the budget
     span_layout.end();
-    HIPC(ctx, idx->arena.alloc(std::max<uint64_t>(idx->total_groups, 1) * kWordsPerGroup));
-    DevBuf<uint32_t> failed_bits;
+    HIPC(ctx, idx->arena.alloc(std::max<uint64_t>(idx->total_groups, 1) * idx->planes));
+    DevBuf<uint32_t> &failed_bits = idx->failed_bits;
     uint64_t fb_words = (idx->nnz + 31) / 32;
     HIPC(ctx, failed_bits.alloc(fb_words + 1));
     HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
@@ -872,7 +940,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // in LDS, one launch per width; the rest go through staging in batches.
     // BM_LDS_BUILD=0 turns the LDS path off.
     const char *lds_env = getenv("BM_LDS_BUILD");
-    const bool lds_on = !(lds_env && atoi(lds_env) == 0);
+    const bool lds_on = !(lds_env && atoi(lds_env) == 0) && idx->planes == 8;
     auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / 3); };
     uint32_t p_lds = first_built;
     while (lds_on && p_lds < n && lds_build_field_bits(width_of(p_lds), m) != 0)
@@ -962,8 +1030,12 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
                                          counters.p + 2, s));
             }
             Span span_encode(ctx, PH_ENCODE);
-            HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift, idx->r0,
-                                    codes.p, idx->arena.p, s));
+            if (idx->planes == 8)
+                HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                        idx->r0, codes.p, idx->arena.p, s));
+            else
+                HIPC(ctx, launch_encode_wide(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                             idx->r0, idx->planes, idx->arena.p, s));
         }
         st = join_side(ctx, n_side);
         if (st != BM_OK)
@@ -1054,7 +1126,8 @@ InstDesc whole_desc(const bm_index *idx, uint32_t *out)
     d.out = out;
     d.n_out = idx->n;
     d.gb = idx->gb;
-    d.pad = 0;
+    d.mode = OUT_PACKED;
+    d.carena = d.arena;
     return d;
 }
 
@@ -1148,7 +1221,8 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
     d.out = out.p;
     d.n_out = n_pos;
     d.gb = gb;
-    d.pad = 0;
+    d.mode = OUT_PACKED;
+    d.carena = d.arena;
     hipEvent_t e0, e1;
     HIPC(ctx, hipEventCreate(&e0));
     HIPC(ctx, hipEventCreate(&e1));
@@ -1159,6 +1233,12 @@ bm_status autotune(bm_context *ctx, uint32_t reps)
         const uint32_t ncol = ncols[b];
         Cls A{32768, 0, nrow}, B{32768 * ratios[b], (uint32_t)col_first[b], ncol};
         for (int v = 0; v < nv; v++) {
+            // the synthetic maps have 8-bit slots: shapes of wider slots keep
+            // their catalogue speeds (they are weighed only against each other)
+            if (variant_info(v).planes != 8) {
+                speeds[(size_t)v * kWrapBuckets + b] = variant_info(v).speed;
+                continue;
+            }
             // variant v on this one class pair, cut and ordered by the planner
             // exactly as in a real plan
             Plan plan;
@@ -1201,6 +1281,7 @@ void bm_build_opts_init(bm_build_opts *o)
     o->seed = 0x5eed;
     o->max_loop = 64;
     o->min_support = 0;
+    o->slot_bits = 8;
 }
 
 bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
@@ -1644,9 +1725,10 @@ bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
     out->n_built = idx->n - idx->first_built;
     out->min_support = idx->min_support;
     out->nnz = idx->nnz;
-    out->batmap_bytes = idx->total_groups * kSlotsPerGroup;
+    out->batmap_bytes = idx->total_groups * kSlotsPerGroup * idx->planes / 8;
     out->n_failed = idx->n_failed;
     out->n_corrections = idx->n_corr;
+    out->slot_bits = idx->planes;
     return BM_OK;
 }
 
@@ -1802,8 +1884,10 @@ bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair
     if (!own) {
         Plan plan;
         plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
-                     use_persistent(ctx) ? 1 : 0, forced_variant());
-        flatten_plan(ctx, plan, flat, ranges);
+                     single_launch(ctx, idx->planes) ? 1 : 0, forced_variant(), false, idx->planes);
+        if (!plan.complete)
+            return fail(ctx, BM_EINVAL, "no compare tile shape for %u-bit slots in this launch mode", idx->planes);
+        flatten_plan(plan, single_launch(ctx, idx->planes), flat, ranges);
         slot_pairs = plan.slot_pairs;
     }
     // scratch: counts | per-block counts | their offsets | scan workspace | work list
@@ -1935,9 +2019,11 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.out = dst;
     d.n_out = k;
     d.gb = idx->gb;
-    d.pad = 0;
+    d.mode = OUT_PACKED;
+    d.carena = d.arena;
     Plan plan;
-    plan_classes(cls, 0, target_items(ctx), plan, nullptr, use_persistent(ctx) ? 1 : 0, forced_variant());
+    plan_classes(cls, 0, target_items(ctx), plan, nullptr, single_launch(ctx, idx->planes) ? 1 : 0,
+                 forced_variant(), false, idx->planes);
     std::vector<std::pair<int, uint32_t>> ranges;
     st = upload_plan(idx, plan, idx->sub_work, ranges);
     if (st != BM_OK)
@@ -1992,6 +2078,9 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
             return fail(ctx, BM_EINVAL, "index %u is null or belongs to another context", q);
         if (idx->first_built != 0)
             return fail(ctx, BM_EINVAL, "index %u was built with min_support > 0", q);
+        if (idx->planes != 8)
+            return fail(ctx, BM_EINVAL, "index %u has %u-bit slots; the single launch compares 8-bit slots", q,
+                        idx->planes);
         if (n_pairs(idx->n) && !outs[q])
             return fail(ctx, BM_EINVAL, "outs[%u] is null", q);
         if (n_pairs(idx->n) && ptr_kind(outs[q]) != PTR_DEVICE)
@@ -2225,6 +2314,188 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
     return BM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Two indexes hash alike when they share the universe, the shift, r_0 and
+// the permutations pi_t (then slot positions and codes agree across them).
+bm_status check_cross(bm_index *a, bm_index *b)
+{
+    bm_context *ctx = a->ctx;
+    if (b->ctx != ctx)
+        return fail(ctx, BM_EINVAL, "the two indexes belong to different contexts");
+    if (a->first_built != 0 || b->first_built != 0)
+        return fail(ctx, BM_EINVAL, "an index built with min_support > 0 has no BatMap for some items");
+    if (a->planes != b->planes)
+        return fail(ctx, BM_EINVAL, "the indexes have %u- and %u-bit slots", a->planes, b->planes);
+    if (a->m != b->m || a->shift != b->shift || a->r0 != b->r0)
+        return fail(ctx, BM_EINVAL, "the indexes differ in m, s or r_0 (%u/%u, %u/%u, %u/%u)", a->m, b->m, a->shift,
+                    b->shift, a->r0, b->r0);
+    const PermSpec &P = a->perm, &Q = b->perm;
+    if ((P.table == nullptr) != (Q.table == nullptr))
+        return fail(ctx, BM_EINVAL, "one index uses caller permutations, the other generated ones");
+    if (!P.table) {
+        bool same = P.m == Q.m && P.mask == Q.mask && P.h1 == Q.h1 && P.h2 == Q.h2;
+        for (int t = 0; t < 3; t++)
+            same = same && P.mul1[t] == Q.mul1[t] && P.add1[t] == Q.add1[t] && P.mul2[t] == Q.mul2[t] &&
+                   P.mul3[t] == Q.mul3[t] && P.add3[t] == Q.add3[t];
+        if (!same)
+            return fail(ctx, BM_EINVAL, "the indexes were built with different seeds");
+        return BM_OK;
+    }
+    if (P.table == Q.table)
+        return BM_OK;
+    DevBuf<uint32_t> flag;
+    HIPC(ctx, flag.alloc(1));
+    HIPC(ctx, fill_u32(flag.p, 1, 0, ctx->stream));
+    HIPC(ctx, launch_words_differ(P.table, Q.table, 3ull * a->m, flag.p, ctx->stream));
+    uint32_t h = 0;
+    BMC(read_back(ctx, &h, flag.p, 4));
+    if (h)
+        return fail(ctx, BM_EINVAL, "the indexes were built with different permutations");
+    return BM_OK;
+}
+
+// Counts |A_i cap B_j| into out (device, na * nb, row-major), zeroed here.
+bm_status cross_counts(bm_index *a, bm_index *b, uint32_t *out)
+{
+    bm_context *ctx = a->ctx;
+    hipStream_t s = ctx->stream;
+    const uint32_t na = a->n, nb = b->n;
+    const uint64_t cells = (uint64_t)na * nb;
+    {
+        Span sp(ctx, PH_FILL);
+        HIPC(ctx, fill_u32(out, cells, 0, s));
+    }
+    // instance 0 indexes [A maps, B maps], instance 1 [B maps, A maps]
+    const uint64_t nt = (uint64_t)na + nb;
+    HIPC(ctx, a->x_goff.ensure(2 * nt));
+    HIPC(ctx, a->x_outpos.ensure(2 * nt));
+    uint64_t *g0 = a->x_goff.p, *g1 = a->x_goff.p + nt;
+    uint32_t *o0 = a->x_outpos.p, *o1 = a->x_outpos.p + nt;
+    HIPC(ctx, hipMemcpyAsync(g0, a->goff.p, 8ull * na, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(g0 + na, b->goff.p, 8ull * nb, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(g1, b->goff.p, 8ull * nb, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(g1 + nb, a->goff.p, 8ull * na, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(o0, a->sorted_items.p, 4ull * na, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(o0 + na, b->sorted_items.p, 4ull * nb, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(o1, b->sorted_items.p, 4ull * nb, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, hipMemcpyAsync(o1 + nb, a->sorted_items.p, 4ull * na, hipMemcpyDeviceToDevice, s));
+    InstDesc d[2];
+    d[0] = packed_desc(a->arena.p, g0, o0, out, nb, a->gb);
+    d[0].mode = OUT_RECT_ROWS;
+    d[0].carena = reinterpret_cast<const uint4 *>(b->arena.p);
+    d[1] = packed_desc(b->arena.p, g1, o1, out, nb, b->gb);
+    d[1].mode = OUT_RECT_COLS;
+    d[1].carena = reinterpret_cast<const uint4 *>(a->arena.p);
+    HIPC(ctx, a->x_descs.ensure(2));
+    BMC(upload(ctx, a->x_descs.p, d, sizeof d));
+    Plan plan;
+    plan_cross(a->classes, b->classes, na, nb, target_items(ctx), plan, nullptr,
+               single_launch(ctx, a->planes) ? 1 : 0, forced_variant(), a->planes);
+    std::vector<std::pair<int, uint32_t>> ranges;
+    BMC(upload_plan(a, plan, a->x_work, ranges));
+    ctx->slot_pairs = plan.slot_pairs;
+    {
+        Span sp(ctx, PH_COMPARE);
+        BMC(run_compare(ctx, a->x_work.p, ranges, d[0], a->x_descs.p));
+    }
+    Span sp(ctx, PH_APPLY);
+    HIPC(ctx, launch_cross_corrections(a->failed.p, (uint32_t)a->n_failed, b->off.p, b->tids.p, nb, nullptr, out, nb,
+                                       true, s));
+    HIPC(ctx, launch_cross_corrections(b->failed.p, (uint32_t)b->n_failed, a->off.p, a->tids.p, na,
+                                       a->failed_bits.p, out, nb, false, s));
+    return BM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bm_status bm_cross_pair_supports(bm_index *a, bm_index *b, uint32_t *out, uint64_t out_len)
+{
+    if (!a || !b)
+        return BM_EINVAL;
+    bm_context *ctx = a->ctx;
+    ctx->err.clear();
+    AllocScope scope(ctx->as);
+    begin_query(ctx);
+    BMC(check_cross(a, b));
+    const uint64_t cells = (uint64_t)a->n * b->n;
+    if (!out)
+        return fail(ctx, BM_EINVAL, "out is null");
+    if (out_len < cells)
+        return fail(ctx, BM_ECAPACITY, "out holds %llu entries, %llu needed", (unsigned long long)out_len,
+                    (unsigned long long)cells);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const bool host = ptr_kind(out) == PTR_HOST;
+    uint32_t *dst = out;
+    if (host) {
+        HIPC(ctx, a->x_out.ensure(cells));
+        dst = a->x_out.p;
+    }
+    BMC(cross_counts(a, b, dst));
+    if (host) {
+        BMC(download(ctx, out, dst, cells * 4));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return BM_OK;
+}
+
+bm_status bm_cross_pairs(bm_index *a, bm_index *b, uint32_t min_support, bm_pair *out, uint64_t capacity,
+                         uint64_t *n_out)
+{
+    if (!a || !b)
+        return BM_EINVAL;
+    bm_context *ctx = a->ctx;
+    ctx->err.clear();
+    AllocScope scope(ctx->as);
+    begin_query(ctx);
+    if (!n_out)
+        return fail(ctx, BM_EINVAL, "n_out is null");
+    *n_out = 0;
+    BMC(check_cross(a, b));
+    const uint64_t cells = (uint64_t)a->n * b->n;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    HIPC(ctx, a->x_out.ensure(cells));
+    BMC(cross_counts(a, b, a->x_out.p));
+    const uint32_t nbk = threshold_blocks(cells);
+    DevBuf<uint32_t> counts;
+    DevBuf<uint64_t> offs;
+    DevBuf<char> tmp;
+    HIPC(ctx, counts.alloc((uint64_t)nbk + 1));
+    HIPC(ctx, offs.alloc((uint64_t)nbk + 1));
+    HIPC(ctx, tmp.alloc(scan_tmp_bytes((uint64_t)nbk + 1)));
+    Span span_thr(ctx, PH_THRESHOLD);
+    HIPC(ctx, fill_u32(counts.p + nbk, 1, 0, s));
+    HIPC(ctx, launch_threshold_count(a->x_out.p, cells, min_support, counts.p, nbk, s));
+    HIPC(ctx, exclusive_scan_u32_to_u64(counts.p, offs.p, (uint64_t)nbk + 1, tmp.p, s));
+    const bool host = out && ptr_kind(out) == PTR_HOST;
+    if (out && !host)
+        HIPC(ctx, launch_threshold_write_rect(a->x_out.p, cells, b->n, min_support, offs.p, nbk, capacity, out, s));
+    span_thr.end();
+    uint64_t total = 0;
+    BMC(read_back(ctx, &total, offs.p + nbk, 8));
+    *n_out = total;
+    if (total == 0)
+        return BM_OK;
+    if (!out)
+        return fail(ctx, BM_EINVAL, "out is null");
+    if (total > capacity)
+        return fail(ctx, BM_ECAPACITY, "%llu pairs, capacity %llu", (unsigned long long)total,
+                    (unsigned long long)capacity);
+    if (host) {
+        DevBuf<bm_pair> dev;
+        HIPC(ctx, dev.alloc(total));
+        HIPC(ctx, launch_threshold_write_rect(a->x_out.p, cells, b->n, min_support, offs.p, nbk, total, dev.p, s));
+        BMC(download(ctx, out, dev.p, total * sizeof(bm_pair)));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+    return BM_OK;
+}
+
 bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t *r, uint8_t *bytes, uint32_t *failed,
                           uint32_t *perms)
 {
@@ -2240,9 +2511,10 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
         memcpy(r, idx->h_r_sorted.data() + idx->first_built, (size_t)nb * 4);
     if (bytes && idx->total_groups) {
         DevBuf<uint8_t> tmp;
-        HIPC(ctx, tmp.alloc(idx->total_groups * kSlotsPerGroup));
-        HIPC(ctx, launch_decode(idx->arena.p, idx->total_groups, tmp.p, ctx->stream));
-        bm_status st = read_back(ctx, bytes, tmp.p, idx->total_groups * kSlotsPerGroup);
+        const uint64_t nbytes = idx->total_groups * kSlotsPerGroup * idx->planes / 8;
+        HIPC(ctx, tmp.alloc(nbytes));
+        HIPC(ctx, launch_decode(idx->arena.p, idx->total_groups, tmp.p, ctx->stream, idx->planes));
+        bm_status st = download(ctx, bytes, tmp.p, nbytes);
         if (st != BM_OK)
             return st;
     }
@@ -2434,7 +2706,8 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         d.out = reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res);
         d.n_out = k;
         d.gb = ix->gb;
-        d.pad = 0;
+        d.mode = OUT_PACKED;
+        d.carena = d.arena;
     }
     // the launch's items shared among its queries in proportion to their work
     std::vector<double> q_work(nq);
@@ -2630,6 +2903,9 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
     if (o.streams == 0 || o.streams > 16 || o.max_batch == 0 || o.max_batch > 65535 || o.memory_budget < 4096 ||
         o.flags != 0)
         return fail(ctx, BM_EINVAL, "bad server options");
+    if (idx->planes != 8)
+        return fail(ctx, BM_EINVAL, "the server's launches compare 8-bit slots; this index has %u-bit slots",
+                    idx->planes);
     HIPC(ctx, hipSetDevice(idx->device));
     std::unique_ptr<bm_server> srv(new (std::nothrow) bm_server());
     if (!srv)

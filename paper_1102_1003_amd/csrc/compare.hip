@@ -71,6 +71,23 @@ __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
     return i * n - i * (i + 1) / 2 + (j - i - 1);
 }
 
+// Adds the count v of row map p against column map q (sorted indices) into
+// the output, in the descriptor's layout.
+__device__ inline void emit(const InstDesc &d, uint32_t p, uint32_t q, uint32_t v)
+{
+    const uint32_t a = d.outpos[p], b = d.outpos[q];
+    uint64_t k;
+    if (d.mode == OUT_PACKED) {
+        const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        k = packed_index(d.n_out, lo, hi);
+    } else if (d.mode == OUT_RECT_ROWS) {
+        k = (uint64_t)a * d.n_out + b;
+    } else {
+        k = (uint64_t)b * d.n_out + a;
+    }
+    atomicAdd(&d.out[k], v);
+}
+
 template <int MI, int MJ, int TX>
 __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, TX> &sm)
 {
@@ -104,7 +121,7 @@ __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, 
         }
         for (int u = tid; u < S::BJ * KG * 2; u += 256) {
             int kap = u / (KG * 2), rem = u % (KG * 2);
-            sm.col[rem / 2][kap][rem % 2] = d.arena[(sm.goff_c[kap] + c + rem / 2) * 2 + (rem % 2)];
+            sm.col[rem / 2][kap][rem % 2] = d.carena[(sm.goff_c[kap] + c + rem / 2) * 2 + (rem % 2)];
         }
         __syncthreads();
 #pragma unroll
@@ -143,9 +160,7 @@ __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, 
                 uint32_t p = w.row0 + rho, q = w.col0 + kap;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                uint32_t a = d.outpos[p], b = d.outpos[q];
-                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[i][j]);
+                emit(d, p, q, acc[i][j]);
             }
         }
     }
@@ -205,7 +220,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
@@ -308,9 +323,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
                 uint32_t p = w.row0 + rho, q = w.col0 + j;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                uint32_t a = d.outpos[p], b = d.outpos[q];
-                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[r][j]);
+                emit(d, p, q, acc[r][j]);
             }
         }
     }
@@ -329,7 +342,7 @@ __device__ void process_rows_pipe(const WorkItem &w, const InstDesc &d)
     constexpr int NK = MJ / CH;
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
@@ -417,9 +430,7 @@ __device__ void process_rows_pipe(const WorkItem &w, const InstDesc &d)
                 uint32_t p = w.row0 + rho, q = w.col0 + j;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                uint32_t a = d.outpos[p], b = d.outpos[q];
-                uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[r][j]);
+                emit(d, p, q, acc[r][j]);
             }
         }
     }
@@ -447,6 +458,7 @@ __device__ void process_gp(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)d.carena);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint32_t rb[MI], cb[MJ];
 #pragma unroll
@@ -481,15 +493,15 @@ __device__ void process_gp(const WorkItem &w, const InstDesc &d)
             // one column group in flight ahead of the one compared (the
             // barriers stop the compiler from hoisting all MJ loads, which
             // would cost registers the single-launch kernel cannot spare)
-            u32x4 na = arena[2 * (uint64_t)(cb[0] + c)], nb = arena[2 * (uint64_t)(cb[0] + c) + 1];
+            u32x4 na = carena[2 * (uint64_t)(cb[0] + c)], nb = carena[2 * (uint64_t)(cb[0] + c) + 1];
 #pragma unroll
             for (int j = 0; j < MJ; j++) {
                 uint32_t y[8];
                 unpack4(na, nb, y);
                 if (j + 1 < MJ) {
                     const uint64_t g2 = 2 * (uint64_t)(cb[j + 1] + c);
-                    na = arena[g2];
-                    nb = arena[g2 + 1];
+                    na = carena[g2];
+                    nb = carena[g2 + 1];
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -518,9 +530,7 @@ __device__ void process_gp(const WorkItem &w, const InstDesc &d)
                     uint32_t p = w.row0 + i, q = w.col0 + j;
                     if ((w.flags & 1u) && p >= q)
                         continue;
-                    uint32_t a = d.outpos[p], b = d.outpos[q];
-                    uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                    atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], acc[i][j]);
+                    emit(d, p, q, acc[i][j]);
                 }
             }
     }
@@ -543,6 +553,210 @@ __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__rest
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
     process_rows<R, MJ, H>(w, d);
+}
+
+
+// ------------------------------------------------- wider slots (W planes)
+// Maps with W-bit slots (the uncompressed case of Sec. III-A: W - 1 code
+// bits, indicator in the top bit) are stored as W planes per group of 32
+// slots; a group pair costs W - 1 bitwise ops, one and-not and one popcount.
+template <int W>
+__device__ inline uint32_t group_hits_w(const uint32_t (&x)[W], const uint32_t (&y)[W], uint32_t acc)
+{
+    uint32_t mm = x[0] ^ y[0];
+#pragma unroll
+    for (int b = 1; b < W - 1; b++)
+        mm = __builtin_amdgcn_bitop3_b32(x[b], y[b], mm, kXorOr);
+    uint32_t hit = __builtin_amdgcn_bitop3_b32(mm, x[W - 1], y[W - 1], kNotAndOr);
+    acc += __builtin_popcount(hit);
+    asm("" : "+v"(acc));
+    return acc;
+}
+
+template <int W>
+__device__ inline void load_group(GlobalU4 *arena, uint64_t g, uint32_t (&v)[W])
+{
+#pragma unroll
+    for (int k = 0; k < W / 4; k++) {
+        const u32x4 a = arena[g * (W / 4) + k];
+        v[4 * k] = a.x;
+        v[4 * k + 1] = a.y;
+        v[4 * k + 2] = a.z;
+        v[4 * k + 3] = a.w;
+    }
+}
+
+// Row-resident tile over W-plane maps: R rows per lane (64 R rows), MJ
+// column maps whose groups arrive as scalar loads, one row group per step,
+// the next one prefetched (the loop order of process_rows).
+template <int W, int R, int MJ>
+__device__ void process_rows_w(const WorkItem &w, const InstDesc &d)
+{
+    const int lane = threadIdx.x & 63;
+    GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
+    GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
+    ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
+    uint64_t rbase[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+        uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
+        rbase[r] = goff[w.row0 + rr];
+    }
+    uint32_t cbase[MJ];
+#pragma unroll
+    for (int j = 0; j < MJ; j++) {
+        uint32_t cc = j < w.ncol ? j : w.ncol - 1;
+        cbase[j] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.col0 + cc)]);
+    }
+    uint32_t acc[R][MJ];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[r][j] = 0;
+    const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
+    const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
+    const uint32_t h0 = __builtin_amdgcn_readfirstlane(w.c0), h1 = __builtin_amdgcn_readfirstlane(w.c1);
+    uint32_t nx[R][W];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        load_group<W>(arena, rbase[r] + h0, nx[r]);
+    for (uint32_t h = h0; h < h1; h++) {
+        uint32_t x[R][W];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int b = 0; b < W; b++)
+                x[r][b] = nx[r][b];
+        if (h + 1 < h1) {
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                load_group<W>(arena, rbase[r] + h + 1, nx[r]);
+        }
+        for (uint32_t u = 0; u < wraps; u++) {
+            const uint32_t c = h + u * row_groups;
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                const uint64_t g = (uint64_t)(cbase[j] + c) * (W / 4);
+                uint32_t y[W];
+#pragma unroll
+                for (int k = 0; k < W / 4; k++) {
+                    const u32x4 a = carena[g + k];
+                    y[4 * k] = a.x;
+                    y[4 * k + 1] = a.y;
+                    y[4 * k + 2] = a.z;
+                    y[4 * k + 3] = a.w;
+                }
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r][j] = group_hits_w<W>(x[r], y, acc[r][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int rho = lane + 64 * r;
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            if (rho < w.nrow && j < w.ncol && acc[r][j] != 0) {
+                uint32_t p = w.row0 + rho, q = w.col0 + j;
+                if ((w.flags & 1u) && p >= q)
+                    continue;
+                emit(d, p, q, acc[r][j]);
+            }
+        }
+    }
+}
+
+// Group-parallel small tile over W-plane maps (lanes over row-group
+// positions, as process_gp).
+template <int W, int MI, int MJ>
+__device__ void process_gp_w(const WorkItem &w, const InstDesc &d)
+{
+    const int lane = threadIdx.x & 63;
+    GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
+    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)d.carena);
+    ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
+    uint32_t rb[MI], cb[MJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++) {
+        uint32_t ii = i < w.nrow ? i : w.nrow - 1;
+        rb[i] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.row0 + ii)]);
+    }
+#pragma unroll
+    for (int j = 0; j < MJ; j++) {
+        uint32_t jj = j < w.ncol ? j : w.ncol - 1;
+        cb[j] = __builtin_amdgcn_readfirstlane((uint32_t)cgoff[__builtin_amdgcn_readfirstlane(w.col0 + jj)]);
+    }
+    uint32_t acc[MI][MJ];
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+            acc[i][j] = 0;
+    const uint32_t wraps = __builtin_amdgcn_readfirstlane(w.col_groups / w.row_groups);
+    const uint32_t row_groups = __builtin_amdgcn_readfirstlane(w.row_groups);
+    const uint32_t h1 = __builtin_amdgcn_readfirstlane(w.c1);
+    for (uint32_t h = __builtin_amdgcn_readfirstlane(w.c0) + lane; h < h1; h += 64) {
+        uint32_t x[MI][W];
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+            load_group<W>(arena, (uint64_t)rb[i] + h, x[i]);
+        for (uint32_t u = 0; u < wraps; u++) {
+            const uint32_t c = h + u * row_groups;
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                uint32_t y[W];
+                load_group<W>(carena, (uint64_t)cb[j] + c, y);
+#pragma unroll
+                for (int i = 0; i < MI; i++)
+                    acc[i][j] = group_hits_w<W>(x[i], y, acc[i][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MJ; j++) {
+            uint32_t v = acc[i][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                v += __shfl_xor(v, o, 64);
+            acc[i][j] = v;
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int j = 0; j < MJ; j++) {
+                if (i < w.nrow && j < w.ncol && acc[i][j] != 0) {
+                    uint32_t p = w.row0 + i, q = w.col0 + j;
+                    if ((w.flags & 1u) && p >= q)
+                        continue;
+                    emit(d, p, q, acc[i][j]);
+                }
+            }
+    }
+}
+
+template <int W, int R, int MJ>
+__global__ __launch_bounds__(64) void compare_rows_w_kernel(const WorkItem *__restrict__ items,
+                                                            const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_rows_w<W, R, MJ>(w, d);
+}
+
+template <int W, int MI, int MJ>
+__global__ __launch_bounds__(64) void compare_gp_w_kernel(const WorkItem *__restrict__ items,
+                                                          const InstDesc *__restrict__ descs, InstDesc d0)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDesc d = descs ? descs[w.inst] : d0;
+    process_gp_w<W, MI, MJ>(w, d);
 }
 
 
@@ -602,6 +816,8 @@ struct Kernels {
 #define BM_ROWS(R, MJ, H) Kernels{64, compare_rows_kernel<R, MJ, H>}
 #define BM_PIPE(R, MJ, CH) Kernels{64, compare_pipe_kernel<R, MJ, CH>}
 #define BM_GP(MI, MJ) Kernels{64, compare_gp_kernel<MI, MJ>}
+#define BM_ROWS_W(W, R, MJ) Kernels{64, compare_rows_w_kernel<W, R, MJ>}
+#define BM_GP_W(W, MI, MJ) Kernels{64, compare_gp_w_kernel<W, MI, MJ>}
 
 const Kernels kKernels[] = {
     BM_STAGED(4, 4, 16), BM_STAGED(4, 4, 32), BM_STAGED(4, 4, 64), BM_STAGED(2, 4, 128),
@@ -611,6 +827,7 @@ const Kernels kKernels[] = {
     BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),
     BM_GP(4, 4),         BM_GP(2, 8),
     BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),    BM_ROWS(3, 12, 2),
+    BM_ROWS_W(16, 2, 8), BM_GP_W(16, 4, 4),   BM_ROWS_W(32, 1, 8), BM_GP_W(32, 2, 4),
 };
 static_assert(sizeof(kKernels) / sizeof(kKernels[0]) == kVariantCount, "one kernel entry per tile shape");
 

@@ -873,6 +873,77 @@ __global__ void invert_perms_kernel(const uint32_t *pi, uint32_t m, uint32_t *in
     }
 }
 
+// Wider slots (W = 16 or 32 bits, the uncompressed case of Sec. III-A):
+// one wavefront per two groups of a map (64 canonical slots; every map
+// holds a multiple of 12 groups, so the pair never straddles two maps).
+// Lane l takes slot 32 g + (l mod 32) of group g = l / 32: its staged
+// element x (or empty), code pi_t(x) >> s, and the indicator set when x's
+// other copy sits in the cyclically preceding table (reading C1, read
+// straight from the staging).  Plane b of each group is the ballot of bit b.
+template <int W>
+__global__ void __launch_bounds__(kBlock) encode_wide_kernel(const uint32_t *__restrict__ stage,
+                                                             const uint32_t *__restrict__ r_sorted,
+                                                             const uint64_t *__restrict__ goff, uint32_t p0,
+                                                             uint32_t np, uint64_t g0, uint64_t n_groups, PermSpec P,
+                                                             uint32_t shift, uint32_t r0, uint32_t *__restrict__ arena)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t units = n_groups / 2;
+    const uint64_t wstride = (uint64_t)gridDim.x * (blockDim.x / 64u);
+    const uint64_t wave = uniform_u64((uint64_t)blockIdx.x * (blockDim.x / 64u) + threadIdx.x / 64u);
+    for (uint64_t u = wave; u < units; u += wstride) {
+        const uint64_t gl = g0 + 2 * u;  // the pair's first group (arena index)
+        const uint32_t j = __builtin_amdgcn_readfirstlane(find_segment(goff + p0, np, gl));
+        const uint32_t p = p0 + j;
+        const uint32_t r = r_sorted[p];
+        const uint64_t mg0 = goff[p];
+        const uint64_t v = (gl - mg0) * kSlotsPerGroup + lane;  // canonical slot in the map (Fig. 4)
+        const uint64_t blk = v / (3ull * r0);
+        const uint32_t within = (uint32_t)(v - blk * 3ull * r0);
+        const uint32_t t = within / r0;
+        const uint32_t q = (uint32_t)(blk * r0 + within % r0);
+        const uint32_t *T = stage + (mg0 - g0) * kSlotsPerGroup;
+        const uint32_t x = T[(uint64_t)t * r + q];
+        uint32_t slot = (uint32_t)((1ull << (W - 1)) - 1);  // empty: every code bit set, indicator 0
+        if (x != kEmpty) {
+            const uint32_t code = perm_eval_lane(P, (int)t, x) >> shift;
+            const int prev = t == 0 ? 2 : (int)t - 1;
+            const uint32_t qp = perm_eval_lane(P, prev, x) & (r - 1);
+            const uint32_t bit = T[(uint64_t)prev * r + qp] == x ? 1u : 0u;
+            slot = (bit << (W - 1)) | code;
+        }
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < W; b++) {
+            const uint64_t bal = __ballot((slot >> b) & 1u);
+            const uint32_t half = lane < 32 ? (uint32_t)bal : (uint32_t)(bal >> 32);
+            if ((lane & 31u) == (uint32_t)b)
+                word = half;
+        }
+        if ((lane & 31u) < (uint32_t)W)
+            arena[(gl + (lane >> 5)) * W + (lane & 31u)] = word;
+    }
+}
+
+// Canonical form of W-bit slots: W / 8 bytes per slot, little-endian.
+template <int W>
+__global__ void decode_wide_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_groups * kSlotsPerGroup;
+         sl += stride) {
+        uint64_t g = sl / kSlotsPerGroup;
+        uint32_t k = (uint32_t)(sl % kSlotsPerGroup);
+        uint32_t value = 0;
+#pragma unroll
+        for (int b = 0; b < W; b++)
+            value |= ((arena[g * W + b] >> k) & 1u) << b;
+#pragma unroll
+        for (int c = 0; c < W / 8; c++)
+            bytes[sl * (W / 8) + c] = (uint8_t)(value >> (8 * c));
+    }
+}
+
 __global__ void decode_kernel(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes)
 {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1125,11 +1196,34 @@ hipError_t launch_invert_perms(const uint32_t *pi, uint32_t m, uint32_t *inv, hi
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s)
+hipError_t launch_decode(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s, uint32_t planes)
 {
     if (n_groups == 0)
         return hipSuccess;
-    decode_kernel<<<blocks_for(n_groups * kSlotsPerGroup, 65536), kBlock, 0, s>>>(arena, n_groups, bytes);
+    const uint32_t blocks = blocks_for(n_groups * kSlotsPerGroup, 65536);
+    if (planes == 16)
+        decode_wide_kernel<16><<<blocks, kBlock, 0, s>>>(arena, n_groups, bytes);
+    else if (planes == 32)
+        decode_wide_kernel<32><<<blocks, kBlock, 0, s>>>(arena, n_groups, bytes);
+    else
+        decode_kernel<<<blocks, kBlock, 0, s>>>(arena, n_groups, bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_wide(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
+                              uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t planes,
+                              uint32_t *arena, hipStream_t s)
+{
+    const uint64_t units = n_groups / 2;
+    if (units == 0)
+        return hipSuccess;
+    const uint32_t blocks = blocks_for(units * 64, 65536);
+    if (planes == 16)
+        encode_wide_kernel<16><<<blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_groups, P,
+                                                         shift, r0, arena);
+    else
+        encode_wide_kernel<32><<<blocks, kBlock, 0, s>>>(stage, r_sorted, goff, b.p0, b.p1 - b.p0, b.g0, n_groups, P,
+                                                         shift, r0, arena);
     return hipGetLastError();
 }
 

@@ -60,6 +60,35 @@ __global__ void corrections_kernel(const uint32_t *failed, uint32_t n_failed, co
     }
 }
 
+// Two families A (output rows) and B (output columns), out[i * n_b + j]:
+// the pair (i, j) lost every shared element that failed in A_i or in B_j.
+// Thread per (failure f of family X, item c of the other family Y): when
+// the failed tid is in Y_c the pair gains one, unless the tid failed in Y_c
+// too and X is B (then A's pass adds it).  x_is_a: X is A (the failure's
+// item is the row).  failed_bits_y: Y's failed incidences (bit per tid of
+// its tidlists), consulted only when X is B.
+__global__ void cross_corrections_kernel(const uint32_t *failed, uint32_t n_failed, const uint64_t *off_y,
+                                         const uint32_t *tids_y, uint32_t n_y, const uint32_t *failed_bits_y,
+                                         uint32_t *out, uint64_t n_b, int x_is_a)
+{
+    const uint64_t total = (uint64_t)n_failed * n_y;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const uint32_t f = (uint32_t)(e / n_y), c = (uint32_t)(e % n_y);
+        const uint32_t item = failed[2 * (uint64_t)f], t = failed[2 * (uint64_t)f + 1];
+        const int64_t k = find_tid(tids_y + off_y[c], off_y[c + 1] - off_y[c], t);
+        if (k < 0)
+            continue;
+        if (!x_is_a) {
+            const uint64_t kk = off_y[c] + (uint64_t)k;
+            if ((failed_bits_y[kk / 32] >> (kk % 32)) & 1u)
+                continue;  // failed on both sides: counted from A's failure
+        }
+        const uint64_t cell = x_is_a ? (uint64_t)item * n_b + c : (uint64_t)c * n_b + item;
+        atomicAdd(&out[cell], 1u);
+    }
+}
+
 __global__ void apply_corrections_kernel(const uint32_t *pairs, uint64_t n_corr, uint32_t *out, uint64_t n)
 {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -188,6 +217,42 @@ __global__ void threshold_write_kernel(const uint32_t *sup, uint64_t n_pairs, ui
     }
 }
 
+// The same compaction over a row-major rectangle of n_cols columns: entry k
+// is the pair (k / n_cols, k % n_cols).
+__global__ void threshold_write_rect_kernel(const uint32_t *sup, uint64_t n_cells, uint64_t n_cols, uint32_t sigma,
+                                            const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity,
+                                            bm_pair *out)
+{
+    if (block_off[n_blocks] > capacity)
+        return;  // the same value for every thread of the grid
+    uint64_t base = (uint64_t)blockIdx.x * kThrTile + (uint64_t)threadIdx.x * kThrItems;
+    uint32_t v[kThrItems];
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kThrItems; i++) {
+        uint64_t k = base + i;
+        v[i] = k < n_cells ? sup[k] : 0u;
+        c += (k < n_cells && v[i] >= sigma) ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t before = block_excl_scan_u32(c, &total);
+    if (c == 0)
+        return;
+    uint64_t pos = block_off[blockIdx.x] + before;
+    for (int i = 0; i < kThrItems; i++) {
+        uint64_t k = base + i;
+        if (k >= n_cells)
+            break;
+        if (v[i] >= sigma) {
+            bm_pair pr;
+            pr.i = (uint32_t)(k / n_cols);
+            pr.j = (uint32_t)(k % n_cols);
+            pr.support = v[i];
+            out[pos++] = pr;
+        }
+    }
+}
+
 // Subset query preparation: pos_of_item[item] = query position; flags repeats,
 // out-of-range ids and items without a BatMap.
 __global__ void subset_prepare_kernel(const uint32_t *items, uint32_t k, uint32_t n, const int32_t *sorted_pos,
@@ -221,6 +286,32 @@ hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const u
         blocks = 1u << 20;
     corrections_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(failed, n_failed, off, tids, failed_bits, has_map, n,
                                                             pairs, cap, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off_y,
+                                    const uint32_t *tids_y, uint32_t n_y, const uint32_t *failed_bits_y, uint32_t *out,
+                                    uint64_t n_b, bool x_is_a, hipStream_t s)
+{
+    const uint64_t total = (uint64_t)n_failed * n_y;
+    if (total == 0)
+        return hipSuccess;
+    uint64_t blocks = (total + kBlock - 1) / kBlock;
+    if (blocks > (1u << 20))
+        blocks = 1u << 20;
+    cross_corrections_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(failed, n_failed, off_y, tids_y, n_y, failed_bits_y,
+                                                                  out, n_b, x_is_a ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold_write_rect(const uint32_t *sup, uint64_t n_cells, uint64_t n_cols, uint32_t sigma,
+                                       const uint64_t *block_off, uint32_t n_blocks, uint64_t capacity, bm_pair *out,
+                                       hipStream_t s)
+{
+    if (n_blocks == 0)
+        return hipSuccess;
+    threshold_write_rect_kernel<<<n_blocks, kBlock, 0, s>>>(sup, n_cells, n_cols, sigma, block_off, n_blocks,
+                                                             capacity, out);
     return hipGetLastError();
 }
 

@@ -48,18 +48,30 @@ const VariantInfo kInfo[kVariantCount] = {
     // 5.98 ms for 128 x 12 on the large Zipf instance, but 2.40 against 2.28
     // between maps of one width (the paper-replica instance).
     {192, 12, true, 2, 0, true, 1.40f, 1.20f},
+    // wider slots (Sec. III-A, uncompressed case): 16 planes per group, then
+    // 32; a group pair costs W + 1 ops instead of 9, so their speeds are
+    // relative to each other only (the planner never mixes slot widths)
+    {128, 8, true, 1, -1, true, 1.00f, 0.f, 16},
+    {4, 4, true, 64, -1, true, 0.30f, 0.f, 16},
+    {64, 8, true, 1, -1, true, 1.00f, 0.f, 32},
+    {2, 4, true, 64, -1, true, 0.30f, 0.f, 32},
 };
 
 }  // namespace
 
 const VariantInfo &variant_info(int v) { return kInfo[v]; }
 
-bool shape_allowed(int v, int single, int pinned)
+bool shape_allowed(int v, int single, int pinned, uint32_t planes)
 {
     const VariantInfo &V = kInfo[v];
+    if (V.planes != planes)
+        return false;
     if (single)  // the single-launch kernel runs row-resident bodies only
         return V.multi >= 0 && V.row_resident;
-    return pinned >= 0 ? v == pinned : V.default_choice;
+    // a pinned shape of another slot width leaves this width on its defaults
+    if (pinned >= 0 && kInfo[pinned].planes == planes)
+        return v == pinned;
+    return V.default_choice;
 }
 
 uint64_t item_cost(const WorkItem &w)
@@ -136,33 +148,65 @@ void xcd_order(std::vector<WorkItem> &v)
 }  // namespace
 
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds, int single, int pinned, bool cross_only)
+                  const std::vector<float> *speeds, int single, int pinned, bool cross_only, uint32_t planes)
+{
+    std::vector<ClassPair> pairs;
+    for (size_t a = 0; a < cls.size(); a++) {
+        for (size_t b = a; b < cls.size(); b++) {
+            const bool same = a == b;
+            if (same && (cls[a].count < 2 || cross_only))
+                continue;
+            pairs.push_back({cls[a], cls[b], same, (uint16_t)inst});
+        }
+    }
+    plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+}
+
+void plan_cross(const std::vector<Cls> &a_cls, const std::vector<Cls> &b_cls, uint32_t na, uint32_t nb,
+                uint64_t target_items, Plan &plan, const std::vector<float> *speeds, int single, int pinned,
+                uint32_t planes)
+{
+    // instance 0 indexes [A maps, B maps], instance 1 [B maps, A maps]; the
+    // narrower class of each pair gives the rows
+    std::vector<ClassPair> pairs;
+    for (const Cls &A : a_cls)
+        for (const Cls &B : b_cls) {
+            if (A.r <= B.r)
+                pairs.push_back({A, Cls{B.r, na + B.start, B.count}, false, 0});
+            else
+                pairs.push_back({B, Cls{A.r, nb + A.start, A.count}, false, 1});
+        }
+    plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+}
+
+void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan &plan,
+                const std::vector<float> *speeds, int single, int pinned, uint32_t planes)
 {
     const int nv = kVariantCount;
     plan.by_variant.assign(nv, {});
     plan.slot_pairs = 0;
+    plan.complete = true;
     struct Choice {
-        size_t a, b;
+        size_t k;  // class pair
         int v;
         double speed;
     };
     std::vector<Choice> choices;
     double total_work = 0;  // padded pair-groups over speed: wave time, arbitrary unit
-    for (size_t a = 0; a < cls.size(); a++) {
-        for (size_t b = a; b < cls.size(); b++) {
-            bool same = a == b;
-            if (same && (cls[a].count < 2 || cross_only))
-                continue;
+    for (size_t k = 0; k < pairs.size(); k++) {
+        const Cls &rowc = pairs[k].A, &colc = pairs[k].B;
+        const bool same = pairs[k].same;
+        {
             int best = -1;
             double best_cost = 1e300, best_speed = 1;
-            const int bucket = wrap_bucket(cls[b].r / cls[a].r);
+            const int bucket = wrap_bucket(colc.r / rowc.r);
             const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
             for (int v = 0; v < nv; v++) {
                 // measured speeds weigh the default shapes against each other; the
                 // staged-tile shapes time well on uniform synthetic tiles but lose on
                 // skewed instances, so they are used only when pinned
                 const VariantInfo &V = variant_info(v);
-                if (!shape_allowed(v, single, pinned))
+                if (!shape_allowed(v, single, pinned, planes))
                     continue;
                 const float builtin = bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed;
                 float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : builtin;
@@ -172,7 +216,7 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                     speed = builtin;
                 const uint32_t bi = V.bi, bj = V.bj;
                 uint64_t cnt;
-                tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
+                tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
                 double cost = (double)cnt * bi * bj / speed;
                 // prefer larger tiles on ties (more reuse per loaded group)
                 if (cost < best_cost) {  // variants are listed largest tile first
@@ -181,26 +225,32 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                     best_speed = speed;
                 }
             }
-            // every mode allows at least one shape, and every catalogue speed is
-            // > 0, so some shape was chosen above
+            // every catalogue speed is > 0, so a shape was chosen above unless
+            // none runs this mode and slot width (the single launch has 8-bit
+            // bodies only): the plan is then marked incomplete for the caller
             for (int v = 0; best < 0 && v < nv; v++)
-                if (shape_allowed(v, single, -1))
+                if (shape_allowed(v, single, -1, planes))
                     best = v, best_speed = variant_info(v).speed;
+            if (best < 0) {
+                plan.complete = false;
+                continue;
+            }
             const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
             uint64_t cnt;
-            tiles_for(cls[a], cls[b], same, bi, bj, nullptr, &cnt);
-            double pairs = same ? 0.5 * cls[a].count * (cls[a].count - 1.0) : (double)cls[a].count * cls[b].count;
-            plan.slot_pairs += pairs * 3.0 * cls[b].r;
-            total_work += (double)cnt * bi * bj * (3.0 * cls[b].r / kSlotsPerGroup) / best_speed;
-            choices.push_back({a, b, best, best_speed});
+            tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
+            double np = same ? 0.5 * rowc.count * (rowc.count - 1.0) : (double)rowc.count * colc.count;
+            plan.slot_pairs += np * 3.0 * colc.r;
+            total_work += (double)cnt * bi * bj * (3.0 * colc.r / kSlotsPerGroup) / best_speed;
+            choices.push_back({k, best, best_speed});
         }
     }
     // every item should take about the same time: work_per_item of wave time
     const double work_per_item = total_work / (double)std::max<uint64_t>(target_items, 1);
     std::vector<std::pair<uint32_t, uint32_t>> tiles;
     for (const Choice &ch : choices) {
-        const Cls &A = cls[ch.a], &B = cls[ch.b];
-        bool same = ch.a == ch.b;
+        const Cls &A = pairs[ch.k].A, &B = pairs[ch.k].B;
+        const bool same = pairs[ch.k].same;
+        const uint16_t inst = pairs[ch.k].inst;
         const VariantInfo &V = variant_info(ch.v);
         const uint32_t bi = V.bi, bj = V.bj;
         tiles.clear();
@@ -248,7 +298,7 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
                 w.c1 = (uint32_t)c1;
                 w.row_groups = Ga;
                 w.col_groups = Gb;
-                w.inst = (uint16_t)inst;
+                w.inst = inst;
                 w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u) | (V.multi >= 0 ? (uint32_t)V.multi << 2 : 0u));
                 plan.by_variant[ch.v].push_back(w);
             }

@@ -45,13 +45,15 @@ struct VariantInfo {
     bool default_choice;  // offered to the planner unless a shape is pinned
     float speed;          // relative group-pair rate of an unpadded tile (planner weight)
     float speed_nowrap = 0;  // the same between maps of one width, when it differs (0: as speed)
+    uint32_t planes = 8;  // bits per slot of the maps it compares (8, 16, 32)
 };
-constexpr int kVariantCount = 22;
+constexpr int kVariantCount = 26;
 const VariantInfo &variant_info(int v);
-// Whether plan_classes may choose shape v: single-launch mode (single != 0)
-// takes only shapes with a body in the persistent kernel (multi >= 0, row
-// groups walked); otherwise the pinned shape alone, or the default shapes.
-bool shape_allowed(int v, int single, int pinned);
+// Whether plan_classes may choose shape v for maps of `planes`-bit slots:
+// only shapes of that slot width; single-launch mode (single != 0) takes
+// only shapes with a body in the persistent kernel (multi >= 0, row groups
+// walked); otherwise the pinned shape alone, or the default shapes.
+bool shape_allowed(int v, int single, int pinned, uint32_t planes = 8);
 
 // Measured speeds are kept per wrap ratio G_col / G_row: 1 | 2..8 | >= 16.
 constexpr int kWrapBuckets = 3;
@@ -75,6 +77,7 @@ struct Cls {
 struct Plan {
     std::vector<std::vector<WorkItem>> by_variant;
     double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
+    bool complete = true;   // false when some class pair had no shape for the mode and slot width
 };
 
 // Groups an item visits (longest first gives a better tail).
@@ -94,7 +97,33 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
 // single-launch kernel only.  pinned >= 0 forces that shape (single == 0 only).
 // cross_only: only pairs of different classes.
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds, int single, int pinned, bool cross_only = false);
+                  const std::vector<float> *speeds, int single, int pinned, bool cross_only = false,
+                  uint32_t planes = 8);
+
+// One pair of width classes to plan: rows from A (the narrower), columns from
+// B; same: A and B are one class (only row < column); inst: the work items'
+// instance (descriptor index).
+struct ClassPair {
+    Cls A, B;
+    bool same;
+    uint16_t inst;
+};
+
+// The planner behind plan_classes and plan_cross, over an explicit list of
+// class pairs (each A.r <= B.r).
+void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan &plan,
+                const std::vector<float> *speeds, int single, int pinned, uint32_t planes = 8);
+
+// Every pair (i, j) of two families' maps, i < na of the first (classes
+// a_cls) and j < nb of the second (b_cls), each class list over its own
+// family's sorted indices.  A pair of classes is tiled with the narrower one
+// as rows: instance 0 holds the items whose rows come from the first family
+// (sorted indices [0, na) for it, then na + j for the second), instance 1
+// those whose rows come from the second (sorted indices [0, nb) for it, then
+// nb + i for the first).
+void plan_cross(const std::vector<Cls> &a_cls, const std::vector<Cls> &b_cls, uint32_t na, uint32_t nb,
+                uint64_t target_items, Plan &plan, const std::vector<float> *speeds, int single, int pinned,
+                uint32_t planes = 8);
 
 // Slot pairs compared by an all-pairs plan of the classes: the sum over
 // pairs of 3 max(r_i, r_j) (what plan_classes reports as slot_pairs).

@@ -28,6 +28,15 @@ __global__ void fill_u32x4_kernel(uint4 *p, uint64_t n4, uint32_t v)
         p[i] = w;
 }
 
+__global__ void words_differ_kernel(const uint32_t *a, const uint32_t *b, uint64_t n, uint32_t *flag)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        if (a[i] != b[i]) {
+            atomicOr(flag, 1u);
+            return;
+        }
+}
+
 __global__ void fill_u8_kernel(uint8_t *p, uint64_t n, uint8_t v)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -303,6 +312,14 @@ hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s)
         return hipGetLastError();
     }
     fill_u32_kernel<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_words_differ(const uint32_t *a, const uint32_t *b, uint64_t n, uint32_t *flag, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    words_differ_kernel<<<grid_for(n), kBlock, 0, s>>>(a, b, n, flag);
     return hipGetLastError();
 }
 

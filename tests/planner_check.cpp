@@ -6,7 +6,7 @@
 // Built with -DPLAN_CHECK_MAIN it is also a program (compiled with the
 // address and undefined-behaviour sanitizers by the same test) that reads
 // cases from stdin, one per line:
-//   single pinned inst target speed_kind n_cls r[0..n_cls) count[0..n_cls)
+//   planes single pinned inst target speed_kind n_cls r[0..n_cls) count[0..n_cls)
 // speed_kind: 0 built-in speeds, 1 all measured speeds 0, 2 all NaN,
 // 3 all negative, 4 seeded random positive, 5 only the single-launch shapes
 // unusable (0).
@@ -35,8 +35,8 @@ int fail(char *msg, uint32_t len, int code, const char *fmt, ...)
 }  // namespace
 
 extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *count, uint64_t target, int single,
-                          int pinned, uint32_t inst, const float *speeds, char *msg, uint32_t msg_len,
-                          uint64_t *n_items)
+                          int pinned, uint32_t inst, const float *speeds, uint32_t planes, char *msg,
+                          uint32_t msg_len, uint64_t *n_items)
 {
     std::vector<Cls> cls;
     uint32_t n = 0;
@@ -52,9 +52,19 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
     std::vector<float> sp_table;
     if (speeds)
         sp_table.assign(speeds, speeds + kVariantCount * kWrapBuckets);
-    plan_classes(cls, inst, target, plan, speeds ? &sp_table : nullptr, single, pinned);
+    plan_classes(cls, inst, target, plan, speeds ? &sp_table : nullptr, single, pinned, false, planes);
     if ((int)plan.by_variant.size() != kVariantCount)
         return fail(msg, msg_len, 1, "plan has %zu shape lists", plan.by_variant.size());
+    // the single launch has bodies for 8-bit slots only: a plan for wider
+    // slots in that mode must say it is incomplete
+    if (plan.complete != !(single && planes != 8))
+        return fail(msg, msg_len, 1, "plan.complete %d for single %d, %u-bit slots", (int)plan.complete, single,
+                    planes);
+    if (!plan.complete) {
+        *n_items = 0;
+        return 0;
+    }
+    const bool pin_applies = pinned >= 0 && variant_info(pinned).planes == planes;
     std::vector<uint64_t> cov((uint64_t)n * (n ? n - 1 : 0) / 2, 0);
     auto pidx = [&](uint64_t i, uint64_t j) { return i * n - i * (i + 1) / 2 + (j - i - 1); };
     uint64_t items = 0;
@@ -62,11 +72,13 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
         const VariantInfo &V = variant_info(v);
         for (const WorkItem &w : plan.by_variant[v]) {
             items++;
+            if (V.planes != planes)
+                return fail(msg, msg_len, 2, "shape %d of %u-bit slots for %u-bit maps", v, V.planes, planes);
             if (single && (V.multi < 0 || !V.row_resident))
                 return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
-            if (!single && pinned < 0 && !V.default_choice)
+            if (!single && !pin_applies && !V.default_choice)
                 return fail(msg, msg_len, 2, "tuning-only shape %d chosen without a pin", v);
-            if (!single && pinned >= 0 && v != pinned)
+            if (!single && pin_applies && v != pinned)
                 return fail(msg, msg_len, 3, "shape %d while %d is pinned", v, pinned);
             if (w.inst != inst)
                 return fail(msg, msg_len, 4, "instance %u", w.inst);
@@ -113,6 +125,85 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
         for (uint32_t b = a; b < n_cls; b++) {
             double pairs = a == b ? 0.5 * count[a] * (count[a] - 1.0) : (double)count[a] * count[b];
             sp += pairs * 3.0 * r[b];
+        }
+    if (sp != plan.slot_pairs)
+        return fail(msg, msg_len, 14, "slot pairs %.0f, expected %.0f", plan.slot_pairs, sp);
+    *n_items = items;
+    return 0;
+}
+
+// plan_cross: every item's rows come from the narrower family of its class
+// pair, indices fall inside the instance's index space (instance 0: [A, B],
+// instance 1: [B, A]), and every (i, j), i of A, j of B, is visited over all
+// 3 max(r_i, r_j) / 32 groups of the wider map exactly once.
+extern "C" int cross_check(uint32_t na_cls, const uint32_t *ra, const uint32_t *ca, uint32_t nb_cls, const uint32_t *rb,
+                           const uint32_t *cb, uint64_t target, int single, int pinned, uint32_t planes, char *msg,
+                           uint32_t msg_len, uint64_t *n_items)
+{
+    std::vector<Cls> acls, bcls;
+    std::vector<uint32_t> a_r, b_r;
+    uint32_t na = 0, nb = 0;
+    for (uint32_t c = 0; c < na_cls; c++) {
+        acls.push_back({ra[c], na, ca[c]});
+        na += ca[c];
+        a_r.insert(a_r.end(), ca[c], ra[c]);
+    }
+    for (uint32_t c = 0; c < nb_cls; c++) {
+        bcls.push_back({rb[c], nb, cb[c]});
+        nb += cb[c];
+        b_r.insert(b_r.end(), cb[c], rb[c]);
+    }
+    Plan plan;
+    plan_cross(acls, bcls, na, nb, target, plan, nullptr, single, pinned, planes);
+    if (!plan.complete)
+        return fail(msg, msg_len, 1, "incomplete cross plan");
+    std::vector<uint64_t> cov((uint64_t)na * nb, 0);
+    uint64_t items = 0;
+    for (int v = 0; v < kVariantCount; v++) {
+        const VariantInfo &V = variant_info(v);
+        for (const WorkItem &w : plan.by_variant[v]) {
+            items++;
+            if (single && (V.multi < 0 || !V.row_resident))
+                return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
+            if (V.planes != planes)
+                return fail(msg, msg_len, 2, "shape %d of %u-bit slots for %u-bit maps", v, V.planes, planes);
+            if (w.inst > 1 || (w.flags & 1u))
+                return fail(msg, msg_len, 3, "instance %u flags 0x%x", w.inst, w.flags);
+            const uint32_t nrows_fam = w.inst == 0 ? na : nb, ncols_fam = w.inst == 0 ? nb : na;
+            const std::vector<uint32_t> &row_r = w.inst == 0 ? a_r : b_r, &col_r = w.inst == 0 ? b_r : a_r;
+            if (w.nrow < 1 || w.nrow > V.bi || w.ncol < 1 || w.ncol > V.bj)
+                return fail(msg, msg_len, 5, "shape %d tile %u x %u", v, w.nrow, w.ncol);
+            if ((uint64_t)w.row0 + w.nrow > nrows_fam || w.col0 < nrows_fam ||
+                (uint64_t)w.col0 + w.ncol > (uint64_t)nrows_fam + ncols_fam)
+                return fail(msg, msg_len, 6, "tile outside its families");
+            const uint32_t r_row = row_r[w.row0], r_col = col_r[w.col0 - nrows_fam];
+            if (row_r[w.row0 + w.nrow - 1] != r_row || col_r[w.col0 - nrows_fam + w.ncol - 1] != r_col || r_row > r_col)
+                return fail(msg, msg_len, 7, "tile spans classes or rows wider than columns");
+            if (w.inst == 1 && r_row == r_col)
+                return fail(msg, msg_len, 7, "equal widths must take rows from the first family");
+            const uint32_t Ga = 3 * r_row / kSlotsPerGroup, Gb = 3 * r_col / kSlotsPerGroup;
+            if (w.row_groups != Ga || w.col_groups != Gb)
+                return fail(msg, msg_len, 10, "group counts %u / %u", w.row_groups, w.col_groups);
+            const uint32_t span = V.row_resident ? Ga : Gb;
+            if (!(w.c0 < w.c1 && w.c1 <= span) || w.c0 % V.step != 0 || (w.c1 % V.step != 0 && w.c1 != span))
+                return fail(msg, msg_len, 11, "range [%u, %u) of %u, step %u", w.c0, w.c1, span, V.step);
+            const uint64_t unit = V.row_resident ? Gb / Ga : 1;
+            for (uint32_t i = 0; i < w.nrow; i++)
+                for (uint32_t j = 0; j < w.ncol; j++) {
+                    const uint32_t p = w.row0 + i, q = w.col0 + j - nrows_fam;
+                    const uint64_t cell = w.inst == 0 ? (uint64_t)p * nb + q : (uint64_t)q * nb + p;
+                    cov[cell] += (uint64_t)(w.c1 - w.c0) * unit;
+                }
+        }
+    }
+    double sp = 0;
+    for (uint32_t i = 0; i < na; i++)
+        for (uint32_t j = 0; j < nb; j++) {
+            const uint32_t wide = std::max(a_r[i], b_r[j]);
+            sp += 3.0 * wide;
+            if (cov[(uint64_t)i * nb + j] != 3ull * wide / kSlotsPerGroup)
+                return fail(msg, msg_len, 13, "pair (%u, %u) visits %llu groups, not %llu", i, j,
+                            (unsigned long long)cov[(uint64_t)i * nb + j], 3ull * wide / kSlotsPerGroup);
         }
     if (sp != plan.slot_pairs)
         return fail(msg, msg_len, 14, "slot pairs %.0f, expected %.0f", plan.slot_pairs, sp);
@@ -181,7 +272,8 @@ int main()
     unsigned inst, n_cls;
     unsigned long long target;
     int line = 0, bad = 0;
-    while (scanf("%d %d %u %llu %d %u", &single, &pinned, &inst, &target, &kind, &n_cls) == 6) {
+    unsigned planes;
+    while (scanf("%u %d %d %u %llu %d %u", &planes, &single, &pinned, &inst, &target, &kind, &n_cls) == 7) {
         line++;
         std::vector<uint32_t> r(n_cls), count(n_cls);
         for (auto &x : r)
@@ -207,8 +299,8 @@ int main()
         char msg[256];
         uint64_t items = 0;
         int st = plan_check(n_cls, r.data(), count.data(), target, single, pinned, inst, kind ? sp.data() : nullptr,
-                            msg, sizeof msg, &items);
-        if (st == 0 && single)
+                            planes, msg, sizeof msg, &items);
+        if (st == 0 && single && planes == 8)
             st = queues_check(n_cls, r.data(), count.data(), target, single, msg, sizeof msg);
         if (st != 0) {
             printf("case %d: %s\n", line, msg);

@@ -33,9 +33,29 @@ def test_library_exports_every_declared_symbol():
     assert set(bm.EXPORTED) <= declared_functions()
 
 
-def test_opts_defaults_and_struct_sizes():
+def test_opts_defaults_and_struct_sizes(tmp_path):
+    """The binding's structures match the header's, field by field (a C program built
+    against include/batmap.h prints their sizes and offsets)."""
     import ctypes
+    import subprocess
     o = bm.build_opts()
-    assert o.max_loop == 64 and o.min_support == 0 and o.flags == 0
-    assert ctypes.sizeof(bm.bm_pair) == 12
-    assert ctypes.sizeof(bm.bm_index_stats) == 8 * 4 + 4 * 8
+    assert o.max_loop == 64 and o.min_support == 0 and o.flags == 0 and o.slot_bits == 8
+    structs = {"bm_build_opts": bm.bm_build_opts, "bm_pair": bm.bm_pair, "bm_index_stats": bm.bm_index_stats,
+               "bm_timings": bm.bm_timings, "bm_server_opts": bm.bm_server_opts,
+               "bm_request_info": bm.bm_request_info, "bm_server_stats": bm.bm_server_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "batmap.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)], check=True)
+    want = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert ctypes.sizeof(cls) == int(want[name]), name
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == int(want[f"{name}.{field}"]), f"{name}.{field}"

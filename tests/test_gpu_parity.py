@@ -259,7 +259,7 @@ def test_subset_queries(ctx):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.subset_pairs(off, tids, q))
 
 
-N_SHAPES = 22   # tile shapes in the catalogue (plan.cpp / compare.hip)
+N_SHAPES = 26   # tile shapes in the catalogue (plan.cpp / compare.hip)
 
 
 def test_single_launch_and_every_shape(monkeypatch):

@@ -12,7 +12,8 @@ import datagen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1102_1003_amd", "csrc")
-N_SHAPES = 22
+N_SHAPES = 26
+PLANES = [8] * 22 + [16, 16, 32, 32]   # slot width of each catalogue shape
 CU64 = 256 * 64     # items a full MI355X plan aims at
 
 
@@ -28,10 +29,25 @@ def checker(tmp_path_factory):
                                  ctypes.c_char_p, ctypes.c_uint32]
     lib.plan_check.restype = ctypes.c_int
     lib.plan_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint32,
-                               ctypes.POINTER(ctypes.c_uint64)]
+                               ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_char_p,
+                               ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
 
-    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0, speeds=None):
+    lib.cross_check.restype = ctypes.c_int
+    lib.cross_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                                ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+
+    def check_cross(wa, ca, wb, cb, target=CU64, single=0, pinned=-1, planes=8):
+        ra, na_ = np.ascontiguousarray(wa, np.uint32), np.ascontiguousarray(ca, np.uint32)
+        rb, nb_ = np.ascontiguousarray(wb, np.uint32), np.ascontiguousarray(cb, np.uint32)
+        msg = ctypes.create_string_buffer(256)
+        n_items = ctypes.c_uint64(0)
+        st = lib.cross_check(ra.size, ra.ctypes.data, na_.ctypes.data, rb.size, rb.ctypes.data, nb_.ctypes.data,
+                             target, single, pinned, planes, msg, 256, ctypes.byref(n_items))
+        assert st == 0, f"{msg.value.decode()} (A {list(ra)} x {list(na_)}, B {list(rb)} x {list(nb_)}, single {single})"
+        return n_items.value
+
+    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0, speeds=None, planes=8):
         r = np.ascontiguousarray(widths, dtype=np.uint32)
         c = np.ascontiguousarray(counts, dtype=np.uint32)
         msg = ctypes.create_string_buffer(256)
@@ -39,12 +55,14 @@ def checker(tmp_path_factory):
         sp = None if speeds is None else np.ascontiguousarray(speeds, dtype=np.float32)
         assert sp is None or sp.size == N_SHAPES * 3
         st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst,
-                            None if sp is None else sp.ctypes.data, msg, 256, ctypes.byref(n_items))
-        assert st == 0, f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned})"
-        if single:
+                            None if sp is None else sp.ctypes.data, planes, msg, 256, ctypes.byref(n_items))
+        assert st == 0, (f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned},"
+                         f" planes {planes})")
+        if single and planes == 8:
             st = lib.queues_check(r.size, r.ctypes.data, c.ctypes.data, target, single, msg, 256)
             assert st == 0, f"{msg.value.decode()} (queues; widths {list(r)}, counts {list(c)})"
         return n_items.value
+    check.cross = check_cross
     return check
 
 
@@ -106,7 +124,20 @@ def test_every_shape_pinned(checker, pinned):
         n_cls = int(rng.integers(1, 5))
         vals = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536], size=n_cls, replace=False))
         counts = rng.integers(1, 300, size=n_cls)
-        checker(vals, counts, target=int(rng.integers(64, 20000)), pinned=pinned)
+        for planes in (8, 16, 32):   # the pin binds maps of its own slot width only
+            checker(vals, counts, target=int(rng.integers(64, 20000)), pinned=pinned, planes=planes)
+
+
+@pytest.mark.parametrize("planes", [16, 32])
+def test_wide_slot_plans(checker, planes):
+    rng = np.random.default_rng(planes)
+    for _ in range(10):
+        n_cls = int(rng.integers(1, 6))
+        vals = np.sort(rng.choice([128, 256, 512, 1024, 4096, 65536], size=n_cls, replace=False))
+        counts = rng.integers(1, 400, size=n_cls)
+        checker(vals, counts, target=int(rng.integers(16, 30000)), planes=planes)
+        checker(vals, counts, single=1, planes=planes)           # incomplete: no single-launch body
+    checker.cross([128, 512], [30, 4], [128, 1 << 14], [60, 3], planes=planes)
 
 
 def test_edge_class_lists(checker):
@@ -139,10 +170,11 @@ def _case_lines():
                 vals = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536, 1 << 20], size=n_cls, replace=False))
                 counts = rng.integers(1, 260, size=n_cls)
                 target = int(rng.integers(1, 40000))
-                lines.append(f"{single} -1 {int(rng.integers(0, 64))} {target} {kind} {n_cls} "
+                planes = [8, 16, 32][int(rng.integers(0, 3))]
+                lines.append(f"{planes} {single} -1 {int(rng.integers(0, 64))} {target} {kind} {n_cls} "
                              + " ".join(map(str, vals)) + " " + " ".join(map(str, counts)))
     for pinned in range(N_SHAPES):
-        lines.append(f"0 {pinned} 0 {CU64} 0 3 128 1024 8192 300 40 9")
+        lines.append(f"{PLANES[pinned]} 0 {pinned} 0 {CU64} 0 3 128 1024 8192 300 40 9")
     return "\n".join(lines) + "\n"
 
 
@@ -160,3 +192,19 @@ def test_planner_under_sanitizers(tmp_path):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "failed" in r.stdout and ", 0 failed" in r.stdout, r.stdout
     assert "Sanitizer" not in r.stderr, r.stderr[-4000:]
+
+
+def test_cross_plans_cover_every_pair(checker):
+    """Two families with interleaved widths: every (i, j) over the wider map's groups once."""
+    rng = np.random.default_rng(909)
+    checker.cross([128], [1], [128], [1])
+    checker.cross([128, 1024], [300, 3], [256, 1024, 1 << 16], [5, 200, 2], single=1)
+    for _ in range(12):
+        wa = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536], size=int(rng.integers(1, 4)), replace=False))
+        wb = np.sort(rng.choice([128, 256, 512, 2048, 8192, 65536], size=int(rng.integers(1, 4)), replace=False))
+        ca = rng.integers(1, 200, size=wa.size)
+        cb = rng.integers(1, 200, size=wb.size)
+        for single in (0, 1):
+            checker.cross(wa, ca, wb, cb, target=int(rng.integers(16, 30000)), single=single)
+    for pinned in range(N_SHAPES):
+        checker.cross([128, 2048], [40, 7], [256, 2048], [9, 30], pinned=pinned)
