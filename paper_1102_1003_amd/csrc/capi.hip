@@ -519,14 +519,15 @@ void flatten_plan(const Plan &plan, bool single, std::vector<WorkItem> &flat,
     }
 }
 
-bm_status upload_plan(bm_index *idx, const Plan &plan, DevBuf<WorkItem> &dst,
+// single: the plan was made for the single persistent launch
+bm_status upload_plan(bm_index *idx, const Plan &plan, bool single, DevBuf<WorkItem> &dst,
                       std::vector<std::pair<int, uint32_t>> &ranges)
 {
     bm_context *ctx = idx->ctx;
     if (!plan.complete)
         return fail(ctx, BM_EINVAL, "no compare tile shape for %u-bit slots in this launch mode", idx->planes);
     std::vector<WorkItem> flat;
-    flatten_plan(plan, single_launch(ctx, idx->planes), flat, ranges);
+    flatten_plan(plan, single, flat, ranges);
     const uint64_t total = flat.size();
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total)
@@ -542,9 +543,10 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
     if (idx->planned_first == first && idx->planned_gen == ctx->tune_gen)
         return BM_OK;
     Plan plan;
-    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
-                 single_launch(ctx, idx->planes) ? 1 : 0, forced_variant(), false, idx->planes);
-    bm_status st = upload_plan(idx, plan, idx->work, idx->work_ranges);
+    const bool single = single_launch(ctx, idx->planes);
+    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr, single ? 1 : 0,
+                 forced_variant(), false, idx->planes);
+    bm_status st = upload_plan(idx, plan, single, idx->work, idx->work_ranges);
     if (st != BM_OK)
         return st;
     idx->planned_first = first;
@@ -746,10 +748,14 @@ uint32_t slot_shift(uint32_t m, uint32_t w)
     return s;
 }
 
-// Slot width with the least all-pairs compare work for these set sizes:
+// Slot width with the least all-pairs compare time for these set sizes:
 // with widths sorted, the k-th map (from 0) is the wider one of k pairs, and
-// a pair costs 3 max(r) / 32 group pairs of w + 1 VALU ops.  Wider slots pay
-// more per slot but drop the floor r >= 2^s of the 7-bit code.
+// a pair costs 3 max(r) / 32 group pairs.  A group pair of w-bit slots takes
+// w + 1 VALU ops; the wider kernels also run at a lower share of the VALU
+// rate (MI355X, m = 2^20 Bernoulli sweep: 8-bit about 25 TOP/s, 16-bit about
+// 20), so their relative cost per group pair is taken as 1, 2.4 and 5.
+// Wider slots pay more per slot but drop the floor r >= 2^s of the 7-bit
+// code, which is what sparse sets over a large universe need.
 uint32_t choose_slot_bits(const std::vector<uint64_t> &h_off, uint32_t m, uint32_t min_support)
 {
     const size_t n = h_off.size() - 1;
@@ -772,7 +778,7 @@ uint32_t choose_slot_bits(const std::vector<uint64_t> &h_off, uint32_t m, uint32
         double cost = 0;
         for (size_t k = 0; k < r.size(); k++)
             cost += (double)k * (double)r[k];
-        cost *= (double)(w + 1);
+        cost *= w == 8 ? 1.0 : (w == 16 ? 2.4 : 5.0);
         if (w == 8 || cost < best_cost) {
             best = w;
             best_cost = cost;
@@ -2022,10 +2028,10 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.mode = OUT_PACKED;
     d.carena = d.arena;
     Plan plan;
-    plan_classes(cls, 0, target_items(ctx), plan, nullptr, single_launch(ctx, idx->planes) ? 1 : 0,
-                 forced_variant(), false, idx->planes);
+    const bool single = single_launch(ctx, idx->planes);
+    plan_classes(cls, 0, target_items(ctx), plan, nullptr, single ? 1 : 0, forced_variant(), false, idx->planes);
     std::vector<std::pair<int, uint32_t>> ranges;
-    st = upload_plan(idx, plan, idx->sub_work, ranges);
+    st = upload_plan(idx, plan, single, idx->sub_work, ranges);
     if (st != BM_OK)
         return st;
     {
@@ -2392,10 +2398,10 @@ bm_status cross_counts(bm_index *a, bm_index *b, uint32_t *out)
     HIPC(ctx, a->x_descs.ensure(2));
     BMC(upload(ctx, a->x_descs.p, d, sizeof d));
     Plan plan;
-    plan_cross(a->classes, b->classes, na, nb, target_items(ctx), plan, nullptr,
-               single_launch(ctx, a->planes) ? 1 : 0, forced_variant(), a->planes);
+    // per-shape launches: the single persistent launch writes packed output only
+    plan_cross(a->classes, b->classes, na, nb, target_items(ctx), plan, nullptr, 0, forced_variant(), a->planes);
     std::vector<std::pair<int, uint32_t>> ranges;
-    BMC(upload_plan(a, plan, a->x_work, ranges));
+    BMC(upload_plan(a, plan, false, a->x_work, ranges));
     ctx->slot_pairs = plan.slot_pairs;
     {
         Span sp(ctx, PH_COMPARE);

@@ -71,24 +71,31 @@ __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
     return i * n - i * (i + 1) / 2 + (j - i - 1);
 }
 
+// Within one family (kRect = false) the column maps live in the row maps'
+// arena, and the kernels read both through d.arena: one base pointer fewer
+// in the scalar registers the column groups need.
+
 // Adds the count v of row map p against column map q (sorted indices) into
-// the output, in the descriptor's layout.
+// the output.  kRect = false: packed upper triangle (one family); true: the
+// rectangle of a two-family product, rows first or columns first as the
+// descriptor's mode says.  The layout is a template parameter, not a branch
+// on the mode: a branch at every output site of the unrolled epilogue costs
+// the compare loop's scalar-load schedule about 5 %.
+template <bool kRect>
 __device__ inline void emit(const InstDesc &d, uint32_t p, uint32_t q, uint32_t v)
 {
     const uint32_t a = d.outpos[p], b = d.outpos[q];
-    uint64_t k;
-    if (d.mode == OUT_PACKED) {
+    if (!kRect) {
         const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-        k = packed_index(d.n_out, lo, hi);
-    } else if (d.mode == OUT_RECT_ROWS) {
-        k = (uint64_t)a * d.n_out + b;
+        atomicAdd(&d.out[packed_index(d.n_out, lo, hi)], v);
     } else {
-        k = (uint64_t)b * d.n_out + a;
+        const bool cols_first = d.mode == OUT_RECT_COLS;
+        const uint64_t x = cols_first ? b : a, y = cols_first ? a : b;
+        atomicAdd(&d.out[x * d.n_out + y], v);
     }
-    atomicAdd(&d.out[k], v);
 }
 
-template <int MI, int MJ, int TX>
+template <int MI, int MJ, int TX, bool kRect = false>
 __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, TX> &sm)
 {
     using S = Shape<MI, MJ, TX>;
@@ -121,7 +128,7 @@ __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, 
         }
         for (int u = tid; u < S::BJ * KG * 2; u += 256) {
             int kap = u / (KG * 2), rem = u % (KG * 2);
-            sm.col[rem / 2][kap][rem % 2] = d.carena[(sm.goff_c[kap] + c + rem / 2) * 2 + (rem % 2)];
+            sm.col[rem / 2][kap][rem % 2] = (kRect ? d.carena : d.arena)[(sm.goff_c[kap] + c + rem / 2) * 2 + (rem % 2)];
         }
         __syncthreads();
 #pragma unroll
@@ -160,20 +167,20 @@ __device__ void process_item(const WorkItem &w, const InstDesc &d, Smem<MI, MJ, 
                 uint32_t p = w.row0 + rho, q = w.col0 + kap;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                emit(d, p, q, acc[i][j]);
+                emit<kRect>(d, p, q, acc[i][j]);
             }
         }
     }
 }
 
-template <int MI, int MJ, int TX>
+template <int MI, int MJ, int TX, bool kRect>
 __global__ __launch_bounds__(256) void compare_kernel(const WorkItem *__restrict__ items,
                                                       const InstDesc *__restrict__ descs, InstDesc d0)
 {
     __shared__ Smem<MI, MJ, TX> sm;
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_item<MI, MJ, TX>(w, d, sm);
+    process_item<MI, MJ, TX, kRect>(w, d, sm);
 }
 
 // Persistent form: a fixed grid pulls work items from a counter until the
@@ -215,12 +222,12 @@ __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
 // hardware issues oldest first among equal priorities; persistent waves never
 // retire, so without the rotation the oldest wave of each SIMD would keep the
 // lead for the whole launch, and the SIMD completes fewer items in all.
-template <int R, int MJ, int H = 1, int kRotate = 0>
+template <int R, int MJ, int H = 1, int kRotate = 0, bool kRect = false>
 __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)(kRect ? d.carena : d.arena));
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
@@ -323,7 +330,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
                 uint32_t p = w.row0 + rho, q = w.col0 + j;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                emit(d, p, q, acc[r][j]);
+                emit<kRect>(d, p, q, acc[r][j]);
             }
         }
     }
@@ -335,14 +342,14 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 // makes the wait for chunk k come before the loads of chunk k+1 are issued
 // (the first use of chunk k triggers it), and the rest of chunk k's compare
 // then runs while chunk k+1 is in flight.  Scheduling barriers keep that order.
-template <int R, int MJ, int CH>
+template <int R, int MJ, int CH, bool kRect = false>
 __device__ void process_rows_pipe(const WorkItem &w, const InstDesc &d)
 {
     static_assert(MJ % CH == 0 && (MJ / CH) % 2 == 0, "chunks alternate between two buffers");
     constexpr int NK = MJ / CH;
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)(kRect ? d.carena : d.arena));
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
@@ -430,19 +437,19 @@ __device__ void process_rows_pipe(const WorkItem &w, const InstDesc &d)
                 uint32_t p = w.row0 + rho, q = w.col0 + j;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                emit(d, p, q, acc[r][j]);
+                emit<kRect>(d, p, q, acc[r][j]);
             }
         }
     }
 }
 
-template <int R, int MJ, int CH>
+template <int R, int MJ, int CH, bool kRect>
 __global__ __launch_bounds__(64) void compare_pipe_kernel(const WorkItem *__restrict__ items,
                                                           const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_rows_pipe<R, MJ, CH>(w, d);
+    process_rows_pipe<R, MJ, CH, kRect>(w, d);
 }
 
 
@@ -453,12 +460,12 @@ __global__ __launch_bounds__(64) void compare_pipe_kernel(const WorkItem *__rest
 // once and meets the column groups h + u G_row of every wrap u; the counts
 // are summed over the lanes at the end.  Loads are coalesced: neighbouring
 // lanes read neighbouring groups of the same map.
-template <int MI, int MJ>
+template <int MI, int MJ, bool kRect = false>
 __device__ void process_gp(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)d.carena);
+    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)(kRect ? d.carena : d.arena));
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint32_t rb[MI], cb[MJ];
 #pragma unroll
@@ -530,29 +537,29 @@ __device__ void process_gp(const WorkItem &w, const InstDesc &d)
                     uint32_t p = w.row0 + i, q = w.col0 + j;
                     if ((w.flags & 1u) && p >= q)
                         continue;
-                    emit(d, p, q, acc[i][j]);
+                    emit<kRect>(d, p, q, acc[i][j]);
                 }
             }
     }
 }
 
-template <int MI, int MJ>
+template <int MI, int MJ, bool kRect>
 __global__ __launch_bounds__(64) void compare_gp_kernel(const WorkItem *__restrict__ items,
                                                         const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_gp<MI, MJ>(w, d);
+    process_gp<MI, MJ, kRect>(w, d);
 }
 
 
-template <int R, int MJ, int H>
+template <int R, int MJ, int H, bool kRect>
 __global__ __launch_bounds__(64) void compare_rows_kernel(const WorkItem *__restrict__ items,
                                                           const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_rows<R, MJ, H>(w, d);
+    process_rows<R, MJ, H, 0, kRect>(w, d);
 }
 
 
@@ -589,12 +596,12 @@ __device__ inline void load_group(GlobalU4 *arena, uint64_t g, uint32_t (&v)[W])
 // Row-resident tile over W-plane maps: R rows per lane (64 R rows), MJ
 // column maps whose groups arrive as scalar loads, one row group per step,
 // the next one prefetched (the loop order of process_rows).
-template <int W, int R, int MJ>
+template <int W, int R, int MJ, bool kRect = false>
 __device__ void process_rows_w(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)d.carena);
+    ConstU4 *carena = (ConstU4 *)uniform_u64((uint64_t)(kRect ? d.carena : d.arena));
     GlobalU64 *goff = (GlobalU64 *)uniform_u64((uint64_t)d.goff);
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint64_t rbase[R];
@@ -664,7 +671,7 @@ __device__ void process_rows_w(const WorkItem &w, const InstDesc &d)
                 uint32_t p = w.row0 + rho, q = w.col0 + j;
                 if ((w.flags & 1u) && p >= q)
                     continue;
-                emit(d, p, q, acc[r][j]);
+                emit<kRect>(d, p, q, acc[r][j]);
             }
         }
     }
@@ -672,12 +679,12 @@ __device__ void process_rows_w(const WorkItem &w, const InstDesc &d)
 
 // Group-parallel small tile over W-plane maps (lanes over row-group
 // positions, as process_gp).
-template <int W, int MI, int MJ>
+template <int W, int MI, int MJ, bool kRect = false>
 __device__ void process_gp_w(const WorkItem &w, const InstDesc &d)
 {
     const int lane = threadIdx.x & 63;
     GlobalU4 *arena = (GlobalU4 *)uniform_u64((uint64_t)d.arena);
-    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)d.carena);
+    GlobalU4 *carena = (GlobalU4 *)uniform_u64((uint64_t)(kRect ? d.carena : d.arena));
     ConstU64 *cgoff = (ConstU64 *)uniform_u64((uint64_t)d.goff);
     uint32_t rb[MI], cb[MJ];
 #pragma unroll
@@ -735,28 +742,28 @@ __device__ void process_gp_w(const WorkItem &w, const InstDesc &d)
                     uint32_t p = w.row0 + i, q = w.col0 + j;
                     if ((w.flags & 1u) && p >= q)
                         continue;
-                    emit(d, p, q, acc[i][j]);
+                    emit<kRect>(d, p, q, acc[i][j]);
                 }
             }
     }
 }
 
-template <int W, int R, int MJ>
+template <int W, int R, int MJ, bool kRect>
 __global__ __launch_bounds__(64) void compare_rows_w_kernel(const WorkItem *__restrict__ items,
                                                             const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_rows_w<W, R, MJ>(w, d);
+    process_rows_w<W, R, MJ, kRect>(w, d);
 }
 
-template <int W, int MI, int MJ>
+template <int W, int MI, int MJ, bool kRect>
 __global__ __launch_bounds__(64) void compare_gp_w_kernel(const WorkItem *__restrict__ items,
                                                           const InstDesc *__restrict__ descs, InstDesc d0)
 {
     const WorkItem w = items[blockIdx.x];
     const InstDesc d = descs ? descs[w.inst] : d0;
-    process_gp_w<W, MI, MJ>(w, d);
+    process_gp_w<W, MI, MJ, kRect>(w, d);
 }
 
 
@@ -806,30 +813,39 @@ __global__ void store_desc_kernel(InstDesc *dst, InstDesc d)
 }
 
 
-// Kernel of each tile shape, in the order of the shape catalogue (plan.cpp).
+// Kernel of each tile shape, in the order of the shape catalogue (plan.cpp),
+// for packed one-family output (kRect = false) and two-family rectangles.
 struct Kernels {
     uint32_t block;
     void (*grid_fn)(const WorkItem *, const InstDesc *, InstDesc);
 };
 
-#define BM_STAGED(MI, MJ, TX) Kernels{256, compare_kernel<MI, MJ, TX>}
-#define BM_ROWS(R, MJ, H) Kernels{64, compare_rows_kernel<R, MJ, H>}
-#define BM_PIPE(R, MJ, CH) Kernels{64, compare_pipe_kernel<R, MJ, CH>}
-#define BM_GP(MI, MJ) Kernels{64, compare_gp_kernel<MI, MJ>}
-#define BM_ROWS_W(W, R, MJ) Kernels{64, compare_rows_w_kernel<W, R, MJ>}
-#define BM_GP_W(W, MI, MJ) Kernels{64, compare_gp_w_kernel<W, MI, MJ>}
+#define BM_STAGED(MI, MJ, TX) Kernels{256, compare_kernel<MI, MJ, TX, RECT>}
+#define BM_ROWS(R, MJ, H) Kernels{64, compare_rows_kernel<R, MJ, H, RECT>}
+#define BM_PIPE(R, MJ, CH) Kernels{64, compare_pipe_kernel<R, MJ, CH, RECT>}
+#define BM_GP(MI, MJ) Kernels{64, compare_gp_kernel<MI, MJ, RECT>}
+#define BM_ROWS_W(W, R, MJ) Kernels{64, compare_rows_w_kernel<W, R, MJ, RECT>}
+#define BM_GP_W(W, MI, MJ) Kernels{64, compare_gp_w_kernel<W, MI, MJ, RECT>}
+#define BM_KERNEL_TABLE                                                                       \
+    {                                                                                         \
+        BM_STAGED(4, 4, 16), BM_STAGED(4, 4, 32), BM_STAGED(4, 4, 64), BM_STAGED(2, 4, 128), \
+        BM_ROWS(2, 16, 1),   BM_ROWS(2, 12, 1),   BM_ROWS(2, 8, 1),    BM_ROWS(2, 4, 1),     \
+        BM_ROWS(4, 8, 1),    BM_ROWS(1, 16, 1),                                              \
+        BM_ROWS(2, 12, 2),   BM_ROWS(2, 8, 2),    BM_ROWS(1, 16, 2),                         \
+        BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),     \
+        BM_GP(4, 4),         BM_GP(2, 8),                                                    \
+        BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),    BM_ROWS(3, 12, 2),                         \
+        BM_ROWS_W(16, 2, 8), BM_GP_W(16, 4, 4),   BM_ROWS_W(32, 1, 8), BM_GP_W(32, 2, 4),    \
+    }
 
-const Kernels kKernels[] = {
-    BM_STAGED(4, 4, 16), BM_STAGED(4, 4, 32), BM_STAGED(4, 4, 64), BM_STAGED(2, 4, 128),
-    BM_ROWS(2, 16, 1),   BM_ROWS(2, 12, 1),   BM_ROWS(2, 8, 1),    BM_ROWS(2, 4, 1),
-    BM_ROWS(4, 8, 1),    BM_ROWS(1, 16, 1),
-    BM_ROWS(2, 12, 2),   BM_ROWS(2, 8, 2),    BM_ROWS(1, 16, 2),
-    BM_PIPE(2, 8, 4),    BM_PIPE(2, 16, 4),   BM_PIPE(1, 16, 4),   BM_PIPE(2, 4, 2),
-    BM_GP(4, 4),         BM_GP(2, 8),
-    BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),    BM_ROWS(3, 12, 2),
-    BM_ROWS_W(16, 2, 8), BM_GP_W(16, 4, 4),   BM_ROWS_W(32, 1, 8), BM_GP_W(32, 2, 4),
-};
+#define RECT false
+const Kernels kKernels[] = BM_KERNEL_TABLE;
+#undef RECT
+#define RECT true
+const Kernels kKernelsRect[] = BM_KERNEL_TABLE;
+#undef RECT
 static_assert(sizeof(kKernels) / sizeof(kKernels[0]) == kVariantCount, "one kernel entry per tile shape");
+static_assert(sizeof(kKernelsRect) / sizeof(kKernelsRect[0]) == kVariantCount, "one kernel entry per tile shape");
 
 
 }  // namespace
@@ -845,8 +861,9 @@ hipError_t launch_compare(const WorkItem *items, uint32_t n_items, const InstDes
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(kKernels[variant].grid_fn, dim3(n_items), dim3(kKernels[variant].block), 0, s, items, descs,
-                       d0);
+    // every descriptor of one launch shares d0's layout
+    const Kernels &k = d0.mode == OUT_PACKED ? kKernels[variant] : kKernelsRect[variant];
+    hipLaunchKernelGGL(k.grid_fn, dim3(n_items), dim3(k.block), 0, s, items, descs, d0);
     return hipGetLastError();
 }
 
