@@ -12,7 +12,9 @@ use it.  The product library neither imports nor links it.
   :func:`batmap_compare`, :func:`batmap_all_pairs`, :func:`batmap_check`;
   wider slots (Sec. III-A, uncompressed case: ``slot_bits`` 16 or 32,
   :func:`slot_compare`); two set families (Sec. I, boolean matrix product)
-  -> :func:`cross` (definition), :func:`batmap_cross` (method).
+  -> :func:`cross` (definition), :func:`batmap_cross` (method);
+  itemsets of three (Sec. V, maps holding each element in 3 of 4 tables)
+  -> :func:`triples` (definition), :func:`batmap3_triples` (method).
 """
 from __future__ import annotations
 
@@ -92,6 +94,21 @@ def lib():
         L.orc_batmap_cross.restype = ctypes.c_uint64
         L.orc_batmap_cross.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _u32p, ctypes.c_uint32, _u64p,
                                        _u32p] + [_u32p] * 3 + [ctypes.c_uint32] * 3 + [_u32p]
+        L.orc_triples.restype = None
+        L.orc_triples.argtypes = [_u64p, _u32p, _u32p, ctypes.c_uint64, _u32p, ctypes.c_int]
+        L.orc3_shift.restype = ctypes.c_uint32
+        L.orc3_shift.argtypes = [ctypes.c_uint32]
+        L.orc_batmap3_build.restype = ctypes.c_uint32
+        L.orc_batmap3_build.argtypes = [ctypes.c_uint32] * 4 + [_u32p] * 4 + [_u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                                                             _u8p, _u32p]
+        L.orc_batmap3_triple.restype = ctypes.c_uint64
+        L.orc_batmap3_triple.argtypes = [_u8p, ctypes.c_uint32] * 3 + [ctypes.c_uint32]
+        L.orc_batmap3_triples.restype = ctypes.c_uint64
+        L.orc_batmap3_triples.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _u32p] + [_u32p] * 4 + [
+            ctypes.c_uint32, ctypes.c_uint32, _u32p, ctypes.c_uint64, _u32p]
+        L.orc_batmap3_check.restype = ctypes.c_int
+        L.orc_batmap3_check.argtypes = [ctypes.c_uint32] * 4 + [ctypes.c_void_p, ctypes.c_void_p, _u32p,
+                                                                ctypes.c_uint32, _u32p, ctypes.c_uint32, _u8p]
         L.orc_batmap_check.restype = ctypes.c_int
         L.orc_batmap_check.argtypes = [ctypes.c_uint32] * 4 + [_u32p] * 6 + [_u32p, ctypes.c_uint32, _u32p,
                                                                              ctypes.c_uint32, _u8p]
@@ -283,3 +300,69 @@ def batmap_check(m: int, s: int, r0: int, r: int, perms, invs, set_tids, failed,
                                           failed, nf, np.ascontiguousarray(bytes_, dtype=np.uint8)))
     return int(lib().orc_batmap_check_w(m, s, r0, r, p[0], p[1], p[2], iv[0], iv[1], iv[2], set_tids, set_tids.size,
                                         failed, nf, slot_bits, np.ascontiguousarray(bytes_, dtype=np.uint8)))
+
+
+# ---- Part 4: itemsets of three (Sec. V) --------------------------------------
+
+def triples(offsets, tids, trip, threads: int = 1) -> np.ndarray:
+    """|S_a cap S_b cap S_c| for every row (a, b, c) of `trip` by a three-way merge (the definition)."""
+    off, t = _csr(offsets, tids)
+    trip = np.ascontiguousarray(trip, dtype=np.uint32).reshape(-1, 3)
+    out = np.zeros(max(trip.shape[0], 1), dtype=np.uint32)
+    if trip.shape[0]:
+        lib().orc_triples(off, t, trip.reshape(-1), trip.shape[0], out, threads)
+    return out[:trip.shape[0]]
+
+
+def shift3(m: int) -> int:
+    """s of order-3 maps (14-bit codes): min{s : m <= 2^14 2^s}."""
+    return int(lib().orc3_shift(m))
+
+
+def _ptrs(arrs):
+    keep = [np.ascontiguousarray(a, dtype=np.uint32) for a in arrs]
+    table = (ctypes.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
+    return table, keep
+
+
+def batmap3_build(m: int, r0: int, perms4, set_tids, max_loop: int = 64, r: int | None = None):
+    """One order-3 map: 4r slots of 16 bits (little-endian bytes), failed elements, r."""
+    s = shift3(m)
+    set_tids = np.ascontiguousarray(set_tids, dtype=np.uint32)
+    if r is None:
+        r = r_for(set_tids.size, r0)
+    out = np.zeros(8 * r, dtype=np.uint8)
+    failed = np.zeros(2 * set_tids.size + 1, dtype=np.uint32)
+    p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms4]
+    nf = lib().orc_batmap3_build(m, s, r0, r, p[0], p[1], p[2], p[3], set_tids, set_tids.size, max_loop, out, failed)
+    return out, failed[:nf].copy(), r
+
+
+def batmap3_triple(b0, r0w: int, b1, r1w: int, b2, r2w: int, r0: int) -> int:
+    """The order-3 counting rule over three maps (narrower ones wrap)."""
+    c = [np.ascontiguousarray(b, dtype=np.uint8) for b in (b0, b1, b2)]
+    return int(lib().orc_batmap3_triple(c[0], r0w, c[1], r1w, c[2], r2w, r0))
+
+
+def batmap3_triples(m: int, offsets, tids, perms4, r0: int, trip, max_loop: int = 64):
+    """The whole order-3 method for the triples `trip`: (supports, failed elements)."""
+    off, t = _csr(offsets, tids)
+    n = off.size - 1
+    trip = np.ascontiguousarray(trip, dtype=np.uint32).reshape(-1, 3)
+    out = np.zeros(max(trip.shape[0], 1), dtype=np.uint32)
+    p = [np.ascontiguousarray(x, dtype=np.uint32) for x in perms4]
+    nf = lib().orc_batmap3_triples(m, n, off, t, p[0], p[1], p[2], p[3], r0, max_loop, trip.reshape(-1),
+                                   trip.shape[0], out)
+    return out[:trip.shape[0]], int(nf)
+
+
+def batmap3_check(m: int, s: int, r0: int, r: int, perms4, invs4, set_tids, failed, bytes_) -> int:
+    pt, kp = _ptrs(perms4)
+    it, ki = _ptrs(invs4)
+    set_tids = np.ascontiguousarray(set_tids, dtype=np.uint32)
+    failed = np.ascontiguousarray(failed, dtype=np.uint32)
+    nf = failed.size
+    if nf == 0:
+        failed = np.zeros(1, dtype=np.uint32)
+    return int(lib().orc_batmap3_check(m, s, r0, r, pt, it, set_tids, set_tids.size, failed, nf,
+                                       np.ascontiguousarray(bytes_, dtype=np.uint8)))

@@ -30,6 +30,10 @@
  *     matrix multiplication and join-project), by definition and by the
  *     method with both families hashed by the same pi_t, s and r_0.
  *
+ * Part 4 counts itemsets of three (Sec. V): the three-way merge, and maps
+ * that store each element in three of four tables (reading C16 for their
+ * slots and counting rule).
+ *
  * Readings where the paper is silent or loose:
  *   C1 indicator bit = 1 on the copy whose other copy sits in the cyclically
  *      preceding table (Fig. 3);
@@ -742,4 +746,349 @@ uint64_t orc_batmap_cross(uint32_t m, uint32_t na, const uint64_t *offa, const u
         free(rs[f]);
     }
     return total;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Part 4: itemsets of three (Sec. V, maps storing each element in d of    */
+/* d + 1 places, here d = 3)                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Definition: support of {i, j, k} = |S_i cap S_j cap S_k|, by a three-way
+ * merge of the sorted lists.  triples: count x 3 item ids. */
+static uint64_t merge3(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb, const uint32_t *c, uint64_t nc)
+{
+    uint64_t i = 0, j = 0, k = 0, cnt = 0;
+    while (i < na && j < nb && k < nc) {
+        uint32_t x = a[i], y = b[j], z = c[k];
+        uint32_t hi = x > y ? (x > z ? x : z) : (y > z ? y : z);
+        if (x == hi && y == hi && z == hi) {
+            cnt++;
+            i++;
+            j++;
+            k++;
+            continue;
+        }
+        if (x < hi)
+            i++;
+        if (y < hi)
+            j++;
+        if (z < hi)
+            k++;
+    }
+    return cnt;
+}
+
+void orc_triples(const uint64_t *off, const uint32_t *tids, const uint32_t *triples, uint64_t count, uint32_t *out,
+                 int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) if (nthreads != 1)
+#endif
+    for (int64_t t = 0; t < (int64_t)count; t++) {
+        uint32_t a = triples[3 * t], b = triples[3 * t + 1], c = triples[3 * t + 2];
+        out[t] = (uint32_t)merge3(tids + off[a], off[a + 1] - off[a], tids + off[b], off[b + 1] - off[b],
+                                  tids + off[c], off[c + 1] - off[c]);
+    }
+    (void)nthreads;
+}
+
+/* Order-3 BatMaps.  Four tables A_0..A_3 of r slots, every element held in
+ * three of them, so any three sets holding x share at least one table where
+ * each has x at the same hashed position (Sec. V: "d out of d + 1 places").
+ * A slot is 16 bits: the element's code pi_t(x) >> s in the low 14 bits and,
+ * in the top 2, the table where the element is NOT held; a slot whose
+ * missing-table field equals its own table is empty (reading C16).  Counting
+ * rule (reading C16): a position of table t counts a triple when all three
+ * slots hold the same code and t is the smallest table none of the three
+ * misses, which happens for exactly one of the tables the three copies
+ * share.  s = min{s : m <= 2^14 2^s}; block layout of the hash functions as
+ * Fig. 4 with four tables: 4 r_0 floor(q / r_0) + t r_0 + q mod r_0. */
+#define ORC3_TABLES 4
+
+uint32_t orc3_shift(uint32_t m)
+{
+    uint32_t s = 0;
+    while ((uint64_t)m > ((uint64_t)1 << 14) << s)
+        s++;
+    return s;
+}
+
+typedef struct {
+    uint32_t m, s, r0, r;
+    const uint32_t *perm[ORC3_TABLES];
+    uint32_t *T; /* T[t * r + q] */
+} orc_map3;
+
+static uint32_t h3(const orc_map3 *B, int t, uint32_t x)
+{
+    return B->perm[t][x] & (B->r - 1);
+}
+
+/* INSERT over four tables: push tau through A_0, A_1, A_2, A_3, A_0, ...,
+ * swapping with the occupant, until an empty slot takes it or max_loop
+ * rounds end (the element left in hand is returned). */
+static uint32_t insert3(orc_map3 *B, uint32_t tau, uint32_t max_loop)
+{
+    for (uint32_t loop = 0; loop < max_loop; loop++) {
+        for (int t = 0; t < ORC3_TABLES; t++) {
+            uint32_t *slot = &B->T[(uint64_t)t * B->r + h3(B, t, tau)];
+            uint32_t tmp = *slot;
+            *slot = tau;
+            tau = tmp;
+            if (tau == ORC_EMPTY)
+                return ORC_EMPTY;
+        }
+    }
+    return tau;
+}
+
+static void delete_all3(orc_map3 *B, uint32_t x)
+{
+    for (int t = 0; t < ORC3_TABLES; t++) {
+        uint32_t *slot = &B->T[(uint64_t)t * B->r + h3(B, t, x)];
+        if (*slot == x)
+            *slot = ORC_EMPTY;
+    }
+}
+
+/* Every element inserted three times; a failing insertion removes the
+ * element (and re-inserts the nestless one, recording it as failed too if
+ * that fails), as the two-copy procedure of Sec. II-A (reading C8). */
+static void build_one3(orc_map3 *B, const uint32_t *set, uint32_t size, uint32_t max_loop, uint32_t *failed,
+                       uint32_t *n_failed)
+{
+    for (uint32_t k = 0; k < size; k++) {
+        uint32_t x = set[k];
+        for (int copy = 0; copy < 3; copy++) {
+            uint32_t tau = insert3(B, x, max_loop);
+            if (tau == ORC_EMPTY)
+                continue;
+            delete_all3(B, x);
+            failed[(*n_failed)++] = x;
+            if (tau != x) {
+                uint32_t z = insert3(B, tau, max_loop);
+                if (z != ORC_EMPTY) {
+                    delete_all3(B, z);
+                    failed[(*n_failed)++] = z;
+                }
+            }
+            break;
+        }
+    }
+}
+
+static uint64_t slot_of3(uint32_t r0, int t, uint32_t q)
+{
+    return (uint64_t)ORC3_TABLES * r0 * (q / r0) + (uint64_t)t * r0 + (q % r0);
+}
+
+/* Build one order-3 map: 4r slots of 16 bits (little-endian bytes). */
+uint32_t orc_batmap3_build(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *p0, const uint32_t *p1,
+                           const uint32_t *p2, const uint32_t *p3, const uint32_t *set, uint32_t size,
+                           uint32_t max_loop, uint8_t *bytes, uint32_t *failed)
+{
+    orc_map3 B;
+    B.m = m;
+    B.s = s;
+    B.r0 = r0;
+    B.r = r;
+    B.perm[0] = p0;
+    B.perm[1] = p1;
+    B.perm[2] = p2;
+    B.perm[3] = p3;
+    B.T = (uint32_t *)malloc((size_t)ORC3_TABLES * r * sizeof(uint32_t));
+    for (uint64_t v = 0; v < (uint64_t)ORC3_TABLES * r; v++)
+        B.T[v] = ORC_EMPTY;
+    uint32_t nf = 0;
+    build_one3(&B, set, size, max_loop, failed, &nf);
+    for (int t = 0; t < ORC3_TABLES; t++) {
+        for (uint32_t q = 0; q < r; q++) {
+            uint32_t x = B.T[(uint64_t)t * r + q];
+            uint32_t value = (uint32_t)t << 14; /* empty: the missing-table field names this table */
+            if (x != ORC_EMPTY) {
+                int miss = -1;
+                for (int u = 0; u < ORC3_TABLES; u++)
+                    if (B.T[(uint64_t)u * r + h3(&B, u, x)] != x)
+                        miss = u;
+                value = ((uint32_t)miss << 14) | (B.perm[t][x] >> s);
+            }
+            uint64_t v = slot_of3(r0, t, q);
+            bytes[2 * v] = (uint8_t)value;
+            bytes[2 * v + 1] = (uint8_t)(value >> 8);
+        }
+    }
+    free(B.T);
+    return nf;
+}
+
+/* The triple rule at every position of the widest map (the narrower maps
+ * wrap: their position v mod 4 r).  Maps are passed with their widths. */
+uint64_t orc_batmap3_triple(const uint8_t *b0, uint32_t r0w, const uint8_t *b1, uint32_t r1w, const uint8_t *b2,
+                            uint32_t r2w, uint32_t r0)
+{
+    const uint8_t *b[3] = {b0, b1, b2};
+    uint32_t rr[3] = {r0w, r1w, r2w};
+    uint32_t rmax = r0w > r1w ? (r0w > r2w ? r0w : r2w) : (r1w > r2w ? r1w : r2w);
+    uint64_t total = (uint64_t)ORC3_TABLES * rmax, c = 0;
+    for (uint64_t v = 0; v < total; v++) {
+        const int t = (int)((v % ((uint64_t)ORC3_TABLES * r0)) / r0);
+        uint32_t code[3], miss[3];
+        int occupied = 1;
+        for (int u = 0; u < 3; u++) {
+            uint64_t w = v % ((uint64_t)ORC3_TABLES * rr[u]);
+            uint32_t value = (uint32_t)b[u][2 * w] | ((uint32_t)b[u][2 * w + 1] << 8);
+            code[u] = value & 0x3FFFu;
+            miss[u] = value >> 14;
+            if (miss[u] == (uint32_t)t)
+                occupied = 0;
+        }
+        if (!occupied || code[0] != code[1] || code[0] != code[2])
+            continue;
+        int first_common = -1;
+        for (int u = 0; u < ORC3_TABLES && first_common < 0; u++)
+            if (miss[0] != (uint32_t)u && miss[1] != (uint32_t)u && miss[2] != (uint32_t)u)
+                first_common = u;
+        if (first_common == t)
+            c++;
+    }
+    return c;
+}
+
+/* The whole method for a list of triples: order-3 maps of every set that a
+ * triple names, the triple rule, then the Sec. III-C correction for the
+ * triple (one per shared element that failed in any of the three maps).
+ * perms: four permutations.  Returns the failed elements of all maps. */
+uint64_t orc_batmap3_triples(uint32_t m, uint32_t n, const uint64_t *off, const uint32_t *tids, const uint32_t *p0,
+                             const uint32_t *p1, const uint32_t *p2, const uint32_t *p3, uint32_t r0,
+                             uint32_t max_loop, const uint32_t *triples, uint64_t count, uint32_t *out)
+{
+    const uint32_t s = orc3_shift(m);
+    uint32_t *rs = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+    uint8_t **maps = (uint8_t **)calloc((size_t)n + 1, sizeof(uint8_t *));
+    uint32_t **fails = (uint32_t **)calloc((size_t)n + 1, sizeof(uint32_t *));
+    uint32_t *nfail = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+    uint64_t total = 0;
+    for (uint64_t t = 0; t < 3 * count; t++) {
+        uint32_t i = triples[t];
+        if (maps[i])
+            continue;
+        uint32_t size = (uint32_t)(off[i + 1] - off[i]);
+        rs[i] = orc_r_for(size, r0);
+        maps[i] = (uint8_t *)malloc((size_t)ORC3_TABLES * rs[i] * 2);
+        fails[i] = (uint32_t *)malloc(((size_t)2 * size + 1) * sizeof(uint32_t));
+        nfail[i] = orc_batmap3_build(m, s, r0, rs[i], p0, p1, p2, p3, tids + off[i], size, max_loop, maps[i],
+                                     fails[i]);
+        qsort(fails[i], nfail[i], sizeof(uint32_t), cmp_u32);
+        total += nfail[i];
+    }
+    for (uint64_t t = 0; t < count; t++) {
+        uint32_t a = triples[3 * t], b = triples[3 * t + 1], c = triples[3 * t + 2];
+        uint64_t v = orc_batmap3_triple(maps[a], rs[a], maps[b], rs[b], maps[c], rs[c], r0);
+        /* shared elements lost in any of the three maps */
+        const uint32_t *sa = tids + off[a], *sb = tids + off[b], *sc = tids + off[c];
+        uint64_t na = off[a + 1] - off[a], nb = off[b + 1] - off[b], nc = off[c + 1] - off[c];
+        for (uint64_t x = 0; x < na; x++) {
+            uint32_t e = sa[x];
+            if (!in_sorted(sb, (uint32_t)nb, e) || !in_sorted(sc, (uint32_t)nc, e))
+                continue;
+            if (in_sorted(fails[a], nfail[a], e) || in_sorted(fails[b], nfail[b], e) ||
+                in_sorted(fails[c], nfail[c], e))
+                v++;
+        }
+        out[t] = (uint32_t)v;
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        free(maps[i]);
+        free(fails[i]);
+    }
+    free(maps);
+    free(fails);
+    free(nfail);
+    free(rs);
+    return total;
+}
+
+/* Structural check of one order-3 map: every slot is empty (missing-table
+ * field = its table) or decodes to pi_t(x) of an element of S minus F whose
+ * missing-table field names the one table not holding it; every such x is
+ * held exactly three times, in three different tables; failed elements are
+ * absent.  Returns 0 when valid, else the number of the first violation. */
+int orc_batmap3_check(uint32_t m, uint32_t s, uint32_t r0, uint32_t r, const uint32_t *const *perm,
+                      const uint32_t *const *inv, const uint32_t *set, uint32_t size, const uint32_t *failed,
+                      uint32_t nfailed, const uint8_t *bytes)
+{
+    int rc = 0;
+    if (r < r0 || (r & (r - 1)) != 0 || (r0 & (r0 - 1)) != 0 || ((uint64_t)1 << s) > r0)
+        return 1;
+    uint8_t *in_set = (uint8_t *)calloc((size_t)m + 1, 1);
+    uint8_t *is_failed = (uint8_t *)calloc((size_t)m + 1, 1);
+    uint8_t *seen = (uint8_t *)calloc((size_t)m + 1, 1);
+    uint8_t *miss_of = (uint8_t *)calloc((size_t)m + 1, 1);
+    for (uint32_t k = 0; k < size; k++)
+        in_set[set[k]] = 1;
+    for (uint32_t k = 0; k < nfailed; k++) {
+        if (failed[k] >= m || !in_set[failed[k]]) {
+            rc = 2;
+            goto done;
+        }
+        is_failed[failed[k]] = 1;
+    }
+    for (uint64_t v = 0; v < (uint64_t)ORC3_TABLES * r; v++) {
+        uint32_t value = (uint32_t)bytes[2 * v] | ((uint32_t)bytes[2 * v + 1] << 8);
+        uint64_t blk = v / ((uint64_t)ORC3_TABLES * r0);
+        int t = (int)((v % ((uint64_t)ORC3_TABLES * r0)) / r0);
+        uint32_t q = (uint32_t)(blk * r0 + v % r0);
+        uint32_t miss = value >> 14, code = value & 0x3FFFu;
+        if (miss == (uint32_t)t)
+            continue;
+        uint64_t pi = ((uint64_t)code << s) | (q & ((1u << s) - 1u));
+        if (pi >= m || (pi & (r - 1)) != q) {
+            rc = 3;
+            goto done;
+        }
+        uint32_t x = inv[t][pi];
+        if (perm[t][x] != pi || !in_set[x] || is_failed[x]) {
+            rc = 5;
+            goto done;
+        }
+        if (seen[x] & (1u << t)) {
+            rc = 6;
+            goto done;
+        }
+        if (seen[x] && miss_of[x] != miss) {
+            rc = 10; /* the copies disagree on the missing table */
+            goto done;
+        }
+        seen[x] |= (uint8_t)(1u << t);
+        miss_of[x] = (uint8_t)miss;
+    }
+    for (uint32_t k = 0; k < size; k++) {
+        uint32_t x = set[k];
+        int copies = 0;
+        for (int t = 0; t < ORC3_TABLES; t++)
+            copies += (seen[x] >> t) & 1;
+        if (is_failed[x]) {
+            if (copies) {
+                rc = 7;
+                goto done;
+            }
+            continue;
+        }
+        if (copies != 3) {
+            rc = 8;
+            goto done;
+        }
+        if (seen[x] & (1u << miss_of[x])) {
+            rc = 9; /* the missing-table field names a table that holds x */
+            goto done;
+        }
+    }
+done:
+    free(in_set);
+    free(is_failed);
+    free(seen);
+    free(miss_of);
+    return rc;
 }

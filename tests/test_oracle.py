@@ -496,3 +496,99 @@ def test_batmap_cross_equals_definition(slot_bits, max_loop):
     np.testing.assert_array_equal(got, oracle.cross(oa, ta, ob, tb))
     if max_loop == 0:
         assert nfail == ta.size + tb.size
+
+
+# ---- itemsets of three (Sec. V: d of d + 1 places, d = 3) ----------------------
+
+def _perms4(m, seed):
+    rng = np.random.default_rng([seed, 0x4444])
+    return [rng.permutation(m).astype(np.uint32) for _ in range(4)]
+
+
+def _all_triples(n):
+    return np.array([(i, j, k) for i in range(n) for j in range(i + 1, n) for k in range(j + 1, n)],
+                    dtype=np.uint32).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_triples_equal_dense_product(seed):
+    rng = np.random.default_rng(900 + seed)
+    m = int(rng.integers(1, 200))
+    n = int(rng.integers(3, 12))
+    off, tids = random_instance(rng, m, n)
+    A = dense(m, off, tids)
+    T = _all_triples(n)
+    want = (A[T[:, 0]] * A[T[:, 1]] * A[T[:, 2]]).sum(axis=1)
+    np.testing.assert_array_equal(oracle.triples(off, tids, T), want.astype(np.uint32))
+    # a repeated item reduces to the pair, and to the set size
+    np.testing.assert_array_equal(oracle.triples(off, tids, np.array([[0, 0, 1], [2, 2, 2]], dtype=np.uint32)),
+                                  np.array([(A[0] * A[1]).sum(), A[2].sum()], dtype=np.uint32))
+
+
+def test_triples_closed_form():
+    """Sum over all triples i < j < k = sum over transactions of C(|T_b|, 3)."""
+    rng = np.random.default_rng(91)
+    m, n = 1500, 30
+    off, tids = random_instance(rng, m, n, 0.0, 0.3)
+    got = oracle.triples(off, tids, _all_triples(n), threads=0).astype(np.int64)
+    row_len = np.bincount(tids, minlength=m).astype(np.int64)
+    assert got.sum() == int((row_len * (row_len - 1) * (row_len - 2) // 6).sum())
+
+
+def test_order3_rule_counts_every_shared_element_once():
+    """Reading C16: three maps hold x in any of the four 3-of-4 table sets; at every table the
+    three share, the rule counts x only at the smallest such table: once in all 64 cases."""
+    r0 = r = 4
+    code = 0x155
+    for miss in np.ndindex(4, 4, 4):
+        maps = []
+        for u in range(3):
+            slots = np.array([(t << 14) for t in range(4) for _ in range(r)], dtype=np.uint16)  # all empty
+            for t in range(4):
+                if t != miss[u]:
+                    slots[t * r + 1] = (miss[u] << 14) | code       # x at hash value 1 of table t
+            maps.append(slots.view(np.uint8))
+        assert oracle.batmap3_triple(maps[0], r, maps[1], r, maps[2], r, r0) == 1, miss
+
+
+@pytest.mark.parametrize("seed,max_loop", [(0, 64), (1, 64), (2, 6), (3, 2), (4, 1), (5, 0)])
+def test_order3_method_equals_definition(seed, max_loop):
+    rng = np.random.default_rng(950 + seed)
+    m = int(rng.integers(100, 40_000))
+    n = int(rng.integers(3, 14))
+    off, tids = random_instance(rng, m, n, 0.0, 0.4)
+    perms = _perms4(m, seed)
+    r0 = max(4, 1 << oracle.shift3(m))
+    T = _all_triples(n)
+    got, nfail = oracle.batmap3_triples(m, off, tids, perms, r0, T, max_loop)
+    np.testing.assert_array_equal(got, oracle.triples(off, tids, T))
+    if max_loop == 0:
+        assert nfail == tids.size
+
+
+def test_order3_maps_pass_check_and_planted_mistakes_fail():
+    m = 20_000
+    rng = np.random.default_rng(97)
+    perms = _perms4(m, 3)
+    invs = oracle.inverse_perms(perms)
+    s = oracle.shift3(m)
+    r0 = max(4, 1 << s)
+    for size in (0, 1, 13, 400, 2048):
+        S = np.sort(rng.choice(m, size=size, replace=False)).astype(np.uint32)
+        for ml in (64, 1):
+            B, F, r = oracle.batmap3_build(m, r0, perms, S, ml)
+            assert oracle.batmap3_check(m, s, r0, r, perms, invs, S, F, B) == 0
+            slots = B.view(np.uint16)
+            own = np.repeat(np.tile(np.arange(4, dtype=np.uint16), r // r0), r0)   # table of each slot
+            occupied = np.nonzero((slots >> 14) != own)[0]
+            if not occupied.size:
+                continue
+            v = int(occupied[0])
+            t = int(own[v])
+            other_miss = next(u for u in range(4) if u != t and u != (slots[v] >> 14))
+            for planted in ((slots[v] & 0x3FFF) | (other_miss << 14),   # wrong missing table
+                            t << 14,                                     # one copy lost
+                            slots[v] ^ 0x2000):                          # top code bit
+                bad = slots.copy()
+                bad[v] = planted
+                assert oracle.batmap3_check(m, s, r0, r, perms, invs, S, F, bad.view(np.uint8)) != 0
