@@ -65,6 +65,11 @@ typedef struct {
                                every map has r_i >= 2^s with m <= 127 2^s; 16 or 32 keep 15 or 31 bits of
                                pi_t(x) (the paper's "uncompressed case"), so sparse sets get maps near 2|S_i|
                                slots; 0 picks the width with the least compare work for these set sizes */
+    uint32_t order;         /* 2 (default): the paper's maps, every element in 2 of 3 tables, for pairs;
+                               3: every element in 3 of 4 tables (Sec. V, "d out of d + 1 places"), so that
+                               any three sets share a witnessing position -- for bm_triple_supports only; such
+                               maps have 16-bit slots (14-bit code, 2-bit missing table) and generated
+                               permutations (perm must be NULL); slot_bits is ignored */
     uint32_t flags;         /* reserved, must be 0 */
 } bm_build_opts;
 
@@ -86,7 +91,7 @@ typedef struct {
     uint64_t n_failed;       /* failed insertions (Sec. III-C F_b entries) */
     uint64_t n_corrections;  /* +1 pair corrections derived from them */
     uint32_t slot_bits;      /* bits per slot of this index's BatMaps (8, 16 or 32) */
-    uint32_t reserved;
+    uint32_t order;          /* 2 or 3, as built (bm_build_opts.order) */
 } bm_index_stats;
 
 /* Per-phase device times of the last build and the last query on a context,
@@ -217,6 +222,16 @@ bm_status bm_cross_pair_supports(bm_index *a, bm_index *b, uint32_t *out, uint64
 bm_status bm_cross_pairs(bm_index *a, bm_index *b, uint32_t min_support, bm_pair *out, uint64_t capacity,
                          uint64_t *n_out);
 
+/* Itemsets of three (Sec. V): |S_a cap S_b cap S_c| for each of `count`
+ * triples (a, b, c) of distinct item ids, given as 3 * count uint32 (host or
+ * device); out (host or device) receives count uint32 in the same order.
+ * The index must be built with order 3.  Errors: BM_EINVAL for another
+ * order, a repeated item in a triple or an item without a BatMap, BM_ERANGE
+ * for an id >= n.  Every pair call (all pairs, frequent pairs, subsets,
+ * cross products, batches, the server) returns BM_EINVAL on an order-3
+ * index. */
+bm_status bm_triple_supports(bm_index *idx, const uint32_t *triples, uint64_t count, uint32_t *out);
+
 /* Pair supports among a subset of items (k distinct ids, host or device):
  * out (host or device) gets k(k-1)/2 entries, packed upper triangle in the
  * order given.  BM_EINVAL on a repeated id or an item without a BatMap,
@@ -307,9 +322,13 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
  *                          Sec. III-A (slot = indicator << 7 | pi_t(x) >> s,
  *                          empty slot 0x7F; with w-bit slots each slot is
  *                          w/8 bytes, little-endian, indicator in bit w-1,
- *                          empty slot 2^(w-1) - 1), concatenated in that order,
+ *                          empty slot 2^(w-1) - 1; order 3: 4 r_i slots of
+ *                          two bytes, little-endian, missing table in bits
+ *                          14-15, empty when it names the slot's own table),
+ *                          concatenated in that order,
  *   failed[2*n_failed]:    (item, tid) of every failed insertion,
- *   perms[3*m]:            pi_0, pi_1, pi_2.
+ *   perms[3*m]:            pi_0, pi_1, pi_2 (perms[4*m], with pi_3, for an
+ *                          index of order 3).
  * Any pointer may be NULL to skip that output. */
 bm_status bm_index_export(const bm_index *idx, uint32_t *sorted_items, uint32_t *r, uint8_t *bytes, uint32_t *failed,
                           uint32_t *perms);

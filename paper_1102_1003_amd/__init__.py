@@ -50,6 +50,7 @@ class bm_build_opts(ctypes.Structure):
         ("min_support", ctypes.c_uint32),
         ("perm", ctypes.c_void_p * 3),
         ("slot_bits", ctypes.c_uint32),
+        ("order", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
     ]
 
@@ -64,7 +65,7 @@ class bm_index_stats(ctypes.Structure):
         ("max_loop", ctypes.c_uint32), ("n_classes", ctypes.c_uint32), ("n_built", ctypes.c_uint32),
         ("min_support", ctypes.c_uint32), ("nnz", ctypes.c_uint64), ("batmap_bytes", ctypes.c_uint64),
         ("n_failed", ctypes.c_uint64), ("n_corrections", ctypes.c_uint64),
-        ("slot_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("slot_bits", ctypes.c_uint32), ("order", ctypes.c_uint32),
     ]
 
 
@@ -158,6 +159,8 @@ def load_library(path: str = LIB_PATH):
     L.bm_cross_pair_supports.argtypes = [vp, vp, vp, u64]
     L.bm_cross_pairs.restype = i32
     L.bm_cross_pairs.argtypes = [vp, vp, u32, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
+    L.bm_triple_supports.restype = i32
+    L.bm_triple_supports.argtypes = [vp, vp, u64, vp]
     L.bm_subset_pair_supports.restype = i32
     L.bm_subset_pair_supports.argtypes = [vp, vp, u32, vp]
     L.bm_batch_all_pair_supports.restype = i32
@@ -301,13 +304,14 @@ class Context:
 
 
 def build_opts(seed: int = 0x5EED, max_loop: int = 64, min_support: int = 0, perms=None,
-               slot_bits: int = 8) -> bm_build_opts:
+               slot_bits: int = 8, order: int = 2) -> bm_build_opts:
     o = bm_build_opts()
     load_library().bm_build_opts_init(ctypes.byref(o))
     o.seed = seed
     o.max_loop = max_loop
     o.min_support = min_support
     o.slot_bits = slot_bits
+    o.order = order
     if perms is not None:
         for t in range(3):
             o.perm[t] = _ptr(perms[t])
@@ -402,6 +406,17 @@ class Index:
             arr = np.frombuffer(buf, dtype=np.uint32, count=3 * k).reshape(k, 3).copy()
             return arr
 
+    def triple_supports(self, triples, out=None):
+        """bm_triple_supports: |S_a cap S_b cap S_c| per row of `triples` (count x 3 item ids, host
+        array or device tensor); an index of order 3."""
+        if isinstance(triples, (list, tuple, np.ndarray)):
+            triples = np.ascontiguousarray(triples, dtype=np.uint32).reshape(-1, 3)
+        count = _numel(triples) // 3
+        if out is None:
+            out = np.zeros(max(count, 1), dtype=np.uint32)
+        self.ctx.check(load_library().bm_triple_supports(self._h, _ptr(triples), count, _ptr(out)))
+        return out[:count] if isinstance(out, np.ndarray) else out
+
     def subset_pair_supports(self, items, out=None):
         items = np.ascontiguousarray(items, dtype=np.uint32) if isinstance(items, (list, tuple, np.ndarray)) else items
         k = _numel(items)
@@ -418,7 +433,8 @@ class Index:
         r = np.zeros(max(nb, 1), dtype=np.uint32)
         b = np.zeros(max(st["batmap_bytes"], 1), dtype=np.uint8)
         failed = np.zeros(max(2 * st["n_failed"], 2), dtype=np.uint32)
-        perms = np.zeros(3 * self.m, dtype=np.uint32)
+        tables = 4 if st["order"] == 3 else 3
+        perms = np.zeros(tables * self.m, dtype=np.uint32)
         self.ctx.check(load_library().bm_index_export(self._h, _ptr(sorted_items), _ptr(r), _ptr(b), _ptr(failed),
                                                       _ptr(perms)))
         return {
@@ -427,7 +443,7 @@ class Index:
             "r": r[:nb],
             "bytes": b[:st["batmap_bytes"]],
             "failed": failed[:2 * st["n_failed"]].reshape(-1, 2),
-            "perms": perms.reshape(3, self.m),
+            "perms": perms.reshape(tables, self.m),
         }
 
     def close(self):

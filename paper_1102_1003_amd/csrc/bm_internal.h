@@ -60,7 +60,8 @@ inline InstDesc packed_desc(const uint32_t *arena, const uint64_t *goff, const u
     return d;
 }
 
-// The three permutations pi_t of [0, m) (Sec. III-A).  Either a table of 3m
+// The permutations pi_t of [0, m) (Sec. III-A): three for the paper's maps,
+// four for maps of itemsets of three (Sec. V).  Either a table of 3m
 // values given by the caller, or a keyed bijection evaluated on the fly: on
 // [0, 2^b) it is a chain of invertible steps (odd multiply, add, xor with a
 // right shift), and cycle walking (Black and Rogaway, "Ciphers with arbitrary
@@ -70,8 +71,8 @@ struct PermSpec {
     const uint32_t *table;      // pi_t(x) = table[t m + x] when not null
     const uint32_t *inv_table;  // pi_t^-1(y) = inv_table[t m + y] (with table), when not null
     uint32_t m, mask, h1, h2;
-    uint32_t mul1[3], add1[3], mul2[3], mul3[3], add3[3];
-    uint32_t inv1[3], inv2[3], inv3[3];  // inverses of the multipliers mod 2^32
+    uint32_t mul1[4], add1[4], mul2[4], mul3[4], add3[4];
+    uint32_t inv1[4], inv2[4], inv3[4];  // inverses of the multipliers mod 2^32
 };
 
 __host__ __device__ inline uint32_t perm_chain(const PermSpec &P, int t, uint32_t v)
@@ -103,22 +104,21 @@ __device__ inline uint32_t perm_eval_lane(const PermSpec &P, int t, uint32_t x)
         return P.table[(uint64_t)t * P.m + x];
     // the keys as scalars first: a select between loads would otherwise be
     // turned into a per-lane load from the argument block
-    auto pick = [t](uint32_t a, uint32_t b, uint32_t c) {
-        a = __builtin_amdgcn_readfirstlane(a);
-        b = __builtin_amdgcn_readfirstlane(b);
-        c = __builtin_amdgcn_readfirstlane(c);
-        return t == 0 ? a : (t == 1 ? b : c);
+    auto pick = [t](const uint32_t (&k)[4]) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(k[0]), b = __builtin_amdgcn_readfirstlane(k[1]);
+        const uint32_t c = __builtin_amdgcn_readfirstlane(k[2]), d = __builtin_amdgcn_readfirstlane(k[3]);
+        return t == 0 ? a : (t == 1 ? b : (t == 2 ? c : d));
     };
     PermSpec Q;
     Q.m = P.m;
     Q.mask = P.mask;
     Q.h1 = P.h1;
     Q.h2 = P.h2;
-    Q.mul1[0] = pick(P.mul1[0], P.mul1[1], P.mul1[2]);
-    Q.add1[0] = pick(P.add1[0], P.add1[1], P.add1[2]);
-    Q.mul2[0] = pick(P.mul2[0], P.mul2[1], P.mul2[2]);
-    Q.mul3[0] = pick(P.mul3[0], P.mul3[1], P.mul3[2]);
-    Q.add3[0] = pick(P.add3[0], P.add3[1], P.add3[2]);
+    Q.mul1[0] = pick(P.mul1);
+    Q.add1[0] = pick(P.add1);
+    Q.mul2[0] = pick(P.mul2);
+    Q.mul3[0] = pick(P.mul3);
+    Q.add3[0] = pick(P.add3);
     uint32_t y = perm_chain(Q, 0, x);
     while (y >= Q.m)
         y = perm_chain(Q, 0, y);
@@ -133,15 +133,14 @@ __device__ inline uint32_t perm_inverse_lane(const PermSpec &P, int t, uint32_t 
 {
     if (P.table)
         return P.inv_table[(uint64_t)t * P.m + y];
-    auto pick = [t](uint32_t a, uint32_t b, uint32_t c) {
-        a = __builtin_amdgcn_readfirstlane(a);
-        b = __builtin_amdgcn_readfirstlane(b);
-        c = __builtin_amdgcn_readfirstlane(c);
-        return t == 0 ? a : (t == 1 ? b : c);
+    auto pick = [t](const uint32_t (&k)[4]) {
+        const uint32_t a = __builtin_amdgcn_readfirstlane(k[0]), b = __builtin_amdgcn_readfirstlane(k[1]);
+        const uint32_t c = __builtin_amdgcn_readfirstlane(k[2]), d = __builtin_amdgcn_readfirstlane(k[3]);
+        return t == 0 ? a : (t == 1 ? b : (t == 2 ? c : d));
     };
-    const uint32_t add1 = pick(P.add1[0], P.add1[1], P.add1[2]), add3 = pick(P.add3[0], P.add3[1], P.add3[2]);
-    const uint32_t inv1 = pick(P.inv1[0], P.inv1[1], P.inv1[2]), inv2 = pick(P.inv2[0], P.inv2[1], P.inv2[2]);
-    const uint32_t inv3 = pick(P.inv3[0], P.inv3[1], P.inv3[2]);
+    const uint32_t add1 = pick(P.add1), add3 = pick(P.add3);
+    const uint32_t inv1 = pick(P.inv1), inv2 = pick(P.inv2);
+    const uint32_t inv3 = pick(P.inv3);
     const uint32_t mask = P.mask, h1 = P.h1, h2 = P.h2;
     uint32_t v = y;
     do {
@@ -208,7 +207,7 @@ hipError_t launch_validate_sets(const uint64_t *off, const uint32_t *tids, uint3
 
 // Construction.
 // Materialises pi_0, pi_1, pi_2 into out[3m].
-hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s);
+hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s, uint32_t tables = 3);
 hipError_t launch_check_perms(const uint32_t *pi, uint32_t m, uint32_t *bits, uint32_t *flag, hipStream_t s);
 hipError_t launch_size_keys(const uint64_t *off, uint32_t n, uint32_t *keys, uint32_t *vals, hipStream_t s);
 // Size order (ascending size, ties by id) of n <= kSmallSortMax maps in one
@@ -324,4 +323,33 @@ uint32_t dense_row_pad();
 hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t k_len, uint32_t *out,
                              uint32_t k_split, hipStream_t s);
 
+}  // namespace bm
+
+namespace bm {
+// Maps of order 3 (itemsets of three, Sec. V): layout, insertion, failure
+// resolution and 16-bit slot encoding of a construction batch, and the
+// triple queries over them.
+hipError_t launch_layout3(const uint32_t *sorted_items, const uint64_t *off, uint32_t n, uint32_t first_built,
+                          uint32_t r0, uint32_t *r_sorted, uint32_t *gcount, hipStream_t s);
+hipError_t launch_insert3(const uint32_t *tids, const uint64_t *off, const uint32_t *sorted_items,
+                          const uint32_t *r_sorted, const uint64_t *goff, const uint64_t *ebase, BuildBatch b,
+                          uint64_t n_elems, const PermSpec &P, uint32_t max_loop, uint32_t *stage, uint32_t *cand,
+                          uint32_t cand_cap, uint32_t *cand_count, hipStream_t s);
+hipError_t launch_resolve3(const uint32_t *cand, const uint32_t *count, uint32_t cap, const uint32_t *tids,
+                           const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                           const uint64_t *goff, BuildBatch b, const PermSpec &P, uint32_t *stage,
+                           uint32_t *failed_bits, uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap,
+                           uint32_t *max_count, hipStream_t s);
+hipError_t launch_encode3(const uint32_t *stage, const uint32_t *r_sorted, const uint64_t *goff, BuildBatch b,
+                          uint64_t n_groups, const PermSpec &P, uint32_t shift, uint32_t r0, uint32_t *arena,
+                          hipStream_t s);
+hipError_t launch_check_triples(const uint32_t *triples, uint64_t count, uint32_t n, const int32_t *sorted_pos,
+                                uint32_t *flag, hipStream_t s);
+hipError_t launch_triple_compare(const uint32_t *triples, uint64_t count, const int32_t *sorted_pos,
+                                 const uint64_t *goff, const uint32_t *r_sorted, const uint32_t *arena, uint32_t r0,
+                                 uint32_t *out, hipStream_t s);
+hipError_t launch_triple_corrections(const uint32_t *triples, uint64_t count, const uint64_t *off,
+                                     const uint32_t *tids, const uint32_t *failed_bits, const uint64_t *fail_off,
+                                     const uint32_t *fail_tids, uint32_t *out, hipStream_t s);
+hipError_t launch_decode3(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
 }  // namespace bm

@@ -352,6 +352,7 @@ struct bm_index {
     uint64_t nnz = 0;
     uint32_t first_built = 0;  // sorted indices below this have no BatMap
     uint32_t planes = 8;       // bits per slot = bit planes per group of 32 slots
+    uint32_t order = 2;        // 2: the paper's 2-of-3 maps; 3: 3-of-4 maps for itemsets of three
     uint64_t total_groups = 0, n_failed = 0, n_corr = 0;
 
     DevBuf<uint64_t> off;
@@ -389,6 +390,9 @@ struct bm_index {
     DevBuf<uint32_t> sub_items, sub_flag, sub_outpos, sub_out;
     DevBuf<uint64_t> sub_goff;
     DevBuf<WorkItem> sub_work;
+    // order 3: each item's failed tids, sorted (CSR over item ids)
+    DevBuf<uint64_t> fail_off;
+    DevBuf<uint32_t> fail_tids;
     // two-family products with this index as the first family
     DevBuf<uint64_t> x_goff;
     DevBuf<uint32_t> x_outpos, x_out;
@@ -458,6 +462,14 @@ bm_status fail(bm_context *ctx, bm_status code, const char *fmt, ...)
 
 
 // BM_COMPARE_VARIANT=<v> pins every class pair to tile shape v (tuning aid).
+// Pair queries need the paper's 2-of-3 maps.
+bm_status need_pairs(bm_index *idx)
+{
+    if (idx->order != 2)
+        return fail(idx->ctx, BM_EINVAL, "the index holds maps of order 3 (itemsets of three): use bm_triple_supports");
+    return BM_OK;
+}
+
 int forced_variant()
 {
     const char *e = getenv("BM_COMPARE_VARIANT");
@@ -793,9 +805,13 @@ bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
         return fail(ctx, BM_EINVAL, "bm_build_opts.flags must be 0");
     if (o->slot_bits != 0 && o->slot_bits != 8 && o->slot_bits != 16 && o->slot_bits != 32)
         return fail(ctx, BM_EINVAL, "bm_build_opts.slot_bits must be 0, 8, 16 or 32");
+    if (o->order != 0 && o->order != 2 && o->order != 3)
+        return fail(ctx, BM_EINVAL, "bm_build_opts.order must be 2 or 3 (0 means 2)");
     int given = (o->perm[0] != nullptr) + (o->perm[1] != nullptr) + (o->perm[2] != nullptr);
     if (given != 0 && given != 3)
         return fail(ctx, BM_EINVAL, "give all three permutations or none");
+    if (o->order == 3 && given)
+        return fail(ctx, BM_EINVAL, "maps of order 3 use generated permutations (perm must be NULL)");
     return BM_OK;
 }
 
@@ -809,12 +825,23 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // Sec. III-A parameters for w-bit slots (reading: the all-ones code is
     // the empty slot, 127 for the paper's bytes); w chosen by the sizes when
     // the caller leaves it to the library
-    const uint32_t w = o->slot_bits ? o->slot_bits : choose_slot_bits(idx->h_off, m, o->min_support);
+    // Maps of order 3 (Sec. V) hold 16-bit slots of a 14-bit code and a
+    // missing-table field: s = min{s : m <= 2^14 2^s}, four tables.
+    idx->order = o->order == 3 ? 3 : 2;
+    const bool order3 = idx->order == 3;
+    const uint32_t w = order3 ? 16 : (o->slot_bits ? o->slot_bits : choose_slot_bits(idx->h_off, m, o->min_support));
     idx->planes = w;
-    uint32_t shift = slot_shift(m, w);
+    uint32_t shift = 0;
+    if (order3) {
+        while ((uint64_t)m > (1ull << 14) << shift)
+            shift++;
+    } else {
+        shift = slot_shift(m, w);
+    }
     idx->shift = shift;
     idx->r0 = std::max<uint32_t>(kMinR0, 1u << shift);
-    idx->gb = 3 * idx->r0 / kSlotsPerGroup;
+    const uint32_t tables = order3 ? 4 : 3;
+    idx->gb = tables * idx->r0 / kSlotsPerGroup;
     idx->max_loop = o->max_loop;
     idx->min_support = o->min_support;
 
@@ -882,8 +909,12 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     HIPC(ctx, gcount.alloc((uint64_t)n + 1));
     HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
     HIPC(ctx, gtmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
-    HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
-                                gcount.p, s));
+    if (order3)
+        HIPC(ctx, launch_layout3(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                 gcount.p, s));
+    else
+        HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                    gcount.p, s));
     HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, gtmp.p, s));
     // sorted_pos: item -> sorted index (or -1 when unbuilt); has_map for the
     // corrections
@@ -946,8 +977,8 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // in LDS, one launch per width; the rest go through staging in batches.
     // BM_LDS_BUILD=0 turns the LDS path off.
     const char *lds_env = getenv("BM_LDS_BUILD");
-    const bool lds_on = !(lds_env && atoi(lds_env) == 0) && idx->planes == 8;
-    auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / 3); };
+    const bool lds_on = !(lds_env && atoi(lds_env) == 0) && idx->planes == 8 && !order3;
+    auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / tables); };
     uint32_t p_lds = first_built;
     while (lds_on && p_lds < n && lds_build_field_bits(width_of(p_lds), m) != 0)
         p_lds++;
@@ -1027,16 +1058,29 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
                 Span span_construct(ctx, PH_CONSTRUCT);
                 HIPC(ctx, fill_u32(stage.p, b.groups * kSlotsPerGroup, kEmpty, s));
                 HIPC(ctx, fill_u32(counters.p, 1, 0, s));
-                HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
-                                        ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop, stage.p, cand.p,
-                                        (uint32_t)cand_cap, counters.p, s));
-                HIPC(ctx, launch_resolve(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
-                                         idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm, stage.p,
-                                         failed_bits.p, idx->failed.p, counters.p + 1, (uint32_t)fail_cap,
-                                         counters.p + 2, s));
+                if (order3) {
+                    HIPC(ctx, launch_insert3(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
+                                             idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
+                                             stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
+                    HIPC(ctx, launch_resolve3(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
+                                              idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
+                                              stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
+                                              (uint32_t)fail_cap, counters.p + 2, s));
+                } else {
+                    HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
+                                            idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
+                                            stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
+                    HIPC(ctx, launch_resolve(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
+                                             idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
+                                             stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
+                                             (uint32_t)fail_cap, counters.p + 2, s));
+                }
             }
             Span span_encode(ctx, PH_ENCODE);
-            if (idx->planes == 8)
+            if (order3)
+                HIPC(ctx, launch_encode3(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                         idx->r0, idx->arena.p, s));
+            else if (idx->planes == 8)
                 HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
                                         idx->r0, codes.p, idx->arena.p, s));
             else
@@ -1050,7 +1094,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         // upload it on the host while the construction kernels run (indexes of
         // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
         // and planning all their pairs takes longer than building them)
-        if (attempt == 0 && n - idx->first_built <= kPlanAtBuild) {
+        if (attempt == 0 && !order3 && n - idx->first_built <= kPlanAtBuild) {
             st = ensure_plan(idx, idx->first_built);
             if (st != BM_OK)
                 return st;
@@ -1084,6 +1128,32 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     codes.reset();
     cand.reset();
     idx->n_failed = n_failed_total;
+
+    // order 3: the failed tids of each item, for the per-triple corrections
+    if (order3) {
+        Span span_correct(ctx, PH_CORRECT);
+        idx->n_corr = 0;
+        std::vector<uint32_t> h_failed(2 * idx->n_failed);
+        if (idx->n_failed)
+            BMC(read_back(ctx, h_failed.data(), idx->failed.p, idx->n_failed * 8));
+        std::vector<uint64_t> h_fo((size_t)n + 1, 0);
+        for (uint64_t f = 0; f < idx->n_failed; f++)
+            h_fo[h_failed[2 * f] + 1]++;
+        for (uint32_t i = 0; i < n; i++)
+            h_fo[i + 1] += h_fo[i];
+        std::vector<uint32_t> h_ft(std::max<uint64_t>(idx->n_failed, 1));
+        std::vector<uint64_t> at(h_fo.begin(), h_fo.end() - 1);
+        for (uint64_t f = 0; f < idx->n_failed; f++)
+            h_ft[at[h_failed[2 * f]]++] = h_failed[2 * f + 1];
+        for (uint32_t i = 0; i < n; i++)
+            std::sort(h_ft.begin() + (int64_t)h_fo[i], h_ft.begin() + (int64_t)h_fo[i + 1]);
+        HIPC(ctx, idx->fail_off.alloc((uint64_t)n + 1));
+        HIPC(ctx, idx->fail_tids.alloc(h_ft.size()));
+        BMC(upload(ctx, idx->fail_off.p, h_fo.data(), ((uint64_t)n + 1) * 8));
+        BMC(upload(ctx, idx->fail_tids.p, h_ft.data(), h_ft.size() * 4));
+        HIPC(ctx, idx->corr.alloc(2));
+        return BM_OK;
+    }
 
     // corrections (Sec. III-C).  One pass into a list sized for the usual
     // count (a failure pairs with the few maps whose sets hold its
@@ -1288,6 +1358,7 @@ void bm_build_opts_init(bm_build_opts *o)
     o->max_loop = 64;
     o->min_support = 0;
     o->slot_bits = 8;
+    o->order = 2;
 }
 
 bm_status bm_context_create(int device, void *hip_stream, bm_context **out)
@@ -1735,6 +1806,7 @@ bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
     out->n_failed = idx->n_failed;
     out->n_corrections = idx->n_corr;
     out->slot_bits = idx->planes;
+    out->order = idx->order;
     return BM_OK;
 }
 
@@ -1766,6 +1838,7 @@ bm_status bm_all_pair_supports(bm_index *idx, uint32_t *out, uint64_t out_len)
     if (out_len < np)
         return fail(ctx, BM_ECAPACITY, "out holds %llu entries, %llu needed", (unsigned long long)out_len,
                     (unsigned long long)np);
+    BMC(need_pairs(idx));
     if (idx->first_built != 0)
         return fail(ctx, BM_EINVAL, "index built with min_support > 0 has no BatMap for some items");
     HIPC(ctx, hipSetDevice(ctx->device));
@@ -1796,6 +1869,7 @@ bm_status bm_frequent_pairs(bm_index *idx, uint32_t min_support, bm_pair *out, u
     if (!n_out)
         return fail(ctx, BM_EINVAL, "n_out is null");
     *n_out = 0;
+    BMC(need_pairs(idx));
     if (min_support < idx->min_support)
         return fail(ctx, BM_EINVAL, "min_support %u is below the build's %u", min_support, idx->min_support);
     uint64_t np = n_pairs(idx->n);
@@ -1864,6 +1938,7 @@ bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair
     if (!n_out)
         return fail(ctx, BM_EINVAL, "n_out is null");
     *n_out = 0;
+    BMC(need_pairs(idx));
     if (min_support < idx->min_support)
         return fail(ctx, BM_EINVAL, "min_support %u is below the build's %u", min_support, idx->min_support);
     const uint64_t np = n_pairs(idx->n);
@@ -1933,6 +2008,80 @@ bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair
     return BM_OK;
 }
 
+bm_status bm_triple_supports(bm_index *idx, const uint32_t *triples, uint64_t count, uint32_t *out)
+{
+    if (!idx)
+        return BM_EINVAL;
+    bm_context *ctx = idx->ctx;
+    ctx->err.clear();
+    AllocScope scope(ctx->as);
+    begin_query(ctx);
+    if (idx->order != 3)
+        return fail(ctx, BM_EINVAL, "itemsets of three need an index of order 3 (bm_build_opts.order = 3)");
+    if (count == 0)
+        return BM_OK;
+    if (!triples || !out)
+        return fail(ctx, BM_EINVAL, "null pointer");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    DevBuf<uint32_t> tri, flag, res;
+    const uint32_t *d_tri = triples;
+    double slot_triples = 0;
+    if (ptr_kind(triples) != PTR_DEVICE) {
+        // the compare's work, for the phase timings: 4 max(r) slots per triple
+        for (uint64_t t = 0; t < count; t++) {
+            uint32_t r = 0;
+            for (int u = 0; u < 3; u++) {
+                const uint32_t it = triples[3 * t + u];
+                if (it < idx->n) {
+                    const uint64_t sz = idx->h_off[it + 1] - idx->h_off[it];
+                    uint64_t rr = 1;
+                    while (rr < 2 * sz)
+                        rr <<= 1;
+                    r = std::max<uint32_t>(r, (uint32_t)std::max<uint64_t>(rr, idx->r0));
+                }
+            }
+            slot_triples += 4.0 * r;
+        }
+        HIPC(ctx, tri.alloc(3 * count));
+        BMC(upload(ctx, tri.p, triples, 12 * count));
+        d_tri = tri.p;
+    }
+    HIPC(ctx, flag.alloc(1));
+    HIPC(ctx, fill_u32(flag.p, 1, 0, s));
+    HIPC(ctx, launch_check_triples(d_tri, count, idx->n, idx->sorted_pos.p, flag.p, s));
+    uint32_t fl = 0;
+    BMC(read_back(ctx, &fl, flag.p, 4));
+    if (fl & 1u)
+        return fail(ctx, BM_ERANGE, "an item id >= n");
+    if (fl & 2u)
+        return fail(ctx, BM_EINVAL, "a triple repeats an item");
+    if (fl & 4u)
+        return fail(ctx, BM_EINVAL, "an item of a triple has no BatMap (pruned at build)");
+    const bool host = ptr_kind(out) == PTR_HOST;
+    uint32_t *dst = out;
+    if (host) {
+        HIPC(ctx, res.alloc(count));
+        dst = res.p;
+    }
+    ctx->slot_pairs = slot_triples;
+    {
+        Span sp(ctx, PH_COMPARE);
+        HIPC(ctx, launch_triple_compare(d_tri, count, idx->sorted_pos.p, idx->goff.p, idx->r_sorted.p, idx->arena.p,
+                                        idx->r0, dst, s));
+    }
+    {
+        Span sp(ctx, PH_APPLY);
+        HIPC(ctx, launch_triple_corrections(d_tri, count, idx->off.p, idx->tids.p, idx->failed_bits.p,
+                                            idx->fail_off.p, idx->fail_tids.p, dst, s));
+    }
+    if (host) {
+        BMC(download(ctx, out, dst, 4 * count));
+        HIPC(ctx, hipStreamSynchronize(s));
+    }
+    return BM_OK;
+}
+
 bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t k, uint32_t *out)
 {
     if (!idx)
@@ -1942,6 +2091,7 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     AllocScope scope(ctx->as);
     begin_query(ctx);
     uint64_t np = n_pairs(k);
+    BMC(need_pairs(idx));
     if (k == 0)
         return BM_OK;
     if (!items || (np && !out))
@@ -2084,9 +2234,9 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
             return fail(ctx, BM_EINVAL, "index %u is null or belongs to another context", q);
         if (idx->first_built != 0)
             return fail(ctx, BM_EINVAL, "index %u was built with min_support > 0", q);
-        if (idx->planes != 8)
-            return fail(ctx, BM_EINVAL, "index %u has %u-bit slots; the single launch compares 8-bit slots", q,
-                        idx->planes);
+        if (idx->planes != 8 || idx->order != 2)
+            return fail(ctx, BM_EINVAL, "index %u has %u-bit slots or order-3 maps; the single launch compares "
+                        "the paper's 8-bit 2-of-3 maps", q, idx->planes);
         if (n_pairs(idx->n) && !outs[q])
             return fail(ctx, BM_EINVAL, "outs[%u] is null", q);
         if (n_pairs(idx->n) && ptr_kind(outs[q]) != PTR_DEVICE)
@@ -2331,6 +2481,8 @@ bm_status check_cross(bm_index *a, bm_index *b)
     bm_context *ctx = a->ctx;
     if (b->ctx != ctx)
         return fail(ctx, BM_EINVAL, "the two indexes belong to different contexts");
+    BMC(need_pairs(a));
+    BMC(need_pairs(b));
     if (a->first_built != 0 || b->first_built != 0)
         return fail(ctx, BM_EINVAL, "an index built with min_support > 0 has no BatMap for some items");
     if (a->planes != b->planes)
@@ -2519,7 +2671,10 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
         DevBuf<uint8_t> tmp;
         const uint64_t nbytes = idx->total_groups * kSlotsPerGroup * idx->planes / 8;
         HIPC(ctx, tmp.alloc(nbytes));
-        HIPC(ctx, launch_decode(idx->arena.p, idx->total_groups, tmp.p, ctx->stream, idx->planes));
+        if (idx->order == 3)
+            HIPC(ctx, launch_decode3(idx->arena.p, idx->total_groups, tmp.p, ctx->stream));
+        else
+            HIPC(ctx, launch_decode(idx->arena.p, idx->total_groups, tmp.p, ctx->stream, idx->planes));
         bm_status st = download(ctx, bytes, tmp.p, nbytes);
         if (st != BM_OK)
             return st;
@@ -2532,12 +2687,13 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
     if (perms) {
         DevBuf<uint32_t> tmp;
         const uint32_t *src = idx->pi.p;
+        const uint32_t tables = idx->order == 3 ? 4 : 3;
         if (!src) {
-            HIPC(ctx, tmp.alloc(3ull * idx->m));
-            HIPC(ctx, launch_gen_perms(idx->perm, tmp.p, ctx->stream));
+            HIPC(ctx, tmp.alloc((uint64_t)tables * idx->m));
+            HIPC(ctx, launch_gen_perms(idx->perm, tmp.p, ctx->stream, tables));
             src = tmp.p;
         }
-        bm_status st = read_back(ctx, perms, src, 3ull * idx->m * 4);
+        bm_status st = download(ctx, perms, src, (uint64_t)tables * idx->m * 4);
         if (st != BM_OK)
             return st;
     }
@@ -2909,9 +3065,9 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
     if (o.streams == 0 || o.streams > 16 || o.max_batch == 0 || o.max_batch > 65535 || o.memory_budget < 4096 ||
         o.flags != 0)
         return fail(ctx, BM_EINVAL, "bad server options");
-    if (idx->planes != 8)
-        return fail(ctx, BM_EINVAL, "the server's launches compare 8-bit slots; this index has %u-bit slots",
-                    idx->planes);
+    if (idx->planes != 8 || idx->order != 2)
+        return fail(ctx, BM_EINVAL, "the server's launches compare the paper's 8-bit 2-of-3 maps; this index has "
+                    "%u-bit slots or order-3 maps", idx->planes);
     HIPC(ctx, hipSetDevice(idx->device));
     std::unique_ptr<bm_server> srv(new (std::nothrow) bm_server());
     if (!srv)

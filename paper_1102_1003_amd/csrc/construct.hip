@@ -44,13 +44,12 @@ uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 22)
 
 // --------------------------------------------------------------- permutations
 
-__global__ void gen_perms_kernel(PermSpec P, uint32_t *out)
+__global__ void gen_perms_kernel(PermSpec P, uint32_t tables, uint32_t *out)
 {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.m; x += stride)
-#pragma unroll
-        for (int t = 0; t < 3; t++)
-            out[(uint64_t)t * P.m + x] = perm_eval(P, t, (uint32_t)x);
+        for (uint32_t t = 0; t < tables; t++)
+            out[(uint64_t)t * P.m + x] = perm_eval(P, (int)t, (uint32_t)x);
 }
 
 // Each value must hit a distinct slot of a bitmap: flag on a repeat or out of range.
@@ -989,7 +988,8 @@ PermSpec make_perm_spec(uint32_t m, uint64_t seed)
             x *= 2u - a * x;
         return x;
     };
-    for (int t = 0; t < 3; t++) {
+    // keys of pi_0 .. pi_2 first (the paper's maps), then pi_3 (order-3 maps)
+    for (int t = 0; t < 4; t++) {
         P.mul1[t] = ((uint32_t)next() & P.mask) | 1u;
         P.add1[t] = (uint32_t)next() & P.mask;
         P.mul2[t] = ((uint32_t)next() & P.mask) | 1u;
@@ -1002,9 +1002,9 @@ PermSpec make_perm_spec(uint32_t m, uint64_t seed)
     return P;
 }
 
-hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s)
+hipError_t launch_gen_perms(const PermSpec &P, uint32_t *out, hipStream_t s, uint32_t tables)
 {
-    gen_perms_kernel<<<blocks_for(P.m, 65536), kBlock, 0, s>>>(P, out);
+    gen_perms_kernel<<<blocks_for(P.m, 65536), kBlock, 0, s>>>(P, tables, out);
     return hipGetLastError();
 }
 
