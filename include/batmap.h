@@ -92,7 +92,25 @@ typedef struct {
     uint64_t n_corrections;  /* +1 pair corrections derived from them */
     uint32_t slot_bits;      /* bits per slot of this index's BatMaps (8, 16 or 32) */
     uint32_t order;          /* 2 or 3, as built (bm_build_opts.order) */
+    uint32_t perm_family;    /* BM_PERM_*: where the permutations pi_t came from */
+    uint32_t reserved;
 } bm_index_stats;
+
+/* bm_index_stats.perm_family.  Any family gives exact counts; they differ in
+ * how the maps are built.
+ *   BM_PERM_CALLER: the three tables of bm_build_opts.perm.
+ *   BM_PERM_CHAIN:  a keyed bijection of [0, m) per table (a chain of odd
+ *                   multiplies, adds and xor-shifts, cycle walked into [0, m)).
+ *   BM_PERM_BLOCK:  the block family: y = sigma(x) by such a bijection, then
+ *                   pi_t(x) = H r_0 + beta_{t,H}(y mod r_0), H = y / r_0, with
+ *                   beta_{t,H} a keyed bijection of the block.  All three
+ *                   tables keep an element in the same block of r_0 hash
+ *                   values, so each block of 3 r_0 slots of a map is built
+ *                   alone.  Used for 8-bit maps of order two with generated
+ *                   permutations when 3 r_0 code bytes fit the device's LDS. */
+#define BM_PERM_CALLER 0u
+#define BM_PERM_CHAIN 1u
+#define BM_PERM_BLOCK 2u
 
 /* Per-phase device times of the last build and the last query on a context,
  * taken with HIP events on the context's stream while profiling is on.

@@ -30,6 +30,10 @@ BM_ECAPACITY = -6
 BM_EBUSY = -7
 BM_ENOTFOUND = -8
 
+BM_PERM_CALLER = 0
+BM_PERM_CHAIN = 1
+BM_PERM_BLOCK = 2
+
 STATUS_NAMES = {
     BM_OK: "BM_OK", BM_EINVAL: "BM_EINVAL", BM_ERANGE: "BM_ERANGE", BM_EUNSORTED: "BM_EUNSORTED",
     BM_ENOMEM: "BM_ENOMEM", BM_EDEVICE: "BM_EDEVICE", BM_ECAPACITY: "BM_ECAPACITY", BM_EBUSY: "BM_EBUSY",
@@ -66,6 +70,7 @@ class bm_index_stats(ctypes.Structure):
         ("min_support", ctypes.c_uint32), ("nnz", ctypes.c_uint64), ("batmap_bytes", ctypes.c_uint64),
         ("n_failed", ctypes.c_uint64), ("n_corrections", ctypes.c_uint64),
         ("slot_bits", ctypes.c_uint32), ("order", ctypes.c_uint32),
+        ("perm_family", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 

@@ -165,6 +165,111 @@ __device__ inline uint64_t uniform_u64(uint64_t v)
 // Keys for the generated permutations, derived from a seed (host).
 PermSpec make_perm_spec(uint32_t m, uint64_t seed);
 
+// The block family of generated permutations (8-bit maps of order two).
+// A keyed bijection sigma of [0, m) (the chain of PermSpec, cycle walked)
+// first relabels the transactions, y = sigma(x); then, with 2^l0 = r_0,
+//   pi_t(x) = H 2^l0 + beta_{t,H}(a),   H = y >> l0,  a = y mod 2^l0,
+// where beta_{t,H} is a keyed bijection of the block [0, L_H), L_H = 2^l0
+// except for the last, partial block (L_H = m - H 2^l0, by cycle walking).
+// Every pi_t is a bijection of [0, m), as Sec. III-A asks.  Its value
+// modulo r_i = R r_0 keeps H mod R as the block index of the Fig. 4 layout,
+// the same in the three tables: block j of map i holds exactly the elements
+// with H = j mod R, so one workgroup can build it whole in LDS.  sigma
+// scatters the transactions over the blocks, so no input order (say, a set
+// of consecutive tids) crowds one block.
+struct BlockPerm {
+    PermSpec sig;      // sigma: key set 0 of a chain over [0, m)
+    uint32_t l0, mask, h;  // block bits, 2^l0 - 1, xorshift of beta (2 h >= l0)
+    uint32_t m;
+    uint32_t key1[3], key2[3];  // per table: hashed with H into beta_{t,H}'s keys
+};
+
+BlockPerm make_block_perm(uint32_t m, uint32_t l0, uint64_t seed);
+
+__host__ __device__ inline uint32_t block_hash(uint32_t H, uint32_t key)
+{
+    uint32_t v = (H + 1u) * 0x9E3779B1u ^ key;
+    v ^= v >> 15;
+    v *= 0x2C1B3C6Du;
+    v ^= v >> 12;
+    v *= 0x297A2D39u;
+    v ^= v >> 15;
+    return v;
+}
+
+// beta_{t,H}: v -> m1 v + c1, xorshift, m2 v + c2, xorshift, all mod 2^l0,
+// with odd m1, m2 and c1, c2 hashed from (t, H).  Keys on both sides of a
+// nonlinear step keep the map from one block's slots to another's (two
+// elements meeting in a table) from being a translation or an affine map
+// shared by the three tables, which would pack collisions into short cycles.
+struct BetaKey {
+    uint32_t m1, c1, m2, c2;
+};
+
+__host__ __device__ inline BetaKey beta_key(const BlockPerm &B, uint32_t H, uint32_t key1, uint32_t key2)
+{
+    const uint32_t h1 = block_hash(H, key1), h2 = block_hash(H, key2);
+    return {(h1 & B.mask) | 1u, (h1 >> 16) & B.mask, (h2 & B.mask) | 1u, (h2 >> 16) & B.mask};
+}
+
+__host__ __device__ inline uint32_t beta_step(const BlockPerm &B, const BetaKey &k, uint32_t v)
+{
+    v = (v * k.m1 + k.c1) & B.mask;
+    v ^= v >> B.h;
+    v = (v * k.m2 + k.c2) & B.mask;
+    v ^= v >> B.h;
+    return v;
+}
+
+// inverse of an odd a modulo 2^16 and beyond (Newton: 3, 6, 12, 24 bits)
+__host__ __device__ inline uint32_t odd_inverse(uint32_t a)
+{
+    uint32_t x = a;
+    x *= 2u - a * x;
+    x *= 2u - a * x;
+    x *= 2u - a * x;
+    return x;
+}
+
+__host__ __device__ inline uint32_t beta_unstep(const BlockPerm &B, const BetaKey &k, uint32_t v)
+{
+    v ^= v >> B.h;  // v ^ (v >> h) undoes itself when 2 h >= l0
+    v = ((v - k.c2) * odd_inverse(k.m2)) & B.mask;
+    v ^= v >> B.h;
+    return ((v - k.c1) * odd_inverse(k.m1)) & B.mask;
+}
+
+// Length of block H: 2^l0, or what is left of [0, m) for the last one.
+__host__ __device__ inline uint32_t block_len(const BlockPerm &B, uint32_t H)
+{
+    const uint64_t lo = (uint64_t)H << B.l0;
+    const uint64_t left = (uint64_t)B.m - lo;
+    return left < (1ull << B.l0) ? (uint32_t)left : (1u << B.l0);
+}
+
+// beta_{t,H}(a) and its inverse, cycle walked into [0, len)
+__host__ __device__ inline uint32_t beta_fwd(const BlockPerm &B, const BetaKey &k, uint32_t a, uint32_t len)
+{
+    uint32_t v = beta_step(B, k, a);
+    while (v >= len)
+        v = beta_step(B, k, v);
+    return v;
+}
+__host__ __device__ inline uint32_t beta_inv(const BlockPerm &B, const BetaKey &k, uint32_t v, uint32_t len)
+{
+    uint32_t a = beta_unstep(B, k, v);
+    while (a >= len)
+        a = beta_unstep(B, k, a);
+    return a;
+}
+
+// pi_t of the block family for an already relabelled y = sigma(x)
+__host__ __device__ inline uint32_t block_pi(const BlockPerm &B, int t, uint32_t y)
+{
+    const uint32_t H = y >> B.l0;
+    return (H << B.l0) | beta_fwd(B, beta_key(B, H, B.key1[t], B.key2[t]), y & B.mask, block_len(B, H));
+}
+
 // ------------------------------------------------------------------ device
 // Host-side launchers.  All take a stream; none synchronises.
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
@@ -352,4 +457,43 @@ hipError_t launch_triple_corrections(const uint32_t *triples, uint64_t count, co
                                      const uint32_t *tids, const uint32_t *failed_bits, const uint64_t *fail_off,
                                      const uint32_t *fail_tids, uint32_t *out, hipStream_t s);
 hipError_t launch_decode3(const uint32_t *arena, uint64_t n_groups, uint8_t *bytes, hipStream_t s);
+
+// Construction with the block family (8-bit maps of order two, r_0 <= kBlockMaxR0).
+// Maps [p_first, n) in size order; their groups start at goff[p_first] = 0 and
+// map p has r_sorted[p] / r_0 blocks of gb = 3 r_0 / 32 groups, block b of
+// the index being groups [b gb, (b + 1) gb).
+constexpr uint32_t kBlockMaxR0 = 32768;
+constexpr uint32_t kBucketChunk = 4096;  // elements per workgroup of the bucket passes
+struct BucketChunk {
+    uint32_t p;   // sorted index of the map
+    uint32_t e0;  // first element (offset in the map's tidlist)
+};
+// bucket_map[b] = sorted index of the map owning block b.
+hipError_t launch_bucket_map(const uint64_t *goff, uint32_t p_first, uint32_t n, uint32_t gb, uint32_t *bucket_map,
+                             hipStream_t s);
+// Counts of the elements of each block (count[b] += ...; zeroed by the caller).
+hipError_t launch_bucket_count(const BucketChunk *chunks, uint32_t n_chunks, const uint32_t *tids,
+                               const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                               const uint64_t *goff, uint32_t gb, const BlockPerm &B, uint32_t *count, hipStream_t s);
+// y = sigma(x) of every element into its block's run of bk; cursor[b] starts at
+// the first position of block b's run and ends at the next block's.
+hipError_t launch_bucket_scatter(const BucketChunk *chunks, uint32_t n_chunks, const uint32_t *tids,
+                                 const uint64_t *off, const uint32_t *sorted_items, const uint32_t *r_sorted,
+                                 const uint64_t *goff, uint32_t gb, const BlockPerm &B, uint32_t *cursor,
+                                 uint32_t *bk, hipStream_t s);
+// One workgroup per block: 2-of-3 insertion (Sec. II-A) in LDS, failures,
+// indicators (Fig. 3) and the bit-sliced bytes of the block written to the
+// arena.  Failed elements go to failed[] as (item, x) with x the caller's
+// tid; *overflow is set when a block leaves more nestless elements than the
+// kernel holds (the caller then builds with the chain family).
+hipError_t launch_block_build(const uint32_t *bk, const uint32_t *bstart, const uint32_t *bucket_map,
+                              uint32_t n_blocks, const uint64_t *goff, const uint32_t *sorted_items,
+                              const uint32_t *r_sorted, const uint32_t *tids, const uint64_t *off, const BlockPerm &B,
+                              uint32_t shift, uint32_t max_loop, uint32_t *arena, uint32_t *failed_bits,
+                              uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *overflow,
+                              hipStream_t s);
+// Largest r_0 whose blocks fit the device's LDS (0 if none).
+uint32_t block_build_max_r0();
+// out[t m + x] = pi_t(x) of the block family, t < 3.
+hipError_t launch_gen_block_perms(const BlockPerm &B, uint32_t *out, hipStream_t s);
 }  // namespace bm

@@ -359,7 +359,9 @@ struct bm_index {
     DevBuf<uint32_t> tids;
     DevBuf<uint32_t> pi;            // 3 m, only for caller-given permutations
     DevBuf<uint32_t> pinv;          // their inverses, 3 m
-    PermSpec perm;                  // pi_t: table (caller's) or keyed bijection
+    PermSpec perm;                  // pi_t: table (caller's) or keyed bijection (chain family)
+    bool block_family = false;      // pi_t of the block family (bperm) built the maps
+    BlockPerm bperm;
     DevBuf<uint32_t> sorted_items;  // n
     DevBuf<uint32_t> r_sorted;      // n
     DevBuf<uint64_t> goff;          // n + 1
@@ -815,6 +817,86 @@ bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
     return BM_OK;
 }
 
+// Construction with the block family (launch_block_build): the elements
+// bucketed by (map, block), then one workgroup per block.  Sets `done` when
+// every block was built.  When a block leaves more nestless elements than
+// the kernel holds it returns with `done` false and the failure bits clear,
+// for the chain family to build the index instead.
+bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t> &failed_bits, uint64_t fb_words,
+                          bool &done)
+{
+    bm_context *ctx = idx->ctx;
+    hipStream_t s = ctx->stream;
+    const uint32_t n = idx->n, first = idx->first_built;
+    done = false;
+    const uint32_t l0 = 31u - (uint32_t)__builtin_clz(idx->r0);
+    idx->bperm = make_block_perm(idx->m, l0, o->seed);
+    const uint32_t gb = idx->gb;
+    const uint64_t n_blocks = idx->total_groups / gb;
+    std::vector<BucketChunk> h_chunks;
+    for (uint32_t p = first; p < n; p++) {
+        // r_i <= 2 * 2^ceil(log2 m) and m <= 127 r_0 give at most 256 blocks a
+        // map (the bucket passes' histogram); anything wider goes to the chain family
+        if (idx->h_r_sorted[p] / idx->r0 > 256)
+            return BM_OK;
+        const uint32_t sz = idx->h_sizes_sorted[p];
+        for (uint32_t e0 = 0; e0 < sz; e0 += kBucketChunk)
+            h_chunks.push_back({p, e0});
+    }
+    Span span_construct(ctx, PH_CONSTRUCT);
+    DevBuf<BucketChunk> chunks;
+    DevBuf<uint32_t> count, bstart, cursor, bmap, bk, counters;
+    DevBuf<char> tmp;
+    HIPC(ctx, chunks.alloc(std::max<size_t>(h_chunks.size(), 1)));
+    HIPC(ctx, count.alloc(n_blocks + 1));
+    HIPC(ctx, bstart.alloc(n_blocks + 1));
+    HIPC(ctx, cursor.alloc(n_blocks + 1));
+    HIPC(ctx, bmap.alloc(n_blocks + 1));
+    HIPC(ctx, bk.alloc(std::max<uint64_t>(idx->nnz, 1)));
+    HIPC(ctx, counters.alloc(2));
+    HIPC(ctx, tmp.alloc(scan_tmp_bytes(n_blocks + 1)));
+    if (!h_chunks.empty())
+        BMC(upload(ctx, chunks.p, h_chunks.data(), h_chunks.size() * sizeof(BucketChunk)));
+    HIPC(ctx, fill_u32(count.p, n_blocks + 1, 0, s));
+    HIPC(ctx, launch_bucket_map(idx->goff.p, first, n, gb, bmap.p, s));
+    HIPC(ctx, launch_bucket_count(chunks.p, (uint32_t)h_chunks.size(), idx->tids.p, idx->off.p, idx->sorted_items.p,
+                                  idx->r_sorted.p, idx->goff.p, gb, idx->bperm, count.p, s));
+    HIPC(ctx, exclusive_scan_u32(count.p, bstart.p, n_blocks + 1, tmp.p, s));
+    HIPC(ctx, hipMemcpyAsync(cursor.p, bstart.p, (n_blocks + 1) * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(ctx, launch_bucket_scatter(chunks.p, (uint32_t)h_chunks.size(), idx->tids.p, idx->off.p,
+                                    idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, gb, idx->bperm, cursor.p, bk.p,
+                                    s));
+    uint64_t fail_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
+    for (int attempt = 0;; attempt++) {
+        HIPC(ctx, idx->failed.alloc(2 * fail_cap));
+        HIPC(ctx, fill_u32(counters.p, 2, 0, s));
+        HIPC(ctx, launch_block_build(bk.p, bstart.p, bmap.p, (uint32_t)n_blocks, idx->goff.p, idx->sorted_items.p,
+                                     idx->r_sorted.p, idx->tids.p, idx->off.p, idx->bperm, idx->shift, o->max_loop,
+                                     idx->arena.p, failed_bits.p, idx->failed.p, counters.p, (uint32_t)fail_cap,
+                                     counters.p + 1, s));
+        // the all-pairs plan is made on the host while the kernels run
+        if (attempt == 0 && n - first <= kPlanAtBuild) {
+            bm_status st = ensure_plan(idx, first);
+            if (st != BM_OK)
+                return st;
+        }
+        uint32_t h[2] = {0, 0};
+        BMC(read_back(ctx, h, counters.p, 8));
+        if (h[1]) {
+            HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+            return BM_OK;
+        }
+        if (h[0] <= fail_cap) {
+            idx->n_failed = h[0];
+            idx->block_family = true;
+            done = true;
+            return BM_OK;
+        }
+        fail_cap = (uint64_t)h[0] + h[0] / 2 + 1024;
+        HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+    }
+}
+
 // Everything after the tidlists (idx->off, idx->tids, idx->h_off) are on the device.
 bm_status build_common(bm_index *idx, const bm_build_opts *o)
 {
@@ -958,176 +1040,193 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     uint64_t fb_words = (idx->nnz + 31) / 32;
     HIPC(ctx, failed_bits.alloc(fb_words + 1));
     HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
-    size_t free_b = 0, total_b = 0;
-    HIPC(ctx, hipMemGetInfo(&free_b, &total_b));
-    // Maps are built in batches whose staging (128 B per group, plus 32 B of
-    // codes) fits a quarter of free device memory; BM_STAGE_MB caps it lower.
-    // A batch holds at least one map.
-    uint64_t budget_bytes = ~0ull;
-    if (const char *e = getenv("BM_STAGE_MB"))
-        if (atoll(e) > 0)
-            budget_bytes = (uint64_t)atoll(e) << 20;
-    budget_bytes = std::min<uint64_t>(budget_bytes, (uint64_t)free_b / 4);
-    const uint64_t budget_groups = std::max<uint64_t>(budget_bytes / (kSlotsPerGroup * 5), 1);
-    struct Batch {
-        uint32_t p, q;
-        uint64_t groups, n_elems, eoff;  // eoff: offset of this batch's element bases
-    };
-    // Maps narrow enough for LDS (a prefix of the size order) are built whole
-    // in LDS, one launch per width; the rest go through staging in batches.
-    // BM_LDS_BUILD=0 turns the LDS path off.
-    const char *lds_env = getenv("BM_LDS_BUILD");
-    const bool lds_on = !(lds_env && atoi(lds_env) == 0) && idx->planes == 8 && !order3;
-    auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / tables); };
-    uint32_t p_lds = first_built;
-    while (lds_on && p_lds < n && lds_build_field_bits(width_of(p_lds), m) != 0)
-        p_lds++;
-    std::vector<Batch> batches;
-    std::vector<uint64_t> eb_all;
-    uint64_t max_groups = 0;
-    auto make_batches = [&](uint32_t from) {
-        for (uint32_t p = from; p < n;) {
-            uint32_t q = p + 1;
-            while (q < n && h_goff[q + 1] - h_goff[p] <= budget_groups)
-                q++;
-            Batch b{p, q, h_goff[q] - h_goff[p], 0, eb_all.size()};
-            eb_all.push_back(0);
-            for (uint32_t k = p; k < q; k++)
-                eb_all.push_back(eb_all.back() + idx->h_sizes_sorted[k]);
-            b.n_elems = eb_all.back();
-            max_groups = std::max(max_groups, b.groups);
-            batches.push_back(b);
-            p = q;
+    // The block family builds the paper's 8-bit maps of order two with
+    // generated permutations whenever a block of 3 r_0 code bytes fits the
+    // LDS; the chain family (staged and whole-map LDS builds below) builds the
+    // rest, and an index whose block build overflowed.  BM_BLOCK_BUILD=0
+    // turns the block family off.
+    bool block_done = false;
+    {
+        const char *bb_env = getenv("BM_BLOCK_BUILD");
+        if (!(bb_env && atoi(bb_env) == 0) && !order3 && idx->planes == 8 && !o->perm[0] && first_built < n &&
+            idx->r0 <= block_build_max_r0()) {
+            st = block_construct(idx, o, failed_bits, fb_words, block_done);
+            if (st != BM_OK)
+                return st;
         }
-    };
-    make_batches(p_lds);
-    DevBuf<uint32_t> stage, cand, counters;
-    DevBuf<uint8_t> codes;
-    DevBuf<uint64_t> ebase;
-    HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
-    HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
-    HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
-    if (!eb_all.empty())
-        BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
-    HIPC(ctx, counters.alloc(4));
-    // counters: [0] candidates of the running batch, [1] failures so far,
-    // [2] largest candidate count of any batch, [3] an LDS-built map left too
-    // many nestless elements.  Capacities are checked once at the end; on
-    // overflow the whole construction runs again, larger (or, for [3],
-    // through staging only).
-    uint64_t cand_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
-    uint64_t fail_cap = cand_cap;
-    uint64_t n_failed_total = 0;
-    for (int attempt = 0;; attempt++) {
-        HIPC(ctx, cand.alloc(2 * cand_cap));
-        HIPC(ctx, idx->failed.alloc(2 * fail_cap));
-        HIPC(ctx, fill_u32(counters.p, 4, 0, s));
-        if (attempt)
-            HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
-        // LDS-built maps, one launch per width, on the side streams: they are
-        // bound by LDS and VALU work, the staged insertion below by device
-        // atomics, so the two overlap (disjoint maps and arena groups; the
-        // failure list and counters are shared through atomics)
-        int n_side = 0;
-        if (p_lds > first_built) {
-            std::vector<std::pair<uint32_t, uint32_t>> runs;
-            for (uint32_t p = first_built; p < p_lds;) {
+    }
+    if (!block_done) {
+        size_t free_b = 0, total_b = 0;
+        HIPC(ctx, hipMemGetInfo(&free_b, &total_b));
+        // Maps are built in batches whose staging (128 B per group, plus 32 B of
+        // codes) fits a quarter of free device memory; BM_STAGE_MB caps it lower.
+        // A batch holds at least one map.
+        uint64_t budget_bytes = ~0ull;
+        if (const char *e = getenv("BM_STAGE_MB"))
+            if (atoll(e) > 0)
+                budget_bytes = (uint64_t)atoll(e) << 20;
+        budget_bytes = std::min<uint64_t>(budget_bytes, (uint64_t)free_b / 4);
+        const uint64_t budget_groups = std::max<uint64_t>(budget_bytes / (kSlotsPerGroup * 5), 1);
+        struct Batch {
+            uint32_t p, q;
+            uint64_t groups, n_elems, eoff;  // eoff: offset of this batch's element bases
+        };
+        // Maps narrow enough for LDS (a prefix of the size order) are built whole
+        // in LDS, one launch per width; the rest go through staging in batches.
+        // BM_LDS_BUILD=0 turns the LDS path off.
+        const char *lds_env = getenv("BM_LDS_BUILD");
+        const bool lds_on = !(lds_env && atoi(lds_env) == 0) && idx->planes == 8 && !order3;
+        auto width_of = [&](uint32_t p) { return (uint32_t)((h_goff[p + 1] - h_goff[p]) * kSlotsPerGroup / tables); };
+        uint32_t p_lds = first_built;
+        while (lds_on && p_lds < n && lds_build_field_bits(width_of(p_lds), m) != 0)
+            p_lds++;
+        std::vector<Batch> batches;
+        std::vector<uint64_t> eb_all;
+        uint64_t max_groups = 0;
+        auto make_batches = [&](uint32_t from) {
+            for (uint32_t p = from; p < n;) {
                 uint32_t q = p + 1;
-                while (q < p_lds && width_of(q) == width_of(p))
+                while (q < n && h_goff[q + 1] - h_goff[p] <= budget_groups)
                     q++;
-                runs.push_back({p, q});
+                Batch b{p, q, h_goff[q] - h_goff[p], 0, eb_all.size()};
+                eb_all.push_back(0);
+                for (uint32_t k = p; k < q; k++)
+                    eb_all.push_back(eb_all.back() + idx->h_sizes_sorted[k]);
+                b.n_elems = eb_all.back();
+                max_groups = std::max(max_groups, b.groups);
+                batches.push_back(b);
                 p = q;
             }
-            n_side = std::min<int>((int)runs.size(), bm_context::kSide);
-            st = fork_side(ctx, n_side);
-            if (st != BM_OK)
-                return st;
-            // widest first: the longest launches start first
-            for (size_t i = 0; i < runs.size(); i++) {
-                const auto &run = runs[runs.size() - 1 - i];
-                HIPC(ctx, launch_lds_build(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
-                                           run.first, run.second - run.first, width_of(run.first), idx->perm, shift,
-                                           idx->r0, o->max_loop, idx->arena.p, failed_bits.p, idx->failed.p,
-                                           counters.p + 1, (uint32_t)fail_cap, counters.p + 3,
-                                           ctx->side[i % n_side]));
-            }
-        }
-        for (const Batch &b : batches) {
-            BuildBatch bb{b.p, b.q, h_goff[b.p]};
-            {
-                Span span_construct(ctx, PH_CONSTRUCT);
-                HIPC(ctx, fill_u32(stage.p, b.groups * kSlotsPerGroup, kEmpty, s));
-                HIPC(ctx, fill_u32(counters.p, 1, 0, s));
-                if (order3) {
-                    HIPC(ctx, launch_insert3(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
-                                             idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
-                                             stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
-                    HIPC(ctx, launch_resolve3(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
-                                              idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
-                                              stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
-                                              (uint32_t)fail_cap, counters.p + 2, s));
-                } else {
-                    HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
-                                            idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
-                                            stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
-                    HIPC(ctx, launch_resolve(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
-                                             idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
-                                             stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
-                                             (uint32_t)fail_cap, counters.p + 2, s));
+        };
+        make_batches(p_lds);
+        DevBuf<uint32_t> stage, cand, counters;
+        DevBuf<uint8_t> codes;
+        DevBuf<uint64_t> ebase;
+        HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
+        HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
+        HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
+        if (!eb_all.empty())
+            BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
+        HIPC(ctx, counters.alloc(4));
+        // counters: [0] candidates of the running batch, [1] failures so far,
+        // [2] largest candidate count of any batch, [3] an LDS-built map left too
+        // many nestless elements.  Capacities are checked once at the end; on
+        // overflow the whole construction runs again, larger (or, for [3],
+        // through staging only).
+        uint64_t cand_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
+        uint64_t fail_cap = cand_cap;
+        uint64_t n_failed_total = 0;
+        for (int attempt = 0;; attempt++) {
+            HIPC(ctx, cand.alloc(2 * cand_cap));
+            HIPC(ctx, idx->failed.alloc(2 * fail_cap));
+            HIPC(ctx, fill_u32(counters.p, 4, 0, s));
+            if (attempt)
+                HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+            // LDS-built maps, one launch per width, on the side streams: they are
+            // bound by LDS and VALU work, the staged insertion below by device
+            // atomics, so the two overlap (disjoint maps and arena groups; the
+            // failure list and counters are shared through atomics)
+            int n_side = 0;
+            if (p_lds > first_built) {
+                std::vector<std::pair<uint32_t, uint32_t>> runs;
+                for (uint32_t p = first_built; p < p_lds;) {
+                    uint32_t q = p + 1;
+                    while (q < p_lds && width_of(q) == width_of(p))
+                        q++;
+                    runs.push_back({p, q});
+                    p = q;
+                }
+                n_side = std::min<int>((int)runs.size(), bm_context::kSide);
+                st = fork_side(ctx, n_side);
+                if (st != BM_OK)
+                    return st;
+                // widest first: the longest launches start first
+                for (size_t i = 0; i < runs.size(); i++) {
+                    const auto &run = runs[runs.size() - 1 - i];
+                    HIPC(ctx, launch_lds_build(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p, idx->goff.p,
+                                               run.first, run.second - run.first, width_of(run.first), idx->perm, shift,
+                                               idx->r0, o->max_loop, idx->arena.p, failed_bits.p, idx->failed.p,
+                                               counters.p + 1, (uint32_t)fail_cap, counters.p + 3,
+                                               ctx->side[i % n_side]));
                 }
             }
-            Span span_encode(ctx, PH_ENCODE);
-            if (order3)
-                HIPC(ctx, launch_encode3(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
-                                         idx->r0, idx->arena.p, s));
-            else if (idx->planes == 8)
-                HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
-                                        idx->r0, codes.p, idx->arena.p, s));
-            else
-                HIPC(ctx, launch_encode_wide(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
-                                             idx->r0, idx->planes, idx->arena.p, s));
-        }
-        st = join_side(ctx, n_side);
-        if (st != BM_OK)
-            return st;
-        // the all-pairs plan depends only on the width classes: make and
-        // upload it on the host while the construction kernels run (indexes of
-        // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
-        // and planning all their pairs takes longer than building them)
-        if (attempt == 0 && !order3 && n - idx->first_built <= kPlanAtBuild) {
-            st = ensure_plan(idx, idx->first_built);
+            for (const Batch &b : batches) {
+                BuildBatch bb{b.p, b.q, h_goff[b.p]};
+                {
+                    Span span_construct(ctx, PH_CONSTRUCT);
+                    HIPC(ctx, fill_u32(stage.p, b.groups * kSlotsPerGroup, kEmpty, s));
+                    HIPC(ctx, fill_u32(counters.p, 1, 0, s));
+                    if (order3) {
+                        HIPC(ctx, launch_insert3(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
+                                                 idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
+                                                 stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
+                        HIPC(ctx, launch_resolve3(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
+                                                  idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
+                                                  stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
+                                                  (uint32_t)fail_cap, counters.p + 2, s));
+                    } else {
+                        HIPC(ctx, launch_insert(idx->tids.p, idx->off.p, idx->sorted_items.p, idx->r_sorted.p,
+                                                idx->goff.p, ebase.p + b.eoff, bb, b.n_elems, idx->perm, o->max_loop,
+                                                stage.p, cand.p, (uint32_t)cand_cap, counters.p, s));
+                        HIPC(ctx, launch_resolve(cand.p, counters.p, (uint32_t)cand_cap, idx->tids.p, idx->off.p,
+                                                 idx->sorted_items.p, idx->r_sorted.p, idx->goff.p, bb, idx->perm,
+                                                 stage.p, failed_bits.p, idx->failed.p, counters.p + 1,
+                                                 (uint32_t)fail_cap, counters.p + 2, s));
+                    }
+                }
+                Span span_encode(ctx, PH_ENCODE);
+                if (order3)
+                    HIPC(ctx, launch_encode3(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                             idx->r0, idx->arena.p, s));
+                else if (idx->planes == 8)
+                    HIPC(ctx, launch_encode(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                            idx->r0, codes.p, idx->arena.p, s));
+                else
+                    HIPC(ctx, launch_encode_wide(stage.p, idx->r_sorted.p, idx->goff.p, bb, b.groups, idx->perm, shift,
+                                                 idx->r0, idx->planes, idx->arena.p, s));
+            }
+            st = join_side(ctx, n_side);
             if (st != BM_OK)
                 return st;
+            // the all-pairs plan depends only on the width classes: make and
+            // upload it on the host while the construction kernels run (indexes of
+            // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
+            // and planning all their pairs takes longer than building them)
+            if (attempt == 0 && !order3 && n - idx->first_built <= kPlanAtBuild) {
+                st = ensure_plan(idx, idx->first_built);
+                if (st != BM_OK)
+                    return st;
+            }
+            uint32_t h[4] = {0, 0, 0, 0};
+            st = read_back(ctx, h, counters.p, 16);
+            if (st != BM_OK)
+                return st;
+            if (h[3]) {
+                // an LDS-built map could not resolve its failures: stage everything
+                p_lds = first_built;
+                batches.clear();
+                eb_all.clear();
+                max_groups = 0;
+                make_batches(first_built);
+                HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
+                HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
+                HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
+                if (!eb_all.empty())
+                    BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
+                continue;
+            }
+            if (h[2] <= cand_cap && h[1] <= fail_cap) {
+                n_failed_total = h[1];
+                break;
+            }
+            cand_cap = std::max<uint64_t>(cand_cap, (uint64_t)h[2] + h[2] / 2 + 1024);
+            fail_cap = std::max<uint64_t>(fail_cap, (uint64_t)h[1] + h[1] / 2 + 1024);
         }
-        uint32_t h[4] = {0, 0, 0, 0};
-        st = read_back(ctx, h, counters.p, 16);
-        if (st != BM_OK)
-            return st;
-        if (h[3]) {
-            // an LDS-built map could not resolve its failures: stage everything
-            p_lds = first_built;
-            batches.clear();
-            eb_all.clear();
-            max_groups = 0;
-            make_batches(first_built);
-            HIPC(ctx, stage.alloc(std::max<uint64_t>(max_groups, 1) * kSlotsPerGroup));
-            HIPC(ctx, codes.alloc(encode_scratch_bytes(std::max<uint64_t>(max_groups, 1))));
-            HIPC(ctx, ebase.alloc(std::max<uint64_t>(eb_all.size(), 1)));
-            if (!eb_all.empty())
-                BMC(upload(ctx, ebase.p, eb_all.data(), eb_all.size() * 8));
-            continue;
-        }
-        if (h[2] <= cand_cap && h[1] <= fail_cap) {
-            n_failed_total = h[1];
-            break;
-        }
-        cand_cap = std::max<uint64_t>(cand_cap, (uint64_t)h[2] + h[2] / 2 + 1024);
-        fail_cap = std::max<uint64_t>(fail_cap, (uint64_t)h[1] + h[1] / 2 + 1024);
+        stage.reset();
+        codes.reset();
+        cand.reset();
+        idx->n_failed = n_failed_total;
     }
-    stage.reset();
-    codes.reset();
-    cand.reset();
-    idx->n_failed = n_failed_total;
 
     // order 3: the failed tids of each item, for the per-triple corrections
     if (order3) {
@@ -1807,6 +1906,7 @@ bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
     out->n_corrections = idx->n_corr;
     out->slot_bits = idx->planes;
     out->order = idx->order;
+    out->perm_family = idx->perm.table ? BM_PERM_CALLER : (idx->block_family ? BM_PERM_BLOCK : BM_PERM_CHAIN);
     return BM_OK;
 }
 
@@ -2493,6 +2593,19 @@ bm_status check_cross(bm_index *a, bm_index *b)
     const PermSpec &P = a->perm, &Q = b->perm;
     if ((P.table == nullptr) != (Q.table == nullptr))
         return fail(ctx, BM_EINVAL, "one index uses caller permutations, the other generated ones");
+    if (a->block_family != b->block_family)
+        return fail(ctx, BM_EINVAL, "the indexes were built with different permutation families");
+    if (a->block_family) {
+        const BlockPerm &A = a->bperm, &B = b->bperm;
+        bool same = A.l0 == B.l0 && A.m == B.m && A.sig.mask == B.sig.mask && A.sig.h1 == B.sig.h1 &&
+                    A.sig.h2 == B.sig.h2 && A.sig.mul1[0] == B.sig.mul1[0] && A.sig.add1[0] == B.sig.add1[0] &&
+                    A.sig.mul2[0] == B.sig.mul2[0] && A.sig.mul3[0] == B.sig.mul3[0] && A.sig.add3[0] == B.sig.add3[0];
+        for (int t = 0; t < 3; t++)
+            same = same && A.key1[t] == B.key1[t] && A.key2[t] == B.key2[t];
+        if (!same)
+            return fail(ctx, BM_EINVAL, "the indexes were built with different seeds");
+        return BM_OK;
+    }
     if (!P.table) {
         bool same = P.m == Q.m && P.mask == Q.mask && P.h1 == Q.h1 && P.h2 == Q.h2;
         for (int t = 0; t < 3; t++)
@@ -2690,7 +2803,10 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
         const uint32_t tables = idx->order == 3 ? 4 : 3;
         if (!src) {
             HIPC(ctx, tmp.alloc((uint64_t)tables * idx->m));
-            HIPC(ctx, launch_gen_perms(idx->perm, tmp.p, ctx->stream, tables));
+            if (idx->block_family)
+                HIPC(ctx, launch_gen_block_perms(idx->bperm, tmp.p, ctx->stream));
+            else
+                HIPC(ctx, launch_gen_perms(idx->perm, tmp.p, ctx->stream, tables));
             src = tmp.p;
         }
         bm_status st = download(ctx, perms, src, (uint64_t)tables * idx->m * 4);
