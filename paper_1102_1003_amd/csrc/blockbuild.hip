@@ -33,17 +33,26 @@ size_t block_lds_bytes(uint32_t r0)
     return sizeof(BlockHead) + 3ull * r0 + 3ull * r0 / 8;
 }
 
-// beta_{t,H}'s keys for a table index that differs between lanes: the
-// table keys by selects between wavefront-uniform scalars.
-__device__ inline BetaKey beta_key_lane(const BlockPerm &B, uint32_t t, uint32_t H)
+// beta_{t,H}'s keys of every block (H < 128: m <= 127 r_0) and table, kept
+// in LDS by each workgroup of the build: x = m1 | m2 << 16, y = c1 | c2 << 16,
+// z = i1 | i2 << 16 (all below 2^15).
+constexpr uint32_t kMaxBlocksH = 128;
+
+__device__ inline uint4 pack_key(const BetaKey &k)
 {
-    auto pick = [t](const uint32_t (&k)[3]) {
-        const uint32_t a = __builtin_amdgcn_readfirstlane(k[0]);
-        const uint32_t b = __builtin_amdgcn_readfirstlane(k[1]);
-        const uint32_t c = __builtin_amdgcn_readfirstlane(k[2]);
-        return t == 0 ? a : (t == 1 ? b : c);
-    };
-    return beta_key(B, H, pick(B.key1), pick(B.key2));
+    return make_uint4(k.m1 | (k.m2 << 16), k.c1 | (k.c2 << 16), k.i1 | (k.i2 << 16), 0u);
+}
+
+__device__ inline BetaKey unpack_key(uint4 w)
+{
+    BetaKey k;
+    k.m1 = w.x & 0xFFFFu;
+    k.m2 = w.x >> 16;
+    k.c1 = w.y & 0xFFFFu;
+    k.c2 = w.y >> 16;
+    k.i1 = w.z & 0xFFFFu;
+    k.i2 = w.z >> 16;
+    return k;
 }
 
 // Byte i of the LDS tables set to v; returns the byte it held.
@@ -130,6 +139,7 @@ __device__ inline ChunkView chunk_view(const BucketChunk &c, const uint32_t *tid
 // Counts per block: a histogram of the chunk in LDS (a map has at most 256
 // blocks, since r_i <= 2 * 2^ceil(log2 m) and m <= 127 r_0), then one atomic
 // per nonempty block.
+template <bool K24>
 __global__ void __launch_bounds__(kBucketThreads)
     bucket_count_kernel(const BucketChunk *chunks, const uint32_t *__restrict__ tids, const uint64_t *off,
                         const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff, uint32_t gb,
@@ -141,7 +151,7 @@ __global__ void __launch_bounds__(kBucketThreads)
         hist[j] = 0;
     __syncthreads();
     for (uint32_t e = v.e0 + threadIdx.x; e < v.e1; e += blockDim.x) {
-        const uint32_t y = perm_eval(B.sig, 0, v.T[e]);
+        const uint32_t y = perm_eval_k<K24>(B.sig, 0, v.T[e]);
         atomicAdd(&hist[(y >> B.l0) & (v.R - 1u)], 1u);
     }
     __syncthreads();
@@ -152,6 +162,7 @@ __global__ void __launch_bounds__(kBucketThreads)
 
 // The chunk's y values into their blocks' runs: the chunk reserves its part
 // of each run with one atomic, then ranks its elements in LDS.
+template <bool K24>
 __global__ void __launch_bounds__(kBucketThreads)
     bucket_scatter_kernel(const BucketChunk *chunks, const uint32_t *__restrict__ tids, const uint64_t *off,
                           const uint32_t *sorted_items, const uint32_t *r_sorted, const uint64_t *goff, uint32_t gb,
@@ -166,7 +177,7 @@ __global__ void __launch_bounds__(kBucketThreads)
 #pragma unroll
     for (int k = 0; k < kBucketPer; k++) {
         const uint32_t e = v.e0 + k * kBucketThreads + threadIdx.x;
-        ys[k] = e < v.e1 ? perm_eval(B.sig, 0, v.T[e]) : 0u;
+        ys[k] = e < v.e1 ? perm_eval_k<K24>(B.sig, 0, v.T[e]) : 0u;
         if (e < v.e1)
             atomicAdd(&hist[(ys[k] >> B.l0) & (v.R - 1u)], 1u);
     }
@@ -199,6 +210,7 @@ __global__ void __launch_bounds__(1024)
                        uint32_t *failed, uint32_t *n_failed, uint32_t fail_cap, uint32_t *overflow)
 {
     extern __shared__ uint32_t lds_dyn[];
+    __shared__ uint4 KT[3 * kMaxBlocksH];  // beta_{t,H}'s keys at t * kMaxBlocksH + H
     BlockHead &Hd = *reinterpret_cast<BlockHead *>(lds_dyn);
     const uint32_t b = blockIdx.x;
     const uint32_t p = bucket_map[b];
@@ -214,6 +226,11 @@ __global__ void __launch_bounds__(1024)
         W[i] = 0x7F7F7F7Fu;
     for (uint32_t i = threadIdx.x; i < 3u * r0 / 32u; i += blockDim.x)
         IND[i] = 0;
+    for (uint32_t i = threadIdx.x; i < 3u * kMaxBlocksH; i += blockDim.x) {
+        const uint32_t t = i / kMaxBlocksH, H = i % kMaxBlocksH;
+        if (H < B.n_blocks)
+            KT[i] = pack_key(beta_key(B, H, B.key1[t], B.key2[t]));
+    }
     if (threadIdx.x == 0)
         Hd.count = 0;
     __syncthreads();
@@ -244,13 +261,13 @@ __global__ void __launch_bounds__(1024)
                 continue;
             }
             const uint32_t H = y >> B.l0;
-            const uint32_t pos = beta_fwd(B, beta_key_lane(B, tb, H), y & B.mask, block_len(B, H));
+            const uint32_t pos = beta_fwd(B, unpack_key(KT[tb * kMaxBlocksH + H]), y & B.mask, block_len(B, H));
             const uint32_t old = lds_swap_byte(W, tb * r0 + pos, (H << csh) | (pos >> shift));
             if (old == kEmptyCode) {
                 busy = false;
             } else {
                 const uint32_t H2 = old >> csh;
-                const uint32_t a2 = beta_inv(B, beta_key_lane(B, tb, H2), pos, block_len(B, H2));
+                const uint32_t a2 = beta_inv(B, unpack_key(KT[tb * kMaxBlocksH + H2]), pos, block_len(B, H2));
                 y = (H2 << B.l0) | a2;
                 tb = tb == 2u ? 0u : tb + 1u;
                 left--;
@@ -275,10 +292,10 @@ __global__ void __launch_bounds__(1024)
         const uint32_t y = Hd.elem[f];
         const uint32_t H = y >> B.l0;
         for (uint32_t t = 0; t < 3; t++) {
-            const uint32_t pos = block_pi(B, (int)t, y) & (r0 - 1u);
+            const uint32_t pos = beta_fwd(B, unpack_key(KT[t * kMaxBlocksH + H]), y & B.mask, block_len(B, H));
             lds_clear_byte(W, t * r0 + pos, (H << csh) | (pos >> shift));
         }
-        const uint32_t x = perm_inverse_lane(B.sig, 0, y);
+        const uint32_t x = perm_inverse_lane(B.sig, 0, y);  // failures are few: 32-bit multiplies
         const int64_t k = find_sorted(tids + e_first, size, x);
         if (k < 0)
             continue;  // cannot happen: x came from this set
@@ -303,9 +320,10 @@ __global__ void __launch_bounds__(1024)
         const uint32_t H = y >> B.l0;
         uint32_t pos[3];
         bool in[3];
+        const uint32_t len = block_len(B, H);
 #pragma unroll
         for (int t = 0; t < 3; t++) {
-            const uint32_t q = block_pi(B, t, y) & (r0 - 1u);
+            const uint32_t q = beta_fwd(B, unpack_key(KT[t * kMaxBlocksH + H]), y & B.mask, len);
             pos[t] = (uint32_t)t * r0 + q;
             in[t] = lds_get_byte(W, pos[t]) == ((H << csh) | (q >> shift));
         }
@@ -358,13 +376,19 @@ int block_lds_limit()
 {
     static int limit = -1;
     if (limit < 0) {
+        // the kernel's static LDS (its key table) comes out of the same budget
         int dev = 0, bytes = 0;
+        hipFuncAttributes attr;
         limit = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(block_build_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess)
-            limit = bytes;
+            hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(block_build_kernel)) == hipSuccess &&
+            bytes > (int)attr.sharedSizeBytes) {
+            const int dyn = bytes - (int)attr.sharedSizeBytes;
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(block_build_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, dyn) == hipSuccess)
+                limit = dyn;
+        }
         (void)hipGetLastError();
     }
     return limit;
@@ -390,6 +414,8 @@ BlockPerm make_block_perm(uint32_t m, uint32_t l0, uint64_t seed)
     B.l0 = l0;
     B.mask = (1u << l0) - 1u;
     B.h = (l0 + 1) / 2;
+    B.n_blocks = (uint32_t)(((uint64_t)m + B.mask) >> l0);
+    B.last_len = m - ((B.n_blocks - 1u) << l0);
     uint64_t x = seed ^ 0xB10CB10Cull;
     auto next = [&x]() {  // splitmix64
         uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -419,8 +445,12 @@ hipError_t launch_bucket_count(const BucketChunk *chunks, uint32_t n_chunks, con
 {
     if (n_chunks == 0)
         return hipSuccess;
-    bucket_count_kernel<<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted, goff, gb, B,
-                                                            count);
+    if (B.sig.mask <= 0xFFFFFFu)
+        bucket_count_kernel<true><<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted, goff,
+                                                                      gb, B, count);
+    else
+        bucket_count_kernel<false><<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted,
+                                                                       goff, gb, B, count);
     return hipGetLastError();
 }
 
@@ -431,8 +461,12 @@ hipError_t launch_bucket_scatter(const BucketChunk *chunks, uint32_t n_chunks, c
 {
     if (n_chunks == 0)
         return hipSuccess;
-    bucket_scatter_kernel<<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted, goff, gb, B,
-                                                              cursor, bk);
+    if (B.sig.mask <= 0xFFFFFFu)
+        bucket_scatter_kernel<true><<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted,
+                                                                        goff, gb, B, cursor, bk);
+    else
+        bucket_scatter_kernel<false><<<n_chunks, kBucketThreads, 0, s>>>(chunks, tids, off, sorted_items, r_sorted,
+                                                                         goff, gb, B, cursor, bk);
     return hipGetLastError();
 }
 

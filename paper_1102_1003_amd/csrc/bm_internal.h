@@ -86,6 +86,37 @@ __host__ __device__ inline uint32_t perm_chain(const PermSpec &P, int t, uint32_
     return v;
 }
 
+// Low 32 bits of a * b from the low 24 bits of each factor: the product
+// modulo 2^24 is exact, which is all a caller masking it to at most 24 bits
+// keeps, and the GPU does it in one full-rate 24-bit multiply (a 32-bit
+// multiply issues at a quarter of that rate).
+__host__ __device__ inline uint32_t mul24(uint32_t a, uint32_t b)
+{
+    return (a & 0xFFFFFFu) * (b & 0xFFFFFFu);
+}
+
+// perm_chain / perm_eval with 24-bit multiplies: the same values whenever
+// P.mask has at most 24 bits (m <= 2^24).
+__host__ __device__ inline uint32_t perm_chain24(const PermSpec &P, int t, uint32_t v)
+{
+    v = (mul24(v, P.mul1[t]) + P.add1[t]) & P.mask;
+    v ^= v >> P.h1;
+    v = mul24(v, P.mul2[t]) & P.mask;
+    v ^= v >> P.h2;
+    v = (mul24(v, P.mul3[t]) + P.add3[t]) & P.mask;
+    v ^= v >> P.h1;
+    return v;
+}
+
+template <bool K24>
+__host__ __device__ inline uint32_t perm_eval_k(const PermSpec &P, int t, uint32_t x)
+{
+    uint32_t y = K24 ? perm_chain24(P, t, x) : perm_chain(P, t, x);
+    while (y >= P.m)
+        y = K24 ? perm_chain24(P, t, y) : perm_chain(P, t, y);
+    return y;
+}
+
 __host__ __device__ inline uint32_t perm_eval(const PermSpec &P, int t, uint32_t x)
 {
     if (P.table)
@@ -181,6 +212,8 @@ struct BlockPerm {
     PermSpec sig;      // sigma: key set 0 of a chain over [0, m)
     uint32_t l0, mask, h;  // block bits, 2^l0 - 1, xorshift of beta (2 h >= l0)
     uint32_t m;
+    uint32_t n_blocks;     // ceil(m / 2^l0) <= 127 (m <= 127 2^s, 2^s <= 2^l0)
+    uint32_t last_len;     // m - (n_blocks - 1) 2^l0: length of the last block
     uint32_t key1[3], key2[3];  // per table: hashed with H into beta_{t,H}'s keys
 };
 
@@ -197,31 +230,7 @@ __host__ __device__ inline uint32_t block_hash(uint32_t H, uint32_t key)
     return v;
 }
 
-// beta_{t,H}: v -> m1 v + c1, xorshift, m2 v + c2, xorshift, all mod 2^l0,
-// with odd m1, m2 and c1, c2 hashed from (t, H).  Keys on both sides of a
-// nonlinear step keep the map from one block's slots to another's (two
-// elements meeting in a table) from being a translation or an affine map
-// shared by the three tables, which would pack collisions into short cycles.
-struct BetaKey {
-    uint32_t m1, c1, m2, c2;
-};
-
-__host__ __device__ inline BetaKey beta_key(const BlockPerm &B, uint32_t H, uint32_t key1, uint32_t key2)
-{
-    const uint32_t h1 = block_hash(H, key1), h2 = block_hash(H, key2);
-    return {(h1 & B.mask) | 1u, (h1 >> 16) & B.mask, (h2 & B.mask) | 1u, (h2 >> 16) & B.mask};
-}
-
-__host__ __device__ inline uint32_t beta_step(const BlockPerm &B, const BetaKey &k, uint32_t v)
-{
-    v = (v * k.m1 + k.c1) & B.mask;
-    v ^= v >> B.h;
-    v = (v * k.m2 + k.c2) & B.mask;
-    v ^= v >> B.h;
-    return v;
-}
-
-// inverse of an odd a modulo 2^16 and beyond (Newton: 3, 6, 12, 24 bits)
+// inverse of an odd a modulo 2^24 (Newton's iteration: 3, 6, 12, 24 bits)
 __host__ __device__ inline uint32_t odd_inverse(uint32_t a)
 {
     uint32_t x = a;
@@ -231,20 +240,51 @@ __host__ __device__ inline uint32_t odd_inverse(uint32_t a)
     return x;
 }
 
+// beta_{t,H}: v -> m1 v + c1, xorshift, m2 v + c2, xorshift, all mod 2^l0,
+// with odd m1, m2 and c1, c2 hashed from (t, H).  Keys on both sides of a
+// nonlinear step keep the map from one block's slots to another's (two
+// elements meeting in a table) from being a translation or an affine map
+// shared by the three tables, which would pack collisions into short cycles.
+// i1, i2: m1^-1, m2^-1 mod 2^l0.
+struct BetaKey {
+    uint32_t m1, c1, m2, c2, i1, i2;
+};
+
+__host__ __device__ inline BetaKey beta_key(const BlockPerm &B, uint32_t H, uint32_t key1, uint32_t key2)
+{
+    const uint32_t h1 = block_hash(H, key1), h2 = block_hash(H, key2);
+    BetaKey k;
+    k.m1 = (h1 & B.mask) | 1u;
+    k.c1 = (h1 >> 16) & B.mask;
+    k.m2 = (h2 & B.mask) | 1u;
+    k.c2 = (h2 >> 16) & B.mask;
+    k.i1 = odd_inverse(k.m1) & B.mask;
+    k.i2 = odd_inverse(k.m2) & B.mask;
+    return k;
+}
+
+// (l0 <= 15, so every factor below has at most 24 bits)
+__host__ __device__ inline uint32_t beta_step(const BlockPerm &B, const BetaKey &k, uint32_t v)
+{
+    v = (mul24(v, k.m1) + k.c1) & B.mask;
+    v ^= v >> B.h;
+    v = (mul24(v, k.m2) + k.c2) & B.mask;
+    v ^= v >> B.h;
+    return v;
+}
+
 __host__ __device__ inline uint32_t beta_unstep(const BlockPerm &B, const BetaKey &k, uint32_t v)
 {
     v ^= v >> B.h;  // v ^ (v >> h) undoes itself when 2 h >= l0
-    v = ((v - k.c2) * odd_inverse(k.m2)) & B.mask;
+    v = mul24(v - k.c2, k.i2) & B.mask;
     v ^= v >> B.h;
-    return ((v - k.c1) * odd_inverse(k.m1)) & B.mask;
+    return mul24(v - k.c1, k.i1) & B.mask;
 }
 
 // Length of block H: 2^l0, or what is left of [0, m) for the last one.
 __host__ __device__ inline uint32_t block_len(const BlockPerm &B, uint32_t H)
 {
-    const uint64_t lo = (uint64_t)H << B.l0;
-    const uint64_t left = (uint64_t)B.m - lo;
-    return left < (1ull << B.l0) ? (uint32_t)left : (1u << B.l0);
+    return H + 1u == B.n_blocks ? B.last_len : (1u << B.l0);
 }
 
 // beta_{t,H}(a) and its inverse, cycle walked into [0, len)
