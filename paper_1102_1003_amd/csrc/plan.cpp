@@ -83,6 +83,24 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
                std::vector<std::pair<uint32_t, uint32_t>> *out, uint64_t *count)
 {
     uint64_t c = 0;
+    if (!out) {
+        // the count alone, a row of tiles at a time: tile (I, J) holds a row
+        // below a column unless min(count, (J + 1) bj) <= I bi + 1, which
+        // drops the first floor((I bi + 1) / bj) tiles of the row (all of
+        // them when I bi + 1 >= count)
+        const uint64_t nJ = (B.count + bj - 1) / bj;
+        for (uint64_t I = 0; I * bi < A.count; I++) {
+            if (!same) {
+                c += nJ;
+                continue;
+            }
+            const uint64_t r1 = I * bi + 1;
+            if (r1 < B.count)
+                c += nJ - std::min<uint64_t>(nJ, r1 / bj);
+        }
+        *count = c;
+        return;
+    }
     for (uint32_t I = 0; I * bi < A.count; I++) {
         for (uint32_t J = 0; J * bj < B.count; J++) {
             if (same) {
@@ -110,7 +128,8 @@ namespace {
 
 void xcd_order(std::vector<WorkItem> &v)
 {
-    std::vector<WorkItem> out(v.size());
+    std::vector<WorkItem> out;
+    out.reserve(v.size());
     std::vector<std::vector<uint32_t>> q(kXcds);
     std::unordered_map<uint64_t, uint32_t> group_of;
     size_t s = 0;
@@ -122,10 +141,16 @@ void xcd_order(std::vector<WorkItem> &v)
         for (auto &x : q)
             x.clear();
         group_of.clear();
+        // a group's items are mostly consecutive: the previous key first
+        uint64_t last_key = ~0ull;
+        uint32_t last_g = 0;
         for (size_t t = s; t < e; t++) {
             const uint64_t key = ((uint64_t)v[t].c0 << 32) | v[t].row0;
-            auto it = group_of.emplace(key, (uint32_t)group_of.size()).first;
-            q[it->second % kXcds].push_back((uint32_t)t);
+            if (key != last_key) {
+                last_g = group_of.emplace(key, (uint32_t)group_of.size()).first->second;
+                last_key = key;
+            }
+            q[last_g % kXcds].push_back((uint32_t)t);
         }
         std::vector<size_t> head(kXcds, 0);
         for (size_t p = s; p < e; p++) {
@@ -138,7 +163,7 @@ void xcd_order(std::vector<WorkItem> &v)
                         x = y;
                     }
             }
-            out[p] = v[q[x][head[x]++]];
+            out.push_back(v[q[x][head[x]++]]);
         }
         s = e;
     }
@@ -315,12 +340,20 @@ void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan
         costs.clear();
         bucket_of.clear();
         item_bucket.resize(v.size());
+        // items come in runs of one cost (a class pair's range), so the
+        // previous item's bucket is checked before the map
+        uint64_t last_c = ~0ull;
+        uint32_t last_b = 0;
         for (size_t t = 0; t < v.size(); t++) {
             const uint64_t c = item_cost(v[t]);
-            auto it = bucket_of.emplace(c, (uint32_t)costs.size()).first;
-            if (it->second == costs.size())
-                costs.push_back(c);
-            item_bucket[t] = it->second;
+            if (c != last_c) {
+                auto it = bucket_of.emplace(c, (uint32_t)costs.size()).first;
+                if (it->second == costs.size())
+                    costs.push_back(c);
+                last_c = c;
+                last_b = it->second;
+            }
+            item_bucket[t] = last_b;
         }
         std::vector<uint32_t> order(costs.size()), start(costs.size() + 1, 0);
         for (uint32_t b = 0; b < costs.size(); b++)
