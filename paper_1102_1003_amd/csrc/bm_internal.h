@@ -461,8 +461,10 @@ hipError_t launch_subset_prepare(const uint32_t *items, uint32_t k, uint32_t n, 
                                  uint32_t *pos_of_item, uint32_t *flag, hipStream_t s);
 
 // Dense comparator.
+// Scratch words launch_bitmap_build needs for the bitmap of n rows of ld bytes.
+uint64_t bitmap_bounds_words(uint32_t n, uint64_t ld);
 hipError_t launch_bitmap_build(const uint64_t *off, const uint32_t *tids, uint32_t n, uint64_t ld, int8_t *A,
-                               hipStream_t s);
+                               uint64_t *bnd, hipStream_t s);
 // Rows of the dense bitmap are padded to a multiple of this.
 uint32_t dense_row_pad();
 hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t k_len, uint32_t *out,

@@ -2538,8 +2538,9 @@ bm_status bm_all_pair_supports_dense(bm_index *idx, uint32_t *out, uint64_t out_
         const uint64_t pad = dense_row_pad();
         uint64_t rows = ((uint64_t)idx->n + pad - 1) / pad * pad;
         HIPC(ctx, idx->dense_A.alloc(rows * ld));
-        HIPC(ctx, fill_u8(reinterpret_cast<uint8_t *>(idx->dense_A.p), rows * ld, 0, s));
-        HIPC(ctx, launch_bitmap_build(idx->off.p, idx->tids.p, idx->n, ld, idx->dense_A.p, s));
+        DevBuf<uint64_t> bnd;
+        HIPC(ctx, bnd.alloc(bitmap_bounds_words(idx->n, ld)));
+        HIPC(ctx, launch_bitmap_build(idx->off.p, idx->tids.p, idx->n, ld, idx->dense_A.p, bnd.p, s));
         idx->dense_ld = ld;
     }
     bool host = ptr_kind(out) == PTR_HOST;
