@@ -89,6 +89,8 @@ def main():
                     help="run one plain 1 GiB device-to-device copy first (the reference dispatch of a counter run)")
     ap.add_argument("--queries", type=int, default=2000, help="serving: queries per arrival rate")
     ap.add_argument("--rates", default="0.5,0.8,1.0", help="serving: Poisson arrival rates as fractions of saturation")
+    ap.add_argument("--saturation-qps", type=float, default=0.0,
+                    help="serving: take this as the saturation rate instead of measuring it")
     ap.add_argument("--no-extras", action="store_true",
                     help="step: skip the short runs of the other workloads (dense 5%%, batch, serving) in the line")
     ap.add_argument("--densities", default="0.0001,0.0005,0.001,0.002,0.005,0.01,0.02,0.05,0.10,0.20")
@@ -350,7 +352,9 @@ def extras(args):
         sat, p = r["saturation"], r["poisson"]
         return {"workload": r["config"]["workload"], "queries_per_rate": sat["queries"],
                 "saturation_queries_per_s": sat["queries_per_s"], "saturation_pairs_per_s": sat["pairs_per_s"],
-                **{f"poisson_{k}": {kk: v[kk] for kk in ("p50_ms", "p99_ms", "queries_per_s")} for k, v in p.items()},
+                **{f"poisson_{k}": {kk: v[kk] for kk in ("p50_ms", "p99_ms", "small_p50_ms", "small_p99_ms",
+                                                        "large_p50_ms", "large_p99_ms", "queries_per_s") if kk in v}
+                   for k, v in p.items()},
                 "exact": r["exact"]}
 
     run("dense_2e20x8192_p5", dense_sweep_mode, {"densities": "0.05"}, dense_keep)
@@ -431,21 +435,46 @@ def serving_mode(args):
                 while time.perf_counter() - t_start < due:
                     time.sleep(min(0.0005, max(0.0, due - (time.perf_counter() - t_start))))
                 ids[i] = srv.submit(q)
+        def consumer():
+            # results are collected as they come (each holds its share of the
+            # server's memory budget until it is collected)
+            for i in range(len(queries)):
+                while ids[i] is None:
+                    time.sleep(0.0002)
+                infos[i] = srv.wait(ids[i])[1]
         th = threading.Thread(target=producer)
+        tc = threading.Thread(target=consumer)
         t = time.perf_counter()
         th.start()
+        tc.start()
         th.join()
-        for i in range(len(queries)):
-            infos[i] = srv.wait(ids[i])[1]
+        tc.join()
         span = time.perf_counter() - t
         lat = np.array([x["total_s"] for x in infos]) * 1e3
         pairs = sum(bm.n_pairs(q.size) for q in queries)
-        return {"queries": len(queries), "seconds": span, "queries_per_s": len(queries) / span,
-                "pairs_per_s": pairs / span, "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([x["batch"] for x in infos]))}
+        # the server's work classes: small queries (at most 2^17 pairs, k up to 512) and large
+        large = np.array([bm.n_pairs(q.size) > (1 << 17) for q in queries])
+        res = {"queries": len(queries), "seconds": span, "queries_per_s": len(queries) / span,
+               "pairs_per_s": pairs / span, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean([x["batch"] for x in infos]))}
+        qd = np.array([x["queued_s"] for x in infos]) * 1e3
+        rn = np.array([x["run_s"] for x in infos]) * 1e3
+        for name, sel in (("small", ~large), ("large", large)):
+            if sel.any():
+                res[f"{name}_queries"] = int(sel.sum())
+                res[f"{name}_p50_ms"] = float(np.percentile(lat[sel], 50))
+                res[f"{name}_p99_ms"] = float(np.percentile(lat[sel], 99))
+                res[f"{name}_mean_queued_ms"] = float(qd[sel].mean())
+                res[f"{name}_mean_run_ms"] = float(rn[sel].mean())
+                res[f"{name}_mean_batch"] = float(np.mean([x["batch"] for x, l in zip(infos, sel) if l]))
+        return res
 
     qs = make_queries(args.queries, 6)
-    sat = run_stream(qs, [0.0] * len(qs))
+    if args.saturation_qps > 0:
+        sat = {"queries": 0, "queries_per_s": args.saturation_qps, "pairs_per_s": 0.0, "p50_ms": 0.0,
+               "p99_ms": 0.0, "given": True}
+    else:
+        sat = run_stream(qs, [0.0] * len(qs))
     log(f"saturation: {sat['queries_per_s']:.1f} q/s, {sat['pairs_per_s']:.3e} pairs/s, p50 {sat['p50_ms']:.1f} ms")
     rates = {}
     for frac in (float(x) for x in args.rates.split(",") if x):
@@ -455,7 +484,9 @@ def serving_mode(args):
         r = run_stream(make_queries(args.queries, 60 + int(frac * 10)), gaps)
         r["arrival_rate_per_s"] = lam
         rates[f"{frac:.1f}x"] = r
-        log(f"poisson {frac:.1f}x ({lam:.1f} q/s): p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+        log(f"poisson {frac:.1f}x ({lam:.1f} q/s): p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms; small "
+            f"queries p50 {r.get('small_p50_ms', 0):.1f} / p99 {r.get('small_p99_ms', 0):.1f} ms, large p50 "
+            f"{r.get('large_p50_ms', 0):.1f} / p99 {r.get('large_p99_ms', 0):.1f} ms")
     st = srv.stats()
     srv.close()
     idx.close()

@@ -282,13 +282,18 @@ bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint
 
 /* Serving: subset queries (as bm_subset_pair_supports) against one resident
  * index, with continuous batching.  bm_server_submit copies the query and
- * returns at once.  A pump thread admits queued queries in arrival order
- * whenever one of `streams` launch slots is free and the query's device
- * memory (result k(k-1)/2 uint32, plus 16 k + 4 n bytes of gather data)
- * fits in what is left of `memory_budget`; everything admitted in one pass
- * runs as one persistent compare launch on its own stream, so queries that
- * arrive while others are on the GPU start as soon as a slot and memory
- * free up, overlapping those still running.  Results land in pinned host
+ * returns at once.  A pump thread admits queued queries whenever one of
+ * `streams` launch slots is free and the query's device memory (result
+ * k(k-1)/2 uint32, plus 16 k + 4 n bytes of gather data) fits in what is
+ * left of `memory_budget`.  Queries of at most 2^17 pairs are small, larger
+ * ones large; one admission takes queries of one class, in arrival order
+ * within it (a small query may pass queued large ones), and runs them as one
+ * group on its own stream: one compare launch per tile shape, one workgroup
+ * per work item.  Large groups hold at most streams - 1 slots, so small
+ * queries always find one, and since workgroups end item by item, the items
+ * of a new group get compute units while earlier groups still run.  Queries
+ * that arrive while others are on the GPU thus start as soon as a slot and
+ * memory free up, overlapping those still running.  Results land in pinned host
  * memory; bm_server_wait copies one into the caller's buffer and releases
  * its memory.  Results are identical to bm_subset_pair_supports.
  * The index must stay alive and must not be destroyed while the server

@@ -2828,8 +2828,16 @@ bm_status bm_index_export(const bm_index *cidx, uint32_t *sorted_items, uint32_t
 // copied up) and the item -> position table for the corrections.  The result
 // comes back down into the host mirror; bm_server_wait copies it out and
 // frees the range.  A pump thread retires finished launches, then admits
-// queued queries (first come, first served, while a launch slot is free and
-// the next query fits) into one new persistent launch on a free stream.
+// queued queries into a new group on a free stream: the group's items, one
+// launch per tile shape and one workgroup per item.
+//
+// Work classes: a query of at most kServeSmallPairs pairs is small, others
+// are large, and a group holds queries of one class (first come, first
+// served within the class; a small query may pass queued large ones).  Large
+// groups take at most streams - 1 slots, so a small query always finds a
+// slot, and since workgroups end item by item its items get compute units
+// while a k = 4096 query (tens of ms) runs; it no longer waits for the large
+// query's completion either, which a shared group would impose.
 
 #include <chrono>
 #include <condition_variable>
@@ -2858,14 +2866,17 @@ struct SrvRequest {
     uint32_t batch = 0;
 };
 
+constexpr uint64_t kServeSmallPairs = 1ull << 17;  // k up to about 512
+
 struct SrvLaunch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool active = false;
+    bool large = false;  // carries large queries
     std::vector<uint64_t> reqs;
     DevBuf<WorkItem> items;
     DevBuf<InstDesc> descs;
-    DevBuf<uint32_t> counter, flag;
+    DevBuf<uint32_t> flag;
     WorkItem *h_items = nullptr;  // pinned staging
     InstDesc *h_descs = nullptr;
     uint64_t cap_items = 0, cap_descs = 0;
@@ -2890,7 +2901,6 @@ struct bm_server {
     uint64_t next_id = 1;
     bm_server_stats stats{};
     std::string err;
-    uint32_t grid = 0;  // persistent workgroups per launch
 
     bool alloc(uint64_t need, uint64_t *off)
     {
@@ -2930,6 +2940,7 @@ struct bm_server {
         // result | group offsets (8k) + output positions (4k) + item ids (4k) | item -> position (4n)
         return align256((uint64_t)k * (k - 1) / 2 * 4) + align256(16ull * k) + align256(4ull * idx->n);
     }
+    static bool is_large(uint32_t k) { return (uint64_t)k * (k - 1) / 2 > kServeSmallPairs; }
     hipError_t launch_group(SrvLaunch &L, const std::vector<uint64_t> &ids);
     void retire();
     void admit();
@@ -2993,14 +3004,23 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
     for (uint32_t j = 0; j < nq; j++)
         q_work[j] = class_work(q_cls[j]);
     const std::vector<uint64_t> q_target = shared_targets(q_work, target_items(ix->ctx), 64);
+    // one launch per tile shape, one workgroup per item: workgroups retire
+    // item by item, so launches of other slots get compute units as soon as
+    // any item ends (a persistent launch would hold its units to the end)
+    std::vector<std::vector<WorkItem>> by_variant(kVariantCount);
     for (uint32_t j = 0; j < nq; j++) {
         Plan plan;
-        plan_classes(q_cls[j], j, q_target[j], plan, nullptr, 1, -1);
-        for (auto &v : plan.by_variant)
-            flat.insert(flat.end(), v.begin(), v.end());
+        plan_classes(q_cls[j], j, q_target[j], plan, nullptr, 0, forced_variant());
+        for (int v = 0; v < kVariantCount; v++)
+            by_variant[v].insert(by_variant[v].end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
     }
-    XcdQueues queues;
-    xcd_queues(flat, queues.off);
+    std::vector<std::pair<int, uint32_t>> ranges;
+    for (int v = 0; v < kVariantCount; v++) {
+        if (by_variant[v].empty())
+            continue;
+        ranges.push_back({v, (uint32_t)by_variant[v].size()});
+        flat.insert(flat.end(), by_variant[v].begin(), by_variant[v].end());
+    }
     if (L.cap_items < flat.size()) {
         if (L.h_items)
             (void)hipHostFree(L.h_items);
@@ -3027,11 +3047,11 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         if (e == hipSuccess)
             e = fill_u32(reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), (uint64_t)r.k * (r.k - 1) / 2, 0, s);
     }
-    if (e == hipSuccess)
-        e = fill_u32(L.counter.p, kQueueCounterWords, 0, s);
-    if (e == hipSuccess)
-        e = launch_compare_multi_persistent(L.items.p, queues, L.descs.p, L.counter.p,
-                                            grid, s);
+    uint64_t at = 0;
+    for (size_t r = 0; r < ranges.size() && e == hipSuccess; r++) {
+        e = launch_compare(L.items.p + at, ranges[r].second, L.descs.p, L.h_descs[0], ranges[r].first, s);
+        at += ranges[r].second;
+    }
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];
         if (ix->n_corr == 0)
@@ -3082,17 +3102,38 @@ void bm_server::retire()
 void bm_server::admit()
 {
     while (!queue.empty()) {
+        // a free slot, and the class it may take: large launches leave one
+        // slot to small ones (with a single slot, either class takes it)
         SrvLaunch *L = nullptr;
-        for (auto &c : launches)
-            if (!c->active) {
+        uint32_t n_large = 0;
+        for (auto &c : launches) {
+            if (c->active)
+                n_large += c->large ? 1u : 0u;
+            else if (!L)
                 L = c.get();
-                break;
-            }
+        }
         if (!L)
             return;
+        const bool large_ok = launches.size() == 1 || n_large + 1 < launches.size();
+        // the class of the first queued query that may run now
+        int klass = -1;
+        for (uint64_t id : queue) {
+            const bool lg = is_large(reqs[id].k);
+            if (!lg || large_ok) {
+                klass = lg ? 1 : 0;
+                break;
+            }
+        }
+        if (klass < 0)
+            return;
+        // that class's queries in arrival order, until one does not fit
         std::vector<uint64_t> ids;
-        while (!queue.empty() && ids.size() < opts.max_batch) {
-            SrvRequest &r = reqs[queue.front()];
+        for (auto it = queue.begin(); it != queue.end() && ids.size() < opts.max_batch;) {
+            SrvRequest &r = reqs[*it];
+            if ((is_large(r.k) ? 1 : 0) != klass) {
+                ++it;
+                continue;
+            }
             uint64_t off;
             if (!alloc(r.need, &off)) {
                 stats.admission_waits++;
@@ -3101,8 +3142,8 @@ void bm_server::admit()
             r.off = off;
             r.state = 1;
             r.t_admit = now_s();
-            ids.push_back(queue.front());
-            queue.pop_front();
+            ids.push_back(*it);
+            it = queue.erase(it);
         }
         if (ids.empty())
             return;
@@ -3124,6 +3165,7 @@ void bm_server::admit()
             continue;
         }
         L->reqs = ids;
+        L->large = klass == 1;
         L->active = true;
         stats.launches++;
     }
@@ -3199,7 +3241,6 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         return fail(ctx, BM_ENOMEM, "pinned host pool of %llu bytes", (unsigned long long)srv->pool_bytes);
     }
     srv->free_ranges[0] = srv->pool_bytes;
-    srv->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     srv->sorted_pos.assign(idx->n, -1);
     for (uint32_t p = idx->first_built; p < idx->n; p++)
         srv->sorted_pos[idx->h_sorted_items[p]] = (int32_t)p;
@@ -3208,7 +3249,6 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         SrvLaunch &L = *srv->launches.back();
         HIPC(ctx, hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
         HIPC(ctx, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
-        HIPC(ctx, L.counter.alloc(kQueueCounterWords));
         HIPC(ctx, L.flag.alloc(1));
     }
     bm_server *raw = srv.get();

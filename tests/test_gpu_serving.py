@@ -66,10 +66,10 @@ def test_mixed_stream_equals_alone(ctx, data):
 
 def test_concurrent_queries_equal_single_calls(ctx):
     """Queries in the mix equal the same queries alone.  Three heavy queries (k = 1000 over
-    maps of 1536 groups, about 7e9 lane-operations each) take both launch slots and the head
-    of the queue, so the small queries submitted right behind them must wait and are admitted
-    together: the test asserts that launches were shared (batch > 1) and that several launches
-    ran.  Forced insertion failures make the corrections part of every result."""
+    maps of 1536 groups, about 7e9 lane-operations each) share the one slot large queries may
+    take; the small queries submitted right behind them queue for the other slot and are
+    admitted together: the test asserts that launches were shared (batch > 1) and that several
+    launches ran.  Forced insertion failures make the corrections part of every result."""
     m, n = 200_000, 1000
     off, tids = datagen.bernoulli_sets(m, n, 0.03, seed=23)
     idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=2)
