@@ -299,7 +299,8 @@ def step_mode(args):
                                f"{w.density:.0%} mean density, sigma={sigma}, transactions resident in HBM",
                    "m": w.m, "n": w.n, "nnz": int(tids.size), "sigma": sigma, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": measured_traffic(),
+                     "frac": achieved_tops / PEAK_VALU_TOPS,
+                     "traffic": measured_traffic() if args.workload == "large-zipf" else None,
                      "kernel": "compare: the launches of one all-pairs call (one per tile shape in the plan)",
                      "algorithmic_ops_per_call": ops},
         "cpu_baseline": cpu,
