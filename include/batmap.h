@@ -93,7 +93,9 @@ typedef struct {
     uint32_t slot_bits;      /* bits per slot of this index's BatMaps (8, 16 or 32) */
     uint32_t order;          /* 2 or 3, as built (bm_build_opts.order) */
     uint32_t perm_family;    /* BM_PERM_*: where the permutations pi_t came from */
-    uint32_t reserved;
+    uint32_t plan_packed;    /* 1 when the index's all-pairs plan (made at build time for up to 4096 items,
+                                else at the first all-pairs or frequent-pairs call) puts maps of several
+                                widths into one row tile; 0 when each tile holds one width, or no plan yet */
 } bm_index_stats;
 
 /* bm_index_stats.perm_family.  Any family gives exact counts; they differ in

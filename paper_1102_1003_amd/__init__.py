@@ -70,7 +70,7 @@ class bm_index_stats(ctypes.Structure):
         ("min_support", ctypes.c_uint32), ("nnz", ctypes.c_uint64), ("batmap_bytes", ctypes.c_uint64),
         ("n_failed", ctypes.c_uint64), ("n_corrections", ctypes.c_uint64),
         ("slot_bits", ctypes.c_uint32), ("order", ctypes.c_uint32),
-        ("perm_family", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("perm_family", ctypes.c_uint32), ("plan_packed", ctypes.c_uint32),
     ]
 
 

@@ -383,6 +383,7 @@ struct bm_index {
     uint32_t planned_first = UINT32_MAX;
     uint32_t planned_gen = 0;
     double planned_slot_pairs = 0;
+    bool planned_packed = false;  // the resident plan packs rows of several widths
     DevBuf<uint32_t> thr_counts;
     DevBuf<uint64_t> thr_off;
     DevBuf<char> scan_tmp;
@@ -483,6 +484,15 @@ int forced_variant()
 
 
 
+// Whether whole-index plans may pack rows of several width classes into one
+// tile (the maps of an index lie in sorted order in its arena); on unless
+// BM_PACKED_ROWS=0.
+bool packed_rows()
+{
+    const char *e = getenv("BM_PACKED_ROWS");
+    return !(e && e[0] == '0');
+}
+
 // Persistent plans run as one single-launch list: range (-1, all items),
 // longest first.
 bool use_persistent(const bm_context *ctx) { return ctx->persistent && forced_variant() < 0; }
@@ -559,13 +569,14 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
     Plan plan;
     const bool single = single_launch(ctx, idx->planes);
     plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr, single ? 1 : 0,
-                 forced_variant(), false, idx->planes);
+                 forced_variant(), false, idx->planes, packed_rows());
     bm_status st = upload_plan(idx, plan, single, idx->work, idx->work_ranges);
     if (st != BM_OK)
         return st;
     idx->planned_first = first;
     idx->planned_gen = ctx->tune_gen;
     idx->planned_slot_pairs = plan.slot_pairs;
+    idx->planned_packed = plan.packed;
     return BM_OK;
 }
 
@@ -1907,6 +1918,7 @@ bm_status bm_index_stats_get(const bm_index *idx, bm_index_stats *out)
     out->slot_bits = idx->planes;
     out->order = idx->order;
     out->perm_family = idx->perm.table ? BM_PERM_CALLER : (idx->block_family ? BM_PERM_BLOCK : BM_PERM_CHAIN);
+    out->plan_packed = idx->planned_first != UINT32_MAX && idx->planned_packed ? 1u : 0u;
     return BM_OK;
 }
 
@@ -2065,7 +2077,7 @@ bm_status bm_frequent_pairs_noalloc(bm_index *idx, uint32_t min_support, bm_pair
     if (!own) {
         Plan plan;
         plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr,
-                     single_launch(ctx, idx->planes) ? 1 : 0, forced_variant(), false, idx->planes);
+                     single_launch(ctx, idx->planes) ? 1 : 0, forced_variant(), false, idx->planes, packed_rows());
         if (!plan.complete)
             return fail(ctx, BM_EINVAL, "no compare tile shape for %u-bit slots in this launch mode", idx->planes);
         flatten_plan(plan, single_launch(ctx, idx->planes), flat, ranges);

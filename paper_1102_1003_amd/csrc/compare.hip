@@ -222,6 +222,13 @@ __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
 // hardware issues oldest first among equal priorities; persistent waves never
 // retire, so without the rotation the oldest wave of each SIMD would keep the
 // lead for the whole launch, and the SIMD completes fewer items in all.
+// Row tiles of mixed widths (kFlagMixed): h walks the widest row's G_row
+// groups while row map p, of G_p = goff[p + 1] - goff[p] groups (the maps lie
+// in sorted order), reads its group h mod G_p, so the column groups h + u G_row
+// that meet it are every column group once, as the wrap requires (G_p divides
+// G_row).  An item's range never crosses a multiple of any of its rows' G_p,
+// so h mod G_p = h - (c0 - c0 mod G_p) throughout: the row's base moves back
+// by that amount once, and the loop is the same as for one width.
 template <int R, int MJ, int H = 1, int kRotate = 0, bool kRect = false>
 __device__ void process_rows(const WorkItem &w, const InstDesc &d)
 {
@@ -236,6 +243,16 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
         int rho = lane + 64 * r;
         uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
         rbase[r] = goff[w.row0 + rr] * 2;
+    }
+    if (w.flags & kFlagMixed) {
+        // base - 2 (c0 - c0 mod G_p), modulo 2^64: h >= c0 brings it back
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int rho = lane + 64 * r;
+            uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
+            const uint32_t gp = (uint32_t)(goff[w.row0 + rr + 1] - goff[w.row0 + rr]);
+            rbase[r] -= 2 * (uint64_t)(w.c0 - w.c0 % gp);
+        }
     }
     // column maps' first groups (arena group indices fit 32 bits: < 128 GB)
     uint32_t cbase[MJ];
@@ -836,6 +853,7 @@ struct Kernels {
         BM_GP(4, 4),         BM_GP(2, 8),                                                    \
         BM_ROWS(2, 16, 2),   BM_ROWS(2, 4, 2),    BM_ROWS(3, 12, 2),                         \
         BM_ROWS_W(16, 2, 8), BM_GP_W(16, 4, 4),   BM_ROWS_W(32, 1, 8), BM_GP_W(32, 2, 4),    \
+        BM_ROWS(3, 11, 2),   BM_ROWS(3, 8, 2),    BM_ROWS(3, 4, 2),    BM_ROWS(2, 11, 2),    \
     }
 
 #define RECT false

@@ -3,6 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <map>
+#include <tuple>
 #include <unordered_map>
 
 namespace bm {
@@ -28,8 +31,8 @@ const VariantInfo kInfo[kVariantCount] = {
     // row-resident, two row groups per step (one 64-byte scalar load per
     // column for both): 128 x 12 and 128 x 8 run at 62 % / 55 % of the VALU
     // peak on the large Zipf instance against 47 % / 42 % with one
-    {128, 12, true, 2, 1, true, 1.30f},
-    {128, 8, true, 2, 2, true, 1.10f},
+    {128, 12, true, 2, 1, true, 1.30f, 0.f, 8, true},
+    {128, 8, true, 2, 2, true, 1.10f, 0.f, 8, true},
     {64, 16, true, 2, -1, false, 0.70f},
     // row-resident, software-pipelined column chunks
     {128, 8, true, 1, -1, false, 0.95f},
@@ -41,13 +44,13 @@ const VariantInfo kInfo[kVariantCount] = {
     {2, 8, true, 64, -1, true, 0.30f},
     // row-resident, two row groups per step, 16 and 4 columns
     {128, 16, true, 2, -1, false, 1.20f},
-    {128, 4, true, 2, 3, false, 0.70f},
+    {128, 4, true, 2, 3, false, 0.70f, 0.f, 8, true},
     // row-resident, three rows per lane (192 x 12), two row groups per step.
     // Its rows are not prefetched (registers), so a step needs the wrapped
     // column groups of a wider class to hide their load: 5.54 ms against
     // 5.98 ms for 128 x 12 on the large Zipf instance, but 2.40 against 2.28
     // between maps of one width (the paper-replica instance).
-    {192, 12, true, 2, 0, true, 1.40f, 1.20f},
+    {192, 12, true, 2, 0, true, 1.40f, 1.20f, 8, true},
     // wider slots (Sec. III-A, uncompressed case): 16 planes per group, then
     // 32; a group pair costs W + 1 ops instead of 9, so their speeds are
     // relative to each other only (the planner never mixes slot widths)
@@ -55,6 +58,12 @@ const VariantInfo kInfo[kVariantCount] = {
     {4, 4, true, 64, -1, true, 0.30f, 0.f, 16},
     {64, 8, true, 1, -1, true, 1.00f, 0.f, 32},
     {2, 4, true, 64, -1, true, 0.30f, 0.f, 32},
+    // column tiles of 11, 8 and 4 maps for the packed planner, which splits a
+    // width class's maps into tiles of 12, 11, 8 and 4 with the least padding
+    {192, 11, true, 2, -1, false, 1.38f, 1.18f, 8, true},
+    {192, 8, true, 2, -1, false, 1.30f, 1.12f, 8, true},
+    {192, 4, true, 2, -1, false, 1.00f, 0.90f, 8, true},
+    {128, 11, true, 2, -1, false, 1.28f, 0.f, 8, true},
 };
 
 }  // namespace
@@ -170,119 +179,77 @@ void xcd_order(std::vector<WorkItem> &v)
     v.swap(out);
 }
 
-}  // namespace
-
-void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
-                  const std::vector<float> *speeds, int single, int pinned, bool cross_only, uint32_t planes)
+// Speed of shape v at a wrap bucket: the measured table when given and
+// usable, else the catalogue's (between maps of one width, its no-wrap rate).
+float shape_speed(int v, int bucket, const std::vector<float> *speeds)
 {
-    std::vector<ClassPair> pairs;
-    for (size_t a = 0; a < cls.size(); a++) {
-        for (size_t b = a; b < cls.size(); b++) {
-            const bool same = a == b;
-            if (same && (cls[a].count < 2 || cross_only))
-                continue;
-            pairs.push_back({cls[a], cls[b], same, (uint16_t)inst});
-        }
-    }
-    plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+    const VariantInfo &V = kInfo[v];
+    const float builtin = bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed;
+    if (!speeds || (int)speeds->size() != kVariantCount * kWrapBuckets)
+        return builtin;
+    // a measured speed that is not a positive finite rate says nothing about
+    // the shape: weigh it by the catalogue instead
+    const float s = (*speeds)[v * kWrapBuckets + bucket];
+    return (s > 0 && std::isfinite(s)) ? s : builtin;
 }
 
-void plan_cross(const std::vector<Cls> &a_cls, const std::vector<Cls> &b_cls, uint32_t na, uint32_t nb,
-                uint64_t target_items, Plan &plan, const std::vector<float> *speeds, int single, int pinned,
-                uint32_t planes)
-{
-    // instance 0 indexes [A maps, B maps], instance 1 [B maps, A maps]; the
-    // narrower class of each pair gives the rows
-    std::vector<ClassPair> pairs;
-    for (const Cls &A : a_cls)
-        for (const Cls &B : b_cls) {
-            if (A.r <= B.r)
-                pairs.push_back({A, Cls{B.r, na + B.start, B.count}, false, 0});
-            else
-                pairs.push_back({B, Cls{A.r, nb + A.start, A.count}, false, 1});
-        }
-    plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
-}
+// One tile of a plan: rows [row0, row0 + nrow) against columns [col0, col0 + ncol).
+struct Tile {
+    uint32_t row0, col0;
+    uint16_t nrow, ncol;
+    uint16_t flags;  // bit 0 (emit only row < col) and kFlagMixed
+};
 
-void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan &plan,
-                const std::vector<float> *speeds, int single, int pinned, uint32_t planes)
+// Tiles of one shape with the same group counts: their group ranges are cut
+// alike, so the tiles running at one time share a range of the maps.
+struct TileGroup {
+    int v = 0;
+    double speed = 1;
+    uint32_t Ga = 0, Gb = 0;  // row groups walked (the widest row's) and column groups
+    uint32_t Gmin = 0;        // the narrowest row's groups (< Ga: its tiles are of mixed widths)
+    uint32_t row_lo = ~0u, row_hi = 0, col_lo = ~0u, col_hi = 0;  // maps the tiles read
+    uint16_t inst = 0;
+    std::vector<Tile> tiles;
+    void add(const Tile &t)
+    {
+        tiles.push_back(t);
+        row_lo = std::min(row_lo, t.row0);
+        row_hi = std::max(row_hi, t.row0 + t.nrow);
+        col_lo = std::min(col_lo, t.col0);
+        col_hi = std::max(col_hi, t.col0 + t.ncol);
+    }
+};
+
+// The largest divisor of G (3 or 1 times a power of two, like every group
+// count) that is a multiple of align and at most x; align itself if none is.
+// Ranges of that length never cross a multiple of G.
+uint32_t divisor_at_most(uint32_t G, uint32_t x, uint32_t align)
 {
-    const int nv = kVariantCount;
-    plan.by_variant.assign(nv, {});
-    plan.slot_pairs = 0;
-    plan.complete = true;
-    struct Choice {
-        size_t k;  // class pair
-        int v;
-        double speed;
-    };
-    std::vector<Choice> choices;
-    double total_work = 0;  // padded pair-groups over speed: wave time, arbitrary unit
-    for (size_t k = 0; k < pairs.size(); k++) {
-        const Cls &rowc = pairs[k].A, &colc = pairs[k].B;
-        const bool same = pairs[k].same;
-        {
-            int best = -1;
-            double best_cost = 1e300, best_speed = 1;
-            const int bucket = wrap_bucket(colc.r / rowc.r);
-            const bool tuned = speeds && (int)speeds->size() == nv * kWrapBuckets;
-            for (int v = 0; v < nv; v++) {
-                // measured speeds weigh the default shapes against each other; the
-                // staged-tile shapes time well on uniform synthetic tiles but lose on
-                // skewed instances, so they are used only when pinned
-                const VariantInfo &V = variant_info(v);
-                if (!shape_allowed(v, single, pinned, planes))
-                    continue;
-                const float builtin = bucket == 0 && V.speed_nowrap > 0 ? V.speed_nowrap : V.speed;
-                float speed = tuned ? (*speeds)[v * kWrapBuckets + bucket] : builtin;
-                // a measured speed that is not a positive finite rate says nothing
-                // about the shape: weigh it by the catalogue instead
-                if (!(speed > 0) || !std::isfinite(speed))
-                    speed = builtin;
-                const uint32_t bi = V.bi, bj = V.bj;
-                uint64_t cnt;
-                tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
-                double cost = (double)cnt * bi * bj / speed;
-                // prefer larger tiles on ties (more reuse per loaded group)
-                if (cost < best_cost) {  // variants are listed largest tile first
-                    best_cost = cost;
-                    best = v;
-                    best_speed = speed;
-                }
-            }
-            // every catalogue speed is > 0, so a shape was chosen above unless
-            // none runs this mode and slot width (the single launch has 8-bit
-            // bodies only): the plan is then marked incomplete for the caller
-            for (int v = 0; best < 0 && v < nv; v++)
-                if (shape_allowed(v, single, -1, planes))
-                    best = v, best_speed = variant_info(v).speed;
-            if (best < 0) {
-                plan.complete = false;
-                continue;
-            }
-            const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
-            uint64_t cnt;
-            tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
-            double np = same ? 0.5 * rowc.count * (rowc.count - 1.0) : (double)rowc.count * colc.count;
-            plan.slot_pairs += np * 3.0 * colc.r;
-            total_work += (double)cnt * bi * bj * (3.0 * colc.r / kSlotsPerGroup) / best_speed;
-            choices.push_back({k, best, best_speed});
+    uint32_t best = align;
+    for (uint32_t odd : {1u, 3u}) {
+        if (G % odd)
+            continue;
+        for (uint32_t d = G / odd; d >= align; d /= 2) {
+            if (G % d == 0 && d % align == 0 && d <= x && d > best)
+                best = d;
+            if (d % 2)
+                break;
         }
     }
+    return best;
+}
+
+// Cuts every group's tiles into group ranges and emits the items: each item
+// about total_work / target_items of wave time, range-major within a group,
+// then all items of a shape longest first and in XCD order.
+void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64_t target_items, Plan &plan)
+{
     // every item should take about the same time: work_per_item of wave time
     const double work_per_item = total_work / (double)std::max<uint64_t>(target_items, 1);
-    std::vector<std::pair<uint32_t, uint32_t>> tiles;
-    for (const Choice &ch : choices) {
-        const Cls &A = pairs[ch.k].A, &B = pairs[ch.k].B;
-        const bool same = pairs[ch.k].same;
-        const uint16_t inst = pairs[ch.k].inst;
-        const VariantInfo &V = variant_info(ch.v);
+    for (const TileGroup &g : groups) {
+        const VariantInfo &V = variant_info(g.v);
         const uint32_t bi = V.bi, bj = V.bj;
-        tiles.clear();
-        uint64_t cnt;
-        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
-        const uint32_t Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
-        const uint32_t Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
+        const uint32_t Ga = g.Ga, Gb = g.Gb;
         const bool rows = V.row_resident;
         // row-resident items walk row groups (each meeting Gb / Ga column
         // groups); staged items walk column groups in stages of kStageGroups
@@ -292,12 +259,12 @@ void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan
         // should hold about work_per_item, and at least min_steps groups
         const uint32_t align = V.step;
         const double min_steps = (double)std::max<uint32_t>(8 * align, kMinPieceGroups);
-        const double steps = std::max(work_per_item / ((double)bi * bj / ch.speed), min_steps);
+        const double steps = std::max(work_per_item / ((double)bi * bj / g.speed), min_steps);
         double pieces_d = std::ceil((double)span * unit / steps);
-        // Locality: one range of every map of the class pair should stay in
-        // the last-level caches while the tiles that share it run, so ranges
+        // Locality: one range of every map the group reads should stay in the
+        // last-level caches while the tiles that share it run, so ranges
         // shrink until that working set is at most kLocalityBytes.
-        const double ws = 32.0 * span * ((double)A.count + (double)B.count * unit);
+        const double ws = 32.0 * span * ((double)(g.row_hi - g.row_lo) + (double)(g.col_hi - g.col_lo) * unit);
         pieces_d = std::max(pieces_d, std::ceil(ws / kLocalityBytes));
         // ranges of at least one step of the shape and min_steps groups of work
         pieces_d = std::min(pieces_d, std::floor((double)span / align));
@@ -306,26 +273,29 @@ void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan
         // equal range lengths (a multiple of `align`), the last one shorter
         uint32_t plen = (span + pieces - 1) / pieces;
         plen = (plen + align - 1) / align * align;
+        if (g.Gmin && g.Gmin < Ga)
+            plen = divisor_at_most(g.Gmin, plen, align);
         pieces = (span + plen - 1) / plen;
+        const uint16_t base_flags = (uint16_t)((rows ? 2u : 0u) | (V.multi >= 0 ? (uint32_t)V.multi << 2 : 0u));
         // range-major order: all tiles of range k before range k + 1, so the
         // waves running at one time share one range of the maps
         for (uint32_t k = 0; k < pieces; k++) {
-            for (auto &t : tiles) {
-                uint64_t c0 = (uint64_t)k * plen, c1 = std::min<uint64_t>(span, c0 + plen);
-                if (c1 <= c0)
-                    continue;
+            const uint64_t c0 = (uint64_t)k * plen, c1 = std::min<uint64_t>(span, c0 + plen);
+            if (c1 <= c0)
+                continue;
+            for (const Tile &t : g.tiles) {
                 WorkItem w;
-                w.row0 = A.start + t.first * bi;
-                w.col0 = B.start + t.second * bj;
-                w.nrow = (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi);
-                w.ncol = (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj);
+                w.row0 = t.row0;
+                w.col0 = t.col0;
+                w.nrow = t.nrow;
+                w.ncol = t.ncol;
                 w.c0 = (uint32_t)c0;
                 w.c1 = (uint32_t)c1;
                 w.row_groups = Ga;
                 w.col_groups = Gb;
-                w.inst = inst;
-                w.flags = (uint16_t)((same ? 1u : 0u) | (rows ? 2u : 0u) | (V.multi >= 0 ? (uint32_t)V.multi << 2 : 0u));
-                plan.by_variant[ch.v].push_back(w);
+                w.inst = g.inst;
+                w.flags = (uint16_t)(base_flags | t.flags);
+                plan.by_variant[g.v].push_back(w);
             }
         }
     }
@@ -372,6 +342,270 @@ void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan
         v.swap(sorted);
         xcd_order(v);
     }
+}
+
+// One shape per class pair (the lowest padded work over speed); returns the
+// plan's total of that cost, and false when some pair has no shape.
+struct Choice {
+    size_t k;  // class pair
+    int v;
+    double speed;
+};
+
+bool classic_choices(const std::vector<ClassPair> &pairs, const std::vector<float> *speeds, int single, int pinned,
+                     uint32_t planes, std::vector<Choice> &choices, double &total_work, double &slot_pairs)
+{
+    bool complete = true;
+    total_work = 0;  // padded pair-groups over speed: wave time, arbitrary unit
+    slot_pairs = 0;
+    for (size_t k = 0; k < pairs.size(); k++) {
+        const Cls &rowc = pairs[k].A, &colc = pairs[k].B;
+        const bool same = pairs[k].same;
+        int best = -1;
+        double best_cost = 1e300, best_speed = 1;
+        const int bucket = wrap_bucket(colc.r / rowc.r);
+        for (int v = 0; v < kVariantCount; v++) {
+            // measured speeds weigh the default shapes against each other; the
+            // staged-tile shapes time well on uniform synthetic tiles but lose on
+            // skewed instances, so they are used only when pinned
+            if (!shape_allowed(v, single, pinned, planes))
+                continue;
+            const VariantInfo &V = variant_info(v);
+            const float speed = shape_speed(v, bucket, speeds);
+            uint64_t cnt;
+            tiles_for(rowc, colc, same, V.bi, V.bj, nullptr, &cnt);
+            const double cost = (double)cnt * V.bi * V.bj / speed;
+            // prefer larger tiles on ties (more reuse per loaded group)
+            if (cost < best_cost) {  // variants are listed largest tile first
+                best_cost = cost;
+                best = v;
+                best_speed = speed;
+            }
+        }
+        // every catalogue speed is > 0, so a shape was chosen above unless
+        // none runs this mode and slot width (the single launch has 8-bit
+        // bodies only): the plan is then marked incomplete for the caller
+        for (int v = 0; best < 0 && v < kVariantCount; v++)
+            if (shape_allowed(v, single, -1, planes))
+                best = v, best_speed = variant_info(v).speed;
+        if (best < 0) {
+            complete = false;
+            continue;
+        }
+        const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
+        uint64_t cnt;
+        tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
+        const double np = same ? 0.5 * rowc.count * (rowc.count - 1.0) : (double)rowc.count * colc.count;
+        slot_pairs += np * 3.0 * colc.r;
+        total_work += (double)cnt * bi * bj * (3.0 * colc.r / kSlotsPerGroup) / best_speed;
+        choices.push_back({k, best, best_speed});
+    }
+    return complete;
+}
+
+// The packed shape of r rows per lane (2 or 3) and mj columns.
+int packed_shape(uint32_t r, uint32_t mj)
+{
+    for (int v = 0; v < kVariantCount; v++) {
+        const VariantInfo &V = kInfo[v];
+        if (V.packed && V.bi == 64 * r && V.bj == mj)
+            return v;
+    }
+    return -1;
+}
+
+// Column tiles of a class of c maps: shapes of {12, 11, 8, 4} columns with
+// the fewest padded columns, then the fewest tiles (largest first); each
+// entry is (columns of the shape, maps in the tile).
+void column_split(uint32_t c, std::vector<std::pair<uint32_t, uint32_t>> &sizes)
+{
+    static const uint32_t kMj[] = {12, 11, 8, 4};
+    std::vector<std::pair<uint32_t, uint32_t>> best(c + 1, {0, 0});  // (padding, tiles)
+    std::vector<uint32_t> first(c + 1, 0);
+    for (uint32_t x = 1; x <= c; x++) {
+        std::pair<uint32_t, uint32_t> b{~0u, ~0u};
+        for (uint32_t m : kMj) {
+            const std::pair<uint32_t, uint32_t> cand =
+                m >= x ? std::make_pair(m - x, 1u) : std::make_pair(best[x - m].first, best[x - m].second + 1);
+            if (cand < b) {
+                b = cand;
+                first[x] = m;
+            }
+        }
+        best[x] = b;
+    }
+    sizes.clear();
+    for (uint32_t x = c; x > 0;) {
+        const uint32_t m = first[x];
+        sizes.push_back({m, std::min(m, x)});
+        x -= std::min(m, x);
+    }
+    std::sort(sizes.begin(), sizes.end(), std::greater<std::pair<uint32_t, uint32_t>>());
+}
+
+// The packed plan: for each column class, every narrower-or-equal map is a
+// row (Sec. III-C's upper triangle: rows below each column's sorted index),
+// in row tiles of 192 (the last one of 128 when cheaper) that may cross
+// width classes.  Column tiles stay inside their class.  Returns the total
+// padded work over speed of its tiles.
+double packed_groups(const std::vector<Cls> &cls, uint16_t inst, const std::vector<float> *speeds,
+                     std::vector<TileGroup> &groups)
+{
+    groups.clear();
+    if (cls.empty())
+        return 0;
+    const uint32_t base = cls.front().start;
+    const uint32_t n_end = cls.back().start + cls.back().count;
+    std::vector<uint32_t> G(n_end - base);
+    for (const Cls &c : cls)
+        for (uint32_t i = 0; i < c.count; i++)
+            G[c.start + i - base] = (uint32_t)(3ull * c.r / kSlotsPerGroup);
+    auto g_of = [&](uint32_t p) { return G[p - base]; };
+    double total = 0;
+    std::map<std::tuple<int, uint32_t, uint32_t, uint32_t>, uint32_t> group_of;
+    std::vector<std::pair<uint32_t, uint32_t>> sizes;
+    for (const Cls &B : cls) {
+        if (B.count == 0)
+            continue;
+        const uint32_t Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+        column_split(B.count, sizes);
+        uint32_t c0 = B.start;
+        for (const auto &sz : sizes) {
+            const uint32_t mj = sz.first, ncol = sz.second;
+            // rows [base, c0 + ncol - 1): every row below some column of the tile
+            const uint32_t hi = c0 + ncol - 1;
+            uint32_t r0 = base;
+            while (r0 < hi) {
+                const uint32_t left = hi - r0;
+                uint32_t R = 3;
+                if (left < 192) {
+                    // one tile of 192 rows or tiles of 128 for the rest
+                    const bool wrap = g_of(hi - 1) < Gb;
+                    const int b3 = packed_shape(3, mj), b2 = packed_shape(2, mj);
+                    const double c3 = 192.0 / shape_speed(b3, wrap ? 1 : 0, speeds);
+                    const double c2 = 128.0 * ((left + 127) / 128) / shape_speed(b2, wrap ? 1 : 0, speeds);
+                    R = c2 < c3 ? 2 : 3;
+                }
+                const uint32_t n = std::min(64 * R, left);
+                // rows sorted by width: the first is the narrowest
+                const uint32_t Ga = g_of(r0 + n - 1), Gmin = g_of(r0);
+                const bool mixed = Gmin != Ga;
+                const int v = packed_shape(R, mj);
+                const int bucket = wrap_bucket(Gb / Ga);
+                auto it = group_of.emplace(std::make_tuple(v, Ga, Gb, Gmin), (uint32_t)groups.size()).first;
+                if (it->second == groups.size()) {
+                    TileGroup g;
+                    g.v = v;
+                    g.speed = shape_speed(v, bucket, speeds);
+                    g.Ga = Ga;
+                    g.Gb = Gb;
+                    g.Gmin = Gmin;
+                    g.inst = inst;
+                    groups.push_back(std::move(g));
+                }
+                TileGroup &g = groups[it->second];
+                // bit 0 when some row index reaches the tile's first column
+                const uint16_t fl = (uint16_t)((r0 + n - 1 >= c0 ? 1u : 0u) | (mixed ? kFlagMixed : 0u));
+                g.add({r0, c0, (uint16_t)n, (uint16_t)ncol, fl});
+                total += (double)(64 * R) * mj * Gb / g.speed;
+                r0 += n;
+            }
+            c0 += ncol;
+        }
+    }
+    return total;
+}
+
+}  // namespace
+
+void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
+                  const std::vector<float> *speeds, int single, int pinned, bool cross_only, uint32_t planes,
+                  bool packed_rows)
+{
+    std::vector<ClassPair> pairs;
+    for (size_t a = 0; a < cls.size(); a++) {
+        for (size_t b = a; b < cls.size(); b++) {
+            const bool same = a == b;
+            if (same && (cls[a].count < 2 || cross_only))
+                continue;
+            pairs.push_back({cls[a], cls[b], same, (uint16_t)inst});
+        }
+    }
+    if (!packed_rows || cross_only || single || pinned >= 0 || planes != 8) {
+        plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+        return;
+    }
+    std::vector<Choice> choices;
+    double classic_work = 0, slot_pairs = 0;
+    const bool complete = classic_choices(pairs, speeds, 0, -1, planes, choices, classic_work, slot_pairs);
+    std::vector<TileGroup> groups;
+    const double packed_work = packed_groups(cls, (uint16_t)inst, speeds, groups);
+    if (!complete || !(packed_work < classic_work)) {
+        plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+        return;
+    }
+    plan.by_variant.assign(kVariantCount, {});
+    plan.complete = true;
+    plan.packed = true;
+    plan.slot_pairs = slot_pairs;
+    emit_groups(groups, packed_work, target_items, plan);
+}
+
+void plan_cross(const std::vector<Cls> &a_cls, const std::vector<Cls> &b_cls, uint32_t na, uint32_t nb,
+                uint64_t target_items, Plan &plan, const std::vector<float> *speeds, int single, int pinned,
+                uint32_t planes)
+{
+    // instance 0 indexes [A maps, B maps], instance 1 [B maps, A maps]; the
+    // narrower class of each pair gives the rows
+    std::vector<ClassPair> pairs;
+    for (const Cls &A : a_cls)
+        for (const Cls &B : b_cls) {
+            if (A.r <= B.r)
+                pairs.push_back({A, Cls{B.r, na + B.start, B.count}, false, 0});
+            else
+                pairs.push_back({B, Cls{A.r, nb + A.start, A.count}, false, 1});
+        }
+    plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
+}
+
+void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan &plan,
+                const std::vector<float> *speeds, int single, int pinned, uint32_t planes)
+{
+    plan.by_variant.assign(kVariantCount, {});
+    plan.packed = false;
+    std::vector<Choice> choices;
+    double total_work = 0;
+    plan.complete = classic_choices(pairs, speeds, single, pinned, planes, choices, total_work, plan.slot_pairs);
+    std::vector<TileGroup> groups;
+    std::vector<std::pair<uint32_t, uint32_t>> tiles;
+    for (const Choice &ch : choices) {
+        const Cls &A = pairs[ch.k].A, &B = pairs[ch.k].B;
+        const bool same = pairs[ch.k].same;
+        const VariantInfo &V = variant_info(ch.v);
+        const uint32_t bi = V.bi, bj = V.bj;
+        tiles.clear();
+        uint64_t cnt;
+        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
+        TileGroup g;
+        g.v = ch.v;
+        g.speed = ch.speed;
+        g.Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
+        g.Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+        g.inst = pairs[ch.k].inst;
+        // the working set is the whole class pair's, whatever tiles it holds
+        g.row_lo = A.start;
+        g.row_hi = A.start + A.count;
+        g.col_lo = B.start;
+        g.col_hi = B.start + B.count;
+        g.tiles.reserve(tiles.size());
+        for (auto &t : tiles)
+            g.tiles.push_back({A.start + t.first * bi, B.start + t.second * bj,
+                               (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi),
+                               (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj),
+                               (uint16_t)(same ? 1u : 0u)});
+        groups.push_back(std::move(g));
+    }
+    emit_groups(groups, total_work, target_items, plan);
 }
 
 void xcd_queues(std::vector<WorkItem> &flat, uint32_t off[kXcds + 1])

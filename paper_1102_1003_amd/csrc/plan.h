@@ -17,7 +17,11 @@ constexpr uint32_t kWordsPerGroup = 8;
 constexpr uint32_t kStageGroups = 4;
 
 // One unit of compare work: a tile of row maps (narrower width class) against
-// a tile of column maps (wider or equal class).  Two loop orders exist:
+// a tile of column maps (wider or equal class).  A row tile of mixed widths
+// (flags bit 5) holds rows of several classes, none wider than the columns:
+// G_row is then the widest row's group count, row map p, of G_p groups, meets
+// row group h mod G_p in place of h, and the item's range [c0, c1) crosses no
+// multiple of any of its rows' G_p.  Two loop orders exist:
 //  - staged tiles walk column groups c in [c0, c1) and meet row group c mod G_row;
 //  - the other shapes walk row groups h in [c0, c1) and, for each, every
 //    column group h + u G_row, u = 0 .. G_col / G_row - 1 (the Fig. 1 wrap).
@@ -30,8 +34,9 @@ struct WorkItem {
     uint32_t row_groups;  // G_row = 3 r_row / 32
     uint32_t col_groups;  // G_col = 3 r_col / 32
     uint16_t inst;        // instance (descriptor index)
-    uint16_t flags;       // bit 0: same width class -> emit only row < col; bit 1: walks row groups;
-                          // bits 2..4: body of the single-launch kernel
+    uint16_t flags;       // bit 0: emit only row < col (some row index >= some column index);
+                          // bit 1: walks row groups; bits 2..4: body of the single-launch kernel;
+                          // bit 5: rows of mixed widths (G_p = goff[p + 1] - goff[p])
 };
 static_assert(sizeof(WorkItem) == 32, "work item layout");
 
@@ -46,8 +51,11 @@ struct VariantInfo {
     float speed;          // relative group-pair rate of an unpadded tile (planner weight)
     float speed_nowrap = 0;  // the same between maps of one width, when it differs (0: as speed)
     uint32_t planes = 8;  // bits per slot of the maps it compares (8, 16, 32)
+    bool packed = false;  // offered to the packed planner (rows of several classes per tile)
 };
-constexpr int kVariantCount = 26;
+constexpr int kVariantCount = 30;
+// Item flag of a mixed-width row tile.
+constexpr uint16_t kFlagMixed = 32;
 const VariantInfo &variant_info(int v);
 // Whether plan_classes may choose shape v for maps of `planes`-bit slots:
 // only shapes of that slot width; single-launch mode (single != 0) takes
@@ -78,6 +86,7 @@ struct Plan {
     std::vector<std::vector<WorkItem>> by_variant;
     double slot_pairs = 0;  // sum over planned pairs of 3 max(r_i, r_j)
     bool complete = true;   // false when some class pair had no shape for the mode and slot width
+    bool packed = false;    // rows packed across width classes (see plan_classes)
 };
 
 // Groups an item visits (longest first gives a better tail).
@@ -96,9 +105,15 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
 // single: 0 = any default shape (one launch per shape); 1 = shapes of the
 // single-launch kernel only.  pinned >= 0 forces that shape (single == 0 only).
 // cross_only: only pairs of different classes.
+// packed_rows: the maps' group offsets are contiguous in sorted order (map p
+// holds goff[p + 1] - goff[p] groups), so row tiles may hold several width
+// classes.  The planner then also tiles every column class against all
+// narrower-or-equal rows at once (rows packed across classes, column tiles
+// of 12, 11, 8 or 4 maps) and keeps that plan when its padded work over speed
+// is lower (8-bit slots, neither single-launch nor pinned).
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
                   const std::vector<float> *speeds, int single, int pinned, bool cross_only = false,
-                  uint32_t planes = 8);
+                  uint32_t planes = 8, bool packed_rows = false);
 
 // One pair of width classes to plan: rows from A (the narrower), columns from
 // B; same: A and B are one class (only row < column); inst: the work items'

@@ -2,7 +2,10 @@
 // tests/test_planner.py; no GPU).  It plans the pairs of a list of width
 // classes and verifies every work item against the shape catalogue, then that
 // the items together visit every pair i < j over all 3 max(r_i, r_j) / 32
-// groups of the wider map exactly once (the Fig. 1 wrap included).
+// groups of the wider map exactly once (the Fig. 1 wrap included): the count
+// of groups visited, their sum and the sum of their squares must all match.
+// With packed rows, a row tile may hold several width classes (flag
+// kFlagMixed); its range must then cross no multiple of any row's group count.
 // Built with -DPLAN_CHECK_MAIN it is also a program (compiled with the
 // address and undefined-behaviour sanitizers by the same test) that reads
 // cases from stdin, one per line:
@@ -35,8 +38,8 @@ int fail(char *msg, uint32_t len, int code, const char *fmt, ...)
 }  // namespace
 
 extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *count, uint64_t target, int single,
-                          int pinned, uint32_t inst, const float *speeds, uint32_t planes, char *msg,
-                          uint32_t msg_len, uint64_t *n_items)
+                          int pinned, uint32_t inst, const float *speeds, uint32_t planes, int packed_rows,
+                          char *msg, uint32_t msg_len, uint64_t *n_items, int *packed_out)
 {
     std::vector<Cls> cls;
     uint32_t n = 0;
@@ -52,7 +55,12 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
     std::vector<float> sp_table;
     if (speeds)
         sp_table.assign(speeds, speeds + kVariantCount * kWrapBuckets);
-    plan_classes(cls, inst, target, plan, speeds ? &sp_table : nullptr, single, pinned, false, planes);
+    plan_classes(cls, inst, target, plan, speeds ? &sp_table : nullptr, single, pinned, false, planes,
+                 packed_rows != 0);
+    if (packed_out)
+        *packed_out = plan.packed;
+    if (plan.packed && (!packed_rows || single || pinned >= 0 || planes != 8))
+        return fail(msg, msg_len, 1, "packed plan where packing does not apply");
     if ((int)plan.by_variant.size() != kVariantCount)
         return fail(msg, msg_len, 1, "plan has %zu shape lists", plan.by_variant.size());
     // the single launch has bodies for 8-bit slots only: a plan for wider
@@ -65,7 +73,9 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
         return 0;
     }
     const bool pin_applies = pinned >= 0 && variant_info(pinned).planes == planes;
-    std::vector<uint64_t> cov((uint64_t)n * (n ? n - 1 : 0) / 2, 0);
+    const uint64_t n_pairs = (uint64_t)n * (n ? n - 1 : 0) / 2;
+    std::vector<uint64_t> cov(n_pairs, 0);
+    std::vector<unsigned __int128> cov1(n_pairs, 0), cov2(n_pairs, 0);  // sum of g, sum of g^2
     auto pidx = [&](uint64_t i, uint64_t j) { return i * n - i * (i + 1) / 2 + (j - i - 1); };
     uint64_t items = 0;
     for (int v = 0; v < kVariantCount; v++) {
@@ -76,8 +86,10 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
                 return fail(msg, msg_len, 2, "shape %d of %u-bit slots for %u-bit maps", v, V.planes, planes);
             if (single && (V.multi < 0 || !V.row_resident))
                 return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
-            if (!single && !pin_applies && !V.default_choice)
+            if (!single && !pin_applies && !V.default_choice && !(plan.packed && V.packed))
                 return fail(msg, msg_len, 2, "tuning-only shape %d chosen without a pin", v);
+            if (plan.packed && !V.packed)
+                return fail(msg, msg_len, 2, "shape %d in a packed plan", v);
             if (!single && pin_applies && v != pinned)
                 return fail(msg, msg_len, 3, "shape %d while %d is pinned", v, pinned);
             if (w.inst != inst)
@@ -86,14 +98,18 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
                 return fail(msg, msg_len, 5, "shape %d tile %u x %u", v, w.nrow, w.ncol);
             if ((uint64_t)w.row0 + w.nrow > n || (uint64_t)w.col0 + w.ncol > n)
                 return fail(msg, msg_len, 6, "tile outside the maps");
-            const uint32_t a = cls_of[w.row0], b = cls_of[w.col0];
-            if (cls_of[w.row0 + w.nrow - 1] != a || cls_of[w.col0 + w.ncol - 1] != b || a > b)
-                return fail(msg, msg_len, 7, "tile spans classes or rows wider than columns");
-            const bool same = a == b;
-            if (((w.flags & 1u) != 0) != same || ((w.flags & 2u) != 0) != V.row_resident)
+            // rows sorted by width: the tile's last row is its widest
+            const uint32_t a = cls_of[w.row0 + w.nrow - 1], a0 = cls_of[w.row0], b = cls_of[w.col0];
+            const bool mixed = (w.flags & kFlagMixed) != 0;
+            if (cls_of[w.col0 + w.ncol - 1] != b || a > b)
+                return fail(msg, msg_len, 7, "columns span classes or rows wider than columns");
+            if ((a0 != a) != mixed || (mixed && !plan.packed))
+                return fail(msg, msg_len, 7, "rows of classes %u .. %u, mixed flag %d", a0, a, (int)mixed);
+            const bool same = (w.flags & 1u) != 0;
+            if ((!plan.packed && same != (a == b)) || ((w.flags & 2u) != 0) != V.row_resident)
                 return fail(msg, msg_len, 8, "flags 0x%x for shape %d", w.flags, v);
             const uint32_t code = (w.flags >> 2) & 7u;
-            if (code != (V.multi >= 0 ? (uint32_t)V.multi : 0u) || (w.flags >> 5) != 0)
+            if (code != (V.multi >= 0 ? (uint32_t)V.multi : 0u) || (w.flags >> 6) != 0)
                 return fail(msg, msg_len, 9, "body code %u for shape %d", code, v);
             const uint32_t Ga = 3 * r[a] / kSlotsPerGroup, Gb = 3 * r[b] / kSlotsPerGroup;
             if (w.row_groups != Ga || w.col_groups != Gb || Gb % Ga != 0)
@@ -101,7 +117,23 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
             const uint32_t span = V.row_resident ? Ga : Gb;
             if (!(w.c0 < w.c1 && w.c1 <= span) || w.c0 % V.step != 0 || (w.c1 % V.step != 0 && w.c1 != span))
                 return fail(msg, msg_len, 11, "range [%u, %u) of %u, step %u", w.c0, w.c1, span, V.step);
+            if (mixed)
+                for (uint32_t i = 0; i < w.nrow; i++) {
+                    const uint32_t Gp = 3 * r[cls_of[w.row0 + i]] / kSlotsPerGroup;
+                    if (Ga % Gp != 0 || w.c0 / Gp != (w.c1 - 1) / Gp)
+                        return fail(msg, msg_len, 11, "range [%u, %u) crosses a multiple of row %u's %u groups",
+                                    w.c0, w.c1, w.row0 + i, Gp);
+                }
             const uint64_t unit = V.row_resident ? Gb / Ga : 1;
+            // column groups visited: h + u Ga for h in [c0, c1), u < unit
+            // (row-resident), or c in [c0, c1) (staged)
+            typedef unsigned __int128 u128;
+            auto sq_below = [](u128 x) -> u128 { return x ? (x - 1) * x * (2 * x - 1) / 6 : 0; };  // sum h^2, h < x
+            const u128 len = w.c1 - w.c0, U = V.row_resident ? unit : 1, step = V.row_resident ? Ga : 0;
+            const u128 sh = (u128)(w.c0 + w.c1 - 1) * len / 2, sh2 = sq_below(w.c1) - sq_below(w.c0);
+            const u128 su = U * (U - 1) / 2, su2 = sq_below(U);
+            const u128 s1 = U * sh + step * len * su;
+            const u128 s2 = U * sh2 + 2 * step * sh * su + len * step * step * su2;
             for (uint32_t i = 0; i < w.nrow; i++)
                 for (uint32_t j = 0; j < w.ncol; j++) {
                     const uint32_t p = w.row0 + i, q = w.col0 + j;
@@ -110,6 +142,8 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
                     if (p >= q)
                         return fail(msg, msg_len, 12, "pair (%u, %u) out of order", p, q);
                     cov[pidx(p, q)] += (uint64_t)(w.c1 - w.c0) * unit;
+                    cov1[pidx(p, q)] += s1;
+                    cov2[pidx(p, q)] += s2;
                 }
         }
     }
@@ -119,6 +153,9 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
             if (cov[pidx(p, q)] != want)
                 return fail(msg, msg_len, 13, "pair (%u, %u) visits %llu groups, not %llu", p, q,
                             (unsigned long long)cov[pidx(p, q)], (unsigned long long)want);
+            const unsigned __int128 W = want;
+            if (cov1[pidx(p, q)] != W * (W - 1) / 2 || cov2[pidx(p, q)] != (W - 1) * W * (2 * W - 1) / 6)
+                return fail(msg, msg_len, 13, "pair (%u, %u) visits some group twice and misses another", p, q);
         }
     double sp = 0;
     for (uint32_t a = 0; a < n_cls; a++)
@@ -298,8 +335,11 @@ int main()
             }
         char msg[256];
         uint64_t items = 0;
-        int st = plan_check(n_cls, r.data(), count.data(), target, single, pinned, inst, kind ? sp.data() : nullptr,
-                            planes, msg, sizeof msg, &items);
+        // each case with and without rows packed across width classes
+        int st = 0;
+        for (int packed = 0; packed < 2 && st == 0; packed++)
+            st = plan_check(n_cls, r.data(), count.data(), target, single, pinned, inst, kind ? sp.data() : nullptr,
+                            planes, packed, msg, sizeof msg, &items, nullptr);
         if (st == 0 && single && planes == 8)
             st = queues_check(n_cls, r.data(), count.data(), target, single, msg, sizeof msg);
         if (st != 0) {

@@ -72,7 +72,7 @@ def test_cross_every_shape(monkeypatch):
     oa, ta = family(11, m, 150, 0.0, 0.15)
     ob, tb = family(12, m, 90, 0.0, 0.4)
     want = oracle.cross(oa, ta, ob, tb)
-    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in range(26)]
+    settings = [("BM_COMPARE_PERSISTENT", "1")] + [("BM_COMPARE_VARIANT", str(v)) for v in range(30)]
     for key, val in settings:
         monkeypatch.setenv(key, val)
         c = bm.Context(0)

@@ -259,7 +259,7 @@ def test_subset_queries(ctx):
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), oracle.subset_pairs(off, tids, q))
 
 
-N_SHAPES = 26   # tile shapes in the catalogue (plan.cpp / compare.hip)
+N_SHAPES = 30   # tile shapes in the catalogue (plan.cpp / compare.hip)
 
 
 def test_single_launch_and_every_shape(monkeypatch):
@@ -282,6 +282,29 @@ def test_single_launch_and_every_shape(monkeypatch):
         idx.close()
         c.close()
         monkeypatch.delenv(key)
+
+
+def test_packed_rows_across_width_classes(monkeypatch):
+    # whole-index plans put maps of several widths into one row tile (each row
+    # wraps at its own group count, ranges never cross it): sizes log-uniform
+    # over eight width classes, the wide ones of a dozen maps or fewer; equal
+    # to the definition with packing on (the plan says so) and off
+    m, n = 60_000, 300
+    rng = np.random.default_rng(61)
+    sizes = np.exp(rng.uniform(0.0, np.log(m / 3), size=n))
+    off, tids = datagen.sets_from_probs(m, sizes / m, 61)
+    ref = oracle.all_pairs(off, tids)
+    ref_fp = oracle.frequent_pairs(off, tids, 40)
+    for val in ("1", "0"):
+        monkeypatch.setenv("BM_PACKED_ROWS", val)
+        c = bm.Context(0)
+        idx = bm.Index.from_sets(c, m, off, tids)
+        np.testing.assert_array_equal(idx.all_pair_supports()[:bm.n_pairs(n)], ref, err_msg=f"BM_PACKED_ROWS={val}")
+        assert idx.stats()["plan_packed"] == (1 if val == "1" else 0)
+        np.testing.assert_array_equal(idx.frequent_pairs(40), ref_fp, err_msg=f"BM_PACKED_ROWS={val}")
+        idx.close()
+        c.close()
+    monkeypatch.delenv("BM_PACKED_ROWS")
 
 
 # ------------------------------------------------------------------- dense

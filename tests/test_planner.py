@@ -12,8 +12,8 @@ import datagen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1102_1003_amd", "csrc")
-N_SHAPES = 26
-PLANES = [8] * 22 + [16, 16, 32, 32]   # slot width of each catalogue shape
+N_SHAPES = 30
+PLANES = [8] * 22 + [16, 16, 32, 32] + [8] * 4   # slot width of each catalogue shape
 CU64 = 256 * 64     # items a full MI355X plan aims at
 
 
@@ -29,8 +29,9 @@ def checker(tmp_path_factory):
                                  ctypes.c_char_p, ctypes.c_uint32]
     lib.plan_check.restype = ctypes.c_int
     lib.plan_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_char_p,
-                               ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+                               ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                               ctypes.c_char_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64),
+                               ctypes.POINTER(ctypes.c_int)]
 
     lib.cross_check.restype = ctypes.c_int
     lib.cross_check.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
@@ -47,17 +48,24 @@ def checker(tmp_path_factory):
         assert st == 0, f"{msg.value.decode()} (A {list(ra)} x {list(na_)}, B {list(rb)} x {list(nb_)}, single {single})"
         return n_items.value
 
-    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0, speeds=None, planes=8):
+    def check(widths, counts, target=CU64, single=0, pinned=-1, inst=0, speeds=None, planes=8, packed_rows=(0, 1)):
+        # each class list is planned with and without rows packed across width
+        # classes (the whole-index plans may pack, subset and batch plans not)
         r = np.ascontiguousarray(widths, dtype=np.uint32)
         c = np.ascontiguousarray(counts, dtype=np.uint32)
         msg = ctypes.create_string_buffer(256)
         n_items = ctypes.c_uint64(0)
+        packed = ctypes.c_int(0)
         sp = None if speeds is None else np.ascontiguousarray(speeds, dtype=np.float32)
         assert sp is None or sp.size == N_SHAPES * 3
-        st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst,
-                            None if sp is None else sp.ctypes.data, planes, msg, 256, ctypes.byref(n_items))
-        assert st == 0, (f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, pinned {pinned},"
-                         f" planes {planes})")
+        check.packed = []
+        for pk in packed_rows:
+            st = lib.plan_check(r.size, r.ctypes.data, c.ctypes.data, target, single, pinned, inst,
+                                None if sp is None else sp.ctypes.data, planes, pk, msg, 256, ctypes.byref(n_items),
+                                ctypes.byref(packed))
+            assert st == 0, (f"{msg.value.decode()} (widths {list(r)}, counts {list(c)}, single {single}, "
+                             f"pinned {pinned}, planes {planes}, packed rows {pk})")
+            check.packed.append(packed.value)
         if single and planes == 8:
             st = lib.queues_check(r.size, r.ctypes.data, c.ctypes.data, target, single, msg, 256)
             assert st == 0, f"{msg.value.decode()} (queues; widths {list(r)}, counts {list(c)})"
@@ -89,6 +97,26 @@ def test_large_instance_all_pairs(checker):
     vals, counts = classes(widths_of(datagen.LARGE.m, np.diff(off.astype(np.int64))))
     for single in (0, 1):
         assert checker(vals, counts, single=single) > 0
+    # the skewed instance's nine width classes: the packed plan wins
+    checker(vals, counts)
+    assert checker.packed == [0, 1]
+
+
+def test_packed_rows_across_many_classes(checker):
+    """Rows packed across width classes: tiles holding up to every class at
+    once (one map per class), classes of one map, a class of one map between
+    large ones, and widths 2^13 apart within one row tile."""
+    rng = np.random.default_rng(77)
+    checker([128 << k for k in range(14)], [1] * 14)
+    checker([128 << k for k in range(14)], [3] * 14, target=100)
+    checker([128, 256, 1024, 1 << 20], [400, 1, 250, 11])
+    checker([128, 1 << 20], [191, 2])
+    checker([8192, 16384, 32768], [551, 725, 362], target=17)
+    for _ in range(40):
+        n_cls = int(rng.integers(1, 9))
+        vals = np.sort(rng.choice([128 << k for k in range(16)], size=n_cls, replace=False))
+        counts = rng.integers(1, 400, size=n_cls)
+        checker(vals, counts, target=int(rng.integers(1, 40000)))
 
 
 def test_serving_test_queries(checker):
