@@ -93,9 +93,9 @@ __device__ inline uint64_t packed_index(uint64_t n, uint64_t i, uint64_t j)
 // MACs.  Per 64 contraction bytes a wavefront reads 12 operand fragments
 // (12 KB) from LDS for 32 MFMAs; at 128 LDS bytes per clock that is about 1.5
 // times the MFMA time of the CU's eight wavefronts, which is what bounds the
-// kernel (128 x 128 wavefront tiles would read 16 KB per 64 MFMAs, but their
-// 256 accumulation registers leave too few architected ones for the staging,
-// which then spills).
+// kernel.  128 x 128 wavefront tiles read 16 KB per 64 MFMAs, but with their
+// 256 accumulation registers only one wavefront fits a SIMD, and its own LDS
+// waits then show (51.7 against 37.3 ms for n = 8192, m = 2^20).
 constexpr int DWR = 2, DWC = 4;                 // wavefronts along rows, columns
 constexpr int DTHREADS = 64 * DWR * DWC;
 constexpr int DMA = DT / DWR / 16, DMB = DT / DWC / 16;  // 16 x 16 blocks of a wavefront
@@ -109,6 +109,7 @@ constexpr int DQ = DT * DK / 16 / DTHREADS;     // 16-byte chunks of each operan
 // walk the contraction at about the same pace, so each row or column panel's
 // lines come from HBM once for all of those tiles and the rest from its L2.
 constexpr uint32_t kSuper = 8;
+template <bool kOff32>
 __global__ __launch_bounds__(DTHREADS, 1) void dense_gram_kernel(const int8_t *__restrict__ A, uint32_t n,
                                                                  uint64_t ld, uint64_t k_len, uint32_t T,
                                                                  uint64_t k_chunk, uint32_t n_chunks, uint32_t *out)
@@ -147,20 +148,36 @@ __global__ __launch_bounds__(DTHREADS, 1) void dense_gram_kernel(const int8_t *_
     // thread tid stages chunks tid + DTHREADS q (q < DQ) of each operand: chunk
     // u is row u / (DK / 16), bytes 16 (u mod (DK / 16)) .. + 16 of the step
     const int ch = tid % (DK / 16), rq = DTHREADS / (DK / 16), row0 = tid / (DK / 16);
-    const int8_t *a0 = Ar + (uint64_t)row0 * ld + ch * 16, *b0 = Br + (uint64_t)row0 * ld + ch * 16;
     const uint64_t rstep = (uint64_t)rq * ld;  // bytes between the rows of chunks q and q + 1
+    // the staging addresses are a uniform base (panel, chunk q, step) plus
+    // this thread's offset; kOff32: the offset fits 32 bits, so every load
+    // takes the base in scalar registers and one shared offset register
+    const uint64_t loff = (uint64_t)row0 * ld + ch * 16;
+    const uint32_t loff32 = (uint32_t)loff;
+    auto ld16 = [&](const int8_t *panel, uint64_t uoff) -> uint4 {
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) const int8_t GlobalI8;
+        typedef __attribute__((address_space(1))) const u32x4 GlobalV4;
+        GlobalI8 *base = (GlobalI8 *)uniform_u64((uint64_t)panel + uoff);
+        u32x4 v;
+        if constexpr (kOff32)
+            v = *(GlobalV4 *)(base + loff32);
+        else
+            v = *(GlobalV4 *)(base + loff);
+        return uint4{v.x, v.y, v.z, v.w};
+    };
     static_assert(DQ == 4, "four 16-byte chunks of each operand per thread and step");
     uint4 ra0{}, ra1{}, ra2{}, ra3{}, rb0{}, rb1{}, rb2{}, rb3{};
 #define BM_DENSE_FETCH(K)                                                   \
     do {                                                                    \
-        ra0 = *reinterpret_cast<const uint4 *>(a0 + (K));                  \
-        ra1 = *reinterpret_cast<const uint4 *>(a0 + rstep + (K));          \
-        ra2 = *reinterpret_cast<const uint4 *>(a0 + 2 * rstep + (K));      \
-        ra3 = *reinterpret_cast<const uint4 *>(a0 + 3 * rstep + (K));      \
-        rb0 = *reinterpret_cast<const uint4 *>(b0 + (K));                  \
-        rb1 = *reinterpret_cast<const uint4 *>(b0 + rstep + (K));          \
-        rb2 = *reinterpret_cast<const uint4 *>(b0 + 2 * rstep + (K));      \
-        rb3 = *reinterpret_cast<const uint4 *>(b0 + 3 * rstep + (K));      \
+        ra0 = ld16(Ar, (K));                  \
+        ra1 = ld16(Ar, 1 * rstep + (K));          \
+        ra2 = ld16(Ar, 2 * rstep + (K));      \
+        ra3 = ld16(Ar, 3 * rstep + (K));      \
+        rb0 = ld16(Br, (K));                  \
+        rb1 = ld16(Br, 1 * rstep + (K));          \
+        rb2 = ld16(Br, 2 * rstep + (K));      \
+        rb3 = ld16(Br, 3 * rstep + (K));      \
     } while (0)
 #define BM_DENSE_STORE(S)                                                   \
     do {                                                                    \
@@ -185,19 +202,28 @@ __global__ __launch_bounds__(DTHREADS, 1) void dense_gram_kernel(const int8_t *_
         const int cur = (int)(st & 1);
 #pragma unroll
         for (int ks = 0; ks < DK / 64; ks++) {
-            v4i fb[DMB];
+            // every fragment of the sub-step in its own registers, all reads
+            // issued before the first MFMA: the reads arrive while the MFMAs
+            // of the fragments before them run (one register set reused for
+            // the row fragments would put a read's whole latency between
+            // every four MFMAs)
+            v4i fa[DMA], fb[DMB];
+            fa[0] = *reinterpret_cast<const v4i *>(
+                &sA[cur][wr * (DT / DWR) + (lane & 15)][ks * 64 + (lane >> 4) * 16]);
 #pragma unroll
             for (int b = 0; b < DMB; b++)
                 fb[b] = *reinterpret_cast<const v4i *>(
                     &sB[cur][wc * (DT / DWC) + b * 16 + (lane & 15)][ks * 64 + (lane >> 4) * 16]);
 #pragma unroll
-            for (int a = 0; a < DMA; a++) {
-                const v4i fa = *reinterpret_cast<const v4i *>(
+            for (int a = 1; a < DMA; a++)
+                fa[a] = *reinterpret_cast<const v4i *>(
                     &sA[cur][wr * (DT / DWR) + a * 16 + (lane & 15)][ks * 64 + (lane >> 4) * 16]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int a = 0; a < DMA; a++)
 #pragma unroll
                 for (int b = 0; b < DMB; b++)
-                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb[b], acc[a][b], 0, 0, 0);
-            }
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
         }
         // the other stage was last read during step st - 1, which every wave
         // finished before the barrier that closed it
@@ -272,7 +298,11 @@ hipError_t launch_dense_gram(const int8_t *A, uint32_t n, uint64_t ld, uint64_t 
     const uint64_t grid = per_chunk * ((ks + kXcds - 1) / kXcds * kXcds);
     if (grid > 0x7FFFFFFFull)
         return hipErrorInvalidValue;
-    dense_gram_kernel<<<(uint32_t)grid, DTHREADS, 0, s>>>(A, n, ld, k_len, T, chunk, ks, out);
+    // a thread's staging offset is at most (rows per chunk - 1) ld + DK
+    if ((uint64_t)(DTHREADS / (DK / 16) - 1) * ld + DK < (1ull << 32))
+        dense_gram_kernel<true><<<(uint32_t)grid, DTHREADS, 0, s>>>(A, n, ld, k_len, T, chunk, ks, out);
+    else
+        dense_gram_kernel<false><<<(uint32_t)grid, DTHREADS, 0, s>>>(A, n, ld, k_len, T, chunk, ks, out);
     return hipGetLastError();
 }
 
