@@ -42,6 +42,10 @@ struct InstDesc {
     uint32_t gb;            // groups per block = 3 r_0 / 32
     uint32_t mode;          // OutMode
     const uint4 *carena;    // BatMap groups of the column maps (== arena within one family)
+    // group count of each sorted index, for row tiles of mixed widths when the
+    // maps do not lie in sorted order in the arena (subset queries); nullptr:
+    // they do, and map p holds goff[p + 1] - goff[p] groups
+    const uint32_t *gcnt = nullptr;
 };
 
 // Descriptor of one family's compare into a packed triangle.

@@ -392,6 +392,7 @@ struct bm_index {
     DevBuf<uint32_t> pos_of_item;
     DevBuf<uint32_t> sub_items, sub_flag, sub_outpos, sub_out;
     DevBuf<uint64_t> sub_goff;
+    DevBuf<uint32_t> sub_gcnt;  // group count of each of the query's maps
     DevBuf<WorkItem> sub_work;
     // order 3: each item's failed tids, sorted (CSR over item ids)
     DevBuf<uint64_t> fail_off;
@@ -2258,13 +2259,14 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
         ord[p] = p;
     std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return sp[a] < sp[b]; });
     std::vector<uint64_t> h_goff(k);
-    std::vector<uint32_t> h_outpos(k);
+    std::vector<uint32_t> h_outpos(k), h_gcnt(k);
     const std::vector<uint64_t> &all_goff = idx->h_goff;
     std::vector<Cls> cls;
     for (uint32_t t = 0; t < k; t++) {
         uint32_t p = ord[t];
         uint32_t r = idx->h_r_sorted[sp[p]];
         h_goff[t] = all_goff[sp[p]];
+        h_gcnt[t] = (uint32_t)(all_goff[sp[p] + 1] - all_goff[sp[p]]);
         h_outpos[t] = p;
         if (cls.empty() || cls.back().r != r)
             cls.push_back({r, t, 0});
@@ -2272,8 +2274,10 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     }
     HIPC(ctx, idx->sub_goff.ensure(k));
     HIPC(ctx, idx->sub_outpos.ensure(k));
+    HIPC(ctx, idx->sub_gcnt.ensure(k));
     BMC(upload(ctx, idx->sub_goff.p, h_goff.data(), (uint64_t)k * 8));
     BMC(upload(ctx, idx->sub_outpos.p, h_outpos.data(), (uint64_t)k * 4));
+    BMC(upload(ctx, idx->sub_gcnt.p, h_gcnt.data(), (uint64_t)k * 4));
     bool host = ptr_kind(out) == PTR_HOST;
     uint32_t *dst = out;
     if (host) {
@@ -2289,9 +2293,11 @@ bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t
     d.gb = idx->gb;
     d.mode = OUT_PACKED;
     d.carena = d.arena;
+    d.gcnt = idx->sub_gcnt.p;
     Plan plan;
     const bool single = single_launch(ctx, idx->planes);
-    plan_classes(cls, 0, target_items(ctx), plan, nullptr, single ? 1 : 0, forced_variant(), false, idx->planes);
+    plan_classes(cls, 0, target_items(ctx), plan, nullptr, single ? 1 : 0, forced_variant(), false, idx->planes,
+                 packed_rows());
     std::vector<std::pair<int, uint32_t>> ranges;
     st = upload_plan(idx, plan, single, idx->sub_work, ranges);
     if (st != BM_OK)
@@ -2872,7 +2878,7 @@ struct SrvRequest {
     std::vector<uint32_t> items;
     uint32_t k = 0;
     uint64_t off = 0, need = 0;
-    uint64_t o_res = 0, o_goff = 0, o_pos = 0, o_item = 0;  // offsets inside the request's range
+    uint64_t o_res = 0, o_goff = 0, o_pos = 0, o_item = 0, o_gcnt = 0;  // offsets inside the request's range
     int state = 0;  // 0 queued, 1 running, 2 done, 3 failed
     double t_submit = 0, t_admit = 0, t_done = 0;
     uint32_t batch = 0;
@@ -2949,8 +2955,9 @@ struct bm_server {
     }
     uint64_t need_for(uint32_t k) const
     {
-        // result | group offsets (8k) + output positions (4k) + item ids (4k) | item -> position (4n)
-        return align256((uint64_t)k * (k - 1) / 2 * 4) + align256(16ull * k) + align256(4ull * idx->n);
+        // result | group offsets (8k) + output positions (4k) + item ids (4k) + group counts (4k) |
+        // item -> position (4n)
+        return align256((uint64_t)k * (k - 1) / 2 * 4) + align256(20ull * k) + align256(4ull * idx->n);
     }
     static bool is_large(uint32_t k) { return (uint64_t)k * (k - 1) / 2 > kServeSmallPairs; }
     hipError_t launch_group(SrvLaunch &L, const std::vector<uint64_t> &ids);
@@ -2988,12 +2995,14 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         uint64_t *hg = reinterpret_cast<uint64_t *>(hpool + r.off + r.o_goff);
         uint32_t *ho = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_pos);
         uint32_t *hi = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_item);
+        uint32_t *hc = reinterpret_cast<uint32_t *>(hpool + r.off + r.o_gcnt);
         std::vector<Cls> &cls = q_cls[j];
         for (uint32_t t = 0; t < k; t++) {
             uint32_t p = ord[t];
             int32_t sp = sorted_pos[r.items[p]];
             uint32_t rr = ix->h_r_sorted[sp];
             hg[t] = ix->h_goff[sp];
+            hc[t] = (uint32_t)(ix->h_goff[sp + 1] - ix->h_goff[sp]);
             ho[t] = p;
             if (cls.empty() || cls.back().r != rr)
                 cls.push_back({rr, t, 0});
@@ -3010,6 +3019,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         d.gb = ix->gb;
         d.mode = OUT_PACKED;
         d.carena = d.arena;
+        d.gcnt = reinterpret_cast<const uint32_t *>(dpool + r.off + r.o_gcnt);
     }
     // the launch's items shared among its queries in proportion to their work
     std::vector<double> q_work(nq);
@@ -3022,7 +3032,7 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
     std::vector<std::vector<WorkItem>> by_variant(kVariantCount);
     for (uint32_t j = 0; j < nq; j++) {
         Plan plan;
-        plan_classes(q_cls[j], j, q_target[j], plan, nullptr, 0, forced_variant());
+        plan_classes(q_cls[j], j, q_target[j], plan, nullptr, 0, forced_variant(), false, 8, packed_rows());
         for (int v = 0; v < kVariantCount; v++)
             by_variant[v].insert(by_variant[v].end(), plan.by_variant[v].begin(), plan.by_variant[v].end());
     }
@@ -3053,8 +3063,8 @@ hipError_t bm_server::launch_group(SrvLaunch &L, const std::vector<uint64_t> &id
         e = hipMemcpyAsync(L.items.p, L.h_items, flat.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
     for (uint32_t j = 0; j < nq && e == hipSuccess; j++) {
         SrvRequest &r = reqs[ids[j]];
-        // goff, outpos and items are contiguous in the range: one upload
-        e = hipMemcpyAsync(dpool + r.off + r.o_goff, hpool + r.off + r.o_goff, r.o_item + 4ull * r.k - r.o_goff,
+        // goff, outpos, items and group counts are contiguous in the range: one upload
+        e = hipMemcpyAsync(dpool + r.off + r.o_goff, hpool + r.off + r.o_goff, r.o_gcnt + 4ull * r.k - r.o_goff,
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = fill_u32(reinterpret_cast<uint32_t *>(dpool + r.off + r.o_res), (uint64_t)r.k * (r.k - 1) / 2, 0, s);
@@ -3295,6 +3305,7 @@ bm_status bm_server_submit(bm_server *srv, const uint32_t *items, uint32_t k, ui
     r.o_goff = align256((uint64_t)k * (k - 1) / 2 * 4);
     r.o_pos = r.o_goff + 8ull * k;
     r.o_item = r.o_pos + 4ull * k;
+    r.o_gcnt = r.o_item + 4ull * k;
     r.need = srv->need_for(k);
     if (r.need > srv->pool_bytes)
         return BM_ENOMEM;

@@ -223,8 +223,8 @@ __device__ inline void unpack4(const u32x4 &a, const u32x4 &b, uint32_t (&v)[8])
 // retire, so without the rotation the oldest wave of each SIMD would keep the
 // lead for the whole launch, and the SIMD completes fewer items in all.
 // Row tiles of mixed widths (kFlagMixed): h walks the widest row's G_row
-// groups while row map p, of G_p = goff[p + 1] - goff[p] groups (the maps lie
-// in sorted order), reads its group h mod G_p, so the column groups h + u G_row
+// groups while row map p, of G_p groups (d.gcnt[p], or goff[p + 1] - goff[p]
+// where the maps lie in sorted order), reads its group h mod G_p, so the column groups h + u G_row
 // that meet it are every column group once, as the wrap requires (G_p divides
 // G_row).  An item's range never crosses a multiple of any of its rows' G_p,
 // so h mod G_p = h - (c0 - c0 mod G_p) throughout: the row's base moves back
@@ -250,7 +250,7 @@ __device__ void process_rows(const WorkItem &w, const InstDesc &d)
         for (int r = 0; r < R; r++) {
             int rho = lane + 64 * r;
             uint32_t rr = rho < w.nrow ? rho : w.nrow - 1;
-            const uint32_t gp = (uint32_t)(goff[w.row0 + rr + 1] - goff[w.row0 + rr]);
+            const uint32_t gp = d.gcnt ? d.gcnt[w.row0 + rr] : (uint32_t)(goff[w.row0 + rr + 1] - goff[w.row0 + rr]);
             rbase[r] -= 2 * (uint64_t)(w.c0 - w.c0 % gp);
         }
     }

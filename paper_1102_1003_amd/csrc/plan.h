@@ -105,9 +105,10 @@ void tiles_for(const Cls &A, const Cls &B, bool same, uint32_t bi, uint32_t bj,
 // single: 0 = any default shape (one launch per shape); 1 = shapes of the
 // single-launch kernel only.  pinned >= 0 forces that shape (single == 0 only).
 // cross_only: only pairs of different classes.
-// packed_rows: the maps' group offsets are contiguous in sorted order (map p
-// holds goff[p + 1] - goff[p] groups), so row tiles may hold several width
-// classes.  The planner then also tiles every column class against all
+// packed_rows: the compare kernels can learn each row map's group count (the
+// maps lie in sorted order in the arena, or the descriptor lists the counts),
+// so row tiles may hold several width classes.  The planner then also tiles
+// every column class against all
 // narrower-or-equal rows at once (rows packed across classes, column tiles
 // of 12, 11, 8 or 4 maps) and keeps that plan when its padded work over speed
 // is lower (8-bit slots, neither single-launch nor pinned).

@@ -295,6 +295,9 @@ def test_packed_rows_across_width_classes(monkeypatch):
     off, tids = datagen.sets_from_probs(m, sizes / m, 61)
     ref = oracle.all_pairs(off, tids)
     ref_fp = oracle.frequent_pairs(off, tids, 40)
+    # a subset query: its maps are gathered, so the kernel reads their group counts from the descriptor
+    q = rng.choice(n, size=120, replace=False).astype(np.uint32)
+    ref_q = oracle.subset_pairs(off, tids, q)
     for val in ("1", "0"):
         monkeypatch.setenv("BM_PACKED_ROWS", val)
         c = bm.Context(0)
@@ -302,6 +305,8 @@ def test_packed_rows_across_width_classes(monkeypatch):
         np.testing.assert_array_equal(idx.all_pair_supports()[:bm.n_pairs(n)], ref, err_msg=f"BM_PACKED_ROWS={val}")
         assert idx.stats()["plan_packed"] == (1 if val == "1" else 0)
         np.testing.assert_array_equal(idx.frequent_pairs(40), ref_fp, err_msg=f"BM_PACKED_ROWS={val}")
+        np.testing.assert_array_equal(idx.subset_pair_supports(q)[:bm.n_pairs(q.size)], ref_q,
+                                      err_msg=f"BM_PACKED_ROWS={val}")
         idx.close()
         c.close()
     monkeypatch.delenv("BM_PACKED_ROWS")
