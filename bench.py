@@ -721,7 +721,8 @@ def triples_mode(args):
 def batch_mode(args):
     """Uneven Bernoulli instances (m log-uniform in [1e4, 1e6], n uniform in [100, 4000], density uniform in
     [1%, 10%], per-instance seeds; tidlists drawn on the GPU) counted all-pairs, first with one call per
-    instance, then as one persistent multi-instance launch replayed from a HIP graph.  Both are checked:
+    instance, then as one multi-instance batch (a launch per tile shape holding every instance's items)
+    replayed from a HIP graph.  Both are checked:
     equal to each other and to the closed forms of every instance (its sum and each of its rows)."""
     import torch
 
@@ -798,7 +799,7 @@ def batch_mode(args):
     log(f"one call per instance: {alone_s * 1e3:.2f} ms; one graph launch: {batch_s * 1e3:.2f} ms "
         f"(graph={batch.is_graph}); equal={equal} closed={all(closed)} rows={rows_ok}")
     res = {
-        "metric": "batched: item-pair supports/s of 64 uneven instances in one persistent graph launch",
+        "metric": "batched: item-pair supports/s of 64 uneven instances in one graph launch",
         "value": total_pairs / batch_s, "unit": "item-pair supports/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{len(specs)} Bernoulli instances, m log-uniform [1e4,1e6], n uniform [100,4000], "

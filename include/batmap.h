@@ -259,10 +259,12 @@ bm_status bm_triple_supports(bm_index *idx, const uint32_t *triples, uint64_t co
 bm_status bm_subset_pair_supports(bm_index *idx, const uint32_t *items, uint32_t k, uint32_t *out);
 
 /* Many instances at once.  A batch plans all pairs of `count` indexes
- * (same context, built with min_support 0) as one work list, longest items
- * first, run by ONE persistent compare launch, and captures the whole
- * sequence (counter reset, output zeroing, compare, corrections) as a HIP
- * graph on the context's stream.  When the context holds autotuned tile
+ * (same context, built with min_support 0) as one work list run by one
+ * compare launch per tile shape, each holding every instance's items of that
+ * shape, longest first (with BM_COMPARE_PERSISTENT=1 in the environment: one
+ * persistent launch over per-XCD queues), and captures the whole sequence
+ * (output zeroing, compare, corrections) as a HIP graph on the context's
+ * stream.  When the context holds autotuned tile
  * speeds, creation runs the batch twice (plans from built-in and from
  * measured speeds) and keeps the faster plan; outs then already hold the
  * result.  outs[q]: device, n_q(n_q-1)/2 uint32, bound to the batch until

@@ -415,7 +415,10 @@ struct bm_batch {
     DevBuf<WorkItem> items;
     DevBuf<uint32_t> counter;
     uint32_t n_items = 0, grid = 0;
-    XcdQueues queues{};  // per-XCD queues of `items`
+    bool persistent = false;  // one persistent launch (else one launch per tile shape)
+    XcdQueues queues{};       // persistent: per-XCD queues of `items`
+    std::vector<std::pair<int, uint32_t>> ranges;  // per shape: (shape, items) runs of `items`
+    InstDesc d0{};            // the first instance's descriptor (its layout selects the kernels)
     double slot_pairs = 0;
     float tuned_ms[2] = {0, 0};  // batch time with catalogue / measured tile speeds (0: not tried)
     hipGraph_t graph = nullptr;
@@ -1351,8 +1354,10 @@ hipError_t bm_batch::enqueue(hipStream_t s)
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         if (n_pairs(idx[q]->n))
             e = fill_u32(outs[q], n_pairs(idx[q]->n), 0, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && persistent)
         e = launch_compare_multi_persistent(items.p, queues, descs.p, counter.p, grid, s);
+    if (e == hipSuccess && !persistent && run_compare(ctx, items.p, ranges, d0, descs.p) != BM_OK)
+        e = hipErrorLaunchFailure;  // the context's message names the call that failed
     for (size_t q = 0; q < idx.size() && e == hipSuccess; q++)
         e = launch_apply_corrections(idx[q]->corr.p, idx[q]->n_corr, outs[q], idx[q]->n, s);
     return e;
@@ -2363,37 +2368,61 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
         b->idx.push_back(idx);
         b->outs.push_back(outs[q]);
     }
-    // one work list over all instances, longest items first; each instance
-    // gets a share of the items in proportion to its work, so that items of
-    // every instance take about the same time
+    // one work list over all instances; each instance gets a share of the
+    // items in proportion to its work, so that items of every instance take
+    // about the same time.  Default: one launch per tile shape holding every
+    // instance's items of that shape, longest first (workgroups retire item by
+    // item, as in single calls); BM_COMPARE_PERSISTENT=1: one persistent
+    // launch over per-XCD queues.
+    b->persistent = use_persistent(ctx);
     std::vector<double> inst_work(count);
     for (uint32_t q = 0; q < count; q++)
         inst_work[q] = class_work(idxs[q]->classes);
     const std::vector<uint64_t> inst_target = shared_targets(inst_work, target_items(ctx), 8);
-    auto make_list = [&](const std::vector<float> *speeds, std::vector<WorkItem> &flat, double &slot_pairs) {
+    typedef std::vector<std::pair<int, uint32_t>> Ranges;
+    auto make_list = [&](const std::vector<float> *speeds, std::vector<WorkItem> &flat, Ranges &ranges,
+                         XcdQueues &queues, double &slot_pairs) {
         flat.clear();
+        ranges.clear();
         slot_pairs = 0;
+        std::vector<std::vector<WorkItem>> by_variant(kVariantCount);
         for (uint32_t q = 0; q < count; q++) {
             Plan one;
-            plan_classes(idxs[q]->classes, q, inst_target[q], one, speeds, 1, -1);
+            if (b->persistent)
+                plan_classes(idxs[q]->classes, q, inst_target[q], one, speeds, 1, -1);
+            else
+                plan_classes(idxs[q]->classes, q, inst_target[q], one, speeds, 0, forced_variant(), false, 8,
+                             packed_rows());
             slot_pairs += one.slot_pairs;
-            for (auto &v : one.by_variant)
-                flat.insert(flat.end(), v.begin(), v.end());
+            for (int v = 0; v < kVariantCount; v++)
+                by_variant[v].insert(by_variant[v].end(), one.by_variant[v].begin(), one.by_variant[v].end());
         }
+        for (int v = 0; v < kVariantCount; v++) {
+            if (by_variant[v].empty())
+                continue;
+            if (!b->persistent) {
+                order_launch(by_variant[v]);
+                ranges.push_back({v, (uint32_t)by_variant[v].size()});
+            }
+            flat.insert(flat.end(), by_variant[v].begin(), by_variant[v].end());
+        }
+        if (b->persistent)
+            xcd_queues(flat, queues.off);
     };
     // Candidate tile-shape choices: the catalogue speeds and, after
     // bm_context_autotune, the measured ones.  Each candidate list is timed
     // once on the batch itself and the faster one is kept.
     std::vector<WorkItem> flat, cand;
+    Ranges r_flat, r_cand;
     double sp = 0, sp2 = 0;
     XcdQueues q_flat{}, q_cand{};
-    make_list(nullptr, flat, sp);
-    xcd_queues(flat, q_flat.off);
+    make_list(nullptr, flat, r_flat, q_flat, sp);
     const bool tuned = trial && (int)ctx->speeds.size() == kVariantCount * kWrapBuckets;
-    if (tuned) {
-        make_list(&ctx->speeds, cand, sp2);
-        xcd_queues(cand, q_cand.off);
-    }
+    if (tuned)
+        make_list(&ctx->speeds, cand, r_cand, q_cand, sp2);
+    b->d0 = descs[0];
+    if (!b->persistent)
+        BMC(create_side(ctx));  // the side streams exist before any capture
     b->grid = multi_persistent_grid((uint32_t)ctx->n_cu);
     HIPC(ctx, b->descs.alloc(count));
     HIPC(ctx, b->items.alloc(std::max<uint64_t>(std::max(flat.size(), cand.size()), 1)));
@@ -2406,10 +2435,12 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
         float ms[2] = {0, 0};
         std::vector<WorkItem> *lists[2] = {&flat, &cand};
         const XcdQueues *qs[2] = {&q_flat, &q_cand};
+        const Ranges *rs[2] = {&r_flat, &r_cand};
         hipError_t e = hipSuccess;
         for (int c = 0; c < 2 && e == hipSuccess; c++) {
             b->n_items = (uint32_t)lists[c]->size();
             b->queues = *qs[c];
+            b->ranges = *rs[c];
             if (b->n_items && upload(ctx, b->items.p, lists[c]->data(), b->n_items * sizeof(WorkItem)) != BM_OK) {
                 (void)hipEventDestroy(e0);
                 (void)hipEventDestroy(e1);
@@ -2433,6 +2464,7 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
             flat.swap(cand);
             sp = sp2;
             q_flat = q_cand;
+            r_flat.swap(r_cand);
         }
         b->tuned_ms[0] = ms[0];
         b->tuned_ms[1] = ms[1];
@@ -2440,11 +2472,13 @@ bm_status batch_create(bm_context *ctx, bm_index *const *idxs, uint32_t count, u
     b->slot_pairs = sp;
     b->n_items = (uint32_t)flat.size();
     b->queues = q_flat;
+    b->ranges = r_flat;
     if (!flat.empty())
         BMC(upload(ctx, b->items.p, flat.data(), flat.size() * sizeof(WorkItem)));
     HIPC(ctx, hipStreamSynchronize(s));
     // the whole sequence as one graph: counter reset, output fills (kernels,
-    // not memsets), one persistent compare launch, corrections
+    // not memsets), the compare launches (on side streams forked and joined
+    // by events, which the capture follows), corrections
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         hipError_t e = b->enqueue(s);
         hipGraph_t g = nullptr;

@@ -154,7 +154,8 @@ void xcd_order(std::vector<WorkItem> &v)
         uint64_t last_key = ~0ull;
         uint32_t last_g = 0;
         for (size_t t = s; t < e; t++) {
-            const uint64_t key = ((uint64_t)v[t].c0 << 32) | v[t].row0;
+            // (instance, range, row tile); a rare clash of keys only merges two groups
+            const uint64_t key = (((uint64_t)v[t].c0 << 32) | v[t].row0) ^ ((uint64_t)v[t].inst << 52);
             if (key != last_key) {
                 last_g = group_of.emplace(key, (uint32_t)group_of.size()).first->second;
                 last_key = key;
@@ -299,49 +300,8 @@ void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64
             }
         }
     }
-    // longest first, ties in emission order (range-major).  A plan has few
-    // distinct costs (about one per class pair), so this is a bucket sort.
-    std::vector<WorkItem> sorted;
-    std::vector<uint64_t> costs, item_bucket;
-    std::unordered_map<uint64_t, uint32_t> bucket_of;
-    for (auto &v : plan.by_variant) {
-        if (v.empty())
-            continue;
-        costs.clear();
-        bucket_of.clear();
-        item_bucket.resize(v.size());
-        // items come in runs of one cost (a class pair's range), so the
-        // previous item's bucket is checked before the map
-        uint64_t last_c = ~0ull;
-        uint32_t last_b = 0;
-        for (size_t t = 0; t < v.size(); t++) {
-            const uint64_t c = item_cost(v[t]);
-            if (c != last_c) {
-                auto it = bucket_of.emplace(c, (uint32_t)costs.size()).first;
-                if (it->second == costs.size())
-                    costs.push_back(c);
-                last_c = c;
-                last_b = it->second;
-            }
-            item_bucket[t] = last_b;
-        }
-        std::vector<uint32_t> order(costs.size()), start(costs.size() + 1, 0);
-        for (uint32_t b = 0; b < costs.size(); b++)
-            order[b] = b;
-        std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return costs[x] > costs[y]; });
-        std::vector<uint32_t> rank(costs.size());
-        for (uint32_t i = 0; i < order.size(); i++)
-            rank[order[i]] = i;
-        for (size_t t = 0; t < v.size(); t++)
-            start[rank[item_bucket[t]] + 1]++;
-        for (size_t b = 0; b < costs.size(); b++)
-            start[b + 1] += start[b];
-        sorted.resize(v.size());
-        for (size_t t = 0; t < v.size(); t++)
-            sorted[start[rank[item_bucket[t]]]++] = v[t];
-        v.swap(sorted);
-        xcd_order(v);
-    }
+    for (auto &v : plan.by_variant)
+        order_launch(v);
 }
 
 // One shape per class pair (the lowest padded work over speed); returns the
@@ -517,6 +477,48 @@ double packed_groups(const std::vector<Cls> &cls, uint16_t inst, const std::vect
 }
 
 }  // namespace
+
+// Longest first, ties in emission order (range-major).  A plan has few
+// distinct costs (about one per class pair), so this is a bucket sort.
+void order_launch(std::vector<WorkItem> &v)
+{
+    if (v.empty())
+        return;
+    std::vector<WorkItem> sorted;
+    std::vector<uint64_t> costs, item_bucket(v.size());
+    std::unordered_map<uint64_t, uint32_t> bucket_of;
+    // items come in runs of one cost (a class pair's range), so the
+    // previous item's bucket is checked before the map
+    uint64_t last_c = ~0ull;
+    uint32_t last_b = 0;
+    for (size_t t = 0; t < v.size(); t++) {
+        const uint64_t c = item_cost(v[t]);
+        if (c != last_c) {
+            auto it = bucket_of.emplace(c, (uint32_t)costs.size()).first;
+            if (it->second == costs.size())
+                costs.push_back(c);
+            last_c = c;
+            last_b = it->second;
+        }
+        item_bucket[t] = last_b;
+    }
+    std::vector<uint32_t> order(costs.size()), start(costs.size() + 1, 0);
+    for (uint32_t b = 0; b < costs.size(); b++)
+        order[b] = b;
+    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return costs[x] > costs[y]; });
+    std::vector<uint32_t> rank(costs.size());
+    for (uint32_t i = 0; i < order.size(); i++)
+        rank[order[i]] = i;
+    for (size_t t = 0; t < v.size(); t++)
+        start[rank[item_bucket[t]] + 1]++;
+    for (size_t b = 0; b < costs.size(); b++)
+        start[b + 1] += start[b];
+    sorted.resize(v.size());
+    for (size_t t = 0; t < v.size(); t++)
+        sorted[start[rank[item_bucket[t]]]++] = v[t];
+    v.swap(sorted);
+    xcd_order(v);
+}
 
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,
                   const std::vector<float> *speeds, int single, int pinned, bool cross_only, uint32_t planes,

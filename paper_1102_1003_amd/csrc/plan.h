@@ -141,6 +141,11 @@ void plan_cross(const std::vector<Cls> &a_cls, const std::vector<Cls> &b_cls, ui
                 uint64_t target_items, Plan &plan, const std::vector<float> *speeds, int single, int pinned,
                 uint32_t planes = 8);
 
+// Orders the items of one launch: longest first (ties in their order), and
+// within each run of equal cost the items of one (instance, range, row tile)
+// group at positions of one XCD (workgroup b runs on XCD b mod kXcds).
+void order_launch(std::vector<WorkItem> &v);
+
 // Slot pairs compared by an all-pairs plan of the classes: the sum over
 // pairs of 3 max(r_i, r_j) (what plan_classes reports as slot_pairs).
 double class_work(const std::vector<Cls> &cls);

@@ -324,7 +324,12 @@ def test_dense_comparator(ctx, seed, m, n):
 
 # ------------------------------------------------------------------- batched
 
-def test_batched_equals_each_instance(ctx):
+@pytest.mark.parametrize("persistent", ["0", "1"])
+def test_batched_equals_each_instance(monkeypatch, persistent):
+    # the batch as one launch per tile shape over all instances (default) and as
+    # one persistent launch; a created batch's graph replayed twice, eager work between
+    monkeypatch.setenv("BM_COMPARE_PERSISTENT", persistent)
+    ctx = bm.Context(0)
     ws = datagen.batch_instances(count=6, seed=77, m_lo=2e3, m_hi=2e4, n_lo=20, n_hi=150)
     idxs, outs, refs = [], [], []
     for w in ws:
@@ -335,6 +340,19 @@ def test_batched_equals_each_instance(ctx):
     bm.batch_all_pair_supports(ctx, idxs, outs)
     for o, r, w in zip(outs, refs, ws):
         np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)], r)
+    batch = bm.Batch(ctx, idxs, outs)
+    for rep in range(2):
+        for o in outs:
+            o.fill_(-1)
+        batch.run()
+        ctx.synchronize()
+        for o, r, w in zip(outs, refs, ws):
+            np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32)[:bm.n_pairs(w.n)], r,
+                                          err_msg=f"replay {rep}, persistent {persistent}")
+    batch.close()
+    for ix in idxs:
+        ix.close()
+    ctx.close()
 
 
 def test_autotuned_batch(ctx):
