@@ -16,8 +16,12 @@ namespace {
 // pairs per unit time relative to 128 x 16, measured on MI355X; the planner
 // uses them until the autotuner has measured the device.
 const VariantInfo kInfo[kVariantCount] = {
-    // staged LDS tiles (64 x 64, 128 x 32, 256 x 16, 256 x 8): only when pinned
-    {64, 64, false, kStageGroups, -1, false, 0.60f},
+    // staged LDS tiles (64 x 64, 128 x 32, 256 x 16, 256 x 8).  64 x 64 is the
+    // default between maps of one width, where a row-resident tile meets each
+    // row group once and its loads show: 1.93 against 2.31 ms for 128 x 12 on
+    // the paper-replica instance.  With wrapped columns, and the other three
+    // shapes always, they serve only when pinned.
+    {64, 64, false, kStageGroups, -1, true, 0.60f, 1.55f, 8, false, true},
     {128, 32, false, kStageGroups, -1, false, 0.60f},
     {256, 16, false, kStageGroups, -1, false, 0.60f},
     {256, 8, false, kStageGroups, -1, false, 0.60f},
@@ -312,6 +316,59 @@ struct Choice {
     double speed;
 };
 
+// The shape of least padded work over speed for one class pair (-1: none
+// runs this mode and slot width); its cost and speed through the pointers.
+int best_shape(const ClassPair &cp, const std::vector<float> *speeds, int single, int pinned, uint32_t planes,
+               double *cost_out, double *speed_out)
+{
+    const Cls &rowc = cp.A, &colc = cp.B;
+    int best = -1;
+    double best_cost = 1e300, best_speed = 1;
+    const int bucket = wrap_bucket(colc.r / rowc.r);
+    const bool pin_applies = pinned >= 0 && kInfo[pinned].planes == planes;
+    for (int v = 0; v < kVariantCount; v++) {
+        // measured speeds weigh the default shapes against each other; the
+        // staged-tile shapes time well on uniform synthetic tiles but lose on
+        // skewed instances: 64 x 64 is offered between maps of one width only
+        if (!shape_allowed(v, single, pinned, planes))
+            continue;
+        const VariantInfo &V = kInfo[v];
+        if (V.nowrap_only && bucket != 0 && !pin_applies)
+            continue;
+        const float speed = shape_speed(v, bucket, speeds);
+        uint64_t cnt;
+        tiles_for(rowc, colc, cp.same, V.bi, V.bj, nullptr, &cnt);
+        const double cost = (double)cnt * V.bi * V.bj / speed;
+        // prefer larger tiles on ties (more reuse per loaded group)
+        if (cost < best_cost) {  // variants are listed largest tile first
+            best_cost = cost;
+            best = v;
+            best_speed = speed;
+        }
+    }
+    // every catalogue speed is > 0, so a shape was chosen above unless none
+    // runs this mode and slot width (the single launch has 8-bit bodies only)
+    for (int v = 0; best < 0 && v < kVariantCount; v++)
+        if (shape_allowed(v, single, -1, planes) && !(kInfo[v].nowrap_only && bucket != 0))
+            best = v, best_speed = kInfo[v].speed;
+    if (best >= 0) {
+        uint64_t cnt;
+        tiles_for(rowc, colc, cp.same, kInfo[best].bi, kInfo[best].bj, nullptr, &cnt);
+        *cost_out = (double)cnt * kInfo[best].bi * kInfo[best].bj * (3.0 * colc.r / kSlotsPerGroup) / best_speed;
+        *speed_out = best_speed;
+    }
+    return best;
+}
+
+// Slot pairs of one class pair: 3 max(r) per pair.
+double pair_slot_pairs(const ClassPair &cp)
+{
+    const double np = cp.same ? 0.5 * cp.A.count * (cp.A.count - 1.0) : (double)cp.A.count * cp.B.count;
+    return np * 3.0 * cp.B.r;
+}
+
+// One shape per class pair (best_shape); returns false when some pair has
+// none (the plan is then incomplete), the plan's total cost and slot pairs.
 bool classic_choices(const std::vector<ClassPair> &pairs, const std::vector<float> *speeds, int single, int pinned,
                      uint32_t planes, std::vector<Choice> &choices, double &total_work, double &slot_pairs)
 {
@@ -319,48 +376,44 @@ bool classic_choices(const std::vector<ClassPair> &pairs, const std::vector<floa
     total_work = 0;  // padded pair-groups over speed: wave time, arbitrary unit
     slot_pairs = 0;
     for (size_t k = 0; k < pairs.size(); k++) {
-        const Cls &rowc = pairs[k].A, &colc = pairs[k].B;
-        const bool same = pairs[k].same;
-        int best = -1;
-        double best_cost = 1e300, best_speed = 1;
-        const int bucket = wrap_bucket(colc.r / rowc.r);
-        for (int v = 0; v < kVariantCount; v++) {
-            // measured speeds weigh the default shapes against each other; the
-            // staged-tile shapes time well on uniform synthetic tiles but lose on
-            // skewed instances, so they are used only when pinned
-            if (!shape_allowed(v, single, pinned, planes))
-                continue;
-            const VariantInfo &V = variant_info(v);
-            const float speed = shape_speed(v, bucket, speeds);
-            uint64_t cnt;
-            tiles_for(rowc, colc, same, V.bi, V.bj, nullptr, &cnt);
-            const double cost = (double)cnt * V.bi * V.bj / speed;
-            // prefer larger tiles on ties (more reuse per loaded group)
-            if (cost < best_cost) {  // variants are listed largest tile first
-                best_cost = cost;
-                best = v;
-                best_speed = speed;
-            }
-        }
-        // every catalogue speed is > 0, so a shape was chosen above unless
-        // none runs this mode and slot width (the single launch has 8-bit
-        // bodies only): the plan is then marked incomplete for the caller
-        for (int v = 0; best < 0 && v < kVariantCount; v++)
-            if (shape_allowed(v, single, -1, planes))
-                best = v, best_speed = variant_info(v).speed;
+        double cost = 0, speed = 1;
+        const int best = best_shape(pairs[k], speeds, single, pinned, planes, &cost, &speed);
         if (best < 0) {
             complete = false;
             continue;
         }
-        const uint32_t bi = variant_info(best).bi, bj = variant_info(best).bj;
-        uint64_t cnt;
-        tiles_for(rowc, colc, same, bi, bj, nullptr, &cnt);
-        const double np = same ? 0.5 * rowc.count * (rowc.count - 1.0) : (double)rowc.count * colc.count;
-        slot_pairs += np * 3.0 * colc.r;
-        total_work += (double)cnt * bi * bj * (3.0 * colc.r / kSlotsPerGroup) / best_speed;
-        choices.push_back({k, best, best_speed});
+        slot_pairs += pair_slot_pairs(pairs[k]);
+        total_work += cost;
+        choices.push_back({k, best, speed});
     }
     return complete;
+}
+
+// The tiles of one class pair in shape v, as one group.
+TileGroup classic_group(const ClassPair &cp, int v, double speed)
+{
+    const Cls &A = cp.A, &B = cp.B;
+    const uint32_t bi = kInfo[v].bi, bj = kInfo[v].bj;
+    std::vector<std::pair<uint32_t, uint32_t>> tiles;
+    uint64_t cnt;
+    tiles_for(A, B, cp.same, bi, bj, &tiles, &cnt);
+    TileGroup g;
+    g.v = v;
+    g.speed = speed;
+    g.Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
+    g.Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
+    g.inst = cp.inst;
+    // the working set is the whole class pair's, whatever tiles it holds
+    g.row_lo = A.start;
+    g.row_hi = A.start + A.count;
+    g.col_lo = B.start;
+    g.col_hi = B.start + B.count;
+    g.tiles.reserve(tiles.size());
+    for (auto &t : tiles)
+        g.tiles.push_back({A.start + t.first * bi, B.start + t.second * bj,
+                           (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi),
+                           (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj), (uint16_t)(cp.same ? 1u : 0u)});
+    return g;
 }
 
 // The packed shape of r rows per lane (2 or 3) and mj columns.
@@ -540,6 +593,10 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
     std::vector<Choice> choices;
     double classic_work = 0, slot_pairs = 0;
     const bool complete = classic_choices(pairs, speeds, 0, -1, planes, choices, classic_work, slot_pairs);
+    // rows packed across classes, the triangle of each class inside the
+    // packed tiles (tiling the triangles on their own, with staged tiles where
+    // cheaper, looks a little cheaper by the speeds but ran 12 % slower on the
+    // large Zipf instance: more launches and partial row tiles)
     std::vector<TileGroup> groups;
     const double packed_work = packed_groups(cls, (uint16_t)inst, speeds, groups);
     if (!complete || !(packed_work < classic_work)) {
@@ -579,34 +636,8 @@ void plan_pairs(const std::vector<ClassPair> &pairs, uint64_t target_items, Plan
     double total_work = 0;
     plan.complete = classic_choices(pairs, speeds, single, pinned, planes, choices, total_work, plan.slot_pairs);
     std::vector<TileGroup> groups;
-    std::vector<std::pair<uint32_t, uint32_t>> tiles;
-    for (const Choice &ch : choices) {
-        const Cls &A = pairs[ch.k].A, &B = pairs[ch.k].B;
-        const bool same = pairs[ch.k].same;
-        const VariantInfo &V = variant_info(ch.v);
-        const uint32_t bi = V.bi, bj = V.bj;
-        tiles.clear();
-        uint64_t cnt;
-        tiles_for(A, B, same, bi, bj, &tiles, &cnt);
-        TileGroup g;
-        g.v = ch.v;
-        g.speed = ch.speed;
-        g.Ga = (uint32_t)(3ull * A.r / kSlotsPerGroup);
-        g.Gb = (uint32_t)(3ull * B.r / kSlotsPerGroup);
-        g.inst = pairs[ch.k].inst;
-        // the working set is the whole class pair's, whatever tiles it holds
-        g.row_lo = A.start;
-        g.row_hi = A.start + A.count;
-        g.col_lo = B.start;
-        g.col_hi = B.start + B.count;
-        g.tiles.reserve(tiles.size());
-        for (auto &t : tiles)
-            g.tiles.push_back({A.start + t.first * bi, B.start + t.second * bj,
-                               (uint16_t)std::min<uint32_t>(bi, A.count - t.first * bi),
-                               (uint16_t)std::min<uint32_t>(bj, B.count - t.second * bj),
-                               (uint16_t)(same ? 1u : 0u)});
-        groups.push_back(std::move(g));
-    }
+    for (const Choice &ch : choices)
+        groups.push_back(classic_group(pairs[ch.k], ch.v, ch.speed));
     emit_groups(groups, total_work, target_items, plan);
 }
 

@@ -52,6 +52,7 @@ struct VariantInfo {
     float speed_nowrap = 0;  // the same between maps of one width, when it differs (0: as speed)
     uint32_t planes = 8;  // bits per slot of the maps it compares (8, 16, 32)
     bool packed = false;  // offered to the packed planner (rows of several classes per tile)
+    bool nowrap_only = false;  // offered by default only between maps of one width
 };
 constexpr int kVariantCount = 30;
 // Item flag of a mixed-width row tile.

@@ -88,7 +88,7 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
                 return fail(msg, msg_len, 2, "shape %d in a single-launch plan", v);
             if (!single && !pin_applies && !V.default_choice && !(plan.packed && V.packed))
                 return fail(msg, msg_len, 2, "tuning-only shape %d chosen without a pin", v);
-            if (plan.packed && !V.packed)
+            if (plan.packed && !V.packed && !V.default_choice)
                 return fail(msg, msg_len, 2, "shape %d in a packed plan", v);
             if (!single && pin_applies && v != pinned)
                 return fail(msg, msg_len, 3, "shape %d while %d is pinned", v, pinned);
@@ -114,6 +114,8 @@ extern "C" int plan_check(uint32_t n_cls, const uint32_t *r, const uint32_t *cou
             const uint32_t Ga = 3 * r[a] / kSlotsPerGroup, Gb = 3 * r[b] / kSlotsPerGroup;
             if (w.row_groups != Ga || w.col_groups != Gb || Gb % Ga != 0)
                 return fail(msg, msg_len, 10, "group counts %u / %u", w.row_groups, w.col_groups);
+            if (V.nowrap_only && Ga != Gb && !pin_applies)
+                return fail(msg, msg_len, 10, "shape %d between widths %u and %u", v, r[a], r[b]);
             const uint32_t span = V.row_resident ? Ga : Gb;
             if (!(w.c0 < w.c1 && w.c1 <= span) || w.c0 % V.step != 0 || (w.c1 % V.step != 0 && w.c1 != span))
                 return fail(msg, msg_len, 11, "range [%u, %u) of %u, step %u", w.c0, w.c1, span, V.step);
