@@ -316,6 +316,13 @@ struct Choice {
     double speed;
 };
 
+// Items a class pair must give before a staged tile is offered by default
+// (about one per CU).
+constexpr uint64_t kMinStagedItems = 256;
+// Padded group pairs over speed below which a plan keeps one class per tile:
+// about 50 us of compare on MI355X (4 10^12 group pairs/s).
+constexpr double kPackedMinWork = 2e8;
+
 // The shape of least padded work over speed for one class pair (-1: none
 // runs this mode and slot width); its cost and speed through the pointers.
 int best_shape(const ClassPair &cp, const std::vector<float> *speeds, int single, int pinned, uint32_t planes,
@@ -338,6 +345,13 @@ int best_shape(const ClassPair &cp, const std::vector<float> *speeds, int single
         const float speed = shape_speed(v, bucket, speeds);
         uint64_t cnt;
         tiles_for(rowc, colc, cp.same, V.bi, V.bj, nullptr, &cnt);
+        // a staged tile is one workgroup of four wavefronts walking its whole
+        // range in steps with two barriers each: a pair of classes that gives
+        // fewer items than CUs then runs on its latency (the 200-map Bernoulli
+        // instance: 0.109 against 0.046 ms with 128 x 12 tiles)
+        const uint64_t span = 3ull * colc.r / kSlotsPerGroup;
+        if (V.nowrap_only && !pin_applies && cnt * std::max<uint64_t>(1, span / kMinPieceGroups) < kMinStagedItems)
+            continue;
         const double cost = (double)cnt * V.bi * V.bj / speed;
         // prefer larger tiles on ties (more reuse per loaded group)
         if (cost < best_cost) {  // variants are listed largest tile first
@@ -599,7 +613,11 @@ void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_it
     // large Zipf instance: more launches and partial row tiles)
     std::vector<TileGroup> groups;
     const double packed_work = packed_groups(cls, (uint16_t)inst, speeds, groups);
-    if (!complete || !(packed_work < classic_work)) {
+    // small instances run on the latency of their longest item, and packed
+    // plans have fewer, longer items (the 200-map Bernoulli instance: 18
+    // items of 192-row tiles, 0.10 against 0.05 ms): below about 50 us of the
+    // whole GPU's compare they keep one class per tile
+    if (!complete || classic_work < kPackedMinWork || !(packed_work < classic_work)) {
         plan_pairs(pairs, target_items, plan, speeds, single, pinned, planes);
         return;
     }

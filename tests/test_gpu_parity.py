@@ -289,7 +289,7 @@ def test_packed_rows_across_width_classes(monkeypatch):
     # wraps at its own group count, ranges never cross it): sizes log-uniform
     # over eight width classes, the wide ones of a dozen maps or fewer; equal
     # to the definition with packing on (the plan says so) and off
-    m, n = 60_000, 300
+    m, n = 100_000, 600     # large enough (work above the small-instance bound) for a packed plan
     rng = np.random.default_rng(61)
     sizes = np.exp(rng.uniform(0.0, np.log(m / 3), size=n))
     off, tids = datagen.sets_from_probs(m, sizes / m, 61)

@@ -112,6 +112,8 @@ def test_packed_rows_across_many_classes(checker):
     checker([128, 256, 1024, 1 << 20], [400, 1, 250, 11])
     checker([128, 1 << 20], [191, 2])
     checker([8192, 16384, 32768], [551, 725, 362], target=17)
+    checker([512, 2048], [200, 30])         # a small instance keeps one class per tile
+    assert checker.packed == [0, 0]
     for _ in range(40):
         n_cls = int(rng.integers(1, 9))
         vals = np.sort(rng.choice([128 << k for k in range(16)], size=n_cls, replace=False))
