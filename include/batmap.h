@@ -163,6 +163,16 @@ bm_status bm_context_autotune(bm_context *ctx, uint32_t reps);
 bm_status bm_context_tile_speeds(bm_context *ctx, float *speeds, uint32_t capacity, uint32_t *n_out);
 bm_status bm_context_set_tile_speeds(bm_context *ctx, const float *speeds, uint32_t n);
 
+/* Compare launches of the calls and batches made after it: one launch per
+ * tile shape (BM_LAUNCH_PER_SHAPE, the default) or one persistent launch over
+ * per-XCD work queues (BM_LAUNCH_PERSISTENT; also set at creation by
+ * BM_COMPARE_PERSISTENT=1 in the environment).  Results are the same; the
+ * persistent form is slower on the measured instances.  BM_EINVAL for another
+ * mode.  Plans made under the other mode are made again. */
+#define BM_LAUNCH_PER_SHAPE 0
+#define BM_LAUNCH_PERSISTENT 1
+bm_status bm_context_set_launch_mode(bm_context *ctx, int mode);
+
 /* Turns per-phase event timing on (enable != 0) or off; off by default. */
 bm_status bm_context_set_profiling(bm_context *ctx, int enable);
 /* Waits for the recorded events and fills *out (phases never run read 0). */

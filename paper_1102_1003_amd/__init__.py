@@ -95,11 +95,14 @@ class bm_server_stats(ctypes.Structure):
                                                 "admission_waits", "peak_bytes")]
 
 
+BM_LAUNCH_PER_SHAPE, BM_LAUNCH_PERSISTENT = 0, 1
+
 EXPORTED = [
     "bm_build_opts_init", "bm_context_create", "bm_context_destroy", "bm_last_error", "bm_synchronize",
     "bm_index_build_sets", "bm_index_build_transactions", "bm_index_stats_get", "bm_index_destroy",
     "bm_all_pair_supports", "bm_frequent_pairs", "bm_subset_pair_supports", "bm_batch_all_pair_supports",
     "bm_all_pair_supports_dense", "bm_index_export", "bm_context_set_profiling", "bm_context_timings",
+    "bm_context_set_launch_mode",
     "bm_context_autotune", "bm_context_tile_speeds", "bm_context_set_tile_speeds",
     "bm_batch_create", "bm_batch_run", "bm_batch_is_graph", "bm_batch_plan_trial", "bm_batch_destroy",
     "bm_server_opts_init", "bm_server_create", "bm_server_submit", "bm_server_wait", "bm_server_stats_get",
@@ -198,6 +201,8 @@ def load_library(path: str = LIB_PATH):
     L.bm_index_export.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bm_context_set_profiling.restype = i32
     L.bm_context_set_profiling.argtypes = [vp, i32]
+    L.bm_context_set_launch_mode.restype = i32
+    L.bm_context_set_launch_mode.argtypes = [vp, i32]
     L.bm_context_timings.restype = i32
     L.bm_context_timings.argtypes = [vp, ctypes.POINTER(bm_timings)]
     L.bm_context_autotune.restype = i32
@@ -265,6 +270,11 @@ class Context:
 
     def set_profiling(self, enable: bool = True):
         self.check(load_library().bm_context_set_profiling(self._h, 1 if enable else 0))
+
+    def set_launch_mode(self, persistent: bool):
+        """Compare launches of later calls and batches: one per tile shape (False) or one persistent launch."""
+        self.check(load_library().bm_context_set_launch_mode(self._h, BM_LAUNCH_PERSISTENT if persistent
+                                                                       else BM_LAUNCH_PER_SHAPE))
 
     def autotune(self, reps: int = 3) -> np.ndarray:
         """Times every compare tile shape and keeps the speeds for planning; returns them

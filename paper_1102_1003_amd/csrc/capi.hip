@@ -1601,6 +1601,20 @@ void bm_context_destroy(bm_context *ctx)
 
 const char *bm_last_error(const bm_context *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
+bm_status bm_context_set_launch_mode(bm_context *ctx, int mode)
+{
+    if (!ctx)
+        return BM_EINVAL;
+    if (mode != BM_LAUNCH_PER_SHAPE && mode != BM_LAUNCH_PERSISTENT)
+        return fail(ctx, BM_EINVAL, "launch mode %d", mode);
+    const bool p = mode == BM_LAUNCH_PERSISTENT;
+    if (p != ctx->persistent) {
+        ctx->persistent = p;
+        ctx->tune_gen++;  // resident plans were cut for the other form
+    }
+    return BM_OK;
+}
+
 bm_status bm_context_set_profiling(bm_context *ctx, int enable)
 {
     if (!ctx)

@@ -324,12 +324,12 @@ def test_dense_comparator(ctx, seed, m, n):
 
 # ------------------------------------------------------------------- batched
 
-@pytest.mark.parametrize("persistent", ["0", "1"])
-def test_batched_equals_each_instance(monkeypatch, persistent):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_equals_each_instance(persistent):
     # the batch as one launch per tile shape over all instances (default) and as
     # one persistent launch; a created batch's graph replayed twice, eager work between
-    monkeypatch.setenv("BM_COMPARE_PERSISTENT", persistent)
     ctx = bm.Context(0)
+    ctx.set_launch_mode(persistent)
     ws = datagen.batch_instances(count=6, seed=77, m_lo=2e3, m_hi=2e4, n_lo=20, n_hi=150)
     idxs, outs, refs = [], [], []
     for w in ws:
