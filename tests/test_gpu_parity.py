@@ -295,8 +295,9 @@ def test_packed_rows_across_width_classes(monkeypatch):
     off, tids = datagen.sets_from_probs(m, sizes / m, 61)
     ref = oracle.all_pairs(off, tids)
     ref_fp = oracle.frequent_pairs(off, tids, 40)
-    # a subset query: its maps are gathered, so the kernel reads their group counts from the descriptor
-    q = rng.choice(n, size=120, replace=False).astype(np.uint32)
+    # a subset query large enough for a packed plan: its maps are gathered, so the kernel reads
+    # their group counts from the descriptor
+    q = rng.choice(n, size=450, replace=False).astype(np.uint32)
     ref_q = oracle.subset_pairs(off, tids, q)
     for val in ("1", "0"):
         monkeypatch.setenv("BM_PACKED_ROWS", val)
