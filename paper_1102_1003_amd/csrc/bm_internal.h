@@ -410,9 +410,12 @@ hipError_t launch_lds_build(const uint32_t *tids, const uint64_t *off, const uin
 hipError_t launch_invert_perms(const uint32_t *pi, uint32_t m, uint32_t *inv, hipStream_t s);
 
 // Corrections (Sec. III-C).
-hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off, const uint32_t *tids,
-                              const uint32_t *failed_bits, const uint8_t *has_map, uint32_t n, uint32_t *pairs,
-                              uint64_t cap, unsigned long long *count, hipStream_t s);
+// n_failed_dev (device, optional): the failure count, read by the kernel and
+// clamped to n_failed (then the bound the grid is sized for).
+hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint32_t *n_failed_dev,
+                              const uint64_t *off, const uint32_t *tids, const uint32_t *failed_bits,
+                              const uint8_t *has_map, uint32_t n, uint32_t *pairs, uint64_t cap,
+                              unsigned long long *count, hipStream_t s);
 // Corrections of a cross product (rows A, columns B, out[i * n_b + j]) for
 // the failures of family X against the items of family Y (x_is_a: X = A).
 hipError_t launch_cross_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off_y,

@@ -516,7 +516,8 @@ uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
 // (defined with the read-back below): the copies are asynchronous, and the
 // runtime is never handed a pageable host address (a caller's array or a
 // vector's storage) to look up.
-bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow = true);
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow = true,
+                 hipStream_t st = nullptr);
 bm_status download(bm_context *ctx, void *dst, const void *src, uint64_t bytes);
 
 // The plan as one work list in launch order: per-shape runs ((shape, count)
@@ -547,9 +548,9 @@ void flatten_plan(const Plan &plan, bool single, std::vector<WorkItem> &flat,
     }
 }
 
-// single: the plan was made for the single persistent launch
+// single: the plan was made for the single persistent launch; st as for upload
 bm_status upload_plan(bm_index *idx, const Plan &plan, bool single, DevBuf<WorkItem> &dst,
-                      std::vector<std::pair<int, uint32_t>> &ranges)
+                      std::vector<std::pair<int, uint32_t>> &ranges, hipStream_t st = nullptr)
 {
     bm_context *ctx = idx->ctx;
     if (!plan.complete)
@@ -559,13 +560,15 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, bool single, DevBuf<WorkI
     const uint64_t total = flat.size();
     HIPC(ctx, dst.ensure(std::max<uint64_t>(total, 1)));
     if (total)
-        return upload(ctx, dst.p, flat.data(), total * sizeof(WorkItem));
+        return upload(ctx, dst.p, flat.data(), total * sizeof(WorkItem), true, st);
     return BM_OK;
 }
 
 // The all-pairs plan of an index over sorted indices >= first, made unless
-// the index holds it for the context's current tile speeds.
-bm_status ensure_plan(bm_index *idx, uint32_t first)
+// the index holds it for the context's current tile speeds.  st: the stream
+// its upload goes on (the context's when null; another one must already be
+// ordered after the context's stream, whose pool the plan's buffer comes from).
+bm_status ensure_plan(bm_index *idx, uint32_t first, hipStream_t st = nullptr)
 {
     bm_context *ctx = idx->ctx;
     if (idx->planned_first == first && idx->planned_gen == ctx->tune_gen)
@@ -574,9 +577,9 @@ bm_status ensure_plan(bm_index *idx, uint32_t first)
     const bool single = single_launch(ctx, idx->planes);
     plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr, single ? 1 : 0,
                  forced_variant(), false, idx->planes, packed_rows());
-    bm_status st = upload_plan(idx, plan, single, idx->work, idx->work_ranges);
-    if (st != BM_OK)
-        return st;
+    bm_status e = upload_plan(idx, plan, single, idx->work, idx->work_ranges, st);
+    if (e != BM_OK)
+        return e;
     idx->planned_first = first;
     idx->planned_gen = ctx->tune_gen;
     idx->planned_slot_pairs = plan.slot_pairs;
@@ -721,8 +724,11 @@ constexpr uint64_t kStageChunk = 16ull << 20;
 
 // grow = false: never reallocates the staging buffer (chunks of its current
 // size; the context allocates it, and the `staged` event, when created).
-bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow)
+// st: the stream the copies go on (the context's when null).
+bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bool grow, hipStream_t st)
 {
+    if (!st)
+        st = ctx->stream;
     const uint64_t chunk = grow ? kStageChunk : std::min<uint64_t>(kStageChunk, ctx->h_stage_bytes);
     if (chunk == 0)
         return fail(ctx, BM_ENOMEM, "no staging buffer");
@@ -742,15 +748,60 @@ bm_status upload(bm_context *ctx, void *dst, const void *src, uint64_t bytes, bo
             ctx->h_stage_bytes = want;
         }
         memcpy(ctx->h_stage, static_cast<const char *>(src) + at, c);
-        const hipError_t e = hipMemcpyAsync(static_cast<char *>(dst) + at, ctx->h_stage, c, hipMemcpyHostToDevice,
-                                            ctx->stream);
+        const hipError_t e = hipMemcpyAsync(static_cast<char *>(dst) + at, ctx->h_stage, c, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(ctx, e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EDEVICE, "uploading %llu bytes to %p: %s",
                         (unsigned long long)c, static_cast<char *>(dst) + at, hipGetErrorString(e));
         }
-        HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
+        HIPC(ctx, hipEventRecord(ctx->staged, st));
     }
+    return BM_OK;
+}
+
+// Several host arrays to the device through one staging chunk (one wait for
+// the staging buffer, one event), on the context's stream.
+struct UploadPiece {
+    void *dst;
+    const void *src;
+    uint64_t bytes;
+};
+
+bm_status upload_many(bm_context *ctx, std::initializer_list<UploadPiece> pieces)
+{
+    uint64_t total = 0;
+    for (const UploadPiece &u : pieces)
+        total += (u.bytes + 15) / 16 * 16;
+    if (total > kStageChunk) {
+        for (const UploadPiece &u : pieces)
+            BMC(upload(ctx, u.dst, u.src, u.bytes));
+        return BM_OK;
+    }
+    if (total == 0)
+        return BM_OK;
+    if (ctx->staged)
+        HIPC(ctx, hipEventSynchronize(ctx->staged));
+    else
+        HIPC(ctx, hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+    if (ctx->h_stage_bytes < total) {
+        if (ctx->h_stage)
+            HIPC(ctx, hipHostFree(ctx->h_stage));
+        ctx->h_stage = nullptr;
+        ctx->h_stage_bytes = 0;
+        const uint64_t want = std::min<uint64_t>(std::max<uint64_t>(total + total / 2, 1 << 20), kStageChunk);
+        HIPC(ctx, hipHostMalloc(&ctx->h_stage, want));
+        ctx->h_stage_bytes = want;
+    }
+    char *h = static_cast<char *>(ctx->h_stage);
+    uint64_t at = 0;
+    for (const UploadPiece &u : pieces) {
+        if (u.bytes) {
+            memcpy(h + at, u.src, u.bytes);
+            HIPC(ctx, hipMemcpyAsync(u.dst, h + at, u.bytes, hipMemcpyHostToDevice, ctx->stream));
+        }
+        at += (u.bytes + 15) / 16 * 16;
+    }
+    HIPC(ctx, hipEventRecord(ctx->staged, ctx->stream));
     return BM_OK;
 }
 
@@ -839,13 +890,43 @@ bm_status check_opts(bm_context *ctx, const bm_build_opts *o)
 // every block was built.  When a block leaves more nestless elements than
 // the kernel holds it returns with `done` false and the failure bits clear,
 // for the chain family to build the index instead.
+// First capacity of the corrections list (Sec. III-C): `want`, the usual
+// count, or less under BM_CORR_CAP (exercises the second pass).
+uint64_t corr_first_cap(uint64_t want)
+{
+    if (const char *e = getenv("BM_CORR_CAP"))
+        if (atoll(e) > 0)
+            return std::min<uint64_t>(want, (uint64_t)atoll(e));
+    return want;
+}
+
+// After a corrections pass counted `total` pairs into a list of `cap`: a
+// second pass into a list of the exact size when that was too small.
+bm_status corr_finish(bm_index *idx, const uint32_t *failed_bits, const uint8_t *has_map, uint64_t total,
+                      uint64_t cap, unsigned long long *cnt)
+{
+    bm_context *ctx = idx->ctx;
+    if (total > cap) {
+        HIPC(ctx, idx->corr.alloc(2 * total));
+        HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt), 2, 0, ctx->stream));
+        HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, nullptr, idx->off.p, idx->tids.p,
+                                     failed_bits, has_map, idx->n, idx->corr.p, total, cnt, ctx->stream));
+    }
+    idx->n_corr = total;
+    return BM_OK;
+}
+
+// The block family's construction.  done: the maps are built (else the chain
+// family builds them); corr_done: the corrections are made too (queued right
+// behind the build and read back with its counters, one wait for both).
 bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t> &failed_bits, uint64_t fb_words,
-                          bool &done)
+                          const uint8_t *has_map, bool &done, bool &corr_done)
 {
     bm_context *ctx = idx->ctx;
     hipStream_t s = ctx->stream;
     const uint32_t n = idx->n, first = idx->first_built;
     done = false;
+    corr_done = false;
     const uint32_t l0 = 31u - (uint32_t)__builtin_clz(idx->r0);
     idx->bperm = make_block_perm(idx->m, l0, o->seed);
     const uint32_t gb = idx->gb;
@@ -870,7 +951,13 @@ bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t
     HIPC(ctx, cursor.alloc(n_blocks + 1));
     HIPC(ctx, bmap.alloc(n_blocks + 1));
     HIPC(ctx, bk.alloc(std::max<uint64_t>(idx->nnz, 1)));
-    HIPC(ctx, counters.alloc(2));
+    // failures, the give-up flag, the corrections count (64-bit)
+    HIPC(ctx, counters.alloc(4));
+    unsigned long long *corr_cnt = reinterpret_cast<unsigned long long *>(counters.p + 2);
+    const bool corr_here = n > 1;
+    const uint64_t corr_cap = corr_first_cap(std::max<uint64_t>(1u << 16, idx->nnz / 256));
+    if (corr_here)
+        HIPC(ctx, idx->corr.alloc(2 * corr_cap));
     HIPC(ctx, tmp.alloc(scan_tmp_bytes(n_blocks + 1)));
     if (!h_chunks.empty())
         BMC(upload(ctx, chunks.p, h_chunks.data(), h_chunks.size() * sizeof(BucketChunk)));
@@ -886,19 +973,35 @@ bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t
     uint64_t fail_cap = std::max<uint64_t>(1u << 16, idx->nnz / 64);
     for (int attempt = 0;; attempt++) {
         HIPC(ctx, idx->failed.alloc(2 * fail_cap));
-        HIPC(ctx, fill_u32(counters.p, 2, 0, s));
+        HIPC(ctx, fill_u32(counters.p, 4, 0, s));
+        // the all-pairs plan is made on the host while the kernels run, and
+        // uploaded on a side stream beside them: after everything queued
+        // before the build (its buffer comes from this stream's pool), and
+        // before anything queued after it
+        const bool plan_here = attempt == 0 && n - first <= kPlanAtBuild;
+        if (plan_here) {
+            BMC(create_side(ctx));
+            HIPC(ctx, hipEventRecord(ctx->fork, s));
+        }
         HIPC(ctx, launch_block_build(bk.p, bstart.p, bmap.p, (uint32_t)n_blocks, idx->goff.p, idx->sorted_items.p,
                                      idx->r_sorted.p, idx->tids.p, idx->off.p, idx->bperm, idx->shift, o->max_loop,
                                      idx->arena.p, failed_bits.p, idx->failed.p, counters.p, (uint32_t)fail_cap,
                                      counters.p + 1, s));
-        // the all-pairs plan is made on the host while the kernels run
-        if (attempt == 0 && n - first <= kPlanAtBuild) {
-            bm_status st = ensure_plan(idx, first);
+        // the corrections of the failures the build lists (it stops listing
+        // at fail_cap; past that the attempt is repeated anyway)
+        if (corr_here)
+            HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)fail_cap, counters.p, idx->off.p, idx->tids.p,
+                                         failed_bits.p, has_map, n, idx->corr.p, corr_cap, corr_cnt, s));
+        if (plan_here) {
+            HIPC(ctx, hipStreamWaitEvent(ctx->side[0], ctx->fork, 0));
+            bm_status st = ensure_plan(idx, first, ctx->side[0]);
             if (st != BM_OK)
                 return st;
+            HIPC(ctx, hipEventRecord(ctx->join[0], ctx->side[0]));
+            HIPC(ctx, hipStreamWaitEvent(s, ctx->join[0], 0));
         }
-        uint32_t h[2] = {0, 0};
-        BMC(read_back(ctx, h, counters.p, 8));
+        uint32_t h[4] = {0, 0, 0, 0};
+        BMC(read_back(ctx, h, counters.p, 16));
         if (h[1]) {
             HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
             return BM_OK;
@@ -907,10 +1010,43 @@ bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t
             idx->n_failed = h[0];
             idx->block_family = true;
             done = true;
+            if (corr_here) {
+                BMC(corr_finish(idx, failed_bits.p, has_map, h[2] | (uint64_t)h[3] << 32, corr_cap, corr_cnt));
+                corr_done = true;
+            }
             return BM_OK;
         }
         fail_cap = (uint64_t)h[0] + h[0] / 2 + 1024;
         HIPC(ctx, fill_u32(failed_bits.p, fb_words + 1, 0, s));
+    }
+}
+
+// The size order on the host: ids by ascending size (clamped to 32 bits),
+// ties by id, as the device's sorts give it.  A stable LSD radix sort of the
+// ids, 8 bits a pass.
+void host_size_order(const std::vector<uint64_t> &h_off, uint32_t n, std::vector<uint32_t> &order)
+{
+    std::vector<uint32_t> key(n), ktmp(n), tmp(n);
+    order.resize(n);
+    uint32_t kmax = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        key[i] = (uint32_t)std::min<uint64_t>(h_off[i + 1] - h_off[i], 0xFFFFFFFFu);
+        order[i] = i;
+        kmax = std::max(kmax, key[i]);
+    }
+    for (uint32_t shift = 0; shift < 32 && (kmax >> shift) != 0; shift += 8) {
+        uint32_t start[257] = {0};
+        for (uint32_t i = 0; i < n; i++)
+            start[((key[i] >> shift) & 255u) + 1]++;
+        for (int b = 0; b < 256; b++)
+            start[b + 1] += start[b];
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t at = start[(key[i] >> shift) & 255u]++;
+            tmp[at] = order[i];
+            ktmp[at] = key[i];
+        }
+        order.swap(tmp);
+        key.swap(ktmp);
     }
 }
 
@@ -987,51 +1123,73 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     }
     idx->first_built = first_built;
     HIPC(ctx, idx->sorted_items.alloc(n));
-    if (n <= kSmallSortMax) {
-        HIPC(ctx, launch_size_order_small(idx->off.p, n, idx->sorted_items.p, s));
-    } else {
-        DevBuf<uint32_t> keys, k2, v2;
-        DevBuf<char> tmp;
-        HIPC(ctx, keys.alloc(n));
-        HIPC(ctx, k2.alloc(n));
-        HIPC(ctx, v2.alloc(n));
-        HIPC(ctx, tmp.alloc(radix_tmp_bytes(n)));
-        HIPC(ctx, launch_size_keys(idx->off.p, n, keys.p, idx->sorted_items.p, s));
-        HIPC(ctx, radix_sort_pairs(keys.p, idx->sorted_items.p, k2.p, v2.p, n, bits_for(max_size), tmp.p, s));
-    }
-
-    // layout: r_i and group offsets
     HIPC(ctx, idx->r_sorted.alloc(n));
     HIPC(ctx, idx->goff.alloc((uint64_t)n + 1));
-    DevBuf<uint32_t> gcount;
-    DevBuf<char> gtmp;
-    HIPC(ctx, gcount.alloc((uint64_t)n + 1));
-    HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
-    HIPC(ctx, gtmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
-    if (order3)
-        HIPC(ctx, launch_layout3(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
-                                 gcount.p, s));
-    else
-        HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
-                                    gcount.p, s));
-    HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, gtmp.p, s));
+    idx->h_sorted_items.resize(n);
+    idx->h_r_sorted.resize(n);
+    std::vector<uint64_t> &h_goff = idx->h_goff;
+    h_goff.assign((size_t)n + 1, 0);
+    bm_status st = BM_OK;
+    if (!order3 && n <= kSmallSortMax) {
+        // few maps: the order and the layout (r_i as in map_layout_kernel,
+        // group offsets) from the sizes the host holds, sent without a wait
+        host_size_order(idx->h_off, n, idx->h_sorted_items);
+        for (uint32_t p = 0; p < n; p++) {
+            uint32_t r = 0;
+            if (p >= first_built) {
+                const uint32_t it = idx->h_sorted_items[p];
+                const uint64_t want = 2 * (idx->h_off[it + 1] - idx->h_off[it]);
+                uint64_t rr = 1;
+                while (rr < want)
+                    rr <<= 1;
+                r = rr < idx->r0 ? idx->r0 : (uint32_t)rr;
+            }
+            idx->h_r_sorted[p] = r;
+            h_goff[p + 1] = h_goff[p] + 3ull * r / kSlotsPerGroup;
+        }
+        st = upload_many(ctx, {{idx->sorted_items.p, idx->h_sorted_items.data(), (uint64_t)n * 4},
+                               {idx->r_sorted.p, idx->h_r_sorted.data(), (uint64_t)n * 4},
+                               {idx->goff.p, h_goff.data(), ((uint64_t)n + 1) * 8}});
+        if (st != BM_OK)
+            return st;
+    } else {
+        if (n <= kSmallSortMax) {
+            HIPC(ctx, launch_size_order_small(idx->off.p, n, idx->sorted_items.p, s));
+        } else {
+            DevBuf<uint32_t> keys, k2, v2;
+            DevBuf<char> tmp;
+            HIPC(ctx, keys.alloc(n));
+            HIPC(ctx, k2.alloc(n));
+            HIPC(ctx, v2.alloc(n));
+            HIPC(ctx, tmp.alloc(radix_tmp_bytes(n)));
+            HIPC(ctx, launch_size_keys(idx->off.p, n, keys.p, idx->sorted_items.p, s));
+            HIPC(ctx, radix_sort_pairs(keys.p, idx->sorted_items.p, k2.p, v2.p, n, bits_for(max_size), tmp.p, s));
+        }
+        // layout: r_i and group offsets
+        DevBuf<uint32_t> gcount;
+        DevBuf<char> gtmp;
+        HIPC(ctx, gcount.alloc((uint64_t)n + 1));
+        HIPC(ctx, fill_u32(gcount.p, (uint64_t)n + 1, 0, s));
+        HIPC(ctx, gtmp.alloc(scan_tmp_bytes((uint64_t)n + 1)));
+        if (order3)
+            HIPC(ctx, launch_layout3(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                     gcount.p, s));
+        else
+            HIPC(ctx, launch_map_layout(idx->sorted_items.p, idx->off.p, n, first_built, idx->r0, idx->r_sorted.p,
+                                        gcount.p, s));
+        HIPC(ctx, exclusive_scan_u32_to_u64(gcount.p, idx->goff.p, (uint64_t)n + 1, gtmp.p, s));
+        st = read_back_many(ctx, {{idx->h_sorted_items.data(), idx->sorted_items.p, (uint64_t)n * 4},
+                                  {idx->h_r_sorted.data(), idx->r_sorted.p, (uint64_t)n * 4},
+                                  {h_goff.data(), idx->goff.p, ((uint64_t)n + 1) * 8}});
+        if (st != BM_OK)
+            return st;
+    }
     // sorted_pos: item -> sorted index (or -1 when unbuilt); has_map for the
     // corrections
     DevBuf<uint8_t> has_map;
     HIPC(ctx, idx->sorted_pos.alloc(n));
     HIPC(ctx, has_map.alloc(std::max<uint32_t>(n, 1)));
     HIPC(ctx, launch_sorted_pos(idx->sorted_items.p, n, first_built, idx->sorted_pos.p, has_map.p, s));
-    idx->h_sorted_items.resize(n);
-    idx->h_r_sorted.resize(n);
-    std::vector<uint64_t> &h_goff = idx->h_goff;
-    h_goff.assign((size_t)n + 1, 0);
-    bm_status st = read_back_many(ctx, {{idx->h_sorted_items.data(), idx->sorted_items.p, (uint64_t)n * 4},
-                                        {idx->h_r_sorted.data(), idx->r_sorted.p, (uint64_t)n * 4},
-                                        {h_goff.data(), idx->goff.p, ((uint64_t)n + 1) * 8}});
-    if (st != BM_OK)
-        return st;
-    gcount.reset();
-    gtmp.reset();
     idx->h_sizes_sorted.resize(n);
     for (uint32_t p = 0; p < n; p++) {
         const uint32_t it = idx->h_sorted_items[p];
@@ -1062,12 +1220,12 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // LDS; the chain family (staged and whole-map LDS builds below) builds the
     // rest, and an index whose block build overflowed.  BM_BLOCK_BUILD=0
     // turns the block family off.
-    bool block_done = false;
+    bool block_done = false, corr_done = false;
     {
         const char *bb_env = getenv("BM_BLOCK_BUILD");
         if (!(bb_env && atoi(bb_env) == 0) && !order3 && idx->planes == 8 && !o->perm[0] && first_built < n &&
             idx->r0 <= block_build_max_r0()) {
-            st = block_construct(idx, o, failed_bits, fb_words, block_done);
+            st = block_construct(idx, o, failed_bits, fb_words, has_map.p, block_done, corr_done);
             if (st != BM_OK)
                 return st;
         }
@@ -1275,7 +1433,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
     // count (a failure pairs with the few maps whose sets hold its
     // transaction; at most n - 1 of them); a second pass, into a list of the
     // exact size, only when that was too small.
-    {
+    if (!corr_done) {
         Span span_correct(ctx, PH_CORRECT);
         idx->n_corr = 0;
         HIPC(ctx, idx->corr.alloc(2));
@@ -1283,26 +1441,17 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             DevBuf<unsigned long long> cnt;
             HIPC(ctx, cnt.alloc(1));
             const uint64_t bound = idx->n_failed * (uint64_t)(n - 1);
-            uint64_t cap = std::min<uint64_t>(bound, std::max<uint64_t>(1u << 16, 64 * idx->n_failed));
-            // BM_CORR_CAP sets a lower first capacity (exercises the second pass)
-            if (const char *e = getenv("BM_CORR_CAP"))
-                if (atoll(e) > 0)
-                    cap = std::min<uint64_t>(cap, (uint64_t)atoll(e));
+            const uint64_t cap =
+                corr_first_cap(std::min<uint64_t>(bound, std::max<uint64_t>(1u << 16, 64 * idx->n_failed)));
             HIPC(ctx, idx->corr.alloc(2 * cap));
             HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
-            HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p,
+            HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, nullptr, idx->off.p, idx->tids.p,
                                          failed_bits.p, has_map.p, n, idx->corr.p, cap, cnt.p, s));
             unsigned long long total = 0;
             st = read_back(ctx, &total, cnt.p, 8);
             if (st != BM_OK)
                 return st;
-            if (total > cap) {
-                HIPC(ctx, idx->corr.alloc(2 * total));
-                HIPC(ctx, fill_u32(reinterpret_cast<uint32_t *>(cnt.p), 2, 0, s));
-                HIPC(ctx, launch_corrections(idx->failed.p, (uint32_t)idx->n_failed, idx->off.p, idx->tids.p,
-                                             failed_bits.p, has_map.p, n, idx->corr.p, total, cnt.p, s));
-            }
-            idx->n_corr = total;
+            BMC(corr_finish(idx, failed_bits.p, has_map.p, total, cap, cnt.p));
         }
     }
 

@@ -34,10 +34,13 @@ __device__ inline int64_t find_tid(const uint32_t *a, uint64_t n, uint32_t x)
 }
 
 // Thread per (failure f, item c).  cap == 0 only counts.
-__global__ void corrections_kernel(const uint32_t *failed, uint32_t n_failed, const uint64_t *off,
-                                   const uint32_t *tids, const uint32_t *failed_bits, const uint8_t *has_map,
-                                   uint32_t n, uint32_t *pairs, uint64_t cap, unsigned long long *count)
+__global__ void corrections_kernel(const uint32_t *failed, uint32_t n_failed, const uint32_t *n_failed_dev,
+                                   const uint64_t *off, const uint32_t *tids, const uint32_t *failed_bits,
+                                   const uint8_t *has_map, uint32_t n, uint32_t *pairs, uint64_t cap,
+                                   unsigned long long *count)
 {
+    if (n_failed_dev)
+        n_failed = min(n_failed, *n_failed_dev);
     uint64_t total = (uint64_t)n_failed * n;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -274,18 +277,20 @@ __global__ void subset_prepare_kernel(const uint32_t *items, uint32_t k, uint32_
 
 }  // namespace
 
-hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint64_t *off, const uint32_t *tids,
-                              const uint32_t *failed_bits, const uint8_t *has_map, uint32_t n, uint32_t *pairs,
-                              uint64_t cap, unsigned long long *count, hipStream_t s)
+hipError_t launch_corrections(const uint32_t *failed, uint32_t n_failed, const uint32_t *n_failed_dev,
+                              const uint64_t *off, const uint32_t *tids, const uint32_t *failed_bits,
+                              const uint8_t *has_map, uint32_t n, uint32_t *pairs, uint64_t cap,
+                              unsigned long long *count, hipStream_t s)
 {
     uint64_t total = (uint64_t)n_failed * n;
     if (total == 0)
         return hipSuccess;
-    uint64_t blocks = (total + kBlock - 1) / kBlock;
-    if (blocks > (1u << 20))
-        blocks = 1u << 20;
-    corrections_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(failed, n_failed, off, tids, failed_bits, has_map, n,
-                                                            pairs, cap, count);
+    // a count read on the device is usually far below the bound n_failed:
+    // one full-occupancy grid strides over whatever it is
+    const uint64_t max_blocks = n_failed_dev ? 2048 : (1u << 20);
+    const uint64_t blocks = std::min<uint64_t>((total + kBlock - 1) / kBlock, max_blocks);
+    corrections_kernel<<<(uint32_t)blocks, kBlock, 0, s>>>(failed, n_failed, n_failed_dev, off, tids, failed_bits,
+                                                            has_map, n, pairs, cap, count);
     return hipGetLastError();
 }
 

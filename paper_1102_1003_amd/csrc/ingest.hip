@@ -120,20 +120,66 @@ __global__ void offsets_from_sorted_kernel(const uint32_t *keys, uint64_t nnz, u
 }
 
 // offsets_from_sorted and, in the same pass, the number of adjacent equal
-// (key, value) pairs (an item repeated within one transaction).
+// (key, value) pairs (an item repeated within one transaction).  A thread
+// takes four consecutive pairs with 16-byte loads (the pair before them is a
+// neighbour's: it comes from the lane below, or from memory for lane 0);
+// position nnz, the end, is handled by thread 0.
+__device__ inline void offsets_at(uint64_t k, uint32_t prev, uint32_t cur, uint32_t n, uint64_t *off)
+{
+    // keys prev + 1 .. cur start at k (all of 0 .. cur when k = 0)
+    for (uint32_t a = k == 0 ? 0u : prev + 1u; a <= cur && a <= n; a++)
+        off[a] = k;
+}
+
 __global__ void offsets_and_dups_kernel(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t n,
                                         uint64_t *off, uint32_t *n_dup)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t quads = nnz / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t lane = threadIdx.x & 63u;
     uint32_t dups = 0;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nnz; k += stride) {
-        const uint32_t cur = k == nnz ? n : keys[k];
-        const uint32_t prev = k == 0 ? 0u : keys[k - 1];
-        uint32_t lo = k == 0 ? 0u : prev + 1u;  // first key not yet started
-        for (uint32_t a = lo; a <= cur && a <= n; a++)
-            off[a] = k;
-        dups += (k > 0 && k < nnz && cur == prev && vals[k] == vals[k - 1]) ? 1u : 0u;
+    // full quads, in rounds that keep every lane of a wavefront active
+    const uint64_t rounds = (quads + stride - 1) / stride;
+    for (uint64_t r = 0; r < rounds; r++) {
+        const uint64_t q = r * stride + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const bool live = q < quads;
+        uint4 kv = make_uint4(0, 0, 0, 0), vv = make_uint4(0, 0, 0, 0);
+        if (live) {
+            kv = reinterpret_cast<const uint4 *>(keys)[q];
+            vv = reinterpret_cast<const uint4 *>(vals)[q];
+        }
+        // the pair before this quad: the lane below's last, or loaded
+        uint32_t pk = __shfl_up(kv.w, 1, 64), pv = __shfl_up(vv.w, 1, 64);
+        if (live && lane == 0 && q > 0) {
+            pk = keys[4 * q - 1];
+            pv = vals[4 * q - 1];
+        }
+        if (live) {
+            const uint64_t k = 4 * q;
+            const uint32_t ks[4] = {kv.x, kv.y, kv.z, kv.w}, vs[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t prev = e == 0 ? pk : ks[e - 1], prevv = e == 0 ? pv : vs[e - 1];
+                const bool first = k + e == 0;
+                if (first || ks[e] != prev)
+                    offsets_at(k + e, prev, ks[e], n, off);
+                else if (vs[e] == prevv)
+                    dups++;
+            }
+        }
     }
+    // the tail (fewer than four pairs) and the end position
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nnz - 4 * quads) {
+        const uint64_t k = 4 * quads + g;
+        const uint32_t cur = keys[k], prev = k == 0 ? 0u : keys[k - 1];
+        if (k == 0 || cur != prev)
+            offsets_at(k, prev, cur, n, off);
+        else if (vals[k] == vals[k - 1])
+            dups++;
+    }
+    if (g == 0)
+        offsets_at(nnz, nnz == 0 ? 0u : keys[nnz - 1], n, n, off);
     if (dups)
         atomicAdd(n_dup, dups);
 }
@@ -169,7 +215,10 @@ hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row
 hipError_t launch_offsets_and_dups(const uint32_t *keys, const uint32_t *vals, uint64_t nnz, uint32_t n, uint64_t *off,
                                   uint32_t *n_dup, hipStream_t s)
 {
-    offsets_and_dups_kernel<<<blocks_for(nnz + 1, 4096), kBlock, 0, s>>>(keys, vals, nnz, n, off, n_dup);
+    // the kernel reads keys and vals 16 bytes at a time
+    if (((uintptr_t)keys | (uintptr_t)vals) & 15u)
+        return hipErrorInvalidValue;
+    offsets_and_dups_kernel<<<blocks_for(nnz / 4 + 4, 4096), kBlock, 0, s>>>(keys, vals, nnz, n, off, n_dup);
     return hipGetLastError();
 }
 

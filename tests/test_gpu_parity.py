@@ -96,6 +96,18 @@ def test_forced_failures_are_corrected(ctx, max_loop):
     np.testing.assert_array_equal(supports_dev(idx, 60), oracle.all_pairs(off, tids))
 
 
+def test_failures_past_the_first_failure_list(ctx):
+    # more failures than the build's first failure list holds: the build is
+    # repeated with a longer one, and the corrections queued behind the first
+    # attempt are made again
+    off, tids = instance(13, 20000, 60, 0.2, 0.4)
+    assert tids.size > 1 << 16
+    idx = bm.Index.from_sets(ctx, 20000, off, tids, max_loop=0)
+    assert idx.stats()["n_failed"] == tids.size
+    np.testing.assert_array_equal(supports_dev(idx, 60), oracle.all_pairs(off, tids))
+    idx.close()
+
+
 @pytest.mark.parametrize("max_loop", [0, 1])
 def test_corrections_list_regrows(ctx, monkeypatch, max_loop):
     # a first correction list of one entry: the exact-size second pass
@@ -182,6 +194,29 @@ def test_transactions_path_with_repeats_and_shuffled_rows(ctx):
     np.testing.assert_array_equal(idx.frequent_pairs(30), oracle.frequent_pairs(soff, stids, 30))
 
 
+
+def test_transactions_ragged_counts_and_repeats(ctx):
+    # incidence counts around the four-pair step of the offsets pass and the
+    # 64-lane step of its neighbour exchange, with repeated items that fall
+    # on both sides of those steps, and items that never occur
+    rng = np.random.default_rng(17)
+    for total in (0, 1, 2, 3, 4, 5, 7, 8, 9, 255, 256, 257, 1023, 4099):
+        n = int(rng.integers(2, 40))
+        m = max(1, total // 3)
+        rows = np.sort(rng.integers(0, m, total))
+        items = rng.integers(0, n - 1, total).astype(np.uint32)  # item n - 1 never occurs
+        if total > 8:
+            items[5:9] = items[4]      # repeats across a four-pair border
+            rows[5:9] = rows[4]
+            rows = np.sort(rows)
+        roff = np.zeros(m + 1, dtype=np.uint64)
+        np.cumsum(np.bincount(rows, minlength=m), out=roff[1:])
+        soff, stids = oracle.transpose(m, roff, items, n)
+        idx = bm.Index.from_transactions(ctx, n, dev(roff), dev(items))
+        assert idx.stats()["nnz"] == stids.size, total
+        np.testing.assert_array_equal(supports_dev(idx, n), oracle.all_pairs(soff, stids), err_msg=str(total))
+
+
 # ---------------------------------------------------------------- structure
 
 def test_exported_batmaps_pass_the_structural_check(ctx):
@@ -210,9 +245,11 @@ def test_exported_batmaps_pass_the_structural_check(ctx):
         assert np.all(np.diff(sizes.astype(np.int64)) >= 0)
 
 
-@pytest.mark.parametrize("n,min_support", [(1, 0), (37, 0), (4096, 3), (4097, 0), (9000, 5)])
-def test_size_order_is_by_size_then_id(ctx, n, min_support):
-    # one-workgroup sort up to 4096 maps, radix sort above: the same order
+@pytest.mark.parametrize("n,min_support,order", [(1, 0, 2), (37, 0, 2), (4096, 3, 2), (4097, 0, 2), (9000, 5, 2),
+                                                 (37, 0, 3), (4096, 3, 3)])
+def test_size_order_is_by_size_then_id(ctx, n, min_support, order):
+    # up to 4096 maps of order two: sorted on the host; of order three: by one
+    # workgroup on the device; more: a device radix sort.  The same order.
     rng = np.random.default_rng(n)
     m = 3000
     sizes = rng.integers(0, 24, size=n)
@@ -220,12 +257,13 @@ def test_size_order_is_by_size_then_id(ctx, n, min_support):
     np.cumsum(sizes, out=off[1:])
     tids = np.concatenate([np.sort(rng.choice(m, size=int(k), replace=False)) for k in sizes]
                           + [np.zeros(0, np.int64)]).astype(np.uint32)
-    idx = bm.Index.from_sets(ctx, m, off, tids, min_support=min_support)
+    idx = bm.Index.from_sets(ctx, m, off, tids, min_support=min_support, order=order)
     ex = idx.export()
-    order = np.lexsort((np.arange(n), sizes))
-    np.testing.assert_array_equal(ex["sorted_items"], order[sizes[order] >= min_support])
-    for item, r in zip(ex["sorted_items"], ex["r"]):
-        assert r == oracle.r_for(int(sizes[item]), ex["stats"]["r0"])
+    want = np.lexsort((np.arange(n), sizes))
+    np.testing.assert_array_equal(ex["sorted_items"], want[sizes[want] >= min_support])
+    if order == 2:
+        for item, r in zip(ex["sorted_items"], ex["r"]):
+            assert r == oracle.r_for(int(sizes[item]), ex["stats"]["r0"])
     idx.close()
 
 
