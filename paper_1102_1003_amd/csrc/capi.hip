@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -510,7 +511,12 @@ bool single_launch(const bm_context *ctx, uint32_t planes) { return use_persiste
 constexpr uint32_t kPlanAtBuild = 4096;
 
 // Items a plan aims at: about 64 per CU.
-uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 64; }
+// Work items a plan aims for: 192 a compute unit, 12 per wave slot (16 waves
+// a CU).  A launch ends as its last items drain, so the tail costs about half
+// an item's time; at 64 a CU (items of about 1 ms in the large Zipf compare)
+// that was 11 % of the compare, and 192 ran it 3.5 % faster.  More, shorter
+// items gained nothing further (each loads its rows and adds its counts).
+uint64_t target_items(bm_context *ctx) { return (uint64_t)ctx->n_cu * 192; }
 
 // Host data to and from the device, through pinned buffers of the context
 // (defined with the read-back below): the copies are asynchronous, and the
@@ -568,15 +574,65 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, bool single, DevBuf<WorkI
 // the index holds it for the context's current tile speeds.  st: the stream
 // its upload goes on (the context's when null; another one must already be
 // ordered after the context's stream, whose pool the plan's buffer comes from).
-bm_status ensure_plan(bm_index *idx, uint32_t first, hipStream_t st = nullptr)
+// early (optional): the same plan, already being made on another thread
+// (start_plan); taken instead of planning here.
+struct PlanArgs {
+    std::vector<Cls> cls;
+    uint64_t target = 0;
+    bool single = false;
+    int forced = -1;
+    uint32_t planes = 8;
+    bool packed = false;
+};
+
+PlanArgs plan_args(const bm_index *idx, uint32_t first)
+{
+    bm_context *ctx = idx->ctx;
+    PlanArgs a;
+    a.cls = classes_from(idx->classes, first);
+    a.target = target_items(ctx);
+    a.single = single_launch(ctx, idx->planes);
+    a.forced = forced_variant();
+    a.planes = idx->planes;
+    a.packed = packed_rows();
+    return a;
+}
+
+Plan make_plan(const PlanArgs &a)
+{
+    Plan plan;
+    plan_classes(a.cls, 0, a.target, plan, nullptr, a.single ? 1 : 0, a.forced, false, a.planes, a.packed);
+    return plan;
+}
+
+// The all-pairs plan over sorted indices >= first made on a host thread, from
+// values read here (the planner only reads them), for ensure_plan to take;
+// invalid when no thread could be started (ensure_plan then plans itself).
+std::future<Plan> start_plan(const bm_index *idx, uint32_t first)
+{
+    try {
+        return std::async(std::launch::async, [a = plan_args(idx, first)]() { return make_plan(a); });
+    } catch (...) {
+        return std::future<Plan>();
+    }
+}
+
+bm_status ensure_plan(bm_index *idx, uint32_t first, hipStream_t st = nullptr, std::future<Plan> *early = nullptr)
 {
     bm_context *ctx = idx->ctx;
     if (idx->planned_first == first && idx->planned_gen == ctx->tune_gen)
         return BM_OK;
     Plan plan;
     const bool single = single_launch(ctx, idx->planes);
-    plan_classes(classes_from(idx->classes, first), 0, target_items(ctx), plan, nullptr, single ? 1 : 0,
-                 forced_variant(), false, idx->planes, packed_rows());
+    if (early && early->valid()) {
+        try {
+            plan = early->get();
+        } catch (...) {
+            return fail(ctx, BM_ENOMEM, "planning the all-pairs compare");
+        }
+    } else {
+        plan = make_plan(plan_args(idx, first));
+    }
     bm_status e = upload_plan(idx, plan, single, idx->work, idx->work_ranges, st);
     if (e != BM_OK)
         return e;
@@ -919,8 +975,9 @@ bm_status corr_finish(bm_index *idx, const uint32_t *failed_bits, const uint8_t 
 // The block family's construction.  done: the maps are built (else the chain
 // family builds them); corr_done: the corrections are made too (queued right
 // behind the build and read back with its counters, one wait for both).
+// early: the all-pairs plan being made on another thread, or null.
 bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t> &failed_bits, uint64_t fb_words,
-                          const uint8_t *has_map, bool &done, bool &corr_done)
+                          const uint8_t *has_map, std::future<Plan> *early, bool &done, bool &corr_done)
 {
     bm_context *ctx = idx->ctx;
     hipStream_t s = ctx->stream;
@@ -974,10 +1031,10 @@ bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t
     for (int attempt = 0;; attempt++) {
         HIPC(ctx, idx->failed.alloc(2 * fail_cap));
         HIPC(ctx, fill_u32(counters.p, 4, 0, s));
-        // the all-pairs plan is made on the host while the kernels run, and
-        // uploaded on a side stream beside them: after everything queued
-        // before the build (its buffer comes from this stream's pool), and
-        // before anything queued after it
+        // the all-pairs plan (made on the host while the kernels run) is
+        // uploaded on a side stream beside the build: after everything queued
+        // before it (its buffer comes from this stream's pool), and before
+        // anything queued after it
         const bool plan_here = attempt == 0 && n - first <= kPlanAtBuild;
         if (plan_here) {
             BMC(create_side(ctx));
@@ -994,7 +1051,7 @@ bm_status block_construct(bm_index *idx, const bm_build_opts *o, DevBuf<uint32_t
                                          failed_bits.p, has_map, n, idx->corr.p, corr_cap, corr_cnt, s));
         if (plan_here) {
             HIPC(ctx, hipStreamWaitEvent(ctx->side[0], ctx->fork, 0));
-            bm_status st = ensure_plan(idx, first, ctx->side[0]);
+            bm_status st = ensure_plan(idx, first, ctx->side[0], early);
             if (st != BM_OK)
                 return st;
             HIPC(ctx, hipEventRecord(ctx->join[0], ctx->side[0]));
@@ -1207,6 +1264,13 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             idx->classes.push_back({r, p, 0});
         idx->classes.back().count++;
     }
+    // the all-pairs plan depends only on the width classes: a host thread
+    // makes it from here on while the construction's kernels run (indexes of
+    // up to kPlanAtBuild maps; larger ones are mostly queried by subsets, and
+    // planning all their pairs takes longer than building them)
+    std::future<Plan> early_plan;
+    if (!order3 && n - first_built <= kPlanAtBuild)
+        early_plan = start_plan(idx, first_built);
 
     // construction, in batches of maps whose staging fits the budget
     span_layout.end();
@@ -1225,7 +1289,7 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
         const char *bb_env = getenv("BM_BLOCK_BUILD");
         if (!(bb_env && atoi(bb_env) == 0) && !order3 && idx->planes == 8 && !o->perm[0] && first_built < n &&
             idx->r0 <= block_build_max_r0()) {
-            st = block_construct(idx, o, failed_bits, fb_words, has_map.p, block_done, corr_done);
+            st = block_construct(idx, o, failed_bits, fb_words, has_map.p, &early_plan, block_done, corr_done);
             if (st != BM_OK)
                 return st;
         }
@@ -1363,12 +1427,9 @@ bm_status build_common(bm_index *idx, const bm_build_opts *o)
             st = join_side(ctx, n_side);
             if (st != BM_OK)
                 return st;
-            // the all-pairs plan depends only on the width classes: make and
-            // upload it on the host while the construction kernels run (indexes of
-            // up to kPlanAtBuild maps; larger ones are mostly queried by subsets,
-            // and planning all their pairs takes longer than building them)
+            // the all-pairs plan, uploaded while the construction kernels run
             if (attempt == 0 && !order3 && n - idx->first_built <= kPlanAtBuild) {
-                st = ensure_plan(idx, idx->first_built);
+                st = ensure_plan(idx, idx->first_built, nullptr, &early_plan);
                 if (st != BM_OK)
                     return st;
             }
@@ -3449,6 +3510,9 @@ bm_status bm_server_create(bm_index *idx, const bm_server_opts *opts, bm_server 
         return fail(ctx, BM_EINVAL, "the server's launches compare the paper's 8-bit 2-of-3 maps; this index has "
                     "%u-bit slots or order-3 maps", idx->planes);
     HIPC(ctx, hipSetDevice(idx->device));
+    // the server's streams do not wait for the context's: whatever the index
+    // still has queued there (a build's last corrections pass) ends first
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
     std::unique_ptr<bm_server> srv(new (std::nothrow) bm_server());
     if (!srv)
         return fail(ctx, BM_ENOMEM, "host allocation");

@@ -139,12 +139,48 @@ namespace {
 // that share a row tile's range run on the XCD that holds those rows.  When a
 // queue runs dry its positions take items from the fullest queue.
 
+// Numbers of distinct keys in order of first appearance: open addressing in
+// a power-of-two table of at least twice the keys it will see.
+struct FirstSeen {
+    std::vector<uint64_t> key;
+    std::vector<uint32_t> id;
+    std::vector<uint8_t> used;
+    uint64_t mask = 0;
+    uint32_t next = 0;
+    void reset(size_t n)
+    {
+        size_t cap = 16;
+        while (cap < 2 * n)
+            cap <<= 1;
+        if (key.size() < cap) {
+            key.resize(cap);
+            id.resize(cap);
+        }
+        used.assign(cap, 0);
+        mask = cap - 1;
+        next = 0;
+    }
+    uint32_t of(uint64_t k)
+    {
+        uint64_t h = k * 0x9E3779B97F4A7C15ull;
+        h = (h ^ (h >> 29)) & mask;
+        while (used[h] && key[h] != k)
+            h = (h + 1) & mask;
+        if (!used[h]) {
+            used[h] = 1;
+            key[h] = k;
+            id[h] = next++;
+        }
+        return id[h];
+    }
+};
+
 void xcd_order(std::vector<WorkItem> &v)
 {
     std::vector<WorkItem> out;
     out.reserve(v.size());
     std::vector<std::vector<uint32_t>> q(kXcds);
-    std::unordered_map<uint64_t, uint32_t> group_of;
+    FirstSeen group_of;
     size_t s = 0;
     while (s < v.size()) {
         size_t e = s + 1;
@@ -153,7 +189,7 @@ void xcd_order(std::vector<WorkItem> &v)
             e++;
         for (auto &x : q)
             x.clear();
-        group_of.clear();
+        group_of.reset(e - s);
         // a group's items are mostly consecutive: the previous key first
         uint64_t last_key = ~0ull;
         uint32_t last_g = 0;
@@ -161,7 +197,7 @@ void xcd_order(std::vector<WorkItem> &v)
             // (instance, range, row tile); a rare clash of keys only merges two groups
             const uint64_t key = (((uint64_t)v[t].c0 << 32) | v[t].row0) ^ ((uint64_t)v[t].inst << 52);
             if (key != last_key) {
-                last_g = group_of.emplace(key, (uint32_t)group_of.size()).first->second;
+                last_g = group_of.of(key);
                 last_key = key;
             }
             q[last_g % kXcds].push_back((uint32_t)t);

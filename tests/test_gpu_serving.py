@@ -102,6 +102,26 @@ def test_concurrent_queries_equal_single_calls(ctx):
     srv.close()
 
 
+def test_server_right_after_a_build_with_a_second_corrections_pass(ctx, monkeypatch):
+    # a first corrections list of one entry: the build's exact-size pass is
+    # queued after its last wait, and the server's streams must not start
+    # before it has ended
+    monkeypatch.setenv("BM_CORR_CAP", "1")
+    m, n = 50_000, 200
+    off, tids = datagen.bernoulli_sets(m, n, 0.03, seed=31)
+    idx = bm.Index.from_sets(ctx, m, off, tids, max_loop=1)
+    srv = bm.Server(idx, streams=2, memory_budget=16 << 20, max_batch=4)
+    rng = np.random.default_rng(32)
+    queries = [rng.choice(n, size=k, replace=False).astype(np.uint32) for k in (2, 17, 60, 200)]
+    ids = [srv.submit(q) for q in queries]
+    for q, i in zip(queries, ids):
+        got, info = srv.wait(i, timeout_s=60.0)
+        np.testing.assert_array_equal(got, oracle.subset_pairs(off, tids, q))
+    assert idx.stats()["n_corrections"] > 1
+    srv.close()
+    idx.close()
+
+
 def test_tight_memory_admission(ctx, data):
     m, n, off, tids = data
     idx = bm.Index.from_sets(ctx, m, off, tids)
