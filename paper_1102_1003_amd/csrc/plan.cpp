@@ -318,12 +318,30 @@ void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64
             plen = divisor_at_most(g.Gmin, plen, align);
         pieces = (span + plen - 1) / plen;
         const uint16_t base_flags = (uint16_t)((rows ? 2u : 0u) | (V.multi >= 0 ? (uint32_t)V.multi << 2 : 0u));
-        // range-major order: all tiles of range k before range k + 1, so the
-        // waves running at one time share one range of the maps
+        // A launch ends as its last items drain: the last range of every tile
+        // of a row-resident group is cut in two (each half a multiple of the
+        // step, and at least half of min_steps groups of work: the few short
+        // items add few flushes), and longest first puts the halves at the
+        // end.  (Large Zipf compare 0.6 % faster; at the full min_steps no
+        // range is cut there.  Staged items, with more fixed work each, ran
+        // 2 % slower cut so.)
+        std::vector<std::pair<uint64_t, uint64_t>> ranges;
         for (uint32_t k = 0; k < pieces; k++) {
             const uint64_t c0 = (uint64_t)k * plen, c1 = std::min<uint64_t>(span, c0 + plen);
             if (c1 <= c0)
                 continue;
+            const uint64_t half = (c1 - c0) / 2 / align * align;
+            if (rows && pieces > 1 && k + 1 == pieces && half > 0 && (double)(half * unit) >= min_steps / 2) {
+                ranges.push_back({c0, c0 + half});
+                ranges.push_back({c0 + half, c1});
+            } else {
+                ranges.push_back({c0, c1});
+            }
+        }
+        // range-major order: all tiles of range k before range k + 1, so the
+        // waves running at one time share one range of the maps
+        for (const auto &range : ranges) {
+            const uint64_t c0 = range.first, c1 = range.second;
             for (const Tile &t : g.tiles) {
                 WorkItem w;
                 w.row0 = t.row0;
