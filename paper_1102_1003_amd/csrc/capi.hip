@@ -570,12 +570,8 @@ bm_status upload_plan(bm_index *idx, const Plan &plan, bool single, DevBuf<WorkI
     return BM_OK;
 }
 
-// The all-pairs plan of an index over sorted indices >= first, made unless
-// the index holds it for the context's current tile speeds.  st: the stream
-// its upload goes on (the context's when null; another one must already be
-// ordered after the context's stream, whose pool the plan's buffer comes from).
-// early (optional): the same plan, already being made on another thread
-// (start_plan); taken instead of planning here.
+// What the all-pairs planner reads, taken on the calling thread so that the
+// plan can be made on another.
 struct PlanArgs {
     std::vector<Cls> cls;
     uint64_t target = 0;
@@ -617,6 +613,12 @@ std::future<Plan> start_plan(const bm_index *idx, uint32_t first)
     }
 }
 
+// The all-pairs plan of an index over sorted indices >= first, made unless
+// the index holds it for the context's current tile speeds.  st: the stream
+// its upload goes on (the context's when null; another one must already be
+// ordered after the context's stream, whose pool the plan's buffer comes from).
+// early (optional): the same plan, already being made on another thread
+// (start_plan); taken instead of planning here.
 bm_status ensure_plan(bm_index *idx, uint32_t first, hipStream_t st = nullptr, std::future<Plan> *early = nullptr)
 {
     bm_context *ctx = idx->ctx;
