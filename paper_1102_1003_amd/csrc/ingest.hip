@@ -20,36 +20,63 @@ uint32_t blocks_for(uint64_t n, uint32_t cap = 1u << 20)
 
 // row_of[k] = b for every k in transaction b.  A wavefront takes 64
 // consecutive transactions, keeps their offsets in LDS and writes their
-// incidences in order, 64 at a time; lane k finds its transaction by binary
-// search (the last offset <= k, which skips empty transactions).
+// incidences in order, 256 at a time: a lane takes four consecutive ones,
+// finds the first one's transaction by binary search (the last offset <= k,
+// which skips empty transactions), steps forward for the other three and
+// stores the four at once.
 __global__ void expand_rows_kernel(const uint64_t *row_off, uint32_t m, uint32_t *row_of)
 {
-    __shared__ uint64_t offs_all[kBlock / 64][65];
+    __shared__ uint32_t offs_all[kBlock / 64][65];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
-    uint64_t *offs = offs_all[wave];
+    uint32_t *offs = offs_all[wave];
     const uint64_t n_blocks = ((uint64_t)m + 63) / 64;
     const uint64_t stride = (uint64_t)gridDim.x * (blockDim.x / 64u);
     for (uint64_t rb = (uint64_t)blockIdx.x * (blockDim.x / 64u) + wave; rb < n_blocks; rb += stride) {
         const uint64_t b0 = rb * 64;
         const uint32_t rows = (uint32_t)(m - b0 < 64 ? m - b0 : 64);
-        offs[lane] = row_off[b0 + (lane < rows ? lane : rows)];
+        // the block's row starts relative to its first element (an index
+        // holds fewer than 2^32 incidences)
+        const uint64_t first = row_off[b0];
+        offs[lane] = (uint32_t)(row_off[b0 + (lane < rows ? lane : rows)] - first);
         if (lane == 0)
-            offs[64] = row_off[b0 + rows];
+            offs[64] = (uint32_t)(row_off[b0 + rows] - first);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint64_t first = offs[0], end = offs[64];
-        for (uint64_t k = first + lane; k < end; k += 64) {
-            uint32_t lo = 0, hi = rows;  // offs[lo] <= k < offs[hi]
+        const uint32_t len = offs[64];
+        // four consecutive outputs a lane, in quads aligned to four elements;
+        // the partial quads at either end hold other blocks' elements too
+        const uint64_t q0 = first & ~3ull;
+        for (uint64_t a = q0 + 4ull * lane; a < first + len; a += 256) {
+            const int64_t rel = (int64_t)(a - first);  // -3 .. -1 in the first quad
+            const uint32_t k0 = rel < 0 ? 0u : (uint32_t)rel;
+            uint32_t lo = 0, hi = rows;  // offs[lo] <= k0 < offs[hi]
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (offs[mid] <= k)
+                if (offs[mid] <= k0)
                     lo = mid;
                 else
                     hi = mid;
             }
-            row_of[k] = (uint32_t)(b0 + lo);
+            uint32_t v[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int64_t k = rel + j;
+                if (k >= 0 && k < (int64_t)len) {
+                    while (offs[lo + 1] <= (uint32_t)k)
+                        lo++;
+                }
+                v[j] = (uint32_t)(b0 + lo);
+            }
+            if (rel >= 0 && rel + 4 <= (int64_t)len) {
+                *reinterpret_cast<uint4 *>(row_of + a) = make_uint4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (rel + j >= 0 && rel + j < (int64_t)len)
+                        row_of[a + j] = v[j];
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -208,6 +235,9 @@ __global__ void validate_sets_kernel(const uint64_t *off, const uint32_t *tids, 
 
 hipError_t launch_expand_rows(const uint64_t *row_off, uint32_t m, uint32_t *row_of, hipStream_t s)
 {
+    // the kernel stores four row ids at a time at 16-byte aligned positions
+    if (reinterpret_cast<uintptr_t>(row_of) & 15u)
+        return hipErrorInvalidValue;
     expand_rows_kernel<<<blocks_for(((uint64_t)m + 63) / 64 * 64, 8192), kBlock, 0, s>>>(row_off, m, row_of);
     return hipGetLastError();
 }

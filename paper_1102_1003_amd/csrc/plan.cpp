@@ -175,17 +175,19 @@ struct FirstSeen {
     }
 };
 
-void xcd_order(std::vector<WorkItem> &v)
+// order: the items of v in launch order so far (positions in v), rewritten
+// in place.  Items are only read here; the caller gathers them once.
+void xcd_order(const std::vector<WorkItem> &v, std::vector<uint32_t> &order)
 {
-    std::vector<WorkItem> out;
-    out.reserve(v.size());
+    std::vector<uint32_t> out;
+    out.reserve(order.size());
     std::vector<std::vector<uint32_t>> q(kXcds);
     FirstSeen group_of;
     size_t s = 0;
-    while (s < v.size()) {
+    while (s < order.size()) {
         size_t e = s + 1;
-        const uint64_t c = item_cost(v[s]);
-        while (e < v.size() && item_cost(v[e]) == c)
+        const uint64_t c = item_cost(v[order[s]]);
+        while (e < order.size() && item_cost(v[order[e]]) == c)
             e++;
         for (auto &x : q)
             x.clear();
@@ -195,7 +197,8 @@ void xcd_order(std::vector<WorkItem> &v)
         uint32_t last_g = 0;
         for (size_t t = s; t < e; t++) {
             // (instance, range, row tile); a rare clash of keys only merges two groups
-            const uint64_t key = (((uint64_t)v[t].c0 << 32) | v[t].row0) ^ ((uint64_t)v[t].inst << 52);
+            const WorkItem &w = v[order[t]];
+            const uint64_t key = (((uint64_t)w.c0 << 32) | w.row0) ^ ((uint64_t)w.inst << 52);
             if (key != last_key) {
                 last_g = group_of.of(key);
                 last_key = key;
@@ -213,11 +216,11 @@ void xcd_order(std::vector<WorkItem> &v)
                         x = y;
                     }
             }
-            out.push_back(v[q[x][head[x]++]]);
+            out.push_back(order[q[x][head[x]++]]);
         }
         s = e;
     }
-    v.swap(out);
+    order.swap(out);
 }
 
 // Speed of shape v at a wrap bucket: the measured table when given and
@@ -605,8 +608,8 @@ void order_launch(std::vector<WorkItem> &v)
 {
     if (v.empty())
         return;
-    std::vector<WorkItem> sorted;
-    std::vector<uint64_t> costs, item_bucket(v.size());
+    std::vector<uint64_t> costs;
+    std::vector<uint32_t> item_bucket(v.size());
     std::unordered_map<uint64_t, uint32_t> bucket_of;
     // items come in runs of one cost (a class pair's range), so the
     // previous item's bucket is checked before the map
@@ -634,11 +637,29 @@ void order_launch(std::vector<WorkItem> &v)
         start[rank[item_bucket[t]] + 1]++;
     for (size_t b = 0; b < costs.size(); b++)
         start[b + 1] += start[b];
-    sorted.resize(v.size());
+    // the order as positions in v (a stable sort by cost, longest first),
+    // then the XCD order, then the items moved into it in place, a cycle of
+    // the permutation at a time (new item slot t takes old item pos[t])
+    std::vector<uint32_t> pos(v.size());
     for (size_t t = 0; t < v.size(); t++)
-        sorted[start[rank[item_bucket[t]]]++] = v[t];
-    v.swap(sorted);
-    xcd_order(v);
+        pos[start[rank[item_bucket[t]]]++] = (uint32_t)t;
+    xcd_order(v, pos);
+    for (size_t i = 0; i < v.size(); i++) {
+        if (pos[i] == i)
+            continue;
+        const WorkItem first = v[i];
+        size_t j = i;
+        for (;;) {
+            const size_t k = pos[j];
+            pos[j] = (uint32_t)j;
+            if (k == i) {
+                v[j] = first;
+                break;
+            }
+            v[j] = v[k];
+            j = k;
+        }
+    }
 }
 
 void plan_classes(const std::vector<Cls> &cls, uint32_t inst, uint64_t target_items, Plan &plan,

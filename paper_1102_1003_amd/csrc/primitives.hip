@@ -172,31 +172,52 @@ hipError_t scan_rec(const In *in, Out *out, uint64_t n, char *tmp, hipStream_t s
 
 // With `bad` set, keys >= limit also set bit 0 of *bad (a validation pass
 // folded into the first histogram).
+// A full tile of 16-byte aligned keys is read 16 bytes a lane, all loads
+// issued before the counting; each wavefront counts into its own histogram.
 __global__ __launch_bounds__(256) void radix_hist_kernel(const uint32_t *keys, uint64_t n, int shift, int bits,
                                                          uint32_t *hist, uint32_t tiles, uint32_t limit,
                                                          uint32_t *bad)
 {
-    __shared__ uint32_t h[256];
+    constexpr int kVec = kRadixTile / 1024;  // 16-byte loads per lane
+    __shared__ uint32_t h[4][256];
     const uint32_t nb = 1u << bits, mask = nb - 1u;
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
-        h[i] = 0;
+    const uint32_t w = threadIdx.x >> 6;
+    for (uint32_t i = threadIdx.x; i < 4 * 256; i += blockDim.x)
+        (&h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t t = blockIdx.x;
     const uint64_t base = (uint64_t)t * kRadixTile;
     bool out = false;
-    for (int r = 0; r < kRadixTile / 256; r++) {
-        uint64_t idx = base + (uint64_t)r * 256 + threadIdx.x;
-        if (idx < n) {
-            const uint32_t k = keys[idx];
-            out |= k >= limit;
-            atomicAdd(&h[(k >> shift) & mask], 1u);
+    if (base + kRadixTile <= n && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + base);
+        uint4 v[kVec];
+#pragma unroll
+        for (int r = 0; r < kVec; r++)
+            v[r] = k4[r * 256 + threadIdx.x];
+#pragma unroll
+        for (int r = 0; r < kVec; r++) {
+            const uint32_t e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                out |= e[j] >= limit;
+                atomicAdd(&h[w][(e[j] >> shift) & mask], 1u);
+            }
+        }
+    } else {
+        for (int r = 0; r < kRadixTile / 256; r++) {
+            const uint64_t idx = base + (uint64_t)r * 256 + threadIdx.x;
+            if (idx < n) {
+                const uint32_t k = keys[idx];
+                out |= k >= limit;
+                atomicAdd(&h[w][(k >> shift) & mask], 1u);
+            }
         }
     }
     if (bad && out)
         atomicOr(bad, 1u);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
-        hist[(uint64_t)i * tiles + t] = h[i];
+        hist[(uint64_t)i * tiles + t] = h[0][i] + h[1][i] + h[2][i] + h[3][i];
 }
 
 // Stable scatter of one tile.  (1) Every wavefront ranks its quarter in input
