@@ -312,7 +312,10 @@ bm_status bm_batch_all_pair_supports(bm_context *ctx, bm_index *const *idx, uint
  * its memory.  Results are identical to bm_subset_pair_supports.
  * The index must stay alive and must not be destroyed while the server
  * runs; other calls on the index may run from the thread that owns the
- * context.  A server's calls are thread-safe among themselves. */
+ * context.  A server's calls are thread-safe among themselves.
+ * bm_server_create first waits for the work queued on the index's context
+ * stream (a build's last passes may still run there); the server's own
+ * streams do not wait for that stream afterwards. */
 typedef struct bm_server bm_server;
 typedef struct {
     uint32_t streams;        /* concurrent launch slots (default 4) */
