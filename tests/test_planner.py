@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1102_1003_amd", "csrc")
 N_SHAPES = 30
 PLANES = [8] * 22 + [16, 16, 32, 32] + [8] * 4   # slot width of each catalogue shape
-CU64 = 256 * 64     # items a full MI355X plan aims at
+CU64 = 256 * 64     # items per launch at 64 a CU
+CU192 = 256 * 192   # items a full MI355X plan aims at
 
 
 @pytest.fixture(scope="module")
@@ -99,6 +100,10 @@ def test_large_instance_all_pairs(checker):
         assert checker(vals, counts, single=single) > 0
     # the skewed instance's nine width classes: the packed plan wins
     checker(vals, counts)
+    assert checker.packed == [0, 1]
+    # at the item count a full MI355X plan aims for (192 a CU), where the
+    # last range of row-resident tiles is halved
+    checker(vals, counts, target=CU192)
     assert checker.packed == [0, 1]
 
 
