@@ -290,7 +290,13 @@ void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64
 {
     // every item should take about the same time: work_per_item of wave time
     const double work_per_item = total_work / (double)std::max<uint64_t>(target_items, 1);
-    for (const TileGroup &g : groups) {
+    // each group's ranges first, then the items (counted, so each shape's list
+    // is allocated once)
+    std::vector<std::vector<std::pair<uint64_t, uint64_t>>> group_ranges(groups.size());
+    std::vector<uint16_t> group_flags(groups.size());
+    std::vector<uint64_t> want(plan.by_variant.size(), 0);
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const TileGroup &g = groups[gi];
         const VariantInfo &V = variant_info(g.v);
         const uint32_t bi = V.bi, bj = V.bj;
         const uint32_t Ga = g.Ga, Gb = g.Gb;
@@ -328,7 +334,7 @@ void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64
         // end.  (Large Zipf compare 0.6 % faster; at the full min_steps no
         // range is cut there.  Staged items, with more fixed work each, ran
         // 2 % slower cut so.)
-        std::vector<std::pair<uint64_t, uint64_t>> ranges;
+        std::vector<std::pair<uint64_t, uint64_t>> &ranges = group_ranges[gi];
         for (uint32_t k = 0; k < pieces; k++) {
             const uint64_t c0 = (uint64_t)k * plen, c1 = std::min<uint64_t>(span, c0 + plen);
             if (c1 <= c0)
@@ -341,22 +347,28 @@ void emit_groups(const std::vector<TileGroup> &groups, double total_work, uint64
                 ranges.push_back({c0, c1});
             }
         }
-        // range-major order: all tiles of range k before range k + 1, so the
-        // waves running at one time share one range of the maps
-        for (const auto &range : ranges) {
-            const uint64_t c0 = range.first, c1 = range.second;
+        group_flags[gi] = base_flags;
+        want[g.v] += ranges.size() * g.tiles.size();
+    }
+    for (size_t v = 0; v < want.size(); v++)
+        plan.by_variant[v].reserve(plan.by_variant[v].size() + want[v]);
+    // range-major order: all tiles of range k before range k + 1, so the
+    // waves running at one time share one range of the maps
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const TileGroup &g = groups[gi];
+        for (const auto &range : group_ranges[gi]) {
             for (const Tile &t : g.tiles) {
                 WorkItem w;
                 w.row0 = t.row0;
                 w.col0 = t.col0;
                 w.nrow = t.nrow;
                 w.ncol = t.ncol;
-                w.c0 = (uint32_t)c0;
-                w.c1 = (uint32_t)c1;
-                w.row_groups = Ga;
-                w.col_groups = Gb;
+                w.c0 = (uint32_t)range.first;
+                w.c1 = (uint32_t)range.second;
+                w.row_groups = g.Ga;
+                w.col_groups = g.Gb;
                 w.inst = g.inst;
-                w.flags = (uint16_t)(base_flags | t.flags);
+                w.flags = (uint16_t)(group_flags[gi] | t.flags);
                 plan.by_variant[g.v].push_back(w);
             }
         }
